@@ -1,0 +1,192 @@
+/*
+ * p3t.h -- C ABI of libp3t.so: the soft-force hot path of the P3T
+ * (particle-particle particle-tree) scheme with individual cut-off radii
+ * (Ishigaki et al. 2021, "GPLUM", PASJ 73), on one AMD MI355X (gfx950).
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers unless the name ends in _host.
+ *   - Particle arrays are in the caller's original order, caller-owned.
+ *     pos3 / vel3 / acc3 are structure-of-arrays FP64 of 3*n doubles:
+ *     x row [0, n), y row [n, 2n), z row [2n, 3n).
+ *   - Units: G = M_* = 1 by default, heliocentric coordinates, no indirect
+ *     term (Section 2.1.1).
+ *   - Calls are asynchronous on the context's HIP stream unless they return
+ *     a host value (documented per call); they allocate only inside
+ *     p3t_reserve or when a capacity must grow.
+ *   - Every call returns a p3t_status.  Argument errors are detected on the
+ *     host before any launch and leave all state unchanged.  Conditions found
+ *     on the device set bits in the context's status word (P3T_FLAG_*), read
+ *     with p3t_get_status.  p3t_last_error() explains the last failure.
+ *   - n = 0 is a valid no-op for every per-particle call.
+ */
+#ifndef P3T_H
+#define P3T_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct p3t_ctx p3t_ctx;
+
+typedef enum {
+  P3T_OK = 0,
+  P3T_ERR_ARG = 1,      /* invalid argument (null pointer, n < 0, bad parameter) */
+  P3T_ERR_CAPACITY = 2, /* caller's output buffer too small; required size returned */
+  P3T_ERR_HIP = 3,      /* HIP runtime error */
+  P3T_ERR_STATE = 4,    /* call order violated (e.g. force before tree) */
+  P3T_ERR_NUMERIC = 5,  /* device reported NaN / coincident particles / step underflow */
+  P3T_ERR_CLUSTER = 6   /* cluster larger than the configured cap */
+} p3t_status;
+
+/* Device status word bits (p3t_get_status). */
+#define P3T_FLAG_COINCIDENT 0x01u     /* two distinct particles at the same position */
+#define P3T_FLAG_NAN 0x02u            /* non-finite force or state */
+#define P3T_FLAG_LIST_OVERFLOW 0x04u  /* interaction list exceeded its capacity (retried internally) */
+#define P3T_FLAG_STACK_OVERFLOW 0x08u /* tree-walk stack exceeded its capacity (retried internally) */
+#define P3T_FLAG_PAIR_OVERFLOW 0x10u  /* neighbour-pair buffer exceeded its capacity (retried internally) */
+#define P3T_FLAG_KMAX 0x20u           /* Hermite step below dt_soft * 2^-k_max */
+#define P3T_FLAG_NSTEPS 0x40u         /* Hermite block-step count limit reached */
+#define P3T_FLAG_BIG_CLUSTER 0x80u    /* a cluster used the large-cluster path */
+
+/* Parameters.  Defaults (p3t_default_params) are the paper's values where it
+ * prints them (Section 3.1: eta = 0.01, eta_0 = 0.1 eta, Rsearch0..3 = 1.1,
+ * 6, 2, 2; Section 2.1.3: Rcut1 = 8; G = M_* = 1) and stated readings where it
+ * does not (gamma = 0.1, Rcut0 = 2, dt_soft = 2 pi / 64, theta = 0.5). */
+typedef struct {
+  double G, m_star;      /* gravitational constant, central mass */
+  double gamma;          /* r_in / r_out of the changeover, 0 < gamma < 1 (eq. (cutfuncW)) */
+  double r_cut0, r_cut1; /* eq. (routi2) */
+  double r_search0, r_search1, r_search2, r_search3; /* eq. (rsearch), eq. (rsearch1) */
+  double dt_soft;        /* soft step */
+  double theta;          /* Barnes-Hut opening angle, >= 0 (0: exact direct sum) */
+  double eta, eta0;      /* Hermite accuracy parameters (Section 3.1) */
+  int32_t multipole;     /* 1: monopole cells, 2: quadrupole cells */
+  int32_t precision;     /* 0: FP64 throughout, 1: mixed (FP32 far field, FP64 near pairs) */
+  int32_t cutoff_mode;   /* 0: individual pair cut-off (eq. (rout2)), 1: shared (eq. (rout1)) */
+  int32_t hill_length;   /* 0: Hill radius from the osculating semi-major axis, 1: from |x| */
+  int32_t n_group_max;   /* max i-particles per interaction group, 1..128 */
+  int32_t n_leaf_max;    /* tree nodes with at most this many particles are opened as leaves */
+  int32_t vran_bins;     /* log-spaced cylindrical-radius bins for the random velocity */
+  int32_t vran_min_count;/* bins with fewer members use the rms over all particles */
+  int32_t k_max;         /* deepest Hermite block level (step dt_soft * 2^-k_max), <= 40 */
+  int32_t cluster_cap;   /* clusters above this size use the one-workgroup large path */
+} p3t_params;
+
+/* Counters and phase times of the last evaluation (p3t_get_stats). */
+typedef struct {
+  int64_t n;            /* particles in the current tree */
+  int64_t n_nodes;      /* tree nodes (2n - 1) */
+  int64_t n_groups;     /* interaction groups */
+  int64_t n_near;       /* i-j evaluations with the changeover (self pairs excluded) */
+  int64_t n_far;        /* i-j evaluations with K = 1 */
+  int64_t n_cell;       /* i-cell multipole evaluations */
+  int64_t n_pairs;      /* neighbour pairs found (directed, = nnz) */
+  int64_t list_entries; /* total interaction-list entries (near + far + cells) */
+  double ms_cutoffs, ms_tree, ms_walk, ms_force, ms_neighbour, ms_hermite; /* event-timed phases */
+  int32_t timing;       /* 1 if the phase times above were measured */
+  int32_t reserved;
+} p3t_stats;
+
+/* Fill *p_host with the defaults described above. */
+void p3t_default_params(p3t_params *p_host);
+
+/* Create a context bound to the current HIP device and to hip_stream (a
+ * hipStream_t; NULL = the null stream).  Validates *p_host (P3T_ERR_ARG).
+ * The context owns all scratch memory; the caller owns every I/O buffer. */
+p3t_status p3t_create(const p3t_params *p_host, void *hip_stream, p3t_ctx **out_host);
+p3t_status p3t_destroy(p3t_ctx *ctx);
+p3t_status p3t_set_stream(p3t_ctx *ctx, void *hip_stream);
+/* Replace the parameters (validated).  Invalidates the tree. */
+p3t_status p3t_set_params(p3t_ctx *ctx, const p3t_params *p_host);
+p3t_status p3t_get_params(p3t_ctx *ctx, p3t_params *p_host);
+
+/* Size scratch for up to n_max particles and nnz_max neighbour pairs.  Not
+ * required (calls grow scratch on demand) but avoids allocation later. */
+p3t_status p3t_reserve(p3t_ctx *ctx, int64_t n_max, int64_t nnz_max);
+
+/* Cut-off and search radii (Hill radius, Section 2.1.1; eq. (routi2);
+ * eq. (rsearch)):  r_out,i = max(Rcut0 r_Hill,i, Rcut1 v_ran,i dt),
+ * r_search,i = Rsearch0 r_out,i + Rsearch1 v_ran,i dt, with v_ran,i the rms
+ * random velocity (|v - v_Kepler|) of the particle's radial bin.  In shared
+ * mode (eq. (rout1)) every r_out,i is replaced by max_k r_out,k before
+ * r_search is formed.  Outputs (n doubles each) r_out, r_search, v_ran
+ * (v_ran nullable). */
+p3t_status p3t_compute_cutoffs(p3t_ctx *ctx, int64_t n, const double *pos3, const double *vel3,
+                               const double *mass, double *r_out, double *r_search, double *v_ran);
+
+/* Build the Barnes-Hut tree over n particles (Morton order, tight bounding
+ * boxes, mass, centre of mass, traceless quadrupole, max search reach per
+ * node) and the interaction groups.  The pointers are read during the call
+ * only (the tree keeps its own sorted copies). */
+p3t_status p3t_build_tree(p3t_ctx *ctx, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                          const double *r_out, const double *r_search);
+
+/* Soft acceleration of every particle of the current tree, eq. (softforce)
+ * divided by m_i with the pair cut-off of eq. (rout2):
+ *   a_i = sum_j G m_j K(r_ij / r_out,ij) (x_j - x_i) / r_ij^3
+ * (star excluded).  Pairs within the search reach are evaluated directly in
+ * FP64 with the changeover K; the rest via particles or multipole cells with
+ * K = 1.  Also collects the neighbour pairs of Section 2.3 for
+ * p3t_neighbour_list.  acc3: 3n doubles, written in original order. */
+p3t_status p3t_compute_soft_force(p3t_ctx *ctx, double *acc3);
+
+/* Neighbour lists (Section 2.3) of the last p3t_compute_soft_force, as CSR in
+ * original indices: row_ptr (n + 1 int64), col (cap int32), rows ascending.
+ * j is in row i iff r_ij < max(r_search,i, r_search,j) and the closest
+ * approach over the soft step is <= Rsearch2 r_out,ij or |v_ij| <
+ * Rsearch3 G (m_i + m_j) / r_ij^2 dt / 2.  Synchronises; *nnz_host = nnz.
+ * If nnz > cap returns P3T_ERR_CAPACITY with *nnz_host set and col
+ * untouched.  label (n int32, nullable) receives the neighbour-cluster index
+ * of every particle (Section 2.3 steps i-iii: the minimum index of its
+ * connected component). */
+p3t_status p3t_neighbour_list(p3t_ctx *ctx, int64_t *row_ptr, int32_t *col, int64_t cap, int64_t *nnz_host,
+                              int32_t *label);
+
+/* Cluster CSR from labels (label[i] = min index of i's cluster): cl_ptr
+ * (n + 1 int32, first n_clusters + 1 used), cl_members (n int32), members
+ * sorted by (cluster, index).  Synchronises; *n_clusters_host set. */
+p3t_status p3t_clusters(p3t_ctx *ctx, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
+                        int64_t *n_clusters_host);
+
+/* Fourth-order Hermite integration of every neighbour cluster over one soft
+ * step with block time steps (Section 2.1.1; Section 2.2 step (5)).  Forces:
+ * central star + all intra-cluster pairs with (1 - K) (eq. (hardforce)),
+ * jerk including dK/dt.  Steps dt_soft * 2^-k from Aarseth's criterion with
+ * eta; the first step uses eta_0 |a|/|jerk| unless dt_hard carries one.
+ * pos3 / vel3 (3n) are updated in place for the listed members.  mass, r_out
+ * (n).  cl_ptr (n_clusters + 1), cl_members (indices into the n particles).
+ * dt_hard (n, nullable) carries each particle's hard step in and out
+ * (<= 0: initial criterion).  e_rel_err (n_clusters, nullable) receives
+ * |E_end - E_start| / |E_start| of eq. (hard) restricted to the cluster;
+ * n_steps (n_clusters int32, nullable) the number of block steps taken.
+ * Clusters of more than 1024 members return P3T_ERR_CLUSTER (nothing is
+ * integrated); malformed cl_ptr / cl_members return P3T_ERR_ARG. */
+p3t_status p3t_hermite_cluster_step(p3t_ctx *ctx, int64_t n, int64_t n_clusters, const int32_t *cl_ptr,
+                                    const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
+                                    const double *r_out, double *dt_hard, double *e_rel_err, int32_t *n_steps);
+
+/* Soft kick, eq. (HamiltonSol): vel3 += h * acc3 (3n each). */
+p3t_status p3t_kick(p3t_ctx *ctx, int64_t n, double h, const double *acc3, double *vel3);
+
+/* Vector-Jacobian product of the soft kick v += h a(x, m) over the current
+ * tree with its interaction lists and pair cut-offs frozen: for the cotangent
+ * lam_v3 (3n) of the velocities, accumulates h * d(lam . a)/dx into g_pos3
+ * (3n) and h * d(lam . a)/dm into g_mass (n).  Requires a prior
+ * p3t_compute_soft_force on the same tree. */
+p3t_status p3t_soft_kick_adjoint(p3t_ctx *ctx, double h, const double *lam_v3, double *g_pos3, double *g_mass);
+
+/* Enable (1) / disable (0) event timing of the phases (p3t_stats). */
+p3t_status p3t_set_timing(p3t_ctx *ctx, int32_t on);
+/* Counters of the last evaluation.  Synchronises. */
+p3t_status p3t_get_stats(p3t_ctx *ctx, p3t_stats *out_host);
+/* Read and clear the device status word.  Synchronises. */
+p3t_status p3t_get_status(p3t_ctx *ctx, uint32_t *flags_host);
+/* Text of the last error on this context (static storage of the context). */
+const char *p3t_last_error(p3t_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* P3T_H */

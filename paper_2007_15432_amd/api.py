@@ -1,0 +1,235 @@
+"""Thin Python binding of libp3t: argument marshalling for torch tensors.
+
+Every computation runs in the library's HIP kernels; this module only checks
+tensor shapes / dtypes / devices and passes device pointers and the current
+HIP stream through the C ABI.  Particle arrays are (3, n) float64 (rows x, y,
+z) or (n,) float64, on the context's GPU, contiguous.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, fields
+
+import torch
+
+from . import _lib
+
+__all__ = ["Params", "Context", "P3TError"]
+
+
+class P3TError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+@dataclass
+class Params:
+    """Mirror of p3t_params (include/p3t.h); defaults from p3t_default_params."""
+
+    G: float = 1.0
+    m_star: float = 1.0
+    gamma: float = 0.1
+    r_cut0: float = 2.0
+    r_cut1: float = 8.0
+    r_search0: float = 1.1
+    r_search1: float = 6.0
+    r_search2: float = 2.0
+    r_search3: float = 2.0
+    dt_soft: float = 0.09817477042468103
+    theta: float = 0.5
+    eta: float = 0.01
+    eta0: float = 0.001
+    multipole: int = 2
+    precision: int = 0
+    cutoff_mode: int = 0
+    hill_length: int = 0
+    n_group_max: int = 128
+    n_leaf_max: int = 16
+    vran_bins: int = 64
+    vran_min_count: int = 8
+    k_max: int = 40
+    cluster_cap: int = 1024
+
+    @classmethod
+    def defaults(cls) -> "Params":
+        cp = _lib.CParams()
+        _lib.load().p3t_default_params(C.byref(cp))
+        return cls(**{f.name: getattr(cp, f.name) for f in fields(cls)})
+
+    def to_c(self) -> _lib.CParams:
+        return _lib.CParams(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+    def replace(self, **kw) -> "Params":
+        d = {f.name: getattr(self, f.name) for f in fields(self)}
+        d.update(kw)
+        return Params(**d)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context bound to a GPU; owns the library's scratch."""
+
+    def __init__(self, params: Params | None = None, device: int | str | torch.device = 0):
+        self.L = _lib.load()
+        idx = device if isinstance(device, int) else (torch.device(device).index or 0)
+        self.device = torch.device("cuda", idx)
+        self.params = params if params is not None else Params.defaults()
+        self.n = 0
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.L.p3t_create(C.byref(self.params.to_c()), C.c_void_p(self._stream()), C.byref(self._h))
+        if st != 0:
+            raise P3TError(st, "p3t_create failed (invalid parameters or no device)")
+
+    # -- plumbing ------------------------------------------------------------
+    def _stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _bind(self):
+        self.L.p3t_set_stream(self._h, C.c_void_p(self._stream()))
+
+    def _check(self, st: int, what: str):
+        if st != 0:
+            msg = self.L.p3t_last_error(self._h)
+            raise P3TError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def _vec3(self, t, n, name):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.device == self.device
+                and tuple(t.shape) == (3, n) and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 (3, {n}) tensor on {self.device}")
+        return t
+
+    def _vec(self, t, n, name, dtype=torch.float64):
+        if not (isinstance(t, torch.Tensor) and t.dtype == dtype and t.device == self.device
+                and tuple(t.shape) == (n,) and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dtype} ({n},) tensor on {self.device}")
+        return t
+
+    def close(self):
+        if self._h:
+            self.L.p3t_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        self._check(self.L.p3t_set_params(self._h, C.byref(params.to_c())), "set_params")
+        self.params = params
+
+    def reserve(self, n_max: int, nnz_max: int = 0):
+        self._check(self.L.p3t_reserve(self._h, int(n_max), int(nnz_max)), "reserve")
+
+    def set_timing(self, on: bool = True):
+        self._check(self.L.p3t_set_timing(self._h, 1 if on else 0), "set_timing")
+
+    def stats(self) -> dict:
+        s = _lib.CStats()
+        self._check(self.L.p3t_get_stats(self._h, C.byref(s)), "get_stats")
+        return {f[0]: getattr(s, f[0]) for f in _lib.CStats._fields_}
+
+    def status(self) -> int:
+        v = C.c_uint32()
+        self._check(self.L.p3t_get_status(self._h, C.byref(v)), "get_status")
+        return int(v.value)
+
+    # -- the hot path --------------------------------------------------------
+    def compute_cutoffs(self, pos, vel, mass):
+        n = int(mass.shape[0])
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        self._vec(mass, n, "mass")
+        ro = torch.empty(n, dtype=torch.float64, device=self.device)
+        rs = torch.empty_like(ro)
+        vr = torch.empty_like(ro)
+        self._bind()
+        self._check(self.L.p3t_compute_cutoffs(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(ro), _ptr(rs),
+                                               _ptr(vr)), "compute_cutoffs")
+        return ro, rs, vr
+
+    def build_tree(self, pos, vel, mass, r_out, r_search):
+        n = int(mass.shape[0])
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        for t, name in ((mass, "mass"), (r_out, "r_out"), (r_search, "r_search")):
+            self._vec(t, n, name)
+        self._bind()
+        self._check(self.L.p3t_build_tree(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(r_out), _ptr(r_search)),
+                    "build_tree")
+        self.n = n
+
+    def compute_soft_force(self, out=None):
+        n = self.n
+        acc = out if out is not None else torch.empty((3, n), dtype=torch.float64, device=self.device)
+        self._vec3(acc, n, "acc")
+        self._bind()
+        self._check(self.L.p3t_compute_soft_force(self._h, _ptr(acc)), "compute_soft_force")
+        return acc
+
+    def neighbour_list(self, labels: bool = True):
+        """(row_ptr int64 (n+1,), col int32 (nnz,), label int32 (n,) or None)."""
+        n = self.n
+        row_ptr = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        label = torch.empty(n, dtype=torch.int32, device=self.device) if labels else None
+        nnz = C.c_int64(0)
+        cap = max(1, getattr(self, "_nnz_hint", 1024))
+        for _ in range(2):
+            col = torch.empty(cap, dtype=torch.int32, device=self.device)
+            self._bind()
+            st = self.L.p3t_neighbour_list(self._h, _ptr(row_ptr), _ptr(col), cap, C.byref(nnz), _ptr(label))
+            if st == _lib.P3T_ERR_CAPACITY:
+                cap = int(nnz.value)
+                self._nnz_hint = cap
+                continue
+            self._check(st, "neighbour_list")
+            return row_ptr, col[: nnz.value], label
+        raise P3TError(_lib.P3T_ERR_CAPACITY, "neighbour_list: capacity retry failed")
+
+    def clusters(self, label):
+        n = int(label.shape[0])
+        self._vec(label, n, "label", torch.int32)
+        cl_ptr = torch.empty(n + 1, dtype=torch.int32, device=self.device)
+        members = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        nc = C.c_int64(0)
+        self._bind()
+        self._check(self.L.p3t_clusters(self._h, n, _ptr(label), _ptr(cl_ptr), _ptr(members), C.byref(nc)),
+                    "clusters")
+        return cl_ptr[: nc.value + 1], members[:n]
+
+    def hermite_cluster_step(self, pos, vel, mass, r_out, cl_ptr, members, dt_hard=None, energy=True,
+                             steps=False):
+        """Integrate every cluster over one soft step in place; returns the
+        per-cluster relative energy error (or None), and with steps=True also
+        the per-cluster block-step counts."""
+        n = int(mass.shape[0])
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        self._vec(mass, n, "mass")
+        self._vec(r_out, n, "r_out")
+        nc = int(cl_ptr.shape[0]) - 1
+        self._vec(cl_ptr, nc + 1, "cl_ptr", torch.int32)
+        self._vec(members, int(members.shape[0]), "members", torch.int32)
+        if dt_hard is not None:
+            self._vec(dt_hard, n, "dt_hard")
+        err = torch.empty(max(nc, 1), dtype=torch.float64, device=self.device) if energy else None
+        nst = torch.empty(max(nc, 1), dtype=torch.int32, device=self.device) if steps else None
+        self._bind()
+        self._check(self.L.p3t_hermite_cluster_step(self._h, n, nc, _ptr(cl_ptr), _ptr(members), _ptr(pos), _ptr(vel),
+                                                    _ptr(mass), _ptr(r_out), _ptr(dt_hard), _ptr(err), _ptr(nst)),
+                    "hermite_cluster_step")
+        e = None if err is None else err[:nc]
+        return (e, nst[:nc]) if steps else e
+
+    def kick(self, acc, vel, h: float):
+        n = int(vel.shape[1])
+        self._vec3(acc, n, "acc")
+        self._vec3(vel, n, "vel")
+        self._bind()
+        self._check(self.L.p3t_kick(self._h, n, float(h), _ptr(acc), _ptr(vel)), "kick")

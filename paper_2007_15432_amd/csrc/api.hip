@@ -1,0 +1,541 @@
+// api.hip -- the C ABI of libp3t (declared in include/p3t.h): context and
+// scratch management, argument checking, capacity growth and retry, phase
+// timing and status reporting.  All compute runs in the kernels of the other
+// translation units; this file only orders launches on the context's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "p3t_internal.h"
+
+using namespace p3t;
+
+namespace {
+
+constexpr unsigned NUMERIC_BITS = P3T_FLAG_COINCIDENT | P3T_FLAG_NAN | P3T_FLAG_KMAX | P3T_FLAG_NSTEPS;
+constexpr unsigned RETRY_BITS = P3T_FLAG_LIST_OVERFLOW | P3T_FLAG_STACK_OVERFLOW | P3T_FLAG_PAIR_OVERFLOW;
+
+p3t_status fail(p3t_ctx *c, p3t_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+p3t_status fail(p3t_ctx *c, p3t_status st, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->last_error = buf;
+  }
+  return st;
+}
+
+#define HIP_OK(c, expr)                                                                              \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess) return fail((c), P3T_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+const char *check_params(const p3t_params &P) {
+  if (!(P.gamma > 0.0 && P.gamma < 1.0)) return "gamma must lie in (0, 1)";
+  if (!(P.G >= 0.0) || !(P.m_star >= 0.0)) return "G and m_star must be >= 0";
+  if (!(P.r_cut0 >= 0.0) || !(P.r_cut1 >= 0.0)) return "r_cut0, r_cut1 must be >= 0";
+  if (!(P.r_search0 >= 0.0) || !(P.r_search1 >= 0.0) || !(P.r_search2 >= 0.0) || !(P.r_search3 >= 0.0))
+    return "r_search0..3 must be >= 0";
+  if (!(P.dt_soft > 0.0) || !std::isfinite(P.dt_soft)) return "dt_soft must be > 0";
+  if (!(P.theta >= 0.0) || !std::isfinite(P.theta)) return "theta must be >= 0";
+  if (!(P.eta > 0.0) || !(P.eta0 > 0.0)) return "eta, eta0 must be > 0";
+  if (P.multipole != 1 && P.multipole != 2) return "multipole must be 1 or 2";
+  if (P.precision != 0 && P.precision != 1) return "precision must be 0 or 1";
+  if (P.cutoff_mode != 0 && P.cutoff_mode != 1) return "cutoff_mode must be 0 or 1";
+  if (P.hill_length != 0 && P.hill_length != 1) return "hill_length must be 0 or 1";
+  if (P.n_group_max < 1 || P.n_group_max > 128) return "n_group_max must be in [1, 128]";
+  if (P.n_leaf_max < 1 || P.n_leaf_max > 256) return "n_leaf_max must be in [1, 256]";
+  if (P.vran_bins < 1 || P.vran_bins > 256) return "vran_bins must be in [1, 256]";
+  if (P.vran_min_count < 1) return "vran_min_count must be >= 1";
+  if (P.k_max < 0 || P.k_max > 40) return "k_max must be in [0, 40]";
+  if (P.cluster_cap < 1) return "cluster_cap must be >= 1";
+  return nullptr;
+}
+
+template <typename T>
+hipError_t dev_alloc(T *&p, int64_t count) {
+  if (p) {
+    hipError_t e = hipFree(p);
+    p = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  if (count <= 0) count = 1;
+  return hipMalloc((void **)&p, (size_t)count * sizeof(T));
+}
+
+// (re)allocate the arena for n_cap particles
+p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
+  if (n_cap < 1024) n_cap = 1024;
+  const int64_t n2 = 2 * n_cap;
+  auto bytes = [](int64_t count, size_t sz) { return ((size_t)count * sz + 255) & ~size_t(255); };
+  const int64_t hist = radix_hist_need(n_cap);
+  const int64_t stmp = scan_tmp_need(std::max<int64_t>(n2 + 1, hist));
+  size_t total = 0;
+  total += bytes(1, sizeof(DevCounters));
+  total += bytes(8 + 6 * 1024, sizeof(double));
+  total += 11 * bytes(n_cap, sizeof(double));
+  total += bytes(n_cap, sizeof(int32_t));                          // sid
+  total += 2 * bytes(n_cap, sizeof(uint64_t)) + 2 * bytes(n_cap, sizeof(int32_t));  // keys, perm
+  total += bytes(hist, sizeof(uint32_t));
+  total += bytes(stmp, sizeof(int64_t));
+  total += bytes(n2, sizeof(int32_t)) + bytes(n_cap, sizeof(int32_t));  // parent, visit
+  total += bytes(n2, sizeof(WalkNode)) + bytes(n2, sizeof(CellMom));
+  total += bytes(n2, sizeof(int32_t)) + bytes(n2 + 1, sizeof(int64_t));  // group_flag, node_scan
+  total += bytes(n_cap, sizeof(int32_t));                               // group_node
+  total += bytes(n_cap, sizeof(GroupList));
+  total += 2 * bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));  // order, keys
+  total += bytes(n_cap, sizeof(int32_t)) + bytes(n_cap + 1, sizeof(int64_t));       // row_cnt, csr_ptr
+  total += bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));      // uf, cl keys
+  total += bytes(cut_part_need(n_cap), sizeof(double));
+  total += bytes(3 * n_cap, sizeof(double));
+  total += bytes(16, sizeof(int32_t)) + bytes(11 * n_cap, sizeof(int32_t));  // hermite buckets
+  total += 4096;
+  if (c->arena.base) {
+    HIP_OK(c, hipFree(c->arena.base));
+    c->arena.base = nullptr;
+  }
+  HIP_OK(c, hipMalloc((void **)&c->arena.base, total));
+  c->arena.size = total;
+  c->arena.used = 0;
+  Arena &A = c->arena;
+  c->cnt = A.take<DevCounters>(1);
+  c->bbox = A.take<double>(8 + 6 * 1024);
+  c->bbox_part = c->bbox + 8;
+  double **soa[11] = {&c->sx, &c->sy, &c->sz, &c->svx, &c->svy, &c->svz, &c->sm, &c->sro, &c->sinv, &c->sreach, &c->srs};
+  for (auto p : soa) *p = A.take<double>(n_cap);
+  c->sid = A.take<int32_t>(n_cap);
+  c->keys = A.take<uint64_t>(n_cap);
+  c->keys_alt = A.take<uint64_t>(n_cap);
+  c->perm = A.take<int32_t>(n_cap);
+  c->perm_alt = A.take<int32_t>(n_cap);
+  c->radix_hist = A.take<uint32_t>(hist);
+  c->radix_hist_cap = hist;
+  c->scan_tmp = A.take<int64_t>(stmp);
+  c->scan_tmp_cap = stmp;
+  c->parent = A.take<int32_t>(n2);
+  c->visit = A.take<int32_t>(n_cap);
+  c->wnode = A.take<WalkNode>(n2);
+  c->cmom = A.take<CellMom>(n2);
+  c->group_flag = A.take<int32_t>(n2);
+  c->node_scan = A.take<int64_t>(n2 + 1);
+  c->group_node = A.take<int32_t>(n_cap);
+  c->glist = A.take<GroupList>(n_cap);
+  c->group_order = A.take<int32_t>(n_cap);
+  c->gorder_alt = A.take<int32_t>(n_cap);
+  c->gkey = A.take<uint64_t>(n_cap);
+  c->gkey_alt = A.take<uint64_t>(n_cap);
+  c->row_cnt = A.take<int32_t>(n_cap);
+  c->csr_ptr = A.take<int64_t>(n_cap + 1);
+  c->uf_parent = A.take<int32_t>(n_cap);
+  c->cl_keys = A.take<uint64_t>(n_cap);
+  c->cl_keys_alt = A.take<uint64_t>(n_cap);
+  c->cut_part = A.take<double>(cut_part_need(n_cap));
+  c->tmp_d = A.take<double>(3 * n_cap);
+  c->herm_bcount = A.take<int32_t>(16);
+  c->herm_blists = A.take<int32_t>(11 * n_cap);
+  if (!c->herm_blists) return fail(c, P3T_ERR_HIP, "arena layout overflow (internal)");
+  HIP_OK(c, hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream));
+  c->n_cap = n_cap;
+  c->tree_valid = c->force_valid = false;
+  return P3T_OK;
+}
+
+p3t_status ensure_n(p3t_ctx *c, int64_t n) {
+  if (n <= c->n_cap) return P3T_OK;
+  return alloc_arena(c, std::max<int64_t>(n, c->n_cap + c->n_cap / 2));
+}
+
+p3t_status ensure_lists(p3t_ctx *c, int64_t n) {
+  if (!c->pool || c->pool_cap < std::max<int64_t>(1 << 20, 32 * n)) {
+    const int64_t cap = std::max<int64_t>(1 << 20, 64 * n);
+    HIP_OK(c, dev_alloc(c->pool, cap));
+    c->pool_cap = cap;
+  }
+  if (!c->slot_lists) {
+    c->walk_slots = c->n_cu * 4;
+    if (c->slot_cap_list == 0) c->slot_cap_list = 16384;
+    if (c->slot_cap_stack == 0) c->slot_cap_stack = 8192;
+    HIP_OK(c, dev_alloc(c->slot_lists, (int64_t)c->walk_slots * 3 * c->slot_cap_list));
+    HIP_OK(c, dev_alloc(c->slot_stack, (int64_t)c->walk_slots * c->slot_cap_stack));
+  }
+  if (!c->pairs) {
+    const int64_t cap = std::max<int64_t>(1 << 16, 2 * n);
+    HIP_OK(c, dev_alloc(c->pairs, cap));
+    HIP_OK(c, dev_alloc(c->csr_col, cap));
+    c->pair_cap = cap;
+  }
+  return P3T_OK;
+}
+
+p3t_status sync_counters(p3t_ctx *c, DevCounters *h) {
+  HIP_OK(c, hipMemcpyAsync(h, c->cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return P3T_OK;
+}
+
+__global__ void k_clear_bits(DevCounters *cnt, unsigned bits) { cnt->status &= ~bits; }
+
+// move numeric bits from the device word into the host-side word
+p3t_status harvest_status(p3t_ctx *c, unsigned *new_bits) {
+  DevCounters h;
+  p3t_status st = sync_counters(c, &h);
+  if (st != P3T_OK) return st;
+  const unsigned bits = h.status;
+  if (bits) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, bits);
+  c->host_status |= bits;
+  if (new_bits) *new_bits = bits;
+  return P3T_OK;
+}
+
+void ev_record(p3t_ctx *c, int k) {
+  if (c->timing) hipEventRecord(c->ev[k], c->stream);
+}
+double ev_ms(p3t_ctx *c, int a, int b) {
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
+  return ms;
+}
+
+bool bad_ptr(const void *p, int64_t n) { return n > 0 && p == nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+void p3t_default_params(p3t_params *P) {
+  if (!P) return;
+  std::memset(P, 0, sizeof(*P));
+  P->G = 1.0;
+  P->m_star = 1.0;
+  P->gamma = 0.1;
+  P->r_cut0 = 2.0;
+  P->r_cut1 = 8.0;
+  P->r_search0 = 1.1;
+  P->r_search1 = 6.0;
+  P->r_search2 = 2.0;
+  P->r_search3 = 2.0;
+  P->dt_soft = 2.0 * M_PI / 64.0;
+  P->theta = 0.5;
+  P->eta = 0.01;
+  P->eta0 = 0.001;
+  P->multipole = 2;
+  P->precision = 0;
+  P->cutoff_mode = 0;
+  P->hill_length = 0;
+  P->n_group_max = 128;
+  P->n_leaf_max = 16;
+  P->vran_bins = 64;
+  P->vran_min_count = 8;
+  P->k_max = 40;
+  P->cluster_cap = 1024;
+}
+
+p3t_status p3t_create(const p3t_params *p, void *stream, p3t_ctx **out) {
+  if (!p || !out) return P3T_ERR_ARG;
+  *out = nullptr;
+  const char *why = check_params(*p);
+  if (why) return P3T_ERR_ARG;
+  p3t_ctx *c = new (std::nothrow) p3t_ctx();
+  if (!c) return P3T_ERR_HIP;
+  c->P = *p;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return P3T_ERR_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  c->force_slots = c->n_cu * 16;
+  c->force_persistent = 1;
+  for (auto &e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return P3T_ERR_HIP;
+    }
+  if (alloc_arena(c, 1024) != P3T_OK) {
+    delete c;
+    return P3T_ERR_HIP;
+  }
+  *out = c;
+  return P3T_OK;
+}
+
+p3t_status p3t_destroy(p3t_ctx *c) {
+  if (!c) return P3T_ERR_ARG;
+  hipStreamSynchronize(c->stream);
+  void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col};
+  for (void *b : bufs)
+    if (b) hipFree(b);
+  for (auto &e : c->ev)
+    if (e) hipEventDestroy(e);
+  delete c;
+  return P3T_OK;
+}
+
+p3t_status p3t_set_stream(p3t_ctx *c, void *stream) {
+  if (!c) return P3T_ERR_ARG;
+  c->stream = (hipStream_t)stream;
+  return P3T_OK;
+}
+
+p3t_status p3t_set_params(p3t_ctx *c, const p3t_params *p) {
+  if (!c || !p) return fail(c, P3T_ERR_ARG, "null argument");
+  const char *why = check_params(*p);
+  if (why) return fail(c, P3T_ERR_ARG, "%s", why);
+  c->P = *p;
+  c->tree_valid = c->force_valid = false;
+  return P3T_OK;
+}
+
+p3t_status p3t_get_params(p3t_ctx *c, p3t_params *p) {
+  if (!c || !p) return P3T_ERR_ARG;
+  *p = c->P;
+  return P3T_OK;
+}
+
+p3t_status p3t_reserve(p3t_ctx *c, int64_t n_max, int64_t nnz_max) {
+  if (!c || n_max < 0 || nnz_max < 0) return fail(c, P3T_ERR_ARG, "reserve: bad argument");
+  p3t_status st = ensure_n(c, n_max);
+  if (st != P3T_OK) return st;
+  if ((st = ensure_lists(c, n_max)) != P3T_OK) return st;
+  if (nnz_max > c->pair_cap) {
+    HIP_OK(c, dev_alloc(c->pairs, nnz_max));
+    HIP_OK(c, dev_alloc(c->csr_col, nnz_max));
+    c->pair_cap = nnz_max;
+    c->force_valid = false;
+  }
+  return P3T_OK;
+}
+
+p3t_status p3t_compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                               double *r_out, double *r_search, double *v_ran) {
+  if (!c) return P3T_ERR_ARG;
+  if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "compute_cutoffs: n out of range");
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(r_search, n))
+    return fail(c, P3T_ERR_ARG, "compute_cutoffs: null pointer");
+  if (n == 0) return P3T_OK;
+  p3t_status st = ensure_n(c, n);
+  if (st != P3T_OK) return st;
+  ev_record(c, 0);
+  HIP_OK(c, compute_cutoffs(c, n, pos3, vel3, mass, r_out, r_search, v_ran));
+  ev_record(c, 1);
+  if (c->timing) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->stats.ms_cutoffs = ev_ms(c, 0, 1);
+  }
+  return P3T_OK;
+}
+
+p3t_status p3t_build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                          const double *r_out, const double *r_search) {
+  if (!c) return P3T_ERR_ARG;
+  if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "build_tree: n out of range");
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(r_search, n))
+    return fail(c, P3T_ERR_ARG, "build_tree: null pointer");
+  c->tree_valid = c->force_valid = false;
+  c->n = n;
+  if (n == 0) {
+    c->tree_valid = true;
+    return P3T_OK;
+  }
+  p3t_status st = ensure_n(c, n);
+  if (st != P3T_OK) return st;
+  if ((st = ensure_lists(c, n)) != P3T_OK) return st;
+  ev_record(c, 2);
+  HIP_OK(c, build_tree(c, n, pos3, vel3, mass, r_out, r_search));
+  ev_record(c, 3);
+  DevCounters h;
+  if ((st = sync_counters(c, &h)) != P3T_OK) return st;
+  c->n_groups = (int64_t)h.n_groups;
+  if (c->timing) c->stats.ms_tree = ev_ms(c, 2, 3);
+  c->stats.n = n;
+  c->stats.n_nodes = 2 * n - 1;
+  c->stats.n_groups = c->n_groups;
+  c->tree_valid = true;
+  return P3T_OK;
+}
+
+p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
+  if (!c) return P3T_ERR_ARG;
+  if (!c->tree_valid) return fail(c, P3T_ERR_STATE, "compute_soft_force: no tree (call p3t_build_tree)");
+  if (bad_ptr(acc3, c->n)) return fail(c, P3T_ERR_ARG, "compute_soft_force: null pointer");
+  c->force_valid = false;
+  if (c->n == 0) {
+    c->n_pairs = 0;
+    c->force_valid = true;
+    return P3T_OK;
+  }
+  p3t_status st;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    ev_record(c, 4);
+    HIP_OK(c, walk_groups(c, c->n_groups));
+    ev_record(c, 5);
+    HIP_OK(c, soft_force(c, c->n_groups, acc3));
+    ev_record(c, 6);
+    DevCounters h;
+    if ((st = sync_counters(c, &h)) != P3T_OK) return st;
+    const unsigned retry = h.status & RETRY_BITS;
+    if (retry) {
+      hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, RETRY_BITS);
+      if (retry & P3T_FLAG_LIST_OVERFLOW) {
+        if ((int64_t)h.pool_cursor > c->pool_cap) {
+          const int64_t cap = (int64_t)h.pool_cursor + (int64_t)h.pool_cursor / 4 + 1024;
+          HIP_OK(c, dev_alloc(c->pool, cap));
+          c->pool_cap = cap;
+        } else {
+          c->slot_cap_list *= 2;
+          HIP_OK(c, dev_alloc(c->slot_lists, (int64_t)c->walk_slots * 3 * c->slot_cap_list));
+        }
+      }
+      if (retry & P3T_FLAG_STACK_OVERFLOW) {
+        c->slot_cap_stack *= 2;
+        HIP_OK(c, dev_alloc(c->slot_stack, (int64_t)c->walk_slots * c->slot_cap_stack));
+      }
+      if (retry & P3T_FLAG_PAIR_OVERFLOW) {
+        const int64_t cap = (int64_t)h.n_pairs + (int64_t)h.n_pairs / 4 + 1024;
+        HIP_OK(c, dev_alloc(c->pairs, cap));
+        HIP_OK(c, dev_alloc(c->csr_col, cap));
+        c->pair_cap = cap;
+      }
+      continue;
+    }
+    c->n_pairs = (int64_t)h.n_pairs;
+    c->stats.n_near = (int64_t)h.n_near;
+    c->stats.n_far = (int64_t)h.n_far;
+    c->stats.n_cell = (int64_t)h.n_cell;
+    c->stats.n_pairs = c->n_pairs;
+    c->stats.list_entries = (int64_t)h.pool_cursor;
+    if (c->timing) {
+      c->stats.ms_walk = ev_ms(c, 4, 5);
+      c->stats.ms_force = ev_ms(c, 5, 6);
+    }
+    const unsigned num = h.status & NUMERIC_BITS;
+    c->host_status |= h.status & ~RETRY_BITS;
+    if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
+    c->force_valid = true;
+    if (num)
+      return fail(c, P3T_ERR_NUMERIC, "compute_soft_force: device status 0x%x (coincident particles or NaN)", num);
+    return P3T_OK;
+  }
+  return fail(c, P3T_ERR_CAPACITY, "compute_soft_force: scratch still too small after repeated growth");
+}
+
+p3t_status p3t_neighbour_list(p3t_ctx *c, int64_t *row_ptr, int32_t *col, int64_t cap, int64_t *nnz_host,
+                              int32_t *label) {
+  if (!c) return P3T_ERR_ARG;
+  if (!c->force_valid) return fail(c, P3T_ERR_STATE, "neighbour_list: call p3t_compute_soft_force first");
+  if (!nnz_host || !row_ptr || cap < 0) return fail(c, P3T_ERR_ARG, "neighbour_list: bad argument");
+  const int64_t n = c->n, np = c->n_pairs;
+  *nnz_host = np;
+  if (n == 0) {
+    HIP_OK(c, hipMemsetAsync(row_ptr, 0, sizeof(int64_t), c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return P3T_OK;
+  }
+  ev_record(c, 7);
+  HIP_OK(c, build_csr(c, n, np));
+  if (np > cap) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return fail(c, P3T_ERR_CAPACITY, "neighbour_list: nnz %lld exceeds cap %lld", (long long)np, (long long)cap);
+  }
+  if (np > 0 && !col) return fail(c, P3T_ERR_ARG, "neighbour_list: null col");
+  HIP_OK(c, hipMemcpyAsync(row_ptr, c->csr_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, c->stream));
+  if (np > 0) HIP_OK(c, hipMemcpyAsync(col, c->csr_col, sizeof(int32_t) * np, hipMemcpyDeviceToDevice, c->stream));
+  if (label) HIP_OK(c, labels_cc(c, n, label));
+  ev_record(c, 8);
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->timing) c->stats.ms_neighbour = ev_ms(c, 7, 8);
+  return P3T_OK;
+}
+
+p3t_status p3t_clusters(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
+                        int64_t *n_clusters_host) {
+  if (!c) return P3T_ERR_ARG;
+  if (n < 0 || n > (int64_t(1) << 30) || !n_clusters_host) return fail(c, P3T_ERR_ARG, "clusters: bad argument");
+  if (bad_ptr(label, n) || bad_ptr(cl_ptr, n) || bad_ptr(cl_members, n)) return fail(c, P3T_ERR_ARG, "clusters: null");
+  *n_clusters_host = 0;
+  if (n == 0) return P3T_OK;
+  p3t_status st = ensure_n(c, n);
+  if (st != P3T_OK) return st;
+  int64_t nc = 0;
+  HIP_OK(c, clusters_csr(c, n, label, cl_ptr, cl_members, &nc));
+  *n_clusters_host = nc;
+  return P3T_OK;
+}
+
+p3t_status p3t_hermite_cluster_step(p3t_ctx *c, int64_t n, int64_t n_clusters, const int32_t *cl_ptr,
+                                    const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
+                                    const double *r_out, double *dt_hard, double *e_rel_err, int32_t *n_steps) {
+  if (!c) return P3T_ERR_ARG;
+  if (n < 0 || n_clusters < 0 || n > (int64_t(1) << 30) || n_clusters > (int64_t(1) << 30))
+    return fail(c, P3T_ERR_ARG, "hermite_cluster_step: size out of range");
+  if (n_clusters == 0) return P3T_OK;
+  if (!cl_ptr || !cl_members || bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n))
+    return fail(c, P3T_ERR_ARG, "hermite_cluster_step: null pointer");
+  p3t_status st = ensure_n(c, std::max(n, n_clusters));
+  if (st != P3T_OK) return st;
+  ev_record(c, 9);
+  hipError_t e =
+      hermite_clusters(c, n, n_clusters, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps);
+  if (e == hipErrorInvalidValue)
+    return fail(c, P3T_ERR_CLUSTER, "hermite_cluster_step: a cluster exceeds 1024 members (percolation)");
+  if (e == hipErrorInvalidDevicePointer)
+    return fail(c, P3T_ERR_ARG, "hermite_cluster_step: cl_ptr not non-decreasing or a member outside [0, n)");
+  HIP_OK(c, e);
+  ev_record(c, 10);
+  unsigned bits = 0;
+  if ((st = harvest_status(c, &bits)) != P3T_OK) return st;
+  if (c->timing) c->stats.ms_hermite = ev_ms(c, 9, 10);
+  if (bits & NUMERIC_BITS)
+    return fail(c, P3T_ERR_NUMERIC, "hermite_cluster_step: device status 0x%x", bits & NUMERIC_BITS);
+  return P3T_OK;
+}
+
+p3t_status p3t_kick(p3t_ctx *c, int64_t n, double h, const double *acc3, double *vel3) {
+  if (!c) return P3T_ERR_ARG;
+  if (n < 0 || bad_ptr(acc3, n) || bad_ptr(vel3, n) || !std::isfinite(h)) return fail(c, P3T_ERR_ARG, "kick: bad argument");
+  HIP_OK(c, kick(n, h, acc3, vel3, c->stream));
+  return P3T_OK;
+}
+
+p3t_status p3t_soft_kick_adjoint(p3t_ctx *c, double h, const double *lam_v3, double *g_pos3, double *g_mass) {
+  if (!c) return P3T_ERR_ARG;
+  return fail(c, P3T_ERR_STATE, "soft_kick_adjoint: not available in this build");
+}
+
+p3t_status p3t_set_timing(p3t_ctx *c, int32_t on) {
+  if (!c) return P3T_ERR_ARG;
+  c->timing = on ? 1 : 0;
+  c->stats.timing = c->timing;
+  return P3T_OK;
+}
+
+p3t_status p3t_get_stats(p3t_ctx *c, p3t_stats *out) {
+  if (!c || !out) return P3T_ERR_ARG;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  *out = c->stats;
+  return P3T_OK;
+}
+
+p3t_status p3t_get_status(p3t_ctx *c, uint32_t *flags) {
+  if (!c || !flags) return P3T_ERR_ARG;
+  unsigned bits = 0;
+  p3t_status st = harvest_status(c, &bits);
+  if (st != P3T_OK) return st;
+  *flags = c->host_status;
+  c->host_status = 0;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return P3T_OK;
+}
+
+const char *p3t_last_error(p3t_ctx *c) { return c ? c->last_error.c_str() : "null context"; }
+
+}  // extern "C"

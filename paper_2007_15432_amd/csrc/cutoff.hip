@@ -1,0 +1,252 @@
+// cutoff.hip -- per-particle cut-off and search radii (Hill radius of
+// Section 2.1.1, eq. (routi2), eq. (rsearch); shared mode eq. (rout1)).
+//
+// The random velocity of a particle is |v - v_K| with v_K the circular speed
+// sqrt(G M_* / |x|) along phi-hat; v_ran,i is the rms of that quantity over
+// the particle's bin among `vran_bins` log-spaced bins in cylindrical radius
+// (bins with too few members fall back to the rms over all particles).
+// Bin sums are formed per block in a fixed order and combined in block order,
+// so the result does not depend on scheduling.
+#include "p3t_internal.h"
+
+namespace p3t {
+
+constexpr int CUT_T = 256;
+constexpr int CUT_PER = 4;
+constexpr int CUT_CHUNK = CUT_T * CUT_PER;
+constexpr int CUT_MAX_BINS = 256;
+
+__global__ __launch_bounds__(CUT_T) void k_cut_prep(int64_t n, const double *__restrict__ pos,
+                                                    const double *__restrict__ vel, const double *__restrict__ m,
+                                                    double GM, double m_star, int hill_length, double *__restrict__ R_out,
+                                                    double *__restrict__ u2_out, double *__restrict__ rh_out,
+                                                    double *__restrict__ part) {
+  __shared__ double sh[2][CUT_T / WAVE];
+  double rmin = INFINITY, rmax = -INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    const double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+    const double r = sqrt(x * x + y * y + z * z);
+    const double Rc = sqrt(x * x + y * y);
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    double a;
+    if (hill_length == 1) {
+      a = r;
+    } else {
+      const double inv_a = 2.0 / r - v2 / GM;
+      a = inv_a > 0.0 ? 1.0 / inv_a : r;  // unbound: fall back to |x|
+    }
+    rh_out[i] = cbrt(m[i] / (3.0 * m_star)) * a;
+    const double vk = sqrt(GM / r);
+    const double phx = Rc > 0.0 ? -y / Rc : 0.0;
+    const double phy = Rc > 0.0 ? x / Rc : 0.0;
+    const double ux = vx - vk * phx, uy = vy - vk * phy, uz = vz;
+    u2_out[i] = ux * ux + uy * uy + uz * uz;
+    R_out[i] = Rc;
+    rmin = fmin(rmin, Rc);
+    rmax = fmax(rmax, Rc);
+  }
+  rmin = wave_min(rmin);
+  rmax = wave_max(rmax);
+  const int t = threadIdx.x;
+  if ((t & (WAVE - 1)) == 0) {
+    sh[0][t / WAVE] = rmin;
+    sh[1][t / WAVE] = rmax;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < CUT_T / WAVE; ++w) {
+      rmin = fmin(rmin, sh[0][w]);
+      rmax = fmax(rmax, sh[1][w]);
+    }
+    part[2 * blockIdx.x] = fmin(sh[0][0], rmin);
+    part[2 * blockIdx.x + 1] = fmax(sh[1][0], rmax);
+  }
+}
+
+__global__ void k_cut_minmax(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  if (threadIdx.x == 0) {
+    double lo = part[0], hi = part[1];
+    for (int b = 1; b < nb; ++b) {
+      lo = fmin(lo, part[2 * b]);
+      hi = fmax(hi, part[2 * b + 1]);
+    }
+    out[0] = lo;
+    out[1] = hi;
+  }
+}
+
+// Per chunk of CUT_CHUNK particles: bin index of each particle and, per bin,
+// the chunk's sum of u^2 and member count (fixed-order reductions).
+__global__ __launch_bounds__(CUT_T) void k_cut_bins(int64_t n, const double *__restrict__ R,
+                                                    const double *__restrict__ u2, const double *__restrict__ mm,
+                                                    int nbins, int32_t *__restrict__ bin_out,
+                                                    double *__restrict__ psum, double *__restrict__ pcnt) {
+  __shared__ double shs[CUT_T / WAVE];
+  __shared__ double shc[CUT_T / WAVE];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * CUT_CHUNK;
+  const double Rmin = mm[0], Rmax = mm[1];
+  const double lspan = (Rmax > Rmin && Rmin > 0.0) ? log(Rmax / Rmin) : 0.0;
+  int b[CUT_PER];
+  double u[CUT_PER];
+#pragma unroll
+  for (int q = 0; q < CUT_PER; ++q) {
+    const int64_t i = base + (int64_t)q * CUT_T + t;
+    b[q] = -1;
+    u[q] = 0.0;
+    if (i < n) {
+      int bb = 0;
+      if (lspan > 0.0) {
+        const double tt = floor((double)nbins * (log(R[i] / Rmin) / lspan));
+        bb = tt < 0.0 ? 0 : (tt > (double)(nbins - 1) ? nbins - 1 : (int)tt);
+      }
+      b[q] = bb;
+      u[q] = u2[i];
+      bin_out[i] = bb;
+    }
+  }
+  for (int k = 0; k < nbins; ++k) {
+    double s = 0.0, c = 0.0;
+#pragma unroll
+    for (int q = 0; q < CUT_PER; ++q)
+      if (b[q] == k) {
+        s += u[q];
+        c += 1.0;
+      }
+    s = wave_sum(s);
+    c = wave_sum(c);
+    if ((t & (WAVE - 1)) == 0) {
+      shs[t / WAVE] = s;
+      shc[t / WAVE] = c;
+    }
+    __syncthreads();
+    if (t == 0) {
+      double ts = 0.0, tc = 0.0;
+      for (int w = 0; w < CUT_T / WAVE; ++w) {
+        ts += shs[w];
+        tc += shc[w];
+      }
+      psum[(int64_t)blockIdx.x * nbins + k] = ts;
+      pcnt[(int64_t)blockIdx.x * nbins + k] = tc;
+    }
+    __syncthreads();
+  }
+}
+
+// One thread per bin: combine the chunks in order; rms per bin, global rms.
+__global__ void k_cut_binfinal(const double *__restrict__ psum, const double *__restrict__ pcnt, int nblk, int nbins,
+                               int min_count, double *__restrict__ vr_bin) {
+  __shared__ double ssum[CUT_MAX_BINS], scnt[CUT_MAX_BINS];
+  __shared__ double vglob;
+  const int k = threadIdx.x;
+  if (k < nbins) {
+    double s = 0.0, c = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      s += psum[(int64_t)b * nbins + k];
+      c += pcnt[(int64_t)b * nbins + k];
+    }
+    ssum[k] = s;
+    scnt[k] = c;
+  }
+  __syncthreads();
+  if (k == 0) {
+    double s = 0.0, c = 0.0;
+    for (int q = 0; q < nbins; ++q) {
+      s += ssum[q];
+      c += scnt[q];
+    }
+    vglob = c > 0.0 ? sqrt(s / c) : 0.0;
+  }
+  __syncthreads();
+  if (k < nbins) vr_bin[k] = scnt[k] >= (double)min_count ? sqrt(ssum[k] / scnt[k]) : vglob;
+}
+
+__global__ void k_cut_out(int64_t n, const int32_t *__restrict__ bin, const double *__restrict__ rh,
+                          const double *__restrict__ vr_bin, double rc0, double rc1, double rs0, double rs1, double dt,
+                          double *__restrict__ r_out, double *__restrict__ r_search, double *__restrict__ v_ran) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double vr = vr_bin[bin[i]];
+    const double ro = fmax(rc0 * rh[i], rc1 * vr * dt);
+    r_out[i] = ro;
+    r_search[i] = rs0 * ro + rs1 * vr * dt;
+    if (v_ran) v_ran[i] = vr;
+  }
+}
+
+// shared cut-off (eq. (rout1)): r_out,i = max_k r_out,k for every particle
+__global__ __launch_bounds__(256) void k_max_part(const double *__restrict__ v, int64_t n, double *__restrict__ part) {
+  __shared__ double sh[256 / WAVE];
+  double mx = -INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    mx = fmax(mx, v[i]);
+  mx = wave_max(mx);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / WAVE; ++w) mx = fmax(mx, sh[w]);
+    part[blockIdx.x] = fmax(mx, sh[0]);
+  }
+}
+
+__global__ void k_max_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  if (threadIdx.x == 0) {
+    double mx = part[0];
+    for (int b = 1; b < nb; ++b) mx = fmax(mx, part[b]);
+    *out = mx;
+  }
+}
+
+__global__ void k_cut_shared(int64_t n, const double *__restrict__ mx, double *__restrict__ r_out,
+                             double *__restrict__ r_search) {
+  const double ro = mx[0], rs = mx[1];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    r_out[i] = ro;
+    r_search[i] = rs;
+  }
+}
+
+hipError_t compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                           double *r_out, double *r_search, double *v_ran) {
+  if (n <= 0) return hipSuccess;
+  const p3t_params &P = c->P;
+  hipStream_t s = c->stream;
+  double *R = c->tmp_d, *u2 = c->tmp_d + n, *rh = c->tmp_d + 2 * n;
+  double *part = c->cut_part;  // [0, 2*1024) min/max partials; then bins
+  double *mm = part + 2048;
+  double *vr_bin = mm + 8;
+  double *psum = vr_bin + CUT_MAX_BINS;
+  const int nbins = P.vran_bins;
+  const int64_t nblk = (n + CUT_CHUNK - 1) / CUT_CHUNK;
+  double *pcnt = psum + nblk * nbins;
+  int32_t *bin = c->row_cnt;
+  const int nb_prep = (int)std::min<int64_t>(1024, (n + CUT_T - 1) / CUT_T);
+  const double GM = P.G * P.m_star;
+  hipLaunchKernelGGL(k_cut_prep, dim3(nb_prep), dim3(CUT_T), 0, s, n, pos3, vel3, mass, GM, P.m_star, P.hill_length, R,
+                     u2, rh, part);
+  hipLaunchKernelGGL(k_cut_minmax, dim3(1), dim3(64), 0, s, part, nb_prep, mm);
+  hipLaunchKernelGGL(k_cut_bins, dim3((unsigned)nblk), dim3(CUT_T), 0, s, n, R, u2, mm, nbins, bin, psum, pcnt);
+  hipLaunchKernelGGL(k_cut_binfinal, dim3(1), dim3(CUT_MAX_BINS), 0, s, psum, pcnt, (int)nblk, nbins,
+                     P.vran_min_count, vr_bin);
+  const unsigned g = (unsigned)std::min<int64_t>(65536, (n + 255) / 256);
+  hipLaunchKernelGGL(k_cut_out, dim3(g), dim3(256), 0, s, n, bin, rh, vr_bin, P.r_cut0, P.r_cut1, P.r_search0,
+                     P.r_search1, P.dt_soft, r_out, r_search, v_ran);
+  if (P.cutoff_mode == 1) {
+    // shared cut-off (eq. (rout1)) and shared search radius (Section 2.3):
+    // every particle takes the maxima over all particles
+    const int nbm = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_max_part, dim3(nbm), dim3(256), 0, s, r_out, n, part);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(64), 0, s, part, nbm, mm + 2);
+    hipLaunchKernelGGL(k_max_part, dim3(nbm), dim3(256), 0, s, r_search, n, part);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(64), 0, s, part, nbm, mm + 3);
+    hipLaunchKernelGGL(k_cut_shared, dim3(g), dim3(256), 0, s, n, mm + 2, r_out, r_search);
+  }
+  return hipGetLastError();
+}
+
+int64_t cut_part_need(int64_t n_cap) {
+  const int64_t nblk = (n_cap + CUT_CHUNK - 1) / CUT_CHUNK;
+  return 2048 + 8 + CUT_MAX_BINS + 2 * nblk * CUT_MAX_BINS + 64;
+}
+
+}  // namespace p3t

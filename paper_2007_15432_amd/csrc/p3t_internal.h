@@ -1,0 +1,251 @@
+// p3t_internal.h -- internal declarations of libp3t (not part of the ABI).
+//
+// Device layout (all library-owned scratch lives in one arena per context):
+//   particles in Morton order, structure of arrays, FP64:
+//     sx sy sz | svx svy svz | sm | sro (r_out) | sinv (1/r_out) | sreach (max(r_search, r_out)) | srs
+//     sid (int32, original index)
+//   tree: 2n-1 nodes (internal 0..n-2, leaf of sorted particle k = n-1+k)
+//     WalkNode (AoS, 96 B): tight bbox, centre of mass, max reach, first, count, left, right
+//     CellMom  (AoS, 80 B): centre of mass, mass, traceless quadrupole
+//   groups: node ids of the interaction groups
+//   lists: per group offsets into one pool of int32 entries (cells | near | far)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/p3t.h"
+
+namespace p3t {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- records
+struct WalkNode {
+  double lo[3];
+  double hi[3];
+  double com[3];
+  double reach;  // max over members of max(r_search, r_out)
+  int32_t first, count, left, right;
+};
+static_assert(sizeof(WalkNode) == 96, "WalkNode layout");
+
+struct CellMom {
+  double com[3];
+  double mass;
+  double q[6];  // xx, yy, zz, xy, xz, yz of sum m (3 s s^T - |s|^2 I), s about com
+};
+static_assert(sizeof(CellMom) == 80, "CellMom layout");
+
+// per-group list descriptor
+struct GroupList {
+  int64_t off;      // offset of the group's entries in the pool
+  int32_t n_cell;   // cells, then near particles, then far particles
+  int32_t n_near;
+  int32_t n_far;
+  int32_t node;     // group node id
+};
+static_assert(sizeof(GroupList) == 24, "GroupList layout");
+
+// device-side counters (one small struct in the arena)
+struct DevCounters {
+  unsigned int status;      // P3T_FLAG_* bits
+  unsigned int pad0;
+  unsigned long long pool_cursor;  // list pool allocation cursor
+  unsigned long long n_pairs;      // neighbour pairs appended
+  unsigned long long n_groups;     // interaction groups
+  unsigned long long walk_queue;   // persistent walk kernel queue head
+  unsigned long long force_queue;  // persistent force kernel queue head
+  unsigned long long n_near, n_far, n_cell;  // interaction counts
+  unsigned long long n_clusters;
+  unsigned long long pad[5];
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+__device__ __forceinline__ int popc_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+}
+
+__device__ __forceinline__ void set_flag(DevCounters *c, unsigned bits) { atomicOr(&c->status, bits); }
+
+// Wave-uniform values that steer loops (queue indices, list lengths, stack
+// tops) must live in scalar registers.  A value broadcast with a shuffle is
+// uniform at run time but not provably so to the compiler, which then
+// compiles the loop exit as divergent and may re-enter the broadcast with its
+// source lane switched off.  readfirstlane / readlane make uniformity explicit
+// and turn such exits into scalar branches.
+__device__ __forceinline__ int uniform_first(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int uniform_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ long long uniform_first64(long long v) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffll));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// inclusive wave scan of int
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int t = __shfl_up(v, o, WAVE);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T t = __shfl_xor(v, o, WAVE);
+    v = t < v ? t : v;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T t = __shfl_xor(v, o, WAVE);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------- context
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+  template <typename T>
+  T *take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (used + bytes > size) return nullptr;
+    T *p = reinterpret_cast<T *>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+}  // namespace p3t
+
+struct p3t_ctx {
+  p3t_params P;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  std::string last_error;
+  int timing = 0;
+  hipEvent_t ev[16] = {};
+  p3t_stats stats = {};
+
+  // capacities
+  int64_t n_cap = 0;         // particles the arena is sized for
+  int64_t pair_cap = 0;      // neighbour-pair buffer capacity
+  int64_t pool_cap = 0;      // list pool entries
+  int64_t slot_cap_list = 0; // per-slot temp list capacity (each of cells/near/far)
+  int64_t slot_cap_stack = 0;
+  int walk_slots = 0;
+
+  // arena (particles, tree, groups, scratch) and separately grown buffers
+  p3t::Arena arena;
+  int32_t *pool = nullptr;          // list pool
+  int32_t *slot_lists = nullptr;    // walk temp lists (walk_slots * 3 * slot_cap_list)
+  int32_t *slot_stack = nullptr;    // walk stacks (walk_slots * slot_cap_stack)
+  int2 *pairs = nullptr;            // neighbour pairs (i_orig, j_orig)
+
+  // state
+  int64_t n = 0;
+  int64_t n_groups = 0;
+  int64_t n_pairs = 0;
+  bool tree_valid = false, force_valid = false;
+  unsigned host_status = 0;   // accumulated device status bits (cleared by p3t_get_status)
+  int force_slots = 0;        // persistent force grid
+  int force_persistent = 1;
+  int32_t *herm_bcount = nullptr;  // Hermite bucket counts (16)
+  int32_t *herm_blists = nullptr;  // Hermite bucket lists (11 * n_cap)
+
+  // arena pointers
+  p3t::DevCounters *cnt = nullptr;
+  double *bbox = nullptr;       // 6 doubles (+ partials)
+  double *bbox_part = nullptr;
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svx = nullptr, *svy = nullptr, *svz = nullptr;
+  double *sm = nullptr, *sro = nullptr, *sinv = nullptr, *sreach = nullptr, *srs = nullptr;
+  int32_t *sid = nullptr;
+  uint64_t *keys = nullptr, *keys_alt = nullptr;
+  int32_t *perm = nullptr, *perm_alt = nullptr;
+  uint32_t *radix_hist = nullptr;
+  int64_t radix_hist_cap = 0;
+  int32_t *parent = nullptr;
+  int32_t *visit = nullptr;
+  p3t::WalkNode *wnode = nullptr;
+  p3t::CellMom *cmom = nullptr;
+  int32_t *group_flag = nullptr;
+  int64_t *node_scan = nullptr;     // exclusive scan over nodes (2n)
+  uint64_t *gkey = nullptr, *gkey_alt = nullptr;  // group work keys (n)
+  int32_t *gorder_alt = nullptr;
+  int32_t *group_node = nullptr;
+  p3t::GroupList *glist = nullptr;
+  int32_t *group_order = nullptr;   // groups sorted by work (longest first)
+  int64_t *scan_tmp = nullptr;
+  int64_t scan_tmp_cap = 0;
+  int32_t *row_cnt = nullptr;       // per-particle counters (n)
+  int64_t *csr_ptr = nullptr;       // internal CSR row pointer (n + 1)
+  int32_t *csr_col = nullptr;       // internal CSR columns (pair_cap)
+  int32_t *uf_parent = nullptr;     // union-find parents (n)
+  uint64_t *cl_keys = nullptr, *cl_keys_alt = nullptr;  // cluster sort keys (n)
+  double *cut_part = nullptr;       // cut-off bin partial sums
+  double *tmp_d = nullptr;          // per-particle FP64 scratch (3n)
+};
+
+// ---------------------------------------------------------------- launchers
+namespace p3t {
+
+// util.hip
+hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap,
+                           hipStream_t s);  // out has n + 1 entries (exclusive, out[n] = total)
+hipError_t scan_u32_inplace(uint32_t *data, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s);
+int64_t scan_tmp_need(int64_t n);
+hipError_t radix_sort_pairs(uint64_t *&keys, int32_t *&vals, uint64_t *&keys_alt, int32_t *&vals_alt, int64_t n_static,
+                            const unsigned long long *n_dev, int bit_lo, int bit_hi, uint32_t *hist, int64_t hist_cap,
+                            int64_t *tmp, int64_t tmp_cap, hipStream_t s);
+int64_t radix_hist_need(int64_t n);
+hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t bbox_reduce(const double *pos3, int64_t n, double *part, double *out, hipStream_t s);
+hipError_t kick(int64_t n, double h, const double *acc3, double *vel3, hipStream_t s);
+
+// cutoff.hip
+int64_t cut_part_need(int64_t n_cap);
+hipError_t compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                           double *r_out, double *r_search, double *v_ran);
+
+// tree.hip
+hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                      const double *r_out, const double *r_search);
+
+// walk.hip
+hipError_t walk_groups(p3t_ctx *c, int64_t n_groups);
+
+// force.hip
+hipError_t soft_force(p3t_ctx *c, int64_t n_groups, double *acc3);
+
+// nbr.hip
+hipError_t build_csr(p3t_ctx *c, int64_t n, int64_t n_pairs);
+hipError_t labels_cc(p3t_ctx *c, int64_t n, int32_t *label);
+hipError_t clusters_csr(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
+                        int64_t *n_clusters);
+
+// hermite.hip
+hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t n_clusters, const int32_t *cl_ptr,
+                            const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
+                            const double *r_out, double *dt_hard, double *e_rel_err, int32_t *n_steps);
+
+}  // namespace p3t

@@ -1,0 +1,237 @@
+// tree.hip -- Barnes-Hut tree over the particles (the paper uses the tree of
+// its particle framework, Section 2.1.1; its construction is not specified
+// there).  Built here for one GPU, fully in parallel:
+//   1. bounding box; 63-bit Morton keys on a cube over the box (21 bits/axis;
+//      the thin disk then splits in x/y first and in z only at small scales);
+//   2. stable radix sort of (key, index); gather of a Morton-ordered SoA copy;
+//   3. binary radix tree over the sorted keys (one thread per internal node,
+//      Karras 2012), ties broken by the sorted position;
+//   4. bottom-up pass (one thread per leaf, second arrival combines): tight
+//      bounding box, mass, centre of mass, traceless quadrupole, max reach;
+//   5. interaction groups: nodes with at most n_group_max particles whose
+//      parent has more.
+#include "p3t_internal.h"
+
+namespace p3t {
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__global__ void k_morton(int64_t n, const double *__restrict__ pos, const double *__restrict__ box,
+                         uint64_t *__restrict__ keys, int32_t *__restrict__ perm) {
+  const double lx = box[0], ly = box[1], lz = box[2];
+  const double ext = fmax(fmax(box[3] - lx, box[4] - ly), box[5] - lz);
+  const double qmax = 2097151.0;  // 2^21 - 1
+  const double scale = ext > 0.0 ? qmax / ext : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double q[3] = {(pos[i] - lx) * scale, (pos[n + i] - ly) * scale, (pos[2 * n + i] - lz) * scale};
+    uint32_t u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = (uint32_t)fmin(fmax(q[c], 0.0), qmax);
+    keys[i] = (spread3(u[0]) << 2) | (spread3(u[1]) << 1) | spread3(u[2]);
+    perm[i] = (int32_t)i;
+  }
+}
+
+__global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ pos,
+                         const double *__restrict__ vel, const double *__restrict__ m, const double *__restrict__ ro,
+                         const double *__restrict__ rs, double *__restrict__ sx, double *__restrict__ sy,
+                         double *__restrict__ sz, double *__restrict__ svx, double *__restrict__ svy,
+                         double *__restrict__ svz, double *__restrict__ sm, double *__restrict__ sro,
+                         double *__restrict__ sinv, double *__restrict__ sreach, double *__restrict__ srs,
+                         int32_t *__restrict__ sid) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = perm[k];
+    sx[k] = pos[i];
+    sy[k] = pos[n + i];
+    sz[k] = pos[2 * n + i];
+    svx[k] = vel[i];
+    svy[k] = vel[n + i];
+    svz[k] = vel[2 * n + i];
+    sm[k] = m[i];
+    const double o = ro[i], s = rs[i];
+    sro[k] = o;
+    sinv[k] = 1.0 / o;
+    sreach[k] = fmax(o, s);
+    srs[k] = s;
+    sid[k] = (int32_t)i;
+  }
+}
+
+// common-prefix length of sorted keys i and j (positions break ties)
+__device__ __forceinline__ int prefix_len(const uint64_t *__restrict__ k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  const uint64_t a = k[i], b = k[j];
+  if (a == b) return 64 + __clz((unsigned)(i ^ j));
+  return __clzll(a ^ b);
+}
+
+// Internal node i of the binary radix tree: its key range and split.
+__global__ void k_radix_tree(int n, const uint64_t *__restrict__ k, p3t::WalkNode *__restrict__ wn,
+                             int32_t *__restrict__ parent) {
+  const int leaf0 = n - 1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n - 1; i += gridDim.x * blockDim.x) {
+    const int d = (prefix_len(k, n, i, i + 1) - prefix_len(k, n, i, i - 1)) > 0 ? 1 : -1;
+    const int dmin = prefix_len(k, n, i, i - d);
+    int lmax = 2;
+    while (prefix_len(k, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
+      if (prefix_len(k, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = prefix_len(k, n, i, j);
+    int s = 0, t = l;
+    do {
+      t = (t + 1) >> 1;
+      if (prefix_len(k, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int split = i + s * d + (d < 0 ? -1 : 0);
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const int left = (lo == split) ? leaf0 + split : split;
+    const int right = (hi == split + 1) ? leaf0 + split + 1 : split + 1;
+    wn[i].left = left;
+    wn[i].right = right;
+    wn[i].first = lo;
+    wn[i].count = hi - lo + 1;
+    parent[left] = i;
+    parent[right] = i;
+    if (i == 0) parent[0] = -1;  // node 0 is the root and never a child
+  }
+}
+
+__device__ __forceinline__ void quad_shift(double q[6], double m, double dx, double dy, double dz) {
+  // add m (3 d d^T - |d|^2 I) for a point mass m at offset d from the new centre
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  q[0] += m * (3.0 * dx * dx - d2);
+  q[1] += m * (3.0 * dy * dy - d2);
+  q[2] += m * (3.0 * dz * dz - d2);
+  q[3] += m * 3.0 * dx * dy;
+  q[4] += m * 3.0 * dx * dz;
+  q[5] += m * 3.0 * dy * dz;
+}
+
+// Leaves and bottom-up moments.  One thread per sorted particle; at each
+// internal node the second child to arrive combines both children.
+__global__ void k_moments(int n, const double *__restrict__ sx, const double *__restrict__ sy,
+                          const double *__restrict__ sz, const double *__restrict__ sm,
+                          const double *__restrict__ sreach, p3t::WalkNode *wn, p3t::CellMom *cm,
+                          const int32_t *__restrict__ parent, int32_t *visit) {
+  const int leaf0 = n - 1;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int leaf = leaf0 + k;
+    p3t::WalkNode w;
+    w.lo[0] = w.hi[0] = w.com[0] = sx[k];
+    w.lo[1] = w.hi[1] = w.com[1] = sy[k];
+    w.lo[2] = w.hi[2] = w.com[2] = sz[k];
+    w.reach = sreach[k];
+    w.first = k;
+    w.count = 1;
+    w.left = -1;
+    w.right = -1;
+    wn[leaf] = w;
+    p3t::CellMom c;
+    c.com[0] = w.com[0];
+    c.com[1] = w.com[1];
+    c.com[2] = w.com[2];
+    c.mass = sm[k];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c.q[q] = 0.0;
+    cm[leaf] = c;
+    __threadfence();
+    int node = (n > 1) ? parent[leaf] : -1;
+    while (node >= 0) {
+      // first arrival: the sibling will finish; only the second arrival
+      // combines (a third would mean a malformed tree: stop, never loop)
+      if (atomicAdd(&visit[node], 1) != 1) break;
+      __threadfence();
+      const int a = wn[node].left, b = wn[node].right;
+      const p3t::WalkNode wa = wn[a], wb = wn[b];
+      const p3t::CellMom ca = cm[a], cb = cm[b];
+      p3t::WalkNode o;
+      p3t::CellMom co;
+      const double M = ca.mass + cb.mass;
+      co.mass = M;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        o.lo[d] = fmin(wa.lo[d], wb.lo[d]);
+        o.hi[d] = fmax(wa.hi[d], wb.hi[d]);
+        co.com[d] = M > 0.0 ? (ca.mass * ca.com[d] + cb.mass * cb.com[d]) / M : 0.5 * (o.lo[d] + o.hi[d]);
+        o.com[d] = co.com[d];
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) co.q[q] = ca.q[q] + cb.q[q];
+      quad_shift(co.q, ca.mass, ca.com[0] - co.com[0], ca.com[1] - co.com[1], ca.com[2] - co.com[2]);
+      quad_shift(co.q, cb.mass, cb.com[0] - co.com[0], cb.com[1] - co.com[1], cb.com[2] - co.com[2]);
+      o.reach = fmax(wa.reach, wb.reach);
+      o.first = wn[node].first;
+      o.count = wn[node].count;
+      o.left = a;
+      o.right = b;
+      wn[node] = o;
+      cm[node] = co;
+      __threadfence();
+      node = parent[node];
+    }
+  }
+}
+
+// group g: count(g) <= ng and (g is the root or count(parent) > ng)
+__global__ void k_group_flag(int n_nodes, const p3t::WalkNode *__restrict__ wn, const int32_t *__restrict__ parent,
+                             int ng, int32_t *__restrict__ flag) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes; g += gridDim.x * blockDim.x) {
+    const int c = wn[g].count;
+    const int p = (g == 0) ? -1 : parent[g];
+    flag[g] = (c <= ng && (p < 0 || wn[p].count > ng)) ? 1 : 0;
+  }
+}
+
+__global__ void k_group_compact(int n_nodes, const int32_t *__restrict__ flag, const int64_t *__restrict__ pos,
+                                int32_t *__restrict__ group_node, p3t::DevCounters *cnt) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes; g += gridDim.x * blockDim.x)
+    if (flag[g]) group_node[pos[g]] = g;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_groups = (unsigned long long)pos[n_nodes];
+}
+
+static inline unsigned g1d(int64_t n, int64_t cap = 65536) {
+  int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                      const double *r_out, const double *r_search) {
+  hipStream_t s = c->stream;
+  hipError_t e;
+  const int64_t n_nodes = 2 * n - 1;
+  if ((e = bbox_reduce(pos3, n, c->bbox_part, c->bbox, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_morton, dim3(g1d(n)), dim3(256), 0, s, n, pos3, c->bbox, c->keys, c->perm);
+  uint64_t *k = c->keys, *ka = c->keys_alt;
+  int32_t *v = c->perm, *va = c->perm_alt;
+  if ((e = radix_sort_pairs(k, v, ka, va, n, nullptr, 0, 64, c->radix_hist, c->radix_hist_cap, c->scan_tmp,
+                            c->scan_tmp_cap, s)) != hipSuccess)
+    return e;
+  // after an even number of passes the result is back in keys / perm
+  hipLaunchKernelGGL(k_gather, dim3(g1d(n)), dim3(256), 0, s, n, v, pos3, vel3, mass, r_out, r_search, c->sx, c->sy,
+                     c->sz, c->svx, c->svy, c->svz, c->sm, c->sro, c->sinv, c->sreach, c->srs, c->sid);
+  if (n > 1) {
+    hipLaunchKernelGGL(k_radix_tree, dim3(g1d(n - 1)), dim3(256), 0, s, (int)n, k, c->wnode, c->parent);
+  }
+  if ((e = fill_i32(c->visit, 0, n > 1 ? n - 1 : 1, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_moments, dim3(g1d(n)), dim3(256), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm, c->sreach, c->wnode,
+                     c->cmom, c->parent, c->visit);
+  hipLaunchKernelGGL(k_group_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->wnode, c->parent,
+                     c->P.n_group_max, c->group_flag);
+  if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_group_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
+                     c->group_node, c->cnt);
+  return hipGetLastError();
+}
+
+}  // namespace p3t
