@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark: soft-force interactions/s of the full P3T soft step on one
+MI355X, N = 2^20 planetesimal disk (0.5-5 au, surface density ~ a^-3/2,
+dN/dm ~ m^-2.5 on [1e-10, 1e-8]), theta = 0.5 quadrupole cells, groups of
+<= 128 i-particles.
+
+A step is one pass of the whole hot path on the GPU (cut-off radii, first
+kick, neighbour clusters, Hermite hard part, tree build, walk, soft force with
+neighbour pairs, neighbour CSR and cluster indices, second kick).  value =
+interactions evaluated per step / wall time per step, inputs resident in HBM.
+The mixed-precision form is the headline; the plain FP64 path runs beside it.
+
+Prints one JSON line.  Only the cpu_baseline leg touches the CPU oracle: it
+times the oracle's direct sum on a sample of i-particles and, with the same
+oracle rows, reports each GPU path's rms force error.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic flops per interaction (FMA = 2, add/sub/mul/min/max = 1,
+# rsqrt = 1), counted from the kernels' arithmetic (see the design notes).
+FLOPS_NEAR = 35   # FP64 pair with the changeover K
+FLOPS_FAR = 18    # pair with K = 1
+FLOPS_MONO = 18   # monopole cell
+FLOPS_QUAD = 51   # quadrupole cell
+PEAK_FP64 = 78.6e12   # MI355X vector FP64 (256 CU x 128 flop/clk x 2.4 GHz)
+PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published, packed)
+METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force error"
+
+
+def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf):
+    from paper_2007_15432_amd.driver import P3TStepper
+
+    dev = "cuda:0"
+    params = p3t.Params.defaults().replace(theta=0.5, multipole=2, precision=precision, n_group_max=n_group,
+                                           n_leaf_max=n_leaf)
+    ctx = p3t.Context(params)
+    ctx.reserve(disk.n, 4 * disk.n)
+    pos = torch.tensor(disk.pos, dtype=torch.float64, device=dev)
+    vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
+    m = torch.tensor(disk.mass, dtype=torch.float64, device=dev)
+    # force at the initial state, kept for the error measurement
+    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True)
+    acc0 = st.acc.clone()
+    r_out0 = st.r_out.clone()
+    for _ in range(warmup):
+        st.step()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inter = near = far = cell = 0
+    stage = {k: 0.0 for k in ("ms_cutoffs", "ms_tree", "ms_walk", "ms_force", "ms_neighbour", "ms_hermite")}
+    for _ in range(steps):
+        st.step()
+        s = ctx.stats()
+        near += s["n_near"]
+        far += s["n_far"]
+        cell += s["n_cell"]
+        for k in stage:
+            stage[k] += s[k]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    inter = near + far + cell
+    sec = (t1 - t0) / steps
+    s = ctx.stats()
+    out = dict(value=inter / steps / sec, ms_per_step=1e3 * sec, interactions_per_step=inter // steps,
+               n_near=near // steps, n_far=far // steps, n_cell=cell // steps, n_groups=s["n_groups"],
+               n_pairs=s["n_pairs"], n_clusters=st.n_clusters,
+               stages_ms={k[3:]: v / steps for k, v in stage.items()})
+    # roofline of the force kernel (the dominant kernel)
+    t_force = stage["ms_force"] / steps * 1e-3
+    w64 = out["n_near"] * FLOPS_NEAR
+    w_far = out["n_far"] * FLOPS_FAR + out["n_cell"] * FLOPS_QUAD
+    if precision == 1:
+        t_min = w64 / PEAK_FP64 + w_far / PEAK_FP32
+    else:
+        t_min = (w64 + w_far) / PEAK_FP64
+    achieved = (w64 + w_far) / t_force
+    out["roofline"] = dict(bound="alu", achieved=achieved / 1e12, peak=(w64 + w_far) / t_min / 1e12,
+                           unit="TFLOP/s", frac=t_min / t_force, traffic=None, kernel="k_force",
+                           avg_ms=t_force * 1e3)
+    out["_acc0"] = acc0.cpu().numpy()
+    out["_r_out0"] = r_out0.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def cpu_baseline(disk, results, sample, seed=33):
+    """Oracle (plain CPU FP64 direct sum) on a bounded sample of i-particles:
+    timing, and the reference rows for the GPU paths' rms force error."""
+    import numpy as np
+
+    import diskgen
+    import oracle
+
+    idx = diskgen.sample_indices(disk.n, sample, seed)
+    p = oracle.Params()
+    ro = results["fp64"]["_r_out0"]
+    t0 = time.perf_counter()
+    ref = oracle.soft_acc(disk.pos, disk.mass, ro, p, idx=idx)
+    dt = time.perf_counter() - t0
+    errs = {}
+    for name, r in results.items():
+        a = r["_acc0"][:, idx]
+        num = ((a - ref) ** 2).sum(0)
+        den = (ref ** 2).sum(0)
+        errs[name] = dict(eps_rms=float(np.sqrt(np.mean(num / den))), eps_global=float(np.sqrt(num.sum() / den.sum())),
+                          eps_max=float(np.sqrt((num / den).max())))
+    base = dict(value=len(idx) * (disk.n - 1) / dt, unit="interactions/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{len(idx)} i-particles (seed {seed}) x all {disk.n} j, direct FP64 sum, {dt:.1f} s")
+    return base, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--n-group", type=int, default=128)
+    ap.add_argument("--n-leaf", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--paths", default="mixed,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU design is "
+              "described but not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import diskgen
+    import paper_2007_15432_amd as p3t
+
+    p3t.load()
+    disk = diskgen.workload("disk1m_masslaw", args.n)
+    print(f"# workload disk1m_masslaw N={disk.n}", file=sys.stderr, flush=True)
+    results = {}
+    for name in args.paths.split(","):
+        prec = 1 if name == "mixed" else 0
+        results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, args.n_group, args.n_leaf)
+        r = results[name]
+        print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
+              f"force {r['stages_ms']['force']:.2f} ms, frac {r['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
+    head = "mixed" if "mixed" in results else next(iter(results))
+    base, errs = (None, {})
+    if not args.no_cpu and "fp64" in results:
+        base, errs = cpu_baseline(disk, results, args.cpu_sample)
+    h = results[head]
+    line = {
+        "metric": METRIC,
+        "value": h["value"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"disk1m_masslaw: N={disk.n} planetesimals, a in [0.5, 5] au, sigma ~ a^-3/2, "
+                        "dN/dm ~ m^-2.5 on [1e-10, 1e-8], rms e = 2 rms i = 2 h(1e-9); theta=0.5 quadrupole; "
+                        f"groups <= {args.n_group}, leaves <= {args.n_leaf}; one P3T soft step per step",
+            "path": head,
+        },
+        "roofline": {k: v for k, v in h["roofline"].items()},
+        "cpu_baseline": base,
+        "interactions_per_step": h["interactions_per_step"],
+        "stages_ms": h["stages_ms"],
+        "force_error": errs.get(head),
+    }
+    for name, r in results.items():
+        if name != head:
+            line[name] = {k: r[k] for k in ("value", "ms_per_step", "interactions_per_step", "stages_ms", "roofline")}
+            line[name]["force_error"] = errs.get(name)
+    line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters")}
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -64,12 +64,25 @@ __global__ __launch_bounds__(CUT_T) void k_cut_prep(int64_t n, const double *__r
   }
 }
 
-__global__ void k_cut_minmax(const double *__restrict__ part, int nb, double *__restrict__ out) {
-  if (threadIdx.x == 0) {
-    double lo = part[0], hi = part[1];
-    for (int b = 1; b < nb; ++b) {
-      lo = fmin(lo, part[2 * b]);
-      hi = fmax(hi, part[2 * b + 1]);
+__global__ __launch_bounds__(256) void k_cut_minmax(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  __shared__ double sh[2][256 / WAVE];
+  const int t = threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int b = t; b < nb; b += 256) {
+    lo = fmin(lo, part[2 * b]);
+    hi = fmax(hi, part[2 * b + 1]);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if ((t & (WAVE - 1)) == 0) {
+    sh[0][t / WAVE] = lo;
+    sh[1][t / WAVE] = hi;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < 256 / WAVE; ++w) {
+      lo = fmin(lo, sh[0][w]);
+      hi = fmax(hi, sh[1][w]);
     }
     out[0] = lo;
     out[1] = hi;
@@ -127,27 +140,50 @@ __global__ __launch_bounds__(CUT_T) void k_cut_bins(int64_t n, const double *__r
         ts += shs[w];
         tc += shc[w];
       }
-      psum[(int64_t)blockIdx.x * nbins + k] = ts;
-      pcnt[(int64_t)blockIdx.x * nbins + k] = tc;
+      psum[(int64_t)k * gridDim.x + blockIdx.x] = ts;  // [bin][chunk]
+      pcnt[(int64_t)k * gridDim.x + blockIdx.x] = tc;
     }
     __syncthreads();
   }
 }
 
-// One thread per bin: combine the chunks in order; rms per bin, global rms.
-__global__ void k_cut_binfinal(const double *__restrict__ psum, const double *__restrict__ pcnt, int nblk, int nbins,
+// One block per bin: the bin's chunk partials in a fixed reduction order.
+__global__ __launch_bounds__(256) void k_cut_binsum(const double *__restrict__ psum, const double *__restrict__ pcnt,
+                                                    int nblk, double *__restrict__ bsum, double *__restrict__ bcnt) {
+  __shared__ double shs[256 / WAVE], shc[256 / WAVE];
+  const int k = blockIdx.x, t = threadIdx.x;
+  double s = 0.0, c = 0.0;
+  for (int b = t; b < nblk; b += 256) {
+    s += psum[(int64_t)k * nblk + b];
+    c += pcnt[(int64_t)k * nblk + b];
+  }
+  s = wave_sum(s);
+  c = wave_sum(c);
+  if ((t & (WAVE - 1)) == 0) {
+    shs[t / WAVE] = s;
+    shc[t / WAVE] = c;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double ts = 0.0, tc = 0.0;
+    for (int w = 0; w < 256 / WAVE; ++w) {
+      ts += shs[w];
+      tc += shc[w];
+    }
+    bsum[k] = ts;
+    bcnt[k] = tc;
+  }
+}
+
+// rms per bin, and the rms over all particles for sparse bins.
+__global__ void k_cut_binfinal(const double *__restrict__ bsum, const double *__restrict__ bcnt, int nbins,
                                int min_count, double *__restrict__ vr_bin) {
   __shared__ double ssum[CUT_MAX_BINS], scnt[CUT_MAX_BINS];
   __shared__ double vglob;
   const int k = threadIdx.x;
   if (k < nbins) {
-    double s = 0.0, c = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      s += psum[(int64_t)b * nbins + k];
-      c += pcnt[(int64_t)b * nbins + k];
-    }
-    ssum[k] = s;
-    scnt[k] = c;
+    ssum[k] = bsum[k];
+    scnt[k] = bcnt[k];
   }
   __syncthreads();
   if (k == 0) {
@@ -224,10 +260,11 @@ hipError_t compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const doub
   const double GM = P.G * P.m_star;
   hipLaunchKernelGGL(k_cut_prep, dim3(nb_prep), dim3(CUT_T), 0, s, n, pos3, vel3, mass, GM, P.m_star, P.hill_length, R,
                      u2, rh, part);
-  hipLaunchKernelGGL(k_cut_minmax, dim3(1), dim3(64), 0, s, part, nb_prep, mm);
+  hipLaunchKernelGGL(k_cut_minmax, dim3(1), dim3(256), 0, s, part, nb_prep, mm);
   hipLaunchKernelGGL(k_cut_bins, dim3((unsigned)nblk), dim3(CUT_T), 0, s, n, R, u2, mm, nbins, bin, psum, pcnt);
-  hipLaunchKernelGGL(k_cut_binfinal, dim3(1), dim3(CUT_MAX_BINS), 0, s, psum, pcnt, (int)nblk, nbins,
-                     P.vran_min_count, vr_bin);
+  double *bsum = part, *bcnt = part + CUT_MAX_BINS;  // the min/max partials are consumed
+  hipLaunchKernelGGL(k_cut_binsum, dim3(nbins), dim3(256), 0, s, psum, pcnt, (int)nblk, bsum, bcnt);
+  hipLaunchKernelGGL(k_cut_binfinal, dim3(1), dim3(CUT_MAX_BINS), 0, s, bsum, bcnt, nbins, P.vran_min_count, vr_bin);
   const unsigned g = (unsigned)std::min<int64_t>(65536, (n + 255) / 256);
   hipLaunchKernelGGL(k_cut_out, dim3(g), dim3(256), 0, s, n, bin, rh, vr_bin, P.r_cut0, P.r_cut1, P.r_search0,
                      P.r_search1, P.dt_soft, r_out, r_search, v_ran);

@@ -10,11 +10,14 @@
 // of the doubled step.  Energy of eq. (hard) restricted to the cluster before
 // and after.
 //
-// Clusters are bucketed by size.  Sizes <= 64: SEG lanes per cluster
-// (SEG = next power of two), 64/SEG clusters per wavefront, one member per
-// lane, reductions by shuffles inside the segment.  Sizes 65..1024: one
-// 256-thread workgroup per cluster, MPT members per thread, block reductions
-// in LDS.  Predicted states are shared through LDS.
+// Clusters are bucketed by size and all buckets run in ONE launch, so the
+// long-running clusters of different sizes overlap instead of queueing:
+//   sizes <= 64: SEG = next power of two lanes per cluster, 64/SEG clusters
+//     per wavefront, one member per lane; each wavefront runs its own block
+//     steps and synchronises only with itself (LDS is private per wave);
+//   sizes 65..256: one 256-thread workgroup per cluster (same launch);
+//   sizes 257..1024: separate launches with 2 or 4 members per thread.
+// Predicted states are shared through LDS.
 #include <climits>
 
 #include "p3t_internal.h"
@@ -23,11 +26,13 @@ namespace p3t {
 
 constexpr int TICK_BITS = 40;
 constexpr int BIG_T = 256;
-constexpr int N_BUCKETS = 11;  // SEG 1..64 (7), big MPT 1, 2, 4 (3), too big (1)
+constexpr int N_BUCKETS = 11;  // SEG 1..64 (7), 256-thread MPT 1, 2, 4 (3), too big (1)
 
 struct HermArgs {
-  const int32_t *cl_ptr, *members, *blist;
-  int nb;
+  const int32_t *cl_ptr, *members, *blists;
+  int64_t nc;                      // clusters (stride of the bucket lists)
+  int bcount[N_BUCKETS];           // clusters per bucket
+  int boff[N_BUCKETS + 1];         // first block of each bucket in the fused launch
   double *pos, *vel;
   const double *mass, *ro;
   double *dt_hard, *e_rel;
@@ -87,8 +92,14 @@ __device__ __forceinline__ void star_term(const double *x, const double *v, doub
   }
 }
 
+// Smallest k >= 0 with dt_soft 2^-k <= dtc (k_max + 1 if none): the same
+// decision as a linear search from k = 0, started two levels below the
+// exponent difference (every comparison is exact: ldexp scales by 2^-k).
 __device__ __forceinline__ int level_for(double dt_soft, double dtc, int kmax) {
-  int k = 0;
+  if (!(dtc < dt_soft)) return 0;
+  if (!(dtc > 0.0)) return kmax + 1;
+  int k = ilogb(dt_soft) - ilogb(dtc) - 1;
+  k = k < 0 ? 0 : k;
   while (k <= kmax && ldexp(dt_soft, -k) > dtc) ++k;
   return k;
 }
@@ -100,14 +111,16 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
                                         const double *a1, const double *j1, double h, int64_t tnew, int &lev,
                                         const HermArgs &A) {
   double a2[3], a3[3];
-  const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
+  const double ih = 1.0 / h;
+  const double ih2 = ih * ih, ih3 = ih2 * ih;
+  const double h3 = h * h * h, h4 = h3 * h, h5 = h4 * h;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double da = a0[d] - a1[d];
-    a2[d] = (-6.0 * da - h * (4.0 * j0[d] + 2.0 * j1[d])) / h2;
-    a3[d] = (12.0 * da + 6.0 * h * (j0[d] + j1[d])) / h3;
-    x[d] = xp[d] + a2[d] * h4 / 24.0 + a3[d] * h5 / 120.0;
-    v[d] = vp[d] + a2[d] * h3 / 6.0 + a3[d] * h4 / 24.0;
+    a2[d] = (-6.0 * da - h * (4.0 * j0[d] + 2.0 * j1[d])) * ih2;
+    a3[d] = (12.0 * da + 6.0 * h * (j0[d] + j1[d])) * ih3;
+    x[d] = xp[d] + a2[d] * h4 * (1.0 / 24.0) + a3[d] * h5 * (1.0 / 120.0);
+    v[d] = vp[d] + a2[d] * h3 * (1.0 / 6.0) + a3[d] * h4 * (1.0 / 24.0);
     a0[d] = a1[d];
     j0[d] = j1[d];
   }
@@ -118,8 +131,9 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
   const int knew = level_for(A.dt_soft, dtc, A.k_max);
   int k = lev;
   if (knew < k) {
+    // grow by at most a factor two, and only on a multiple of the doubled step
     const int64_t dbl = (int64_t)1 << (TICK_BITS - k + 1);
-    if (k > 0 && (tnew % dbl) == 0) k = k - 1;
+    if (k > 0 && (tnew & (dbl - 1)) == 0) k = k - 1;
   } else {
     k = knew;
   }
@@ -128,6 +142,19 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
     k = A.k_max;
   }
   lev = k;
+}
+
+__device__ __forceinline__ int initial_level(const double *a0, const double *j0, bool mem, int gid, const HermArgs &A) {
+  double dtc = A.dt_soft;
+  const double an = norm3(a0), jn = norm3(j0);
+  if (jn > 0.0) dtc = A.eta0 * an / jn;
+  if (mem && A.dt_hard && A.dt_hard[gid] > 0.0) dtc = A.dt_hard[gid];  // step carried from the last soft step
+  int lev = level_for(A.dt_soft, dtc, A.k_max);
+  if (lev > A.k_max) {
+    if (mem) set_flag(A.cnt, P3T_FLAG_KMAX);
+    lev = A.k_max;
+  }
+  return lev;
 }
 
 template <typename T, int SEG>
@@ -146,18 +173,33 @@ __device__ __forceinline__ double seg_sum(double v) {
   return v;
 }
 
+// LDS ordering inside one wavefront: a wave's LDS operations execute in
+// order, so a compiler fence at wavefront scope is enough between a write by
+// one lane and a read by another.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Lds {
+  double *px, *py, *pz, *pvx, *pvy, *pvz, *pgm, *pinv;
+};
+
 // ---------------------------------------------------------------- small clusters
+// One wavefront (lanes [wbase, wbase + 64) of the LDS arrays) runs 64/SEG
+// clusters; cluster index ci of bucket bk.
 template <int SEG>
-__global__ __launch_bounds__(WAVE) void k_herm_seg(HermArgs A) {
-  __shared__ double px[WAVE], py[WAVE], pz[WAVE], pvx[WAVE], pvy[WAVE], pvz[WAVE], pgm[WAVE], pinv[WAVE];
-  const int lane = threadIdx.x, seg = lane / SEG, sl = lane % SEG, sb = seg * SEG;
-  const int ci = blockIdx.x * (WAVE / SEG) + seg;
-  const int c = ci < A.nb ? A.blist[ci] : -1;
+__device__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int ci0, const Lds &L, int wbase) {
+  const int lane = threadIdx.x & (WAVE - 1), seg = lane / SEG, sl = lane % SEG, sb = wbase + seg * SEG;
+  const int ci = ci0 + seg;
+  const int c = ci < count ? blist[ci] : -1;
   const int b = c >= 0 ? A.cl_ptr[c] : 0;
   const int size = c >= 0 ? A.cl_ptr[c + 1] - b : 0;
   const bool mem = sl < size;
   const int gid = mem ? A.members[b + sl] : 0;
   const int64_t n = A.n;
+  const int me = wbase + lane;
   double x[3] = {1.0, 0.0, 0.0}, v[3] = {0.0, 1.0, 0.0}, a0[3], j0[3];
   double m = 0.0, ro = 1.0;
   if (mem) {
@@ -170,43 +212,37 @@ __global__ __launch_bounds__(WAVE) void k_herm_seg(HermArgs A) {
     m = A.mass[gid];
     ro = A.ro[gid];
   }
-  pgm[lane] = A.G * m;
-  pinv[lane] = 1.0 / ro;
-  px[lane] = x[0];
-  py[lane] = x[1];
-  pz[lane] = x[2];
-  pvx[lane] = v[0];
-  pvy[lane] = v[1];
-  pvz[lane] = v[2];
-  __syncthreads();
   const double invi = 1.0 / ro;
+  wave_sync();
+  L.pgm[me] = A.G * m;
+  L.pinv[me] = invi;
+  L.px[me] = x[0];
+  L.py[me] = x[1];
+  L.pz[me] = x[2];
+  L.pvx[me] = v[0];
+  L.pvy[me] = v[1];
+  L.pvz[me] = v[2];
+  wave_sync();
   // forces at t = 0 and the initial energy
   star_term(x, v, A.GM, a0, j0);
-  double e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) : 0.0;
-  for (int jj = 0; jj < size; ++jj) {
-    if (jj == sl || !mem) continue;
-    const int q = sb + jj;
-    const double dx = px[q] - x[0], dy = py[q] - x[1], dz = pz[q] - x[2];
-    const double invR = fmin(invi, pinv[q]);
-    hard_pair(dx, dy, dz, pvx[q] - v[0], pvy[q] - v[1], pvz[q] - v[2], pgm[q], invR, A, a0, j0);
-    if (jj > sl) {
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      e -= m * pgm[q] * (1.0 - changeover_W(r * invR, A)) / r;
+  double e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
+                       A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
+                 : 0.0;
+  if (mem) {
+    for (int jj = 0; jj < size; ++jj) {
+      if (jj == sl) continue;
+      const int q = sb + jj;
+      const double dx = L.px[q] - x[0], dy = L.py[q] - x[1], dz = L.pz[q] - x[2];
+      const double invR = fmin(invi, L.pinv[q]);
+      hard_pair(dx, dy, dz, L.pvx[q] - v[0], L.pvy[q] - v[1], L.pvz[q] - v[2], L.pgm[q], invR, A, a0, j0);
+      if (jj > sl) {
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        e -= m * L.pgm[q] * (1.0 - changeover_W(r * invR, A)) / r;
+      }
     }
   }
   const double E0 = seg_sum<SEG>(e);
-  int lev = 0;
-  {
-    double dtc = A.dt_soft;
-    const double an = norm3(a0), jn = norm3(j0);
-    if (jn > 0.0) dtc = A.eta0 * an / jn;
-    if (mem && A.dt_hard && A.dt_hard[gid] > 0.0) dtc = A.dt_hard[gid];
-    lev = level_for(A.dt_soft, dtc, A.k_max);
-    if (lev > A.k_max) {
-      if (mem) set_flag(A.cnt, P3T_FLAG_KMAX);
-      lev = A.k_max;
-    }
-  }
+  int lev = initial_level(a0, j0, mem, gid, A);
   const int64_t T = (int64_t)1 << TICK_BITS;
   int64_t t = 0;
   int nst = 0;  // block steps of this lane's cluster
@@ -225,7 +261,7 @@ __global__ __launch_bounds__(WAVE) void k_herm_seg(HermArgs A) {
     double xp[3], vp[3];
     if (mem && !done) {
       const double dl = (double)(tn - t) * A.tick;
-      const double d2 = dl * dl / 2.0, d3 = dl * dl * dl / 6.0;
+      const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         xp[d] = x[d] + v[d] * dl + a0[d] * d2 + j0[d] * d3;
@@ -238,22 +274,22 @@ __global__ __launch_bounds__(WAVE) void k_herm_seg(HermArgs A) {
         vp[d] = v[d];
       }
     }
-    __syncthreads();
-    px[lane] = xp[0];
-    py[lane] = xp[1];
-    pz[lane] = xp[2];
-    pvx[lane] = vp[0];
-    pvy[lane] = vp[1];
-    pvz[lane] = vp[2];
-    __syncthreads();
+    wave_sync();
+    L.px[me] = xp[0];
+    L.py[me] = xp[1];
+    L.pz[me] = xp[2];
+    L.pvx[me] = vp[0];
+    L.pvy[me] = vp[1];
+    L.pvz[me] = vp[2];
+    wave_sync();
     if (active) {
       double a1[3], j1[3];
       star_term(xp, vp, A.GM, a1, j1);
       for (int jj = 0; jj < size; ++jj) {
         if (jj == sl) continue;
         const int q = sb + jj;
-        hard_pair(px[q] - xp[0], py[q] - xp[1], pz[q] - xp[2], pvx[q] - vp[0], pvy[q] - vp[1], pvz[q] - vp[2],
-                  pgm[q], fmin(invi, pinv[q]), A, a1, j1);
+        hard_pair(L.px[q] - xp[0], L.py[q] - xp[1], L.pz[q] - xp[2], L.pvx[q] - vp[0], L.pvy[q] - vp[1],
+                  L.pvz[q] - vp[2], L.pgm[q], fmin(invi, L.pinv[q]), A, a1, j1);
       }
       const double h = (double)(tn - t) * A.tick;
       t = tn;
@@ -261,21 +297,24 @@ __global__ __launch_bounds__(WAVE) void k_herm_seg(HermArgs A) {
     }
   }
   // final energy
-  __syncthreads();
-  px[lane] = x[0];
-  py[lane] = x[1];
-  pz[lane] = x[2];
-  pvx[lane] = v[0];
-  pvy[lane] = v[1];
-  pvz[lane] = v[2];
-  __syncthreads();
-  e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) : 0.0;
-  for (int jj = sl + 1; jj < size; ++jj) {
-    if (!mem) break;
-    const int q = sb + jj;
-    const double dx = px[q] - x[0], dy = py[q] - x[1], dz = pz[q] - x[2];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    e -= m * pgm[q] * (1.0 - changeover_W(r * fmin(invi, pinv[q]), A)) / r;
+  wave_sync();
+  L.px[me] = x[0];
+  L.py[me] = x[1];
+  L.pz[me] = x[2];
+  L.pvx[me] = v[0];
+  L.pvy[me] = v[1];
+  L.pvz[me] = v[2];
+  wave_sync();
+  e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
+                A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
+          : 0.0;
+  if (mem) {
+    for (int jj = sl + 1; jj < size; ++jj) {
+      const int q = sb + jj;
+      const double dx = L.px[q] - x[0], dy = L.py[q] - x[1], dz = L.pz[q] - x[2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      e -= m * L.pgm[q] * (1.0 - changeover_W(r * fmin(invi, L.pinv[q]), A)) / r;
+    }
   }
   const double E1 = seg_sum<SEG>(e);
   if (mem) {
@@ -314,15 +353,10 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// One 256-thread workgroup per cluster c, MPT members per thread.
 template <int MPT>
-__global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
-  constexpr int CAP = BIG_T * MPT;
-  __shared__ double px[CAP], py[CAP], pz[CAP], pvx[CAP], pvy[CAP], pvz[CAP], pgm[CAP], pinv[CAP];
-  __shared__ int64_t shi[BIG_T / WAVE];
-  __shared__ double shd[BIG_T / WAVE];
+__device__ void big_body(const HermArgs &A, int c, const Lds &L, int64_t *shi, double *shd) {
   const int tid = threadIdx.x;
-  const int c = blockIdx.x < (unsigned)A.nb ? A.blist[blockIdx.x] : -1;
-  if (c < 0) return;  // whole block uniform
   const int b = A.cl_ptr[c];
   const int size = A.cl_ptr[c + 1] - b;
   const int64_t n = A.n;
@@ -350,14 +384,14 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
       ro = A.ro[gid[u]];
     }
     invi[u] = 1.0 / ro;
-    px[k] = x[u][0];
-    py[k] = x[u][1];
-    pz[k] = x[u][2];
-    pvx[k] = v[u][0];
-    pvy[k] = v[u][1];
-    pvz[k] = v[u][2];
-    pgm[k] = A.G * m[u];
-    pinv[k] = invi[u];
+    L.px[k] = x[u][0];
+    L.py[k] = x[u][1];
+    L.pz[k] = x[u][2];
+    L.pvx[k] = v[u][0];
+    L.pvy[k] = v[u][1];
+    L.pvz[k] = v[u][2];
+    L.pgm[k] = A.G * m[u];
+    L.pinv[k] = invi[u];
     t[u] = 0;
   }
   __syncthreads();
@@ -366,32 +400,23 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
   for (int u = 0; u < MPT; ++u) {
     const int k = tid + BIG_T * u;
     star_term(x[u], v[u], A.GM, a0[u], j0[u]);
+    lev[u] = 0;
     if (!mem[u]) continue;
     e += 0.5 * m[u] * (v[u][0] * v[u][0] + v[u][1] * v[u][1] + v[u][2] * v[u][2]) -
          A.GM * m[u] * rsqrt(x[u][0] * x[u][0] + x[u][1] * x[u][1] + x[u][2] * x[u][2]);
     for (int q = 0; q < size; ++q) {
       if (q == k) continue;
-      const double dx = px[q] - x[u][0], dy = py[q] - x[u][1], dz = pz[q] - x[u][2];
-      const double invR = fmin(invi[u], pinv[q]);
-      hard_pair(dx, dy, dz, pvx[q] - v[u][0], pvy[q] - v[u][1], pvz[q] - v[u][2], pgm[q], invR, A, a0[u], j0[u]);
+      const double dx = L.px[q] - x[u][0], dy = L.py[q] - x[u][1], dz = L.pz[q] - x[u][2];
+      const double invR = fmin(invi[u], L.pinv[q]);
+      hard_pair(dx, dy, dz, L.pvx[q] - v[u][0], L.pvy[q] - v[u][1], L.pvz[q] - v[u][2], L.pgm[q], invR, A, a0[u],
+                j0[u]);
       if (q > k) {
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        e -= m[u] * pgm[q] * (1.0 - changeover_W(r * invR, A)) / r;
+        e -= m[u] * L.pgm[q] * (1.0 - changeover_W(r * invR, A)) / r;
       }
     }
-    double dtc = A.dt_soft;
-    const double an = norm3(a0[u]), jn = norm3(j0[u]);
-    if (jn > 0.0) dtc = A.eta0 * an / jn;
-    if (A.dt_hard && A.dt_hard[gid[u]] > 0.0) dtc = A.dt_hard[gid[u]];
-    lev[u] = level_for(A.dt_soft, dtc, A.k_max);
-    if (lev[u] > A.k_max) {
-      set_flag(A.cnt, P3T_FLAG_KMAX);
-      lev[u] = A.k_max;
-    }
+    lev[u] = initial_level(a0[u], j0[u], true, gid[u], A);
   }
-#pragma unroll
-  for (int u = 0; u < MPT; ++u)
-    if (!mem[u]) lev[u] = 0;
   const double E0 = block_sum(e, shd);
   const int64_t T = (int64_t)1 << TICK_BITS;
   int it = 0;  // block steps taken
@@ -415,7 +440,7 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
       const double dl = mem[u] ? (double)(tn - t[u]) * A.tick : 0.0;
-      const double d2 = dl * dl / 2.0, d3 = dl * dl * dl / 6.0;
+      const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
       for (int d = 0; d < 3; ++d) {
         xp[u][d] = x[u][d] + v[u][d] * dl + a0[u][d] * d2 + j0[u][d] * d3;
         vp[u][d] = v[u][d] + a0[u][d] * dl + j0[u][d] * d2;
@@ -425,12 +450,12 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
       const int k = tid + BIG_T * u;
-      px[k] = xp[u][0];
-      py[k] = xp[u][1];
-      pz[k] = xp[u][2];
-      pvx[k] = vp[u][0];
-      pvy[k] = vp[u][1];
-      pvz[k] = vp[u][2];
+      L.px[k] = xp[u][0];
+      L.py[k] = xp[u][1];
+      L.pz[k] = xp[u][2];
+      L.pvx[k] = vp[u][0];
+      L.pvy[k] = vp[u][1];
+      L.pvz[k] = vp[u][2];
     }
     __syncthreads();
 #pragma unroll
@@ -441,8 +466,8 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
       star_term(xp[u], vp[u], A.GM, a1, j1);
       for (int q = 0; q < size; ++q) {
         if (q == k) continue;
-        hard_pair(px[q] - xp[u][0], py[q] - xp[u][1], pz[q] - xp[u][2], pvx[q] - vp[u][0], pvy[q] - vp[u][1],
-                  pvz[q] - vp[u][2], pgm[q], fmin(invi[u], pinv[q]), A, a1, j1);
+        hard_pair(L.px[q] - xp[u][0], L.py[q] - xp[u][1], L.pz[q] - xp[u][2], L.pvx[q] - vp[u][0],
+                  L.pvy[q] - vp[u][1], L.pvz[q] - vp[u][2], L.pgm[q], fmin(invi[u], L.pinv[q]), A, a1, j1);
       }
       const double h = (double)(tn - t[u]) * A.tick;
       t[u] = tn;
@@ -453,12 +478,12 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
 #pragma unroll
   for (int u = 0; u < MPT; ++u) {
     const int k = tid + BIG_T * u;
-    px[k] = x[u][0];
-    py[k] = x[u][1];
-    pz[k] = x[u][2];
-    pvx[k] = v[u][0];
-    pvy[k] = v[u][1];
-    pvz[k] = v[u][2];
+    L.px[k] = x[u][0];
+    L.py[k] = x[u][1];
+    L.pz[k] = x[u][2];
+    L.pvx[k] = v[u][0];
+    L.pvy[k] = v[u][1];
+    L.pvz[k] = v[u][2];
   }
   __syncthreads();
   e = 0.0;
@@ -469,9 +494,9 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
     e += 0.5 * m[u] * (v[u][0] * v[u][0] + v[u][1] * v[u][1] + v[u][2] * v[u][2]) -
          A.GM * m[u] * rsqrt(x[u][0] * x[u][0] + x[u][1] * x[u][1] + x[u][2] * x[u][2]);
     for (int q = k + 1; q < size; ++q) {
-      const double dx = px[q] - x[u][0], dy = py[q] - x[u][1], dz = pz[q] - x[u][2];
+      const double dx = L.px[q] - x[u][0], dy = L.py[q] - x[u][1], dz = L.pz[q] - x[u][2];
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      e -= m[u] * pgm[q] * (1.0 - changeover_W(r * fmin(invi[u], pinv[q]), A)) / r;
+      e -= m[u] * L.pgm[q] * (1.0 - changeover_W(r * fmin(invi[u], L.pinv[q]), A)) / r;
     }
   }
   const double E1 = block_sum(e, shd);
@@ -489,6 +514,46 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A) {
   if (tid == 0 && A.nsteps) A.nsteps[c] = it;
 }
 
+// Buckets 0..7 (sizes 1..256) in one launch of 256-thread workgroups; the
+// block index selects the bucket (uniform per workgroup).
+__global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
+  __shared__ double lds[8][BIG_T];
+  __shared__ int64_t shi[BIG_T / WAVE];
+  __shared__ double shd[BIG_T / WAVE];
+  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7]};
+  const int blk = blockIdx.x;
+  int bk = 0;
+  while (bk < 7 && A.boff[bk + 1] <= blk) ++bk;  // uniform per workgroup
+  const int local = blk - A.boff[bk];
+  const int32_t *blist = A.blists + (int64_t)bk * A.nc;
+  if (bk == 7) {
+    big_body<1>(A, blist[local], L, shi, shd);
+    return;
+  }
+  const int w = threadIdx.x / WAVE;
+  const int wbase = w * WAVE;
+  const int per_wave = WAVE >> bk;  // clusters per wavefront
+  const int ci0 = (local * (BIG_T / WAVE) + w) * per_wave;
+  switch (bk) {
+    case 0: seg_body<1>(A, blist, A.bcount[0], ci0, L, wbase); break;
+    case 1: seg_body<2>(A, blist, A.bcount[1], ci0, L, wbase); break;
+    case 2: seg_body<4>(A, blist, A.bcount[2], ci0, L, wbase); break;
+    case 3: seg_body<8>(A, blist, A.bcount[3], ci0, L, wbase); break;
+    case 4: seg_body<16>(A, blist, A.bcount[4], ci0, L, wbase); break;
+    case 5: seg_body<32>(A, blist, A.bcount[5], ci0, L, wbase); break;
+    default: seg_body<64>(A, blist, A.bcount[6], ci0, L, wbase); break;
+  }
+}
+
+template <int MPT>
+__global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A, int bk) {
+  __shared__ double lds[8][BIG_T * MPT];
+  __shared__ int64_t shi[BIG_T / WAVE];
+  __shared__ double shd[BIG_T / WAVE];
+  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7]};
+  big_body<MPT>(A, A.blists[(int64_t)bk * A.nc + blockIdx.x], L, shi, shd);
+}
+
 // ---------------------------------------------------------------- bucketing
 __device__ __forceinline__ int bucket_of(int size) {
   if (size <= 1) return 0;
@@ -504,32 +569,38 @@ __device__ __forceinline__ int bucket_of(int size) {
   return 10;
 }
 
-// Bucket the clusters by size; also validate the caller's cluster arrays
-// (offsets non-decreasing from >= 0, members in [0, n)); any violation sets
-// bcount[15] and nothing is integrated.
-__global__ void k_herm_bucket(int64_t nc, int64_t n, const int32_t *__restrict__ cl_ptr,
-                              const int32_t *__restrict__ members, int32_t *__restrict__ bcount,
-                              int32_t *__restrict__ blists) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
-    const int a = cl_ptr[c], b = cl_ptr[c + 1];
-    if (a < 0 || b < a) {
-      atomicOr(&bcount[15], 1);
-      continue;
+// Bucket the clusters by size with one atomic per bucket per wavefront; also
+// validate the caller's cluster arrays (offsets non-decreasing from >= 0,
+// members in [0, n)); a violation sets bcount[15] and nothing is integrated.
+__global__ __launch_bounds__(256) void k_herm_bucket(int64_t nc, int64_t n, const int32_t *__restrict__ cl_ptr,
+                                                     const int32_t *__restrict__ members, int32_t *__restrict__ bcount,
+                                                     int32_t *__restrict__ blists) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += stride) {  // uniform loop
+    const int64_t c = base + threadIdx.x;
+    int bk = -1;
+    if (c < nc) {
+      const int a = cl_ptr[c], b = cl_ptr[c + 1];
+      bool ok = a >= 0 && b >= a;
+      for (int k = a; ok && k < b; ++k) {
+        const int g = members[k];
+        ok = g >= 0 && (int64_t)g < n;
+      }
+      if (!ok)
+        atomicOr(&bcount[15], 1);
+      else if (b > a)
+        bk = bucket_of(b - a);
     }
-    bool ok = true;
-    for (int k = a; k < b; ++k) {
-      const int g = members[k];
-      ok &= (g >= 0 && (int64_t)g < n);
+    for (int q = 0; q < N_BUCKETS; ++q) {
+      const unsigned long long mask = __ballot(bk == q);
+      if (mask == 0ull) continue;
+      // every lane executes the atomic, only the lowest lane of the bucket adds
+      const int leader = __ffsll((long long)mask) - 1;
+      const int start =
+          __builtin_amdgcn_readlane(atomicAdd(&bcount[q], lane == leader ? (int)__popcll(mask) : 0), leader);
+      if (bk == q) blists[(int64_t)q * nc + start + popc_below(mask)] = (int32_t)c;
     }
-    if (!ok) {
-      atomicOr(&bcount[15], 1);
-      continue;
-    }
-    const int size = b - a;
-    if (size <= 0) continue;
-    const int bk = bucket_of(size);
-    const int p = atomicAdd(&bcount[bk], 1);
-    blists[(int64_t)bk * nc + p] = (int32_t)c;
   }
 }
 
@@ -561,7 +632,7 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   int32_t *bcount = c->herm_bcount;
   int32_t *blists = c->herm_blists;
   if ((e = fill_i32(bcount, 0, 16, s)) != hipSuccess) return e;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (nc + 255) / 256));
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nc + 255) / 256));
   hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, nc, n, cl_ptr, cl_members, bcount, blists);
   int32_t hc[16];
   if ((e = hipMemcpyAsync(hc, bcount, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
@@ -572,6 +643,8 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   HermArgs A;
   A.cl_ptr = cl_ptr;
   A.members = cl_members;
+  A.blists = blists;
+  A.nc = nc;
   A.pos = pos3;
   A.vel = vel3;
   A.mass = mass;
@@ -592,30 +665,18 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   A.max_iter = 1 << 22;
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
-  for (int bk = 0; bk < 10; ++bk) {
-    if (hc[bk] == 0) continue;
-    A.blist = blists + (int64_t)bk * nc;
-    A.nb = hc[bk];
-    if (bk < 7) {
-      const int seg = 1 << bk;
-      const unsigned grid = (unsigned)((hc[bk] + (WAVE / seg) - 1) / (WAVE / seg));
-      switch (seg) {
-        case 1: hipLaunchKernelGGL(k_herm_seg<1>, dim3(grid), dim3(WAVE), 0, s, A); break;
-        case 2: hipLaunchKernelGGL(k_herm_seg<2>, dim3(grid), dim3(WAVE), 0, s, A); break;
-        case 4: hipLaunchKernelGGL(k_herm_seg<4>, dim3(grid), dim3(WAVE), 0, s, A); break;
-        case 8: hipLaunchKernelGGL(k_herm_seg<8>, dim3(grid), dim3(WAVE), 0, s, A); break;
-        case 16: hipLaunchKernelGGL(k_herm_seg<16>, dim3(grid), dim3(WAVE), 0, s, A); break;
-        case 32: hipLaunchKernelGGL(k_herm_seg<32>, dim3(grid), dim3(WAVE), 0, s, A); break;
-        default: hipLaunchKernelGGL(k_herm_seg<64>, dim3(grid), dim3(WAVE), 0, s, A); break;
-      }
-    } else if (bk == 7) {
-      hipLaunchKernelGGL(k_herm_big<1>, dim3(hc[bk]), dim3(BIG_T), 0, s, A);
-    } else if (bk == 8) {
-      hipLaunchKernelGGL(k_herm_big<2>, dim3(hc[bk]), dim3(BIG_T), 0, s, A);
-    } else {
-      hipLaunchKernelGGL(k_herm_big<4>, dim3(hc[bk]), dim3(BIG_T), 0, s, A);
-    }
+  for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = hc[bk];
+  // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG), bucket 7 (one per block)
+  int blocks = 0;
+  for (int bk = 0; bk < 8; ++bk) {
+    A.boff[bk] = blocks;
+    const int per_block = bk < 7 ? (BIG_T / WAVE) * (WAVE >> bk) : 1;
+    blocks += (hc[bk] + per_block - 1) / per_block;
   }
+  for (int bk = 8; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
+  if (blocks > 0) hipLaunchKernelGGL(k_herm_fused, dim3(blocks), dim3(BIG_T), 0, s, A);
+  if (hc[8] > 0) hipLaunchKernelGGL(k_herm_big<2>, dim3(hc[8]), dim3(BIG_T), 0, s, A, 8);
+  if (hc[9] > 0) hipLaunchKernelGGL(k_herm_big<4>, dim3(hc[9]), dim3(BIG_T), 0, s, A, 9);
   return hipGetLastError();
 }
 

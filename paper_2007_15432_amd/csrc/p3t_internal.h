@@ -59,7 +59,8 @@ struct DevCounters {
   unsigned long long force_queue;  // persistent force kernel queue head
   unsigned long long n_near, n_far, n_cell;  // interaction counts
   unsigned long long n_clusters;
-  unsigned long long pad[5];
+  unsigned long long n_chunks;     // subtree roots of the bottom-up moment pass
+  unsigned long long pad[4];
 };
 
 // ---------------------------------------------------------------- device helpers

@@ -117,66 +117,126 @@ __device__ __forceinline__ void quad_shift(double q[6], double m, double dx, dou
   q[5] += m * 3.0 * dy * dz;
 }
 
-// Leaves and bottom-up moments.  One thread per sorted particle; at each
-// internal node the second child to arrive combines both children.
-__global__ void k_moments(int n, const double *__restrict__ sx, const double *__restrict__ sy,
-                          const double *__restrict__ sz, const double *__restrict__ sm,
-                          const double *__restrict__ sreach, p3t::WalkNode *wn, p3t::CellMom *cm,
-                          const int32_t *__restrict__ parent, int32_t *visit) {
+// Internal node from its two children: tight box, mass, centre of mass,
+// traceless quadrupole about the centre of mass (parallel-axis shift of each
+// child's moment), max reach.  Fixed order (left, right): deterministic.
+__device__ __forceinline__ void combine_node(int node, p3t::WalkNode *wn, p3t::CellMom *cm) {
+  const int a = wn[node].left, b = wn[node].right;
+  const p3t::WalkNode wa = wn[a], wb = wn[b];
+  const p3t::CellMom ca = cm[a], cb = cm[b];
+  p3t::WalkNode o;
+  p3t::CellMom co;
+  const double M = ca.mass + cb.mass;
+  co.mass = M;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    o.lo[d] = fmin(wa.lo[d], wb.lo[d]);
+    o.hi[d] = fmax(wa.hi[d], wb.hi[d]);
+    co.com[d] = M > 0.0 ? (ca.mass * ca.com[d] + cb.mass * cb.com[d]) / M : 0.5 * (o.lo[d] + o.hi[d]);
+    o.com[d] = co.com[d];
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) co.q[q] = ca.q[q] + cb.q[q];
+  quad_shift(co.q, ca.mass, ca.com[0] - co.com[0], ca.com[1] - co.com[1], ca.com[2] - co.com[2]);
+  quad_shift(co.q, cb.mass, cb.com[0] - co.com[0], cb.com[1] - co.com[1], cb.com[2] - co.com[2]);
+  o.reach = fmax(wa.reach, wb.reach);
+  o.first = wn[node].first;
+  o.count = wn[node].count;
+  o.left = a;
+  o.right = b;
+  wn[node] = o;
+  cm[node] = co;
+}
+
+// Bottom-up moments in two phases so that every hand-over between threads
+// stays inside one workgroup (workgroup-scope fences only; device-scope
+// fences would write back and invalidate the L2 of every XCD per level).
+//   chunk roots: nodes with <= CHUNK leaves whose parent has more;
+//   phase 1: one workgroup per chunk writes the leaf records and climbs to the
+//            chunk root (second arrival at a node combines its children);
+//   phase 2: one workgroup climbs from every chunk root to the tree root.
+constexpr int CHUNK = 1024;
+
+__global__ void k_chunk_flag(int n, const p3t::WalkNode *__restrict__ wn, const int32_t *__restrict__ parent,
+                             int32_t *__restrict__ flag) {
+  const int n_nodes = 2 * n - 1, leaf0 = n - 1;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes; g += gridDim.x * blockDim.x) {
+    const int c = g >= leaf0 ? 1 : wn[g].count;
+    const int p = (g == 0) ? -1 : parent[g];
+    flag[g] = (c <= CHUNK && (p < 0 || wn[p].count > CHUNK)) ? 1 : 0;
+  }
+}
+
+__global__ void k_chunk_compact(int n_nodes, const int32_t *__restrict__ flag, const int64_t *__restrict__ pos,
+                                int32_t *__restrict__ chunk, p3t::DevCounters *cnt) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes; g += gridDim.x * blockDim.x)
+    if (flag[g]) chunk[pos[g]] = g;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_chunks = (unsigned long long)pos[n_nodes];
+}
+
+__global__ __launch_bounds__(256) void k_moments_local(int n, const double *__restrict__ sx,
+                                                       const double *__restrict__ sy, const double *__restrict__ sz,
+                                                       const double *__restrict__ sm,
+                                                       const double *__restrict__ sreach, p3t::WalkNode *wn,
+                                                       p3t::CellMom *cm, const int32_t *__restrict__ parent,
+                                                       int32_t *visit, const int32_t *__restrict__ chunk,
+                                                       const p3t::DevCounters *cnt) {
   const int leaf0 = n - 1;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const int leaf = leaf0 + k;
-    p3t::WalkNode w;
-    w.lo[0] = w.hi[0] = w.com[0] = sx[k];
-    w.lo[1] = w.hi[1] = w.com[1] = sy[k];
-    w.lo[2] = w.hi[2] = w.com[2] = sz[k];
-    w.reach = sreach[k];
-    w.first = k;
-    w.count = 1;
-    w.left = -1;
-    w.right = -1;
-    wn[leaf] = w;
-    p3t::CellMom c;
-    c.com[0] = w.com[0];
-    c.com[1] = w.com[1];
-    c.com[2] = w.com[2];
-    c.mass = sm[k];
+  const int nch = (int)cnt->n_chunks;
+  for (int ci = blockIdx.x; ci < nch; ci += gridDim.x) {
+    const int r = chunk[ci];
+    const int first = r >= leaf0 ? r - leaf0 : wn[r].first;
+    const int count = r >= leaf0 ? 1 : wn[r].count;
+    for (int t = threadIdx.x; t < count; t += blockDim.x) {
+      const int k = first + t;
+      const int leaf = leaf0 + k;
+      p3t::WalkNode w;
+      w.lo[0] = w.hi[0] = w.com[0] = sx[k];
+      w.lo[1] = w.hi[1] = w.com[1] = sy[k];
+      w.lo[2] = w.hi[2] = w.com[2] = sz[k];
+      w.reach = sreach[k];
+      w.first = k;
+      w.count = 1;
+      w.left = -1;
+      w.right = -1;
+      wn[leaf] = w;
+      p3t::CellMom c;
+      c.com[0] = w.com[0];
+      c.com[1] = w.com[1];
+      c.com[2] = w.com[2];
+      c.mass = sm[k];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) c.q[q] = 0.0;
-    cm[leaf] = c;
-    __threadfence();
-    int node = (n > 1) ? parent[leaf] : -1;
-    while (node >= 0) {
-      // first arrival: the sibling will finish; only the second arrival
-      // combines (a third would mean a malformed tree: stop, never loop)
-      if (atomicAdd(&visit[node], 1) != 1) break;
-      __threadfence();
-      const int a = wn[node].left, b = wn[node].right;
-      const p3t::WalkNode wa = wn[a], wb = wn[b];
-      const p3t::CellMom ca = cm[a], cb = cm[b];
-      p3t::WalkNode o;
-      p3t::CellMom co;
-      const double M = ca.mass + cb.mass;
-      co.mass = M;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        o.lo[d] = fmin(wa.lo[d], wb.lo[d]);
-        o.hi[d] = fmax(wa.hi[d], wb.hi[d]);
-        co.com[d] = M > 0.0 ? (ca.mass * ca.com[d] + cb.mass * cb.com[d]) / M : 0.5 * (o.lo[d] + o.hi[d]);
-        o.com[d] = co.com[d];
+      for (int q = 0; q < 6; ++q) c.q[q] = 0.0;
+      cm[leaf] = c;
+      __threadfence_block();
+      int node = (leaf == r) ? -1 : parent[leaf];
+      while (node >= 0) {
+        // first arrival: the sibling will finish; only the second arrival
+        // combines (a third would mean a malformed tree: stop, never loop)
+        if (atomicAdd(&visit[node], 1) != 1) break;
+        __threadfence_block();
+        combine_node(node, wn, cm);
+        __threadfence_block();
+        if (node == r) break;
+        node = parent[node];
       }
-#pragma unroll
-      for (int q = 0; q < 6; ++q) co.q[q] = ca.q[q] + cb.q[q];
-      quad_shift(co.q, ca.mass, ca.com[0] - co.com[0], ca.com[1] - co.com[1], ca.com[2] - co.com[2]);
-      quad_shift(co.q, cb.mass, cb.com[0] - co.com[0], cb.com[1] - co.com[1], cb.com[2] - co.com[2]);
-      o.reach = fmax(wa.reach, wb.reach);
-      o.first = wn[node].first;
-      o.count = wn[node].count;
-      o.left = a;
-      o.right = b;
-      wn[node] = o;
-      cm[node] = co;
-      __threadfence();
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::CellMom *cm,
+                                                      const int32_t *__restrict__ parent, int32_t *visit,
+                                                      const int32_t *__restrict__ chunk, const p3t::DevCounters *cnt) {
+  const int nch = (int)cnt->n_chunks;
+  for (int ci = threadIdx.x; ci < nch; ci += blockDim.x) {
+    const int r = chunk[ci];
+    int node = r == 0 ? -1 : parent[r];
+    while (node >= 0) {
+      if (atomicAdd(&visit[node], 1) != 1) break;
+      __threadfence_block();
+      combine_node(node, wn, cm);
+      __threadfence_block();
       node = parent[node];
     }
   }
@@ -223,8 +283,16 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
     hipLaunchKernelGGL(k_radix_tree, dim3(g1d(n - 1)), dim3(256), 0, s, (int)n, k, c->wnode, c->parent);
   }
   if ((e = fill_i32(c->visit, 0, n > 1 ? n - 1 : 1, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_moments, dim3(g1d(n)), dim3(256), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm, c->sreach, c->wnode,
-                     c->cmom, c->parent, c->visit);
+  // chunk roots (into group_node / node_scan, both free until the groups are formed)
+  hipLaunchKernelGGL(k_chunk_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n, c->wnode, c->parent, c->group_flag);
+  if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_chunk_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
+                     c->group_node, c->cnt);
+  hipLaunchKernelGGL(k_moments_local, dim3(c->n_cu * 8), dim3(256), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm,
+                     c->sreach, c->wnode, c->cmom, c->parent, c->visit, c->group_node, c->cnt);
+  hipLaunchKernelGGL(k_moments_top, dim3(1), dim3(1024), 0, s, c->wnode, c->cmom, c->parent, c->visit, c->group_node,
+                     c->cnt);
   hipLaunchKernelGGL(k_group_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->wnode, c->parent,
                      c->P.n_group_max, c->group_flag);
   if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)

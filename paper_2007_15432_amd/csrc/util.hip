@@ -284,11 +284,34 @@ __global__ __launch_bounds__(256) void k_bbox_part(const double *__restrict__ po
   }
 }
 
-__global__ void k_bbox_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+// one 256-thread block: min / max over the per-block partials
+__global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  __shared__ double sh[6][256 / WAVE];
   const int t = threadIdx.x;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = t; b < nb; b += 256) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = fmin(lo[c], part[b * 6 + c]);
+      hi[c] = fmax(hi[c], part[b * 6 + 3 + c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = wave_min(lo[c]);
+    hi[c] = wave_max(hi[c]);
+  }
+  if ((t & (WAVE - 1)) == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sh[c][t / WAVE] = lo[c];
+      sh[3 + c][t / WAVE] = hi[c];
+    }
+  }
+  __syncthreads();
   if (t < 6) {
-    double v = part[t];
-    for (int b = 1; b < nb; ++b) v = t < 3 ? fmin(v, part[b * 6 + t]) : fmax(v, part[b * 6 + t]);
+    double v = sh[t][0];
+    for (int w = 1; w < 256 / WAVE; ++w) v = t < 3 ? fmin(v, sh[t][w]) : fmax(v, sh[t][w]);
     out[t] = v;
   }
 }
@@ -296,7 +319,7 @@ __global__ void k_bbox_final(const double *__restrict__ part, int nb, double *__
 hipError_t bbox_reduce(const double *pos3, int64_t n, double *part, double *out, hipStream_t s) {
   const int nb = (int)grid_for(n, 256, BB_BLOCKS);
   hipLaunchKernelGGL(k_bbox_part, dim3(nb), dim3(256), 0, s, pos3, n, part);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, nb, out);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nb, out);
   return hipGetLastError();
 }
 

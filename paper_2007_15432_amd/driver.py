@@ -1,0 +1,60 @@
+"""The P3T soft step (Section 2.2, steps (2)-(8) without collisions) as a
+sequence of library calls.  Orchestration only: every numerical step runs in
+libp3t's kernels.
+
+    init:  cut-off radii; tree; soft force a_soft and neighbour lists  (2)
+    step:  v += a_soft dt/2                                           (3)
+           neighbour clusters from the lists of the last evaluation   (4)
+           Hermite integration of every cluster over dt               (5)
+           tree; soft force and neighbour lists at the new state      (7)
+           v += a_soft dt/2                                           (8)
+
+The cut-off radii are fixed between collisions (Section 2.4: they are
+recomputed after a merger); `recompute_cutoffs` recomputes them every step
+instead (used to time the cut-off stage as part of the step).
+"""
+from __future__ import annotations
+
+import torch
+
+from .api import Context, Params
+
+
+class P3TStepper:
+    def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False):
+        self.ctx = ctx
+        self.pos, self.vel, self.mass = pos, vel, mass
+        self.n = int(mass.shape[0])
+        self.dt = ctx.params.dt_soft
+        self.recompute = recompute_cutoffs
+        self.r_out, self.r_search, self.v_ran = ctx.compute_cutoffs(pos, vel, mass)
+        self.dt_hard = torch.zeros(self.n, dtype=torch.float64, device=pos.device)
+        self.acc = torch.empty((3, self.n), dtype=torch.float64, device=pos.device)
+        self.last = {}
+        self._evaluate()
+
+    def _evaluate(self):
+        c = self.ctx
+        c.build_tree(self.pos, self.vel, self.mass, self.r_out, self.r_search)
+        c.compute_soft_force(out=self.acc)
+        self.row_ptr, self.col, self.label = c.neighbour_list(labels=True)
+        self.last = c.stats()
+
+    def step(self):
+        c = self.ctx
+        c.kick(self.acc, self.vel, 0.5 * self.dt)
+        cl_ptr, members = c.clusters(self.label)
+        self.n_clusters = int(cl_ptr.shape[0]) - 1
+        c.hermite_cluster_step(self.pos, self.vel, self.mass, self.r_out, cl_ptr, members, dt_hard=self.dt_hard,
+                               energy=False)
+        if self.recompute:
+            self.r_out, self.r_search, self.v_ran = c.compute_cutoffs(self.pos, self.vel, self.mass)
+        self._evaluate()
+        c.kick(self.acc, self.vel, 0.5 * self.dt)
+
+    def interactions(self) -> int:
+        s = self.last
+        return int(s["n_near"] + s["n_far"] + s["n_cell"])
+
+
+__all__ = ["P3TStepper", "Params"]
