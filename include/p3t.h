@@ -179,6 +179,28 @@ p3t_status p3t_soft_kick_adjoint(p3t_ctx *ctx, double h, const double *lam_v3, d
 
 /* Enable (1) / disable (0) event timing of the phases (p3t_stats). */
 p3t_status p3t_set_timing(p3t_ctx *ctx, int32_t on);
+
+/* Launch shapes of the soft-force kernels.  None of them changes what is
+   computed beyond the order of floating-point summation; they exist so that an
+   autotuner can pick the fastest shape for a workload.
+     force_split      1: one kernel per interaction class (near with the
+                      changeover and neighbour candidates, far particles,
+                      cells) plus an exact-test kernel over the candidates;
+                      0: one fused kernel.
+     force_unroll     j-loop unroll of the split kernels: 1, 2, 4 or 8.
+     force_persistent 1: persistent grids that take groups from a queue in
+                      longest-list-first order; 0: one workgroup per group.
+     waves_per_cu     persistent grid of the split kernels in wavefronts per
+                      compute unit (1..64; capped by the kernel's occupancy).
+     walk_waves_per_cu persistent grid of the walk (1..64).
+   Host memory; p3t_set_kernel_config rejects values outside these ranges
+   with P3T_ERR_ARG and leaves the previous shape in place. */
+typedef struct {
+  int32_t force_split, force_unroll, force_persistent, waves_per_cu, walk_waves_per_cu;
+  int32_t reserved[3];
+} p3t_kernel_config;
+p3t_status p3t_set_kernel_config(p3t_ctx *ctx, const p3t_kernel_config *cfg_host);
+p3t_status p3t_get_kernel_config(p3t_ctx *ctx, p3t_kernel_config *cfg_host);
 /* Counters of the last evaluation.  Synchronises. */
 p3t_status p3t_get_stats(p3t_ctx *ctx, p3t_stats *out_host);
 /* Read and clear the device status word.  Synchronises. */

@@ -48,6 +48,13 @@ class CStats(C.Structure):
     ]
 
 
+class CKernelConfig(C.Structure):
+    _fields_ = [
+        ("force_split", C.c_int32), ("force_unroll", C.c_int32), ("force_persistent", C.c_int32),
+        ("waves_per_cu", C.c_int32), ("walk_waves_per_cu", C.c_int32), ("reserved", C.c_int32 * 3),
+    ]
+
+
 # name -> (restype, argtypes)
 _vp, _i64, _i32, _d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
 SIGNATURES = {
@@ -67,6 +74,8 @@ SIGNATURES = {
     "p3t_kick": (C.c_int, [_vp, _i64, _d, _vp, _vp]),
     "p3t_soft_kick_adjoint": (C.c_int, [_vp, _d, _vp, _vp, _vp]),
     "p3t_set_timing": (C.c_int, [_vp, _i32]),
+    "p3t_set_kernel_config": (C.c_int, [_vp, C.POINTER(CKernelConfig)]),
+    "p3t_get_kernel_config": (C.c_int, [_vp, C.POINTER(CKernelConfig)]),
     "p3t_get_stats": (C.c_int, [_vp, C.POINTER(CStats)]),
     "p3t_get_status": (C.c_int, [_vp, C.POINTER(C.c_uint32)]),
     "p3t_last_error": (C.c_char_p, [_vp]),

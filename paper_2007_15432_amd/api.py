@@ -130,6 +130,24 @@ class Context:
     def set_timing(self, on: bool = True):
         self._check(self.L.p3t_set_timing(self._h, 1 if on else 0), "set_timing")
 
+    KERNEL_KEYS = ("force_split", "force_unroll", "force_persistent", "waves_per_cu", "walk_waves_per_cu")
+
+    def kernel_config(self) -> dict:
+        k = _lib.CKernelConfig()
+        self._check(self.L.p3t_get_kernel_config(self._h, C.byref(k)), "get_kernel_config")
+        return {f: getattr(k, f) for f in self.KERNEL_KEYS}
+
+    def set_kernel_config(self, **kw) -> dict:
+        """Change launch shapes (see p3t_kernel_config); returns the new shape."""
+        cur = self.kernel_config()
+        bad = set(kw) - set(self.KERNEL_KEYS)
+        if bad:
+            raise ValueError(f"unknown kernel config keys {sorted(bad)}")
+        cur.update(kw)
+        k = _lib.CKernelConfig(*(int(cur[f]) for f in self.KERNEL_KEYS))
+        self._check(self.L.p3t_set_kernel_config(self._h, C.byref(k)), "set_kernel_config")
+        return cur
+
     def stats(self) -> dict:
         s = _lib.CStats()
         self._check(self.L.p3t_get_stats(self._h, C.byref(s)), "get_stats")

@@ -94,7 +94,7 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   total += bytes(n_cap, sizeof(int32_t)) + bytes(n_cap + 1, sizeof(int64_t));       // row_cnt, csr_ptr
   total += bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));      // uf, cl keys
   total += bytes(cut_part_need(n_cap), sizeof(double));
-  total += bytes(3 * n_cap, sizeof(double));
+  total += 2 * bytes(3 * n_cap, sizeof(double));
   total += bytes(16, sizeof(int32_t)) + bytes(11 * n_cap, sizeof(int32_t));  // hermite buckets
   total += 4096;
   if (c->arena.base) {
@@ -138,6 +138,7 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   c->cl_keys_alt = A.take<uint64_t>(n_cap);
   c->cut_part = A.take<double>(cut_part_need(n_cap));
   c->tmp_d = A.take<double>(3 * n_cap);
+  c->acc_s = A.take<double>(3 * n_cap);
   c->herm_bcount = A.take<int32_t>(16);
   c->herm_blists = A.take<int32_t>(11 * n_cap);
   if (!c->herm_blists) return fail(c, P3T_ERR_HIP, "arena layout overflow (internal)");
@@ -159,7 +160,7 @@ p3t_status ensure_lists(p3t_ctx *c, int64_t n) {
     c->pool_cap = cap;
   }
   if (!c->slot_lists) {
-    c->walk_slots = c->n_cu * 4;
+    c->walk_slots = c->n_cu * c->walk_waves_per_cu;
     if (c->slot_cap_list == 0) c->slot_cap_list = 16384;
     if (c->slot_cap_stack == 0) c->slot_cap_stack = 8192;
     HIP_OK(c, dev_alloc(c->slot_lists, (int64_t)c->walk_slots * 3 * c->slot_cap_list));
@@ -170,6 +171,11 @@ p3t_status ensure_lists(p3t_ctx *c, int64_t n) {
     HIP_OK(c, dev_alloc(c->pairs, cap));
     HIP_OK(c, dev_alloc(c->csr_col, cap));
     c->pair_cap = cap;
+  }
+  if (!c->cands) {
+    const int64_t cap = std::max<int64_t>(1 << 16, 8 * n);
+    HIP_OK(c, dev_alloc(c->cands, cap));
+    c->cand_cap = cap;
   }
   return P3T_OK;
 }
@@ -271,7 +277,7 @@ p3t_status p3t_create(const p3t_params *p, void *stream, p3t_ctx **out) {
 p3t_status p3t_destroy(p3t_ctx *c) {
   if (!c) return P3T_ERR_ARG;
   hipStreamSynchronize(c->stream);
-  void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col};
+  void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col, c->cands};
   for (void *b : bufs)
     if (b) hipFree(b);
   for (auto &e : c->ev)
@@ -400,10 +406,17 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
         HIP_OK(c, dev_alloc(c->slot_stack, (int64_t)c->walk_slots * c->slot_cap_stack));
       }
       if (retry & P3T_FLAG_PAIR_OVERFLOW) {
-        const int64_t cap = (int64_t)h.n_pairs + (int64_t)h.n_pairs / 4 + 1024;
-        HIP_OK(c, dev_alloc(c->pairs, cap));
-        HIP_OK(c, dev_alloc(c->csr_col, cap));
-        c->pair_cap = cap;
+        if ((int64_t)h.n_pairs > c->pair_cap) {
+          const int64_t cap = (int64_t)h.n_pairs + (int64_t)h.n_pairs / 4 + 1024;
+          HIP_OK(c, dev_alloc(c->pairs, cap));
+          HIP_OK(c, dev_alloc(c->csr_col, cap));
+          c->pair_cap = cap;
+        }
+        if ((int64_t)h.n_cand > c->cand_cap) {
+          const int64_t cap = (int64_t)h.n_cand + (int64_t)h.n_cand / 4 + 1024;
+          HIP_OK(c, dev_alloc(c->cands, cap));
+          c->cand_cap = cap;
+        }
       }
       continue;
     }
@@ -515,6 +528,40 @@ p3t_status p3t_set_timing(p3t_ctx *c, int32_t on) {
   if (!c) return P3T_ERR_ARG;
   c->timing = on ? 1 : 0;
   c->stats.timing = c->timing;
+  return P3T_OK;
+}
+
+p3t_status p3t_set_kernel_config(p3t_ctx *c, const p3t_kernel_config *k) {
+  if (!c || !k) return P3T_ERR_ARG;
+  const int u = k->force_unroll;
+  if ((k->force_split != 0 && k->force_split != 1) || (u != 1 && u != 2 && u != 4 && u != 8) ||
+      (k->force_persistent != 0 && k->force_persistent != 1) || k->waves_per_cu < 1 || k->waves_per_cu > 64 ||
+      k->walk_waves_per_cu < 1 || k->walk_waves_per_cu > 64)
+    return fail(c, P3T_ERR_ARG, "set_kernel_config: value out of range");
+  c->fcfg.split = k->force_split;
+  c->fcfg.unroll = u;
+  c->fcfg.waves_per_cu = k->waves_per_cu;
+  c->force_persistent = k->force_persistent;
+  if (c->walk_waves_per_cu != k->walk_waves_per_cu) {
+    c->walk_waves_per_cu = k->walk_waves_per_cu;
+    if (c->slot_lists) {  // the walk's per-slot scratch follows the grid
+      HIP_OK(c, hipStreamSynchronize(c->stream));
+      c->walk_slots = c->n_cu * c->walk_waves_per_cu;
+      HIP_OK(c, dev_alloc(c->slot_lists, (int64_t)c->walk_slots * 3 * c->slot_cap_list));
+      HIP_OK(c, dev_alloc(c->slot_stack, (int64_t)c->walk_slots * c->slot_cap_stack));
+    }
+  }
+  return P3T_OK;
+}
+
+p3t_status p3t_get_kernel_config(p3t_ctx *c, p3t_kernel_config *k) {
+  if (!c || !k) return P3T_ERR_ARG;
+  *k = p3t_kernel_config{};
+  k->force_split = c->fcfg.split;
+  k->force_unroll = c->fcfg.unroll;
+  k->force_persistent = c->force_persistent;
+  k->waves_per_cu = c->fcfg.waves_per_cu;
+  k->walk_waves_per_cu = c->walk_waves_per_cu;
   return P3T_OK;
 }
 

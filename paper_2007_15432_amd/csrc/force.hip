@@ -17,66 +17,17 @@
 //     offsets from the group centre (offsets formed in FP64) with per-tile
 //     FP32 partial sums folded into a compensated (hi, lo) FP32 accumulator.
 //   Cells are monopoles or traceless quadrupoles about their centre of mass.
-#include "p3t_internal.h"
+#include "force_common.h"
 
 namespace p3t {
 
-struct ForceArgs {
-  const double *sx, *sy, *sz, *sm, *sinv, *sreach, *svx, *svy, *svz, *srs, *sro;
-  const int32_t *sid;
-  const WalkNode *wn;
-  const CellMom *cm;
-  const GroupList *gl;
-  const int32_t *order;
-  const int32_t *pool;
-  DevCounters *cnt;
-  int2 *pairs;
-  int64_t pair_cap;
-  double *acc;
-  int64_t n;
-  double G, gamma, inv1mg;
-  double rsch2, rsch3, dt;  // neighbour-test parameters
-  int persistent;
-};
-
-// Neighbour test of Section 2.3 (closest approach over the step compared
-// with Rsearch2 r_out,ij, or slow pair), in a fixed division- and root-free
-// FP64 operation order, contraction disabled, so that every decision is
-// reproducible bit for bit.
+// The fused kernel calls the exact test out of line (it is rare).
 __device__ __noinline__ bool pair_is_neighbour(double xi, double yi, double zi, double vxi, double vyi, double vzi,
                                                double mi, double roi, double rsi, double xj, double yj, double zj,
                                                double vxj, double vyj, double vzj, double mj, double roj, double rsj,
                                                double G, double rsch2, double rsch3, double dt) {
-#pragma clang fp contract(off)
-  const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-  const double ux = vxi - vxj, uy = vyi - vyj, uz = vzi - vzj;
-  const double rr = ((dx * dx) + (dy * dy)) + (dz * dz);
-  const double rs = rsi > rsj ? rsi : rsj;
-  if (!(rr < rs * rs)) return false;
-  const double rv = ((dx * ux) + (dy * uy)) + (dz * uz);
-  const double vv = ((ux * ux) + (uy * uy)) + (uz * uz);
-  const double ro = roi > roj ? roi : roj;
-  const double R2 = rsch2 * ro;
-  const double RR = R2 * R2;
-  bool close;
-  if (vv == 0.0 || rv >= 0.0) {
-    close = rr <= RR;
-  } else if (-rv < dt * vv) {
-    close = (rr * vv - rv * rv) <= RR * vv;
-  } else {
-    close = (rr + (2.0 * dt) * rv) + (dt * dt) * vv <= RR;
-  }
-  if (close) return true;
-  const double A = (rsch3 * (G * (mi + mj))) * (0.5 * dt);
-  return vv * (rr * rr) < A * A;
-}
-
-__device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float v) {
-  const float s = hi + v;
-  const float bp = s - hi;
-  const float err = (hi - (s - bp)) + (v - bp);
-  hi = s;
-  lo += err;
+  return neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, xj, yj, zj, vxj, vyj, vzj, mj, roj, rsj, G, rsch2,
+                        rsch3, dt);
 }
 
 template <bool MIXED, bool QUAD, int IPL>
@@ -95,7 +46,7 @@ __global__ __launch_bounds__(WAVE) void k_force(ForceArgs A) {
     int gi;
     if (A.persistent) {
       // all lanes execute the atomic (only lane 0 adds); see uniform_first
-      gi = uniform_first((int)atomicAdd(&A.cnt->force_queue, lane == 0 ? 1ull : 0ull));
+      gi = next_group(A.queue, lane);
     } else {
       gi = iter == 0 ? (int)blockIdx.x : ngroups;
     }
@@ -442,6 +393,8 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3) {
   A.cnt = c->cnt;
   A.pairs = c->pairs;
   A.pair_cap = c->pair_cap;
+  A.cands = c->cands;
+  A.cand_cap = c->cand_cap;
   A.acc = acc3;
   A.n = c->n;
   A.G = P.G;
@@ -451,8 +404,10 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3) {
   A.rsch3 = P.r_search3;
   A.dt = P.dt_soft;
   A.persistent = c->force_persistent;
-  const int ipl = P.n_group_max > WAVE ? 2 : 1;
+  A.queue = &c->cnt->force_queue;
   unsigned grid = A.persistent ? (unsigned)c->force_slots : (unsigned)std::max<int64_t>(1, n_groups_max);
+  if (c->fcfg.split) return soft_force_split(c, A, (unsigned)std::max<int64_t>(1, n_groups_max), acc3);
+  const int ipl = P.n_group_max > WAVE ? 2 : 1;
   const bool mixed = P.precision == 1, quad = P.multipole == 2;
   if (mixed && quad)
     launch_ipl<true, true>(A, ipl, grid, c->stream);

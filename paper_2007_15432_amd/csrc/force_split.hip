@@ -1,0 +1,634 @@
+// force_split.hip -- the soft force as one lean kernel per interaction class
+// (eq. (softforce) with the pair cut-off of eq. (rout2); neighbour pairs of
+// Section 2.3), an alternative to the fused kernel of force.hip.
+//
+//   k_near   FP64 with the changeover K; while it runs, each lane records in
+//            a bit mask which j of the current tile are neighbour candidates
+//            (r^2 <= max reach^2, with a relative margin that covers the
+//            rounding of r^2) and appends them after the tile to a candidate
+//            buffer.  Writes the sorted-order accumulator (=).
+//   k_cand_test  the exact neighbour test of Section 2.3 on every candidate,
+//            one thread each; neighbours go to the pair buffer.
+//   k_far    K = 1 particles, FP64 or (mixed) FP32 offsets from the group
+//            centre with compensated accumulation.  Adds (+=).
+//   k_cell   monopole or traceless-quadrupole cells, FP64 or FP32.  Adds.
+//   k_scatter  sorted-order accumulator -> caller's order, NaN check.
+//
+// Every kernel is one wavefront per group; a lane owns one i-particle, or
+// two when the group holds more than 64 (the choice is per group, so small
+// groups do not pay for an idle second slot).  j data are staged 64 at a
+// time in LDS and read back as broadcasts; the tile is padded to the unroll
+// width with massless dummies placed far from the group.
+#include "force_common.h"
+
+namespace p3t {
+
+namespace {
+
+struct GroupHdr {
+  long long off;
+  int n_cell, n_near, n_far, first, count;
+  double cx, cy, cz;
+};
+
+// Reads the list header of the gi-th group (in work order); every field is
+// wave-uniform.  Returns false for a group whose walk overflowed.
+__device__ __forceinline__ bool group_header(const ForceArgs &A, int gi, GroupHdr &h) {
+  const int q = uniform_first(A.order ? A.order[gi] : gi);
+  const GroupList L = A.gl[q];
+  h.off = uniform_first64(L.off);
+  if (h.off < 0) return false;
+  h.n_cell = uniform_first(L.n_cell);
+  h.n_near = uniform_first(L.n_near);
+  h.n_far = uniform_first(L.n_far);
+  const int node = uniform_first(L.node);
+  h.first = uniform_first(A.wn[node].first);
+  h.count = uniform_first(A.wn[node].count);
+  h.cx = 0.5 * (A.wn[node].lo[0] + A.wn[node].hi[0]);
+  h.cy = 0.5 * (A.wn[node].lo[1] + A.wn[node].hi[1]);
+  h.cz = 0.5 * (A.wn[node].lo[2] + A.wn[node].hi[2]);
+  return true;
+}
+
+__device__ __forceinline__ int next_gi(const ForceArgs &A, int lane, int iter, int ngroups) {
+  if (A.persistent) return next_group(A.queue, lane);
+  return iter == 0 ? (int)blockIdx.x : ngroups;
+}
+
+constexpr double kDummyOffset = 1.0e3;  // distance of padding entries from the group centre
+
+// ------------------------------------------------------------------ near
+struct NearTile {
+  double4 a[WAVE];  // x, y, z, G m
+  double2 b[WAVE];  // 1/r_out, reach^2
+  int j[WAVE];      // sorted index (-2: padding)
+};
+
+template <int IPL, int UNR>
+__device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h, NearTile &T, int lane) {
+  int ii[IPL];
+  double xi[IPL], yi[IPL], zi[IPL], invi[IPL], rch2[IPL], ax[IPL], ay[IPL], az[IPL];
+#pragma unroll
+  for (int s = 0; s < IPL; ++s) {
+    const int k = lane + WAVE * s;
+    ii[s] = k < h.count ? h.first + k : -1;
+    const int i = ii[s] >= 0 ? ii[s] : h.first;
+    // an empty slot sits far from the group and from the padding entries
+    xi[s] = ii[s] >= 0 ? A.sx[i] : h.cx - 2.0 * kDummyOffset;
+    yi[s] = A.sy[i];
+    zi[s] = A.sz[i];
+    invi[s] = A.sinv[i];
+    rch2[s] = A.sreach[i] * A.sreach[i];
+    ax[s] = ay[s] = az[s] = 0.0;
+  }
+  bool coincident = false;
+  const int32_t *Ln = A.pool + h.off + h.n_cell;
+  for (int t0 = 0; t0 < h.n_near; t0 += WAVE) {
+    const int nt = min(WAVE, h.n_near - t0);
+    const int ntp = min(WAVE, (nt + UNR - 1) / UNR * UNR);
+    __syncthreads();
+    if (lane < nt) {
+      const int j = Ln[t0 + lane];
+      const double r = A.sreach[j];
+      T.a[lane] = make_double4(A.sx[j], A.sy[j], A.sz[j], A.G * A.sm[j]);
+      T.b[lane] = make_double2(A.sinv[j], r * r);
+      T.j[lane] = j;
+    } else if (lane < ntp) {
+      T.a[lane] = make_double4(h.cx + kDummyOffset, h.cy, h.cz, 0.0);
+      T.b[lane] = make_double2(1.0, 0.0);
+      T.j[lane] = -2;
+    }
+    __syncthreads();
+    unsigned cm[2][IPL];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) cm[half][s] = 0u;
+      const int lo = half * 32, hi = min(ntp, lo + 32);
+      for (int jj = lo; jj < hi; jj += UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const double4 a = T.a[jj + u];
+          const double2 b = T.b[jj + u];
+          const int jidx = T.j[jj + u];
+          const unsigned bit = 1u << ((jj + u) & 31);
+#pragma unroll
+          for (int s = 0; s < IPL; ++s) {
+            const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const bool other = jidx != ii[s];
+            const bool ok = other && (r2 > 0.0);
+            coincident |= other && !(r2 > 0.0);
+            const double r2s = ok ? r2 : 1.0;
+            const double rinv = rsqrt(r2s);
+            const double y = r2s * rinv * fmin(invi[s], b.x);
+            const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
+            const double x2 = x * x;
+            const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+            const double f = ok ? a.w * K * rinv * rinv * rinv : 0.0;
+            ax[s] += f * dx;
+            ay[s] += f * dy;
+            az[s] += f * dz;
+            const bool cand = other && r2 <= fmax(rch2[s], b.y) * (1.0 + 1e-12);
+            cm[half][s] |= cand ? bit : 0u;
+          }
+        }
+      }
+    }
+    // hand this tile's candidates (sorted indices) to the exact test
+    int nc = 0;
+#pragma unroll
+    for (int s = 0; s < IPL; ++s) {
+      if (ii[s] < 0) cm[0][s] = cm[1][s] = 0u;
+      nc += __popc(cm[0][s]) + __popc(cm[1][s]);
+    }
+    const int incl = wave_incl_scan(nc);
+    const int total = uniform_lane(incl, WAVE - 1);
+    if (total > 0) {
+      const long long base =
+          uniform_first64((long long)atomicAdd(&A.cnt->n_cand, lane == 0 ? (unsigned long long)total : 0ull));
+      long long o = base + incl - nc;
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          unsigned m = cm[half][s];
+          while (m != 0u) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            if (o < A.cand_cap) A.cands[o] = make_int2(ii[s], T.j[32 * half + b]);
+            ++o;
+          }
+        }
+      }
+      if (base + total > A.cand_cap && lane == 0) set_flag(A.cnt, P3T_FLAG_PAIR_OVERFLOW);
+    }
+  }
+  double *acc = A.acc;
+#pragma unroll
+  for (int s = 0; s < IPL; ++s) {
+    if (ii[s] >= 0) {
+      acc[ii[s]] = ax[s];
+      acc[A.n + ii[s]] = ay[s];
+      acc[2 * A.n + ii[s]] = az[s];
+    }
+  }
+  if (__ballot(coincident) != 0ull && lane == 0) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
+}
+
+template <int UNR>
+__global__ __launch_bounds__(WAVE) void k_near(ForceArgs A) {
+  __shared__ NearTile T;
+  const int lane = threadIdx.x;
+  const int ngroups = uniform_first((int)A.cnt->n_groups);
+  for (int iter = 0;; ++iter) {
+    const int gi = next_gi(A, lane, iter, ngroups);
+    if (gi >= ngroups) break;
+    GroupHdr h;
+    if (!group_header(A, gi, h)) continue;
+    if (h.count > WAVE)
+      near_group<2, UNR>(A, h, T, lane);
+    else
+      near_group<1, UNR>(A, h, T, lane);
+    if (lane == 0) {
+      const unsigned long long ni = (unsigned long long)h.count;
+      atomicAdd(&A.cnt->n_near, ni * (unsigned long long)h.n_near - ni);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ far
+union FarTile {
+  double4 d[WAVE];  // x, y, z, G m
+  float4 f[WAVE];   // offsets from the group centre, G m
+};
+
+template <bool MIXED, int IPL, int UNR>
+__device__ __forceinline__ void far_group(const ForceArgs &A, const GroupHdr &h, FarTile &T, int lane) {
+  int ii[IPL];
+  double xi[IPL], yi[IPL], zi[IPL], ax[IPL], ay[IPL], az[IPL];
+#pragma unroll
+  for (int s = 0; s < IPL; ++s) {
+    const int k = lane + WAVE * s;
+    ii[s] = k < h.count ? h.first + k : -1;
+    const int i = ii[s] >= 0 ? ii[s] : h.first;
+    xi[s] = A.sx[i];
+    yi[s] = A.sy[i];
+    zi[s] = A.sz[i];
+    ax[s] = ay[s] = az[s] = 0.0;
+  }
+  const int32_t *Lf = A.pool + h.off + h.n_cell + h.n_near;
+  if (!MIXED) {
+    for (int t0 = 0; t0 < h.n_far; t0 += WAVE) {
+      const int nt = min(WAVE, h.n_far - t0);
+      const int ntp = min(WAVE, (nt + UNR - 1) / UNR * UNR);
+      __syncthreads();
+      if (lane < nt) {
+        const int j = Lf[t0 + lane];
+        T.d[lane] = make_double4(A.sx[j], A.sy[j], A.sz[j], A.G * A.sm[j]);
+      } else if (lane < ntp) {
+        T.d[lane] = make_double4(h.cx + kDummyOffset, h.cy, h.cz, 0.0);
+      }
+      __syncthreads();
+      for (int jj = 0; jj < ntp; jj += UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const double4 a = T.d[jj + u];
+#pragma unroll
+          for (int s = 0; s < IPL; ++s) {
+            const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double rinv = rsqrt(r2);
+            const double f = a.w * rinv * rinv * rinv;
+            ax[s] += f * dx;
+            ay[s] += f * dy;
+            az[s] += f * dz;
+          }
+        }
+      }
+    }
+  } else {
+    float fxi[IPL], fyi[IPL], fzi[IPL], hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
+#pragma unroll
+    for (int s = 0; s < IPL; ++s) {
+      fxi[s] = (float)(xi[s] - h.cx);
+      fyi[s] = (float)(yi[s] - h.cy);
+      fzi[s] = (float)(zi[s] - h.cz);
+      hx[s] = hy[s] = hz[s] = lx[s] = ly[s] = lz[s] = 0.0f;
+    }
+    for (int t0 = 0; t0 < h.n_far; t0 += WAVE) {
+      const int nt = min(WAVE, h.n_far - t0);
+      const int ntp = min(WAVE, (nt + UNR - 1) / UNR * UNR);
+      __syncthreads();
+      if (lane < nt) {
+        const int j = Lf[t0 + lane];
+        T.f[lane] = make_float4((float)(A.sx[j] - h.cx), (float)(A.sy[j] - h.cy), (float)(A.sz[j] - h.cz),
+                                (float)(A.G * A.sm[j]));
+      } else if (lane < ntp) {
+        T.f[lane] = make_float4((float)kDummyOffset, 0.0f, 0.0f, 0.0f);
+      }
+      __syncthreads();
+      float tx[IPL], ty[IPL], tz[IPL];
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) tx[s] = ty[s] = tz[s] = 0.0f;
+      for (int jj = 0; jj < ntp; jj += UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const float4 a = T.f[jj + u];
+#pragma unroll
+          for (int s = 0; s < IPL; ++s) {
+            const float dx = a.x - fxi[s], dy = a.y - fyi[s], dz = a.z - fzi[s];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float rinv = __frsqrt_rn(r2);
+            const float f = a.w * rinv * rinv * rinv;
+            tx[s] += f * dx;
+            ty[s] += f * dy;
+            tz[s] += f * dz;
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) {
+        two_sum_acc(hx[s], lx[s], tx[s]);
+        two_sum_acc(hy[s], ly[s], ty[s]);
+        two_sum_acc(hz[s], lz[s], tz[s]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < IPL; ++s) {
+      ax[s] = (double)hx[s] + (double)lx[s];
+      ay[s] = (double)hy[s] + (double)ly[s];
+      az[s] = (double)hz[s] + (double)lz[s];
+    }
+  }
+  double *acc = A.acc;
+#pragma unroll
+  for (int s = 0; s < IPL; ++s) {
+    if (ii[s] >= 0) {
+      acc[ii[s]] += ax[s];
+      acc[A.n + ii[s]] += ay[s];
+      acc[2 * A.n + ii[s]] += az[s];
+    }
+  }
+}
+
+template <bool MIXED, int UNR>
+__global__ __launch_bounds__(WAVE) void k_far(ForceArgs A) {
+  __shared__ FarTile T;
+  const int lane = threadIdx.x;
+  const int ngroups = uniform_first((int)A.cnt->n_groups);
+  for (int iter = 0;; ++iter) {
+    const int gi = next_gi(A, lane, iter, ngroups);
+    if (gi >= ngroups) break;
+    GroupHdr h;
+    if (!group_header(A, gi, h)) continue;
+    if (h.n_far == 0) continue;
+    if (h.count > WAVE)
+      far_group<MIXED, 2, UNR>(A, h, T, lane);
+    else
+      far_group<MIXED, 1, UNR>(A, h, T, lane);
+    if (lane == 0) atomicAdd(&A.cnt->n_far, (unsigned long long)h.count * (unsigned long long)h.n_far);
+  }
+}
+
+// ------------------------------------------------------------------ cells
+union CellTile {
+  struct {
+    double4 a[WAVE];  // centre of mass, G M
+    double4 qa[WAVE];  // G q_xx, q_yy, q_zz, q_xy
+    double2 qb[WAVE];  // G q_xz, q_yz
+  } d;
+  struct {
+    float4 a[WAVE];
+    float4 qa[WAVE];
+    float2 qb[WAVE];
+  } f;
+};
+
+template <typename R>
+__device__ __forceinline__ void cell_term(R dx, R dy, R dz, R gm, R q0, R q1, R q2, R q3, R q4, R q5, bool quad,
+                                          R rinv, R &fx, R &fy, R &fz) {
+  // a = G [ M d / r^3 - Q d / r^5 + (5/2) (d.Q d) d / r^7 ],  d = X_c - x_i
+  const R rinv2 = rinv * rinv;
+  const R rinv3 = rinv * rinv2;
+  fx = gm * rinv3 * dx;
+  fy = gm * rinv3 * dy;
+  fz = gm * rinv3 * dz;
+  if (quad) {
+    const R qx = q0 * dx + q3 * dy + q4 * dz;
+    const R qy = q3 * dx + q1 * dy + q5 * dz;
+    const R qz = q4 * dx + q5 * dy + q2 * dz;
+    const R dqd = dx * qx + dy * qy + dz * qz;
+    const R rinv5 = rinv3 * rinv2;
+    const R c7 = R(2.5) * dqd * rinv5 * rinv2;
+    fx += c7 * dx - qx * rinv5;
+    fy += c7 * dy - qy * rinv5;
+    fz += c7 * dz - qz * rinv5;
+  }
+}
+
+template <bool MIXED, bool QUAD, int IPL, int UNR>
+__device__ __forceinline__ void cell_group(const ForceArgs &A, const GroupHdr &h, CellTile &T, int lane) {
+  int ii[IPL];
+  double xi[IPL], yi[IPL], zi[IPL], ax[IPL], ay[IPL], az[IPL];
+#pragma unroll
+  for (int s = 0; s < IPL; ++s) {
+    const int k = lane + WAVE * s;
+    ii[s] = k < h.count ? h.first + k : -1;
+    const int i = ii[s] >= 0 ? ii[s] : h.first;
+    xi[s] = A.sx[i];
+    yi[s] = A.sy[i];
+    zi[s] = A.sz[i];
+    ax[s] = ay[s] = az[s] = 0.0;
+  }
+  const int32_t *Lc = A.pool + h.off;
+  const double G = A.G;
+  if (!MIXED) {
+    for (int t0 = 0; t0 < h.n_cell; t0 += WAVE) {
+      const int nt = min(WAVE, h.n_cell - t0);
+      const int ntp = min(WAVE, (nt + UNR - 1) / UNR * UNR);
+      __syncthreads();
+      if (lane < nt) {
+        const CellMom c = A.cm[Lc[t0 + lane]];
+        T.d.a[lane] = make_double4(c.com[0], c.com[1], c.com[2], G * c.mass);
+        if (QUAD) {
+          T.d.qa[lane] = make_double4(G * c.q[0], G * c.q[1], G * c.q[2], G * c.q[3]);
+          T.d.qb[lane] = make_double2(G * c.q[4], G * c.q[5]);
+        }
+      } else if (lane < ntp) {
+        T.d.a[lane] = make_double4(h.cx + kDummyOffset, h.cy, h.cz, 0.0);
+        if (QUAD) {
+          T.d.qa[lane] = make_double4(0.0, 0.0, 0.0, 0.0);
+          T.d.qb[lane] = make_double2(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+      for (int jj = 0; jj < ntp; jj += UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const double4 a = T.d.a[jj + u];
+          double4 qa = make_double4(0.0, 0.0, 0.0, 0.0);
+          double2 qb = make_double2(0.0, 0.0);
+          if (QUAD) {
+            qa = T.d.qa[jj + u];
+            qb = T.d.qb[jj + u];
+          }
+#pragma unroll
+          for (int s = 0; s < IPL; ++s) {
+            const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            double fx, fy, fz;
+            cell_term<double>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, rsqrt(r2), fx, fy, fz);
+            ax[s] += fx;
+            ay[s] += fy;
+            az[s] += fz;
+          }
+        }
+      }
+    }
+  } else {
+    float fxi[IPL], fyi[IPL], fzi[IPL], hx[IPL], hy[IPL], hz[IPL], lx[IPL], ly[IPL], lz[IPL];
+#pragma unroll
+    for (int s = 0; s < IPL; ++s) {
+      fxi[s] = (float)(xi[s] - h.cx);
+      fyi[s] = (float)(yi[s] - h.cy);
+      fzi[s] = (float)(zi[s] - h.cz);
+      hx[s] = hy[s] = hz[s] = lx[s] = ly[s] = lz[s] = 0.0f;
+    }
+    for (int t0 = 0; t0 < h.n_cell; t0 += WAVE) {
+      const int nt = min(WAVE, h.n_cell - t0);
+      const int ntp = min(WAVE, (nt + UNR - 1) / UNR * UNR);
+      __syncthreads();
+      if (lane < nt) {
+        const CellMom c = A.cm[Lc[t0 + lane]];
+        T.f.a[lane] = make_float4((float)(c.com[0] - h.cx), (float)(c.com[1] - h.cy), (float)(c.com[2] - h.cz),
+                                  (float)(G * c.mass));
+        if (QUAD) {
+          T.f.qa[lane] = make_float4((float)(G * c.q[0]), (float)(G * c.q[1]), (float)(G * c.q[2]),
+                                     (float)(G * c.q[3]));
+          T.f.qb[lane] = make_float2((float)(G * c.q[4]), (float)(G * c.q[5]));
+        }
+      } else if (lane < ntp) {
+        T.f.a[lane] = make_float4((float)kDummyOffset, 0.0f, 0.0f, 0.0f);
+        if (QUAD) {
+          T.f.qa[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          T.f.qb[lane] = make_float2(0.0f, 0.0f);
+        }
+      }
+      __syncthreads();
+      float tx[IPL], ty[IPL], tz[IPL];
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) tx[s] = ty[s] = tz[s] = 0.0f;
+      for (int jj = 0; jj < ntp; jj += UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const float4 a = T.f.a[jj + u];
+          float4 qa = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          float2 qb = make_float2(0.0f, 0.0f);
+          if (QUAD) {
+            qa = T.f.qa[jj + u];
+            qb = T.f.qb[jj + u];
+          }
+#pragma unroll
+          for (int s = 0; s < IPL; ++s) {
+            const float dx = a.x - fxi[s], dy = a.y - fyi[s], dz = a.z - fzi[s];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            float fx, fy, fz;
+            cell_term<float>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, __frsqrt_rn(r2), fx, fy,
+                             fz);
+            tx[s] += fx;
+            ty[s] += fy;
+            tz[s] += fz;
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) {
+        two_sum_acc(hx[s], lx[s], tx[s]);
+        two_sum_acc(hy[s], ly[s], ty[s]);
+        two_sum_acc(hz[s], lz[s], tz[s]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < IPL; ++s) {
+      ax[s] = (double)hx[s] + (double)lx[s];
+      ay[s] = (double)hy[s] + (double)ly[s];
+      az[s] = (double)hz[s] + (double)lz[s];
+    }
+  }
+  double *acc = A.acc;
+#pragma unroll
+  for (int s = 0; s < IPL; ++s) {
+    if (ii[s] >= 0) {
+      acc[ii[s]] += ax[s];
+      acc[A.n + ii[s]] += ay[s];
+      acc[2 * A.n + ii[s]] += az[s];
+    }
+  }
+}
+
+template <bool MIXED, bool QUAD, int UNR>
+__global__ __launch_bounds__(WAVE) void k_cell(ForceArgs A) {
+  __shared__ CellTile T;
+  const int lane = threadIdx.x;
+  const int ngroups = uniform_first((int)A.cnt->n_groups);
+  for (int iter = 0;; ++iter) {
+    const int gi = next_gi(A, lane, iter, ngroups);
+    if (gi >= ngroups) break;
+    GroupHdr h;
+    if (!group_header(A, gi, h)) continue;
+    if (h.n_cell == 0) continue;
+    if (h.count > WAVE)
+      cell_group<MIXED, QUAD, 2, UNR>(A, h, T, lane);
+    else
+      cell_group<MIXED, QUAD, 1, UNR>(A, h, T, lane);
+    if (lane == 0) atomicAdd(&A.cnt->n_cell, (unsigned long long)h.count * (unsigned long long)h.n_cell);
+  }
+}
+
+// exact neighbour test of every candidate (sorted indices) -> pairs in the
+// caller's indices
+__global__ void k_cand_test(ForceArgs A) {
+  const long long nc = (long long)A.cnt->n_cand;
+  const long long m = nc < A.cand_cap ? nc : A.cand_cap;
+  const int lane = lane_id();
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  // the loop runs wave by wave, so the ballot below sees every lane
+  for (long long p0 = blockIdx.x * (long long)blockDim.x + (threadIdx.x - lane); p0 < m; p0 += stride) {
+    const long long p = p0 + lane;
+    bool nb = false;
+    int i = 0, j = 0;
+    if (p < m) {
+      const int2 c = A.cands[p];
+      i = c.x;
+      j = c.y;
+      nb = neighbour_test(A.sx[i], A.sy[i], A.sz[i], A.svx[i], A.svy[i], A.svz[i], A.sm[i], A.sro[i], A.srs[i],
+                          A.sx[j], A.sy[j], A.sz[j], A.svx[j], A.svy[j], A.svz[j], A.sm[j], A.sro[j], A.srs[j], A.G,
+                          A.rsch2, A.rsch3, A.dt);
+    }
+    const unsigned long long bal = __ballot(nb);
+    if (bal == 0ull) continue;
+    const int leader = __ffsll((long long)bal) - 1;
+    const unsigned long long o0 = (unsigned long long)uniform_lane64(
+        (long long)atomicAdd(&A.cnt->n_pairs, lane == leader ? (unsigned long long)__popcll(bal) : 0ull), leader);
+    if (nb) {
+      const unsigned long long q = o0 + popc_below(bal);
+      if ((int64_t)q < A.pair_cap)
+        A.pairs[q] = make_int2(A.sid[i], A.sid[j]);
+      else
+        set_flag(A.cnt, P3T_FLAG_PAIR_OVERFLOW);
+    }
+  }
+}
+
+// sorted-order accumulator -> caller's order
+__global__ void k_scatter(const double *__restrict__ acc_s, const int32_t *__restrict__ sid, int64_t n,
+                          double *__restrict__ acc, DevCounters *cnt) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = acc_s[i], y = acc_s[n + i], z = acc_s[2 * n + i];
+    const int64_t o = sid[i];
+    acc[o] = x;
+    acc[n + o] = y;
+    acc[2 * n + o] = z;
+    bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+  }
+  if (__ballot(bad) != 0ull && lane_id() == 0) set_flag(cnt, P3T_FLAG_NAN);
+}
+
+template <typename K>
+unsigned persistent_grid(K kernel, int n_cu, int waves_cap) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, WAVE, 0) != hipSuccess || nb <= 0) nb = 8;
+  return (unsigned)(n_cu * std::min(nb, waves_cap));
+}
+
+template <int UNR>
+hipError_t launch_split(p3t_ctx *c, ForceArgs A, unsigned nonpersistent_grid, double *acc3) {
+  const bool mixed = c->P.precision == 1, quad = c->P.multipole == 2;
+  const hipStream_t s = c->stream;
+  const int cap = c->fcfg.waves_per_cu;
+  A.acc = c->acc_s;
+  auto grid = [&](auto kernel) {
+    return A.persistent ? persistent_grid(kernel, c->n_cu, cap) : nonpersistent_grid;
+  };
+  A.queue = &c->cnt->queue[0];
+  hipLaunchKernelGGL((k_near<UNR>), dim3(grid(k_near<UNR>)), dim3(WAVE), 0, s, A);
+  A.queue = &c->cnt->queue[1];
+  if (mixed)
+    hipLaunchKernelGGL((k_far<true, UNR>), dim3(grid(k_far<true, UNR>)), dim3(WAVE), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_far<false, UNR>), dim3(grid(k_far<false, UNR>)), dim3(WAVE), 0, s, A);
+  A.queue = &c->cnt->queue[2];
+  if (mixed && quad)
+    hipLaunchKernelGGL((k_cell<true, true, UNR>), dim3(grid(k_cell<true, true, UNR>)), dim3(WAVE), 0, s, A);
+  else if (mixed)
+    hipLaunchKernelGGL((k_cell<true, false, UNR>), dim3(grid(k_cell<true, false, UNR>)), dim3(WAVE), 0, s, A);
+  else if (quad)
+    hipLaunchKernelGGL((k_cell<false, true, UNR>), dim3(grid(k_cell<false, true, UNR>)), dim3(WAVE), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_cell<false, false, UNR>), dim3(grid(k_cell<false, false, UNR>)), dim3(WAVE), 0, s, A);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 8, (c->n + 255) / 256));
+  const unsigned gc = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 8, (c->cand_cap + 255) / 256));
+  hipLaunchKernelGGL(k_cand_test, dim3(gc), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, (const double *)c->acc_s, (const int32_t *)c->sid, c->n,
+                     acc3, c->cnt);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t soft_force_split(p3t_ctx *c, const ForceArgs &A, unsigned nonpersistent_grid, double *acc3) {
+  switch (c->fcfg.unroll) {
+    case 1:
+      return launch_split<1>(c, A, nonpersistent_grid, acc3);
+    case 2:
+      return launch_split<2>(c, A, nonpersistent_grid, acc3);
+    case 8:
+      return launch_split<8>(c, A, nonpersistent_grid, acc3);
+    default:
+      return launch_split<4>(c, A, nonpersistent_grid, acc3);
+  }
+}
+
+}  // namespace p3t

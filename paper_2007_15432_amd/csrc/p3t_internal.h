@@ -60,7 +60,8 @@ struct DevCounters {
   unsigned long long n_near, n_far, n_cell;  // interaction counts
   unsigned long long n_clusters;
   unsigned long long n_chunks;     // subtree roots of the bottom-up moment pass
-  unsigned long long pad[4];
+  unsigned long long queue[3];    // persistent queues of the split force kernels
+  unsigned long long n_cand;      // neighbour candidates appended (split force)
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -83,6 +84,12 @@ __device__ __forceinline__ int uniform_lane(int v, int l) { return __builtin_amd
 __device__ __forceinline__ long long uniform_first64(long long v) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffll));
   const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ long long uniform_lane64(long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)v >> 32), l);
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
@@ -162,6 +169,8 @@ struct p3t_ctx {
   int32_t *slot_lists = nullptr;    // walk temp lists (walk_slots * 3 * slot_cap_list)
   int32_t *slot_stack = nullptr;    // walk stacks (walk_slots * slot_cap_stack)
   int2 *pairs = nullptr;            // neighbour pairs (i_orig, j_orig)
+  int2 *cands = nullptr;            // neighbour candidates (sorted indices)
+  int64_t cand_cap = 0;
 
   // state
   int64_t n = 0;
@@ -171,6 +180,12 @@ struct p3t_ctx {
   unsigned host_status = 0;   // accumulated device status bits (cleared by p3t_get_status)
   int force_slots = 0;        // persistent force grid
   int force_persistent = 1;
+  int walk_waves_per_cu = 4;  // persistent walk grid
+  struct {
+    int split = 1;         // 1: one kernel per interaction class, 0: the fused kernel
+    int unroll = 4;        // j-loop unroll of the split kernels (1, 2, 4, 8)
+    int waves_per_cu = 32; // persistent grid of the split kernels: waves per CU (capped by occupancy)
+  } fcfg;
   int32_t *herm_bcount = nullptr;  // Hermite bucket counts (16)
   int32_t *herm_blists = nullptr;  // Hermite bucket lists (11 * n_cap)
 
@@ -205,6 +220,7 @@ struct p3t_ctx {
   uint64_t *cl_keys = nullptr, *cl_keys_alt = nullptr;  // cluster sort keys (n)
   double *cut_part = nullptr;       // cut-off bin partial sums
   double *tmp_d = nullptr;          // per-particle FP64 scratch (3n)
+  double *acc_s = nullptr;          // soft acceleration in sorted order (3n)
 };
 
 // ---------------------------------------------------------------- launchers

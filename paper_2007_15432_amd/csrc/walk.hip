@@ -160,6 +160,8 @@ __global__ __launch_bounds__(WAVE) void k_walk(const WalkNode *__restrict__ wn, 
 __global__ void k_reset_queues(DevCounters *cnt) {
   cnt->walk_queue = 0;
   cnt->force_queue = 0;
+  for (int k = 0; k < 3; ++k) cnt->queue[k] = 0;
+  cnt->n_cand = 0;
   cnt->pool_cursor = 0;
   cnt->n_pairs = 0;
   cnt->n_near = 0;

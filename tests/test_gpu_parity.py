@@ -74,8 +74,10 @@ def ring(orc):
     return Case(orc, diskgen.dense_ring(4096, seed=11), orc.Params(r_cut0=10.0))
 
 
-def run_force(p3t, case, **kw):
+def run_force(p3t, case, kcfg=None, **kw):
     ctx = p3t.Context(gparams(p3t, case.p, **kw))
+    if kcfg:
+        ctx.set_kernel_config(**kcfg)
     g = case.g
     ctx.build_tree(g["pos"], g["vel"], g["m"], g["ro"], g["rs"])
     acc = ctx.compute_soft_force()
@@ -164,6 +166,36 @@ def test_neighbour_lists_bit_exact(gpu, orc, disk2k, ring, which):
         assert np.array_equal(lab.cpu().numpy(), lab_o)
     if which == "ring":
         assert rp_o[-1] > 1000  # the stress input really exercises the test
+
+
+SHAPES = [dict(force_split=0), dict(force_split=0, force_persistent=0)] + [
+    dict(force_split=1, force_unroll=u) for u in (1, 2, 4, 8)] + [
+    dict(force_split=1, force_persistent=0), dict(force_split=1, waves_per_cu=1, walk_waves_per_cu=1)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_kernel_shapes_agree(gpu, orc, ring, precision):
+    """Every launch shape the autotuner may pick gives the oracle's neighbour
+    lists bit for bit and the same forces up to summation order."""
+    rp_o, col_o = ring.nbr(orc)
+    ref = ring.acc(orc)
+    accs = []
+    for k in SHAPES:
+        ctx, acc = run_force(gpu, ring, kcfg=k, theta=0.5, multipole=2, precision=precision)
+        rp, col, _ = ctx.neighbour_list(labels=False)
+        assert np.array_equal(rp.cpu().numpy(), rp_o), k
+        assert np.array_equal(col.cpu().numpy(), col_o), k
+        e = errs(acc, ref)
+        print(k, "precision", precision, "eps", e)
+        # the thin dense ring is harder for the tree than the disk: its
+        # quadrupole truncation error at theta = 0.5 is ~7e-4 / 4e-4
+        assert e[0] < 2e-3 and e[1] < 1e-3, k
+        accs.append(acc)
+    # same lists, different summation order: FP64 agrees to rounding, the
+    # mixed form to its FP32 rounding
+    tol = 1e-12 if precision == 0 else 1e-6
+    for k, a in zip(SHAPES[1:], accs[1:]):
+        assert errs(a, accs[0])[2] < tol, k
 
 
 def test_cluster_csr(gpu, orc, ring):
