@@ -27,11 +27,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic flops per interaction (FMA = 2, add/sub/mul/min/max = 1,
-# rsqrt = 1), counted from the kernels' arithmetic (see the design notes).
-FLOPS_NEAR = 35   # FP64 pair with the changeover K
-FLOPS_FAR = 18    # pair with K = 1
-FLOPS_MONO = 18   # monopole cell
-FLOPS_QUAD = 51   # quadrupole cell
+# rsqrt = 1), counted from the arithmetic of the force kernels:
+#   offsets 3, r^2 5 (mul + 2 FMA), rsqrt 1, accumulate 6 (3 FMA);
+#   K = 1 pair / monopole: + G m r^-3 3                                 = 18
+#   near pair: + y 3 (min, 2 mul), x 4 (sub, mul, max, min), K 9
+#     (x^2, x^4, 3 Horner FMA, product), G m K r^-3 4                   = 35
+#   quadrupole cell: monopole 18 + Q d 15 + d.Q d 5 + r^-5 1
+#     + (5/2) dQd r^-7 3 + per-axis c7 d - Q d r^-5 and sum 12           = 54
+FLOPS_NEAR = 35
+FLOPS_FAR = 18
+FLOPS_MONO = 18
+FLOPS_QUAD = 54
 PEAK_FP64 = 78.6e12   # MI355X vector FP64 (256 CU x 128 flop/clk x 2.4 GHz)
 PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published, packed)
 METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force error"
@@ -58,7 +64,8 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     inter = near = far = cell = 0
-    stage = {k: 0.0 for k in ("ms_cutoffs", "ms_tree", "ms_walk", "ms_force", "ms_neighbour", "ms_hermite")}
+    stage = {k: 0.0 for k in ("ms_cutoffs", "ms_tree", "ms_walk", "ms_force", "ms_neighbour", "ms_hermite",
+                              "ms_near", "ms_far", "ms_cell", "ms_cand")}
     for _ in range(steps):
         st.step()
         s = ctx.stats()
@@ -77,22 +84,68 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf):
                n_near=near // steps, n_far=far // steps, n_cell=cell // steps, n_groups=s["n_groups"],
                n_pairs=s["n_pairs"], n_clusters=st.n_clusters,
                stages_ms={k[3:]: v / steps for k, v in stage.items()})
-    # roofline of the force kernel (the dominant kernel)
-    t_force = stage["ms_force"] / steps * 1e-3
-    w64 = out["n_near"] * FLOPS_NEAR
-    w_far = out["n_far"] * FLOPS_FAR + out["n_cell"] * FLOPS_QUAD
-    if precision == 1:
-        t_min = w64 / PEAK_FP64 + w_far / PEAK_FP32
-    else:
-        t_min = (w64 + w_far) / PEAK_FP64
-    achieved = (w64 + w_far) / t_force
-    out["roofline"] = dict(bound="alu", achieved=achieved / 1e12, peak=(w64 + w_far) / t_min / 1e12,
-                           unit="TFLOP/s", frac=t_min / t_force, traffic=None, kernel="k_force",
-                           avg_ms=t_force * 1e3)
+    # roofline of the dominant force kernel, from its own event-timed launches
+    ks = kernel_rooflines(out, stage, steps, precision)
+    dom = max(ks, key=lambda k: ks[k]["avg_ms"])
+    r = dict(ks[dom])
+    r["kernel"] = dom
+    r["traffic"] = measured_traffic(dom, precision)
+    out["roofline"] = r
+    out["kernels"] = ks
     out["_acc0"] = acc0.cpu().numpy()
     out["_r_out0"] = r_out0.cpu().numpy()
     ctx.close()
     return out
+
+
+KERNEL_NAMES = {"near": "k_near", "far": "k_far", "cell": "k_cell"}
+
+
+def kernel_rooflines(out, stage, steps, precision):
+    """Achieved vs peak vector flop rate of each split force kernel: the
+    kernel's algorithmic flops per launch (interactions x flops per
+    interaction) over its event-timed average launch duration."""
+    fp32 = precision == 1
+    spec = {
+        "near": (out["n_near"] * FLOPS_NEAR, PEAK_FP64, "fp64"),
+        "far": (out["n_far"] * FLOPS_FAR, PEAK_FP32 if fp32 else PEAK_FP64, "fp32" if fp32 else "fp64"),
+        "cell": (out["n_cell"] * FLOPS_QUAD, PEAK_FP32 if fp32 else PEAK_FP64, "fp32" if fp32 else "fp64"),
+    }
+    ks = {}
+    for k, (flops, peak, dt) in spec.items():
+        ms = stage["ms_" + k] / steps
+        if ms <= 0.0:
+            continue
+        ach = flops / (ms * 1e-3)
+        ks[KERNEL_NAMES[k]] = dict(bound="alu", achieved=ach / 1e12, peak=peak / 1e12, unit="TFLOP/s",
+                                   frac=ach / peak, avg_ms=ms, flops_per_launch=flops, arith=dt)
+    return ks
+
+
+def source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("force_common.h", "force_split.hip", "p3t_internal.h"):
+        with open(os.path.join(ROOT, "paper_2007_15432_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, or None if the kernel sources changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_force_disk1m.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    rec = t.get("kernels", {}).get(f"{kernel}:{'mixed' if precision == 1 else 'fp64'}")
+    return None if rec is None else rec.get("bytes_per_launch")
 
 
 def cpu_baseline(disk, results, sample, seed=33):
@@ -129,7 +182,7 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--n-group", type=int, default=128)
     ap.add_argument("--n-leaf", type=int, default=16)
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -163,7 +216,8 @@ def main():
         results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, args.n_group, args.n_leaf)
         r = results[name]
         print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
-              f"force {r['stages_ms']['force']:.2f} ms, frac {r['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
+              f"force {r['stages_ms']['force']:.2f} ms, {r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}",
+              file=sys.stderr, flush=True)
     head = "mixed" if "mixed" in results else next(iter(results))
     base, errs = (None, {})
     if not args.no_cpu and "fp64" in results:
@@ -192,11 +246,13 @@ def main():
         "cpu_baseline": base,
         "interactions_per_step": h["interactions_per_step"],
         "stages_ms": h["stages_ms"],
+        "kernels": h["kernels"],
         "force_error": errs.get(head),
     }
     for name, r in results.items():
         if name != head:
-            line[name] = {k: r[k] for k in ("value", "ms_per_step", "interactions_per_step", "stages_ms", "roofline")}
+            line[name] = {k: r[k] for k in ("value", "ms_per_step", "interactions_per_step", "stages_ms", "roofline",
+                                            "kernels")}
             line[name]["force_error"] = errs.get(name)
     line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters")}
     print(json.dumps(line))

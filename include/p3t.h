@@ -85,6 +85,10 @@ typedef struct {
   int64_t n_pairs;      /* neighbour pairs found (directed, = nnz) */
   int64_t list_entries; /* total interaction-list entries (near + far + cells) */
   double ms_cutoffs, ms_tree, ms_walk, ms_force, ms_neighbour, ms_hermite; /* event-timed phases */
+  /* the force phase by kernel (split form; zero for the fused kernel):
+     near particles with the changeover, far particles, cells, exact
+     neighbour test of the candidates */
+  double ms_near, ms_far, ms_cell, ms_cand;
   int32_t timing;       /* 1 if the phase times above were measured */
   int32_t reserved;
 } p3t_stats;

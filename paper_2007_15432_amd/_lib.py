@@ -44,6 +44,7 @@ class CStats(C.Structure):
         ("n_far", C.c_int64), ("n_cell", C.c_int64), ("n_pairs", C.c_int64), ("list_entries", C.c_int64),
         ("ms_cutoffs", C.c_double), ("ms_tree", C.c_double), ("ms_walk", C.c_double), ("ms_force", C.c_double),
         ("ms_neighbour", C.c_double), ("ms_hermite", C.c_double),
+        ("ms_near", C.c_double), ("ms_far", C.c_double), ("ms_cell", C.c_double), ("ms_cand", C.c_double),
         ("timing", C.c_int32), ("reserved", C.c_int32),
     ]
 

@@ -200,6 +200,9 @@ p3t_status harvest_status(p3t_ctx *c, unsigned *new_bits) {
   return P3T_OK;
 }
 
+}  // namespace
+
+namespace p3t {
 void ev_record(p3t_ctx *c, int k) {
   if (c->timing) hipEventRecord(c->ev[k], c->stream);
 }
@@ -211,7 +214,7 @@ double ev_ms(p3t_ctx *c, int a, int b) {
 
 bool bad_ptr(const void *p, int64_t n) { return n > 0 && p == nullptr; }
 
-}  // namespace
+}  // namespace p3t
 
 extern "C" {
 
@@ -429,6 +432,14 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
     if (c->timing) {
       c->stats.ms_walk = ev_ms(c, 4, 5);
       c->stats.ms_force = ev_ms(c, 5, 6);
+      if (c->fcfg.split) {
+        c->stats.ms_near = ev_ms(c, 5, 11);
+        c->stats.ms_far = ev_ms(c, 11, 12);
+        c->stats.ms_cell = ev_ms(c, 12, 13);
+        c->stats.ms_cand = ev_ms(c, 13, 14);
+      } else {
+        c->stats.ms_near = c->stats.ms_far = c->stats.ms_cell = c->stats.ms_cand = 0.0;
+      }
     }
     const unsigned num = h.status & NUMERIC_BITS;
     c->host_status |= h.status & ~RETRY_BITS;

@@ -594,11 +594,13 @@ hipError_t launch_split(p3t_ctx *c, ForceArgs A, unsigned nonpersistent_grid, do
   };
   A.queue = &c->cnt->queue[0];
   hipLaunchKernelGGL((k_near<UNR>), dim3(grid(k_near<UNR>)), dim3(WAVE), 0, s, A);
+  ev_record(c, 11);
   A.queue = &c->cnt->queue[1];
   if (mixed)
     hipLaunchKernelGGL((k_far<true, UNR>), dim3(grid(k_far<true, UNR>)), dim3(WAVE), 0, s, A);
   else
     hipLaunchKernelGGL((k_far<false, UNR>), dim3(grid(k_far<false, UNR>)), dim3(WAVE), 0, s, A);
+  ev_record(c, 12);
   A.queue = &c->cnt->queue[2];
   if (mixed && quad)
     hipLaunchKernelGGL((k_cell<true, true, UNR>), dim3(grid(k_cell<true, true, UNR>)), dim3(WAVE), 0, s, A);
@@ -608,9 +610,11 @@ hipError_t launch_split(p3t_ctx *c, ForceArgs A, unsigned nonpersistent_grid, do
     hipLaunchKernelGGL((k_cell<false, true, UNR>), dim3(grid(k_cell<false, true, UNR>)), dim3(WAVE), 0, s, A);
   else
     hipLaunchKernelGGL((k_cell<false, false, UNR>), dim3(grid(k_cell<false, false, UNR>)), dim3(WAVE), 0, s, A);
+  ev_record(c, 13);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 8, (c->n + 255) / 256));
   const unsigned gc = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 8, (c->cand_cap + 255) / 256));
   hipLaunchKernelGGL(k_cand_test, dim3(gc), dim3(256), 0, s, A);
+  ev_record(c, 14);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, (const double *)c->acc_s, (const int32_t *)c->sid, c->n,
                      acc3, c->cnt);
   return hipGetLastError();

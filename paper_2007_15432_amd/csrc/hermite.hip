@@ -39,6 +39,8 @@ struct HermArgs {
   int32_t *nsteps;
   int64_t n;
   double G, GM, gamma, inv1mg, eta, eta0, dt_soft, tick;
+  // powers of dt_soft for the corrector (scaled per level by exact powers of two)
+  double inv_dt2, inv_dt3, dt3_6, dt4_24, dt5_120;
   int k_max, max_iter;
   double wc, wf1, wlog;
   double wp[8];  // f(y) = sum_k wp[k] y^k + wlog y ln y   (eq. (cutfuncW))
@@ -106,21 +108,23 @@ __device__ __forceinline__ int level_for(double dt_soft, double dtc, int kmax) {
 
 __device__ __forceinline__ double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
 
-// corrector + new level for one active member
+// corrector + new level for one active member; its step is h = dt_soft 2^-lev
+// (h, 1/h^2, 1/h^3, h^3/6, ... are the level-0 powers scaled by exact
+// powers of two, so no division sits on the step's dependency chain)
 __device__ __forceinline__ void correct(double *x, double *v, double *a0, double *j0, const double *xp, const double *vp,
                                         const double *a1, const double *j1, double h, int64_t tnew, int &lev,
                                         const HermArgs &A) {
   double a2[3], a3[3];
-  const double ih = 1.0 / h;
-  const double ih2 = ih * ih, ih3 = ih2 * ih;
-  const double h3 = h * h * h, h4 = h3 * h, h5 = h4 * h;
+  const int l = lev;
+  const double ih2 = ldexp(A.inv_dt2, 2 * l), ih3 = ldexp(A.inv_dt3, 3 * l);
+  const double h3_6 = ldexp(A.dt3_6, -3 * l), h4_24 = ldexp(A.dt4_24, -4 * l), h5_120 = ldexp(A.dt5_120, -5 * l);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double da = a0[d] - a1[d];
     a2[d] = (-6.0 * da - h * (4.0 * j0[d] + 2.0 * j1[d])) * ih2;
     a3[d] = (12.0 * da + 6.0 * h * (j0[d] + j1[d])) * ih3;
-    x[d] = xp[d] + a2[d] * h4 * (1.0 / 24.0) + a3[d] * h5 * (1.0 / 120.0);
-    v[d] = vp[d] + a2[d] * h3 * (1.0 / 6.0) + a3[d] * h4 * (1.0 / 24.0);
+    x[d] = xp[d] + a2[d] * h4_24 + a3[d] * h5_120;
+    v[d] = vp[d] + a2[d] * h3_6 + a3[d] * h4_24;
     a0[d] = a1[d];
     j0[d] = j1[d];
   }
@@ -157,13 +161,29 @@ __device__ __forceinline__ int initial_level(const double *a0, const double *j0,
   return lev;
 }
 
-template <typename T, int SEG>
-__device__ __forceinline__ T seg_min(T v) {
-#pragma unroll
-  for (int o = SEG / 2; o > 0; o >>= 1) {
-    T t = __shfl_xor(v, o, SEG);
-    v = t < v ? t : v;
-  }
+// DPP lane permutations inside a row of 16 lanes (no LDS round trip):
+// quad_perm [1,0,3,2] and [2,3,0,1] exchange with lane^1 and lane^2;
+// row_half_mirror and row_mirror reflect 8- and 16-lane blocks, which after
+// the quad steps brings the other half's minimum to every lane.
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_i64(int64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(uint64_t)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xF, 0xF, false);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+// minimum over aligned segments of SEG lanes; every lane of the wave must be
+// active
+template <int SEG>
+__device__ __forceinline__ int64_t seg_min(int64_t v) {
+  int64_t t;
+  if (SEG >= 2) { t = dpp_i64<DPP_XOR1>(v); v = t < v ? t : v; }
+  if (SEG >= 4) { t = dpp_i64<DPP_XOR2>(v); v = t < v ? t : v; }
+  if (SEG >= 8) { t = dpp_i64<DPP_HALF_MIRROR>(v); v = t < v ? t : v; }
+  if (SEG >= 16) { t = dpp_i64<DPP_MIRROR>(v); v = t < v ? t : v; }
+  if (SEG >= 32) { t = __shfl_xor(v, 16, WAVE); v = t < v ? t : v; }
+  if (SEG >= 64) { t = __shfl_xor(v, 32, WAVE); v = t < v ? t : v; }
   return v;
 }
 template <int SEG>
@@ -190,7 +210,7 @@ struct Lds {
 // One wavefront (lanes [wbase, wbase + 64) of the LDS arrays) runs 64/SEG
 // clusters; cluster index ci of bucket bk.
 template <int SEG>
-__device__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int ci0, const Lds &L, int wbase) {
+__device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int ci0, const Lds &L, int wbase) {
   const int lane = threadIdx.x & (WAVE - 1), seg = lane / SEG, sl = lane % SEG, sb = wbase + seg * SEG;
   const int ci = ci0 + seg;
   const int c = ci < count ? blist[ci] : -1;
@@ -248,9 +268,11 @@ __device__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int
   int nst = 0;  // block steps of this lane's cluster
   for (int it = 0;; ++it) {
     const int64_t te = mem ? t + ((int64_t)1 << (TICK_BITS - lev)) : LLONG_MAX;
-    const int64_t tn = seg_min<int64_t, SEG>(te);
-    const int64_t tlow = seg_min<int64_t, SEG>(mem ? t : T);
-    const bool done = (size == 0) || (tlow == T);
+    // every step divides T and each member's time is a multiple of its
+    // step, so a cluster is finished exactly when its earliest next time
+    // lies beyond T
+    const int64_t tn = seg_min<SEG>(te);
+    const bool done = (size == 0) || (tn > T);
     if (__all(done)) break;
     if (it >= A.max_iter) {
       if (lane == 0) set_flag(A.cnt, P3T_FLAG_NSTEPS);
@@ -355,7 +377,7 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 // One 256-thread workgroup per cluster c, MPT members per thread.
 template <int MPT>
-__device__ void big_body(const HermArgs &A, int c, const Lds &L, int64_t *shi, double *shd) {
+__device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L, int64_t *shi, double *shd) {
   const int tid = threadIdx.x;
   const int b = A.cl_ptr[c];
   const int size = A.cl_ptr[c + 1] - b;
@@ -421,17 +443,15 @@ __device__ void big_body(const HermArgs &A, int c, const Lds &L, int64_t *shi, d
   const int64_t T = (int64_t)1 << TICK_BITS;
   int it = 0;  // block steps taken
   for (;; ++it) {
-    int64_t tel = LLONG_MAX, tlow = T;
+    int64_t tel = LLONG_MAX;
 #pragma unroll
     for (int u = 0; u < MPT; ++u)
       if (mem[u]) {
         const int64_t te = t[u] + ((int64_t)1 << (TICK_BITS - lev[u]));
         tel = te < tel ? te : tel;
-        tlow = t[u] < tlow ? t[u] : tlow;
       }
     const int64_t tn = uniform_first64(block_min_i64(tel, shi));
-    const int64_t tl = uniform_first64(block_min_i64(tlow, shi));
-    if (tl == T) break;
+    if (tn > T) break;  // every member has reached T (see seg_body)
     if (it >= A.max_iter) {
       if (tid == 0) set_flag(A.cnt, P3T_FLAG_NSTEPS);
       break;
@@ -522,9 +542,17 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   __shared__ double shd[BIG_T / WAVE];
   const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7]};
   const int blk = blockIdx.x;
-  int bk = 0;
-  while (bk < 7 && A.boff[bk + 1] <= blk) ++bk;  // uniform per workgroup
-  const int local = blk - A.boff[bk];
+  // bucket of this workgroup (boff is non-decreasing).  Only constant
+  // indices into the argument struct: a run-time index would make the
+  // compiler copy the whole struct to per-lane scratch memory.
+  int bk = 0, first = 0;
+#pragma unroll
+  for (int q = 1; q < 8; ++q)
+    if (A.boff[q] <= blk) {
+      bk = q;
+      first = A.boff[q];
+    }
+  const int local = blk - first;
   const int32_t *blist = A.blists + (int64_t)bk * A.nc;
   if (bk == 7) {
     big_body<1>(A, blist[local], L, shi, shd);
@@ -661,6 +689,14 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   A.eta0 = P.eta0;
   A.dt_soft = P.dt_soft;
   A.tick = std::ldexp(P.dt_soft, -TICK_BITS);
+  {
+    const double h = P.dt_soft, h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
+    A.inv_dt2 = 1.0 / h2;
+    A.inv_dt3 = 1.0 / h3;
+    A.dt3_6 = h3 / 6.0;
+    A.dt4_24 = h4 / 24.0;
+    A.dt5_120 = h5 / 120.0;
+  }
   A.k_max = P.k_max;
   A.max_iter = 1 << 22;
   A.cnt = c->cnt;

@@ -231,6 +231,10 @@ hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *
                            hipStream_t s);  // out has n + 1 entries (exclusive, out[n] = total)
 hipError_t scan_u32_inplace(uint32_t *data, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s);
 int64_t scan_tmp_need(int64_t n);
+// timing events of the context (recorded only when timing is on)
+void ev_record(p3t_ctx *c, int k);
+double ev_ms(p3t_ctx *c, int a, int b);
+
 hipError_t radix_sort_pairs(uint64_t *&keys, int32_t *&vals, uint64_t *&keys_alt, int32_t *&vals_alt, int64_t n_static,
                             const unsigned long long *n_dev, int bit_lo, int bit_hi, uint32_t *hist, int64_t hist_cap,
                             int64_t *tmp, int64_t tmp_cap, hipStream_t s);
