@@ -174,11 +174,28 @@ p3t_status p3t_hermite_cluster_step(p3t_ctx *ctx, int64_t n, int64_t n_clusters,
 /* Soft kick, eq. (HamiltonSol): vel3 += h * acc3 (3n each). */
 p3t_status p3t_kick(p3t_ctx *ctx, int64_t n, double h, const double *acc3, double *vel3);
 
-/* Vector-Jacobian product of the soft kick v += h a(x, m) over the current
- * tree with its interaction lists and pair cut-offs frozen: for the cotangent
- * lam_v3 (3n) of the velocities, accumulates h * d(lam . a)/dx into g_pos3
- * (3n) and h * d(lam . a)/dm into g_mass (n).  Requires a prior
- * p3t_compute_soft_force on the same tree. */
+/* Soft force over the CURRENT tree topology and interaction lists at new
+ * positions pos3 (3n) and masses mass (n), in the caller's order, with the
+ * pair cut-offs of the last p3t_build_tree: the sorted positions and masses
+ * are replaced, the cell moments recomputed, and every group is evaluated
+ * over its existing lists (eq. (softforce), eq. (rout2)).  This is the
+ * function whose derivative p3t_soft_kick_adjoint returns; it exists so that
+ * finite differences and checkpointed recomputation see exactly the lists of
+ * the forward pass.  Writes acc3 (3n).  Neighbour pairs are not collected:
+ * p3t_neighbour_list keeps returning those of the last
+ * p3t_compute_soft_force.  P3T_ERR_STATE without a prior
+ * p3t_compute_soft_force. */
+p3t_status p3t_soft_force_frozen(p3t_ctx *ctx, const double *pos3, const double *mass, double *acc3);
+
+/* Vector-Jacobian product of the soft kick v' = v + h a(x, m) (eq.
+ * (HamiltonSol), eq. (softforce)) at the state of the last force evaluation
+ * (p3t_compute_soft_force or p3t_soft_force_frozen), with its interaction lists
+ * and pair cut-offs r_out,ij held fixed.  For the cotangent lam_v3 (3n) of v'
+ * it WRITES g_pos3 (3n) = h d(lam . a)/dx and g_mass (n) = h d(lam . a)/dm,
+ * all in the caller's order (the cotangent of v itself is lam_v3 unchanged).
+ * Cells enter as monopoles: the call returns P3T_ERR_STATE if the evaluation
+ * used quadrupole cells (multipole = 2 with theta > 0).  Device memory; the
+ * library allocates its scratch on the first call for a given size. */
 p3t_status p3t_soft_kick_adjoint(p3t_ctx *ctx, double h, const double *lam_v3, double *g_pos3, double *g_mass);
 
 /* Enable (1) / disable (0) event timing of the phases (p3t_stats). */

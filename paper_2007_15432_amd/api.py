@@ -191,6 +191,30 @@ class Context:
         self._check(self.L.p3t_compute_soft_force(self._h, _ptr(acc)), "compute_soft_force")
         return acc
 
+    def soft_force_frozen(self, pos, mass, out=None):
+        """Soft force at new positions / masses over the current tree topology
+        and interaction lists (the function the adjoint differentiates)."""
+        n = self.n
+        self._vec3(pos, n, "pos")
+        self._vec(mass, n, "mass")
+        acc = out if out is not None else torch.empty((3, n), dtype=torch.float64, device=self.device)
+        self._vec3(acc, n, "acc")
+        self._bind()
+        self._check(self.L.p3t_soft_force_frozen(self._h, _ptr(pos), _ptr(mass), _ptr(acc)), "soft_force_frozen")
+        return acc
+
+    def soft_kick_adjoint(self, lam_v, h: float):
+        """(h dL/dx (3, n), h dL/dm (n,)) for L = lam_v . a at the last force
+        evaluation, lists and pair cut-offs held fixed."""
+        n = self.n
+        self._vec3(lam_v, n, "lam_v")
+        gx = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        gm = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._bind()
+        self._check(self.L.p3t_soft_kick_adjoint(self._h, float(h), _ptr(lam_v), _ptr(gx), _ptr(gm)),
+                    "soft_kick_adjoint")
+        return gx, gm
+
     def neighbour_list(self, labels: bool = True):
         """(row_ptr int64 (n+1,), col int32 (nnz,), label int32 (n,) or None)."""
         n = self.n

@@ -280,7 +280,7 @@ p3t_status p3t_create(const p3t_params *p, void *stream, p3t_ctx **out) {
 p3t_status p3t_destroy(p3t_ctx *c) {
   if (!c) return P3T_ERR_ARG;
   hipStreamSynchronize(c->stream);
-  void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col, c->cands};
+  void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col, c->cands, c->adj_buf};
   for (void *b : bufs)
     if (b) hipFree(b);
   for (auto &e : c->ev)
@@ -530,9 +530,35 @@ p3t_status p3t_kick(p3t_ctx *c, int64_t n, double h, const double *acc3, double 
   return P3T_OK;
 }
 
+p3t_status p3t_soft_force_frozen(p3t_ctx *c, const double *pos3, const double *mass, double *acc3) {
+  if (!c) return P3T_ERR_ARG;
+  if (!c->force_valid) return fail(c, P3T_ERR_STATE, "soft_force_frozen: no interaction lists (call p3t_compute_soft_force)");
+  if (bad_ptr(pos3, c->n) || bad_ptr(mass, c->n) || bad_ptr(acc3, c->n))
+    return fail(c, P3T_ERR_ARG, "soft_force_frozen: null pointer");
+  if (c->n == 0) return P3T_OK;
+  HIP_OK(c, refresh_tree(c, pos3, mass));
+  reset_queues(c);
+  HIP_OK(c, soft_force(c, c->n_groups, acc3, true));
+  // no pair or candidate buffer was offered: their overflow bits mean nothing here
+  hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, (unsigned)P3T_FLAG_PAIR_OVERFLOW);
+  return P3T_OK;
+}
+
 p3t_status p3t_soft_kick_adjoint(p3t_ctx *c, double h, const double *lam_v3, double *g_pos3, double *g_mass) {
   if (!c) return P3T_ERR_ARG;
-  return fail(c, P3T_ERR_STATE, "soft_kick_adjoint: not available in this build");
+  if (!c->force_valid) return fail(c, P3T_ERR_STATE, "soft_kick_adjoint: no interaction lists (call p3t_compute_soft_force)");
+  if (bad_ptr(lam_v3, c->n) || bad_ptr(g_pos3, c->n) || bad_ptr(g_mass, c->n))
+    return fail(c, P3T_ERR_ARG, "soft_kick_adjoint: null pointer");
+  if (c->P.multipole != 1 && c->stats.n_cell > 0)
+    return fail(c, P3T_ERR_STATE, "soft_kick_adjoint: cells must be monopoles (multipole = 1) or absent (theta = 0)");
+  if (c->n == 0) return P3T_OK;
+  if (c->adj_cap < c->n) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    HIP_OK(c, dev_alloc(c->adj_buf, adjoint_buf_need(c->n_cap)));
+    c->adj_cap = c->n_cap;
+  }
+  HIP_OK(c, soft_kick_adjoint(c, h, lam_v3, g_pos3, g_mass));
+  return P3T_OK;
 }
 
 p3t_status p3t_set_timing(p3t_ctx *c, int32_t on) {

@@ -370,7 +370,7 @@ static void launch_ipl(const ForceArgs &A, int ipl, unsigned grid, hipStream_t s
     hipLaunchKernelGGL((k_force<MIXED, QUAD, 2>), dim3(grid), dim3(WAVE), 0, s, A);
 }
 
-hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3) {
+hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3, bool frozen) {
   const p3t_params &P = c->P;
   ForceArgs A;
   A.sx = c->sx;
@@ -395,6 +395,7 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3) {
   A.pair_cap = c->pair_cap;
   A.cands = c->cands;
   A.cand_cap = c->cand_cap;
+  if (frozen) A.pair_cap = A.cand_cap = 0;
   A.acc = acc3;
   A.n = c->n;
   A.G = P.G;

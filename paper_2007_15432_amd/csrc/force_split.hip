@@ -613,7 +613,7 @@ hipError_t launch_split(p3t_ctx *c, ForceArgs A, unsigned nonpersistent_grid, do
   ev_record(c, 13);
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 8, (c->n + 255) / 256));
   const unsigned gc = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 8, (c->cand_cap + 255) / 256));
-  hipLaunchKernelGGL(k_cand_test, dim3(gc), dim3(256), 0, s, A);
+  if (A.cand_cap > 0) hipLaunchKernelGGL(k_cand_test, dim3(gc), dim3(256), 0, s, A);
   ev_record(c, 14);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, (const double *)c->acc_s, (const int32_t *)c->sid, c->n,
                      acc3, c->cnt);

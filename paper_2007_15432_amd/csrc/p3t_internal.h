@@ -221,6 +221,8 @@ struct p3t_ctx {
   double *cut_part = nullptr;       // cut-off bin partial sums
   double *tmp_d = nullptr;          // per-particle FP64 scratch (3n)
   double *acc_s = nullptr;          // soft acceleration in sorted order (3n)
+  double *adj_buf = nullptr;        // soft-kick adjoint scratch (adjoint_buf_need(adj_cap))
+  int64_t adj_cap = 0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -231,6 +233,12 @@ hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *
                            hipStream_t s);  // out has n + 1 entries (exclusive, out[n] = total)
 hipError_t scan_u32_inplace(uint32_t *data, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s);
 int64_t scan_tmp_need(int64_t n);
+void reset_queues(p3t_ctx *c);  // queue heads and per-evaluation counters
+hipError_t tree_moments(p3t_ctx *c, int64_t n);
+hipError_t refresh_tree(p3t_ctx *c, const double *pos3, const double *mass);
+hipError_t soft_kick_adjoint(p3t_ctx *c, double h, const double *lam_v3, double *g_pos3, double *g_mass);
+int64_t adjoint_buf_need(int64_t n_cap);
+
 // timing events of the context (recorded only when timing is on)
 void ev_record(p3t_ctx *c, int k);
 double ev_ms(p3t_ctx *c, int a, int b);
@@ -256,7 +264,8 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
 hipError_t walk_groups(p3t_ctx *c, int64_t n_groups);
 
 // force.hip
-hipError_t soft_force(p3t_ctx *c, int64_t n_groups, double *acc3);
+// frozen: no neighbour pairs or candidates are kept (evaluation over existing lists)
+hipError_t soft_force(p3t_ctx *c, int64_t n_groups, double *acc3, bool frozen = false);
 
 // nbr.hip
 hipError_t build_csr(p3t_ctx *c, int64_t n, int64_t n_pairs);

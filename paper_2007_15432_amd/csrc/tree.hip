@@ -65,6 +65,19 @@ __global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const doub
   }
 }
 
+// new positions and masses into the sorted arrays of the current order
+__global__ void k_regather_xm(int64_t n, const int32_t *__restrict__ sid, const double *__restrict__ pos,
+                              const double *__restrict__ m, double *__restrict__ sx, double *__restrict__ sy,
+                              double *__restrict__ sz, double *__restrict__ sm) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = sid[k];
+    sx[k] = pos[i];
+    sy[k] = pos[n + i];
+    sz[k] = pos[2 * n + i];
+    sm[k] = m[i];
+  }
+}
+
 // common-prefix length of sorted keys i and j (positions break ties)
 __device__ __forceinline__ int prefix_len(const uint64_t *__restrict__ k, int n, int i, int j) {
   if (j < 0 || j >= n) return -1;
@@ -282,6 +295,14 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
   if (n > 1) {
     hipLaunchKernelGGL(k_radix_tree, dim3(g1d(n - 1)), dim3(256), 0, s, (int)n, k, c->wnode, c->parent);
   }
+  return tree_moments(c, n);
+}
+
+// Moments, boxes and groups of the current topology (the bottom-up pass).
+hipError_t tree_moments(p3t_ctx *c, int64_t n) {
+  hipStream_t s = c->stream;
+  hipError_t e;
+  const int64_t n_nodes = 2 * n - 1;
   if ((e = fill_i32(c->visit, 0, n > 1 ? n - 1 : 1, s)) != hipSuccess) return e;
   // chunk roots (into group_node / node_scan, both free until the groups are formed)
   hipLaunchKernelGGL(k_chunk_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n, c->wnode, c->parent, c->group_flag);
@@ -300,6 +321,14 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
   hipLaunchKernelGGL(k_group_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
                      c->group_node, c->cnt);
   return hipGetLastError();
+}
+
+// Same topology, same lists: positions and masses replaced, moments redone.
+hipError_t refresh_tree(p3t_ctx *c, const double *pos3, const double *mass) {
+  const int64_t n = c->n;
+  hipLaunchKernelGGL(k_regather_xm, dim3(g1d(n)), dim3(256), 0, c->stream, n, c->sid, pos3, mass, c->sx, c->sy, c->sz,
+                     c->sm);
+  return tree_moments(c, n);
 }
 
 }  // namespace p3t

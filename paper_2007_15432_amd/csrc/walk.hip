@@ -208,4 +208,6 @@ hipError_t walk_groups(p3t_ctx *c, int64_t n_groups_max) {
   return hipGetLastError();
 }
 
+void reset_queues(p3t_ctx *c) { hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(1), 0, c->stream, c->cnt); }
+
 }  // namespace p3t
