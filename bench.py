@@ -43,7 +43,7 @@ PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published, packed)
 METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force error"
 
 
-def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf):
+def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None):
     from paper_2007_15432_amd.driver import P3TStepper
 
     dev = "cuda:0"
@@ -51,11 +51,13 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf):
                                            n_leaf_max=n_leaf)
     ctx = p3t.Context(params)
     ctx.reserve(disk.n, 4 * disk.n)
+    if kcfg:
+        ctx.set_kernel_config(**kcfg)
     pos = torch.tensor(disk.pos, dtype=torch.float64, device=dev)
     vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
     m = torch.tensor(disk.mass, dtype=torch.float64, device=dev)
     # force at the initial state, kept for the error measurement
-    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True)
+    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph)
     acc0 = st.acc.clone()
     r_out0 = st.r_out.clone()
     for _ in range(warmup):
@@ -84,6 +86,9 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf):
                n_near=near // steps, n_far=far // steps, n_cell=cell // steps, n_groups=s["n_groups"],
                n_pairs=s["n_pairs"], n_clusters=st.n_clusters,
                stages_ms={k[3:]: v / steps for k, v in stage.items()})
+    if graph:  # kernels inside the graph are not timed one by one
+        ctx.close()
+        return out
     # roofline of the dominant force kernel, from its own event-timed launches
     ks = kernel_rooflines(out, stage, steps, precision)
     dom = max(ks, key=lambda k: ks[k]["avg_ms"])
@@ -185,6 +190,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph run of the mixed path")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -218,6 +224,13 @@ def main():
         print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
               f"force {r['stages_ms']['force']:.2f} ms, {r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}",
               file=sys.stderr, flush=True)
+    graph = None
+    if not args.no_graph:
+        g = run_path(p3t, torch, disk, 1, args.steps, args.warmup, args.n_group, args.n_leaf, graph=True)
+        graph = {k: g[k] for k in ("value", "ms_per_step", "interactions_per_step")}
+        graph["path"] = "mixed, tree + walk + force replayed from one captured hipGraph per step"
+        print(f"# mixed (graph): {g['value']:.4g} interactions/s, {g['ms_per_step']:.2f} ms/step", file=sys.stderr,
+              flush=True)
     head = "mixed" if "mixed" in results else next(iter(results))
     base, errs = (None, {})
     if not args.no_cpu and "fp64" in results:
@@ -255,6 +268,8 @@ def main():
                                             "kernels")}
             line[name]["force_error"] = errs.get(name)
     line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters")}
+    if graph:
+        line["graph"] = graph
     print(json.dumps(line))
 
 

@@ -174,6 +174,21 @@ p3t_status p3t_hermite_cluster_step(p3t_ctx *ctx, int64_t n, int64_t n_clusters,
 /* Soft kick, eq. (HamiltonSol): vel3 += h * acc3 (3n each). */
 p3t_status p3t_kick(p3t_ctx *ctx, int64_t n, double h, const double *acc3, double *vel3);
 
+/* p3t_build_tree followed by p3t_compute_soft_force in one call.  With
+ * use_graph = 1 the whole device sequence (bounding box, Morton keys, radix
+ * sort, gather, radix tree, moments, groups, walk, longest-first group order,
+ * force kernels, neighbour candidates) is captured once into a hipGraph on a
+ * private stream and replayed on later calls with the same n, pointers,
+ * parameters and launch shapes; the counts that vary between calls (groups,
+ * list lengths) stay on the device.  The call then synchronises once to read
+ * the counters.  If a list, stack or pair buffer overflowed, the buffers grow
+ * (which also retires the graph) and the force is redone eagerly, so the
+ * result is always complete.  Phase times (p3t_get_stats) cover the graph as
+ * a whole (ms_force) when timing is on.  Same arguments, ownership and errors
+ * as the two calls it replaces; with use_graph = 0 it is exactly those. */
+p3t_status p3t_evaluate(p3t_ctx *ctx, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                        const double *r_out, const double *r_search, double *acc3, int32_t use_graph);
+
 /* Soft force over the CURRENT tree topology and interaction lists at new
  * positions pos3 (3n) and masses mass (n), in the caller's order, with the
  * pair cut-offs of the last p3t_build_tree: the sorted positions and masses

@@ -159,14 +159,21 @@ class Context:
         return int(v.value)
 
     # -- the hot path --------------------------------------------------------
-    def compute_cutoffs(self, pos, vel, mass):
+    def compute_cutoffs(self, pos, vel, mass, out=None):
+        """(r_out, r_search, v_ran), each (n,); out = (r_out, r_search, v_ran)
+        tensors to write into (kept buffers keep a captured graph valid)."""
         n = int(mass.shape[0])
         self._vec3(pos, n, "pos")
         self._vec3(vel, n, "vel")
         self._vec(mass, n, "mass")
-        ro = torch.empty(n, dtype=torch.float64, device=self.device)
-        rs = torch.empty_like(ro)
-        vr = torch.empty_like(ro)
+        if out is not None:
+            ro, rs, vr = out
+            for t, name in ((ro, "r_out"), (rs, "r_search"), (vr, "v_ran")):
+                self._vec(t, n, name)
+        else:
+            ro = torch.empty(n, dtype=torch.float64, device=self.device)
+            rs = torch.empty_like(ro)
+            vr = torch.empty_like(ro)
         self._bind()
         self._check(self.L.p3t_compute_cutoffs(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(ro), _ptr(rs),
                                                _ptr(vr)), "compute_cutoffs")
@@ -189,6 +196,22 @@ class Context:
         self._vec3(acc, n, "acc")
         self._bind()
         self._check(self.L.p3t_compute_soft_force(self._h, _ptr(acc)), "compute_soft_force")
+        return acc
+
+    def evaluate(self, pos, vel, mass, r_out, r_search, out=None, graph: bool = True):
+        """build_tree + compute_soft_force; with graph=True the device sequence
+        is captured once into a hipGraph and replayed."""
+        n = int(mass.shape[0])
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        for t, name in ((mass, "mass"), (r_out, "r_out"), (r_search, "r_search")):
+            self._vec(t, n, name)
+        acc = out if out is not None else torch.empty((3, n), dtype=torch.float64, device=self.device)
+        self._vec3(acc, n, "acc")
+        self._bind()
+        self._check(self.L.p3t_evaluate(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(r_out), _ptr(r_search),
+                                        _ptr(acc), 1 if graph else 0), "evaluate")
+        self.n = n
         return acc
 
     def soft_force_frozen(self, pos, mass, out=None):

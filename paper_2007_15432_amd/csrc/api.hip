@@ -246,6 +246,37 @@ void p3t_default_params(p3t_params *P) {
   P->cluster_cap = 1024;
 }
 
+namespace {
+
+void drop_graph(p3t_ctx *c) {
+  if (c->g_exec) hipGraphExecDestroy(c->g_exec);
+  if (c->g_graph) hipGraphDestroy(c->g_graph);
+  c->g_exec = nullptr;
+  c->g_graph = nullptr;
+  c->g_key = 0;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+// Everything a captured evaluation bakes into its kernel arguments.
+uint64_t graph_key(const p3t_ctx *c, int64_t n, const void *const *ptrs, int np) {
+  uint64_t h = mix(0x51ed270b27a1c3ull, (uint64_t)n);
+  for (int k = 0; k < np; ++k) h = mix(h, (uint64_t)(uintptr_t)ptrs[k]);
+  const void *own[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->cands, c->csr_col};
+  for (const void *q : own) h = mix(h, (uint64_t)(uintptr_t)q);
+  const int64_t caps[] = {c->n_cap, c->pool_cap, c->slot_cap_list, c->slot_cap_stack, c->pair_cap, c->cand_cap,
+                          c->walk_slots, c->fcfg.split, c->fcfg.unroll, c->fcfg.waves_per_cu, c->force_persistent};
+  for (int64_t v : caps) h = mix(h, (uint64_t)v);
+  const unsigned char *pb = reinterpret_cast<const unsigned char *>(&c->P);
+  for (size_t k = 0; k < sizeof(p3t_params); ++k) h = mix(h, pb[k]);
+  return h;
+}
+
+}  // namespace
+
 p3t_status p3t_create(const p3t_params *p, void *stream, p3t_ctx **out) {
   if (!p || !out) return P3T_ERR_ARG;
   *out = nullptr;
@@ -280,6 +311,8 @@ p3t_status p3t_create(const p3t_params *p, void *stream, p3t_ctx **out) {
 p3t_status p3t_destroy(p3t_ctx *c) {
   if (!c) return P3T_ERR_ARG;
   hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col, c->cands, c->adj_buf};
   for (void *b : bufs)
     if (b) hipFree(b);
@@ -372,6 +405,40 @@ p3t_status p3t_build_tree(p3t_ctx *c, int64_t n, const double *pos3, const doubl
   return P3T_OK;
 }
 
+// Clears the retry bits and grows whatever overflowed in the last walk/force.
+p3t_status grow_for_retry(p3t_ctx *c, const DevCounters &h) {
+  const unsigned retry = h.status & RETRY_BITS;
+  hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, RETRY_BITS);
+  if (retry & P3T_FLAG_LIST_OVERFLOW) {
+    if ((int64_t)h.pool_cursor > c->pool_cap) {
+      const int64_t cap = (int64_t)h.pool_cursor + (int64_t)h.pool_cursor / 4 + 1024;
+      HIP_OK(c, dev_alloc(c->pool, cap));
+      c->pool_cap = cap;
+    } else {
+      c->slot_cap_list *= 2;
+      HIP_OK(c, dev_alloc(c->slot_lists, (int64_t)c->walk_slots * 3 * c->slot_cap_list));
+    }
+  }
+  if (retry & P3T_FLAG_STACK_OVERFLOW) {
+    c->slot_cap_stack *= 2;
+    HIP_OK(c, dev_alloc(c->slot_stack, (int64_t)c->walk_slots * c->slot_cap_stack));
+  }
+  if (retry & P3T_FLAG_PAIR_OVERFLOW) {
+    if ((int64_t)h.n_pairs > c->pair_cap) {
+      const int64_t cap = (int64_t)h.n_pairs + (int64_t)h.n_pairs / 4 + 1024;
+      HIP_OK(c, dev_alloc(c->pairs, cap));
+      HIP_OK(c, dev_alloc(c->csr_col, cap));
+      c->pair_cap = cap;
+    }
+    if ((int64_t)h.n_cand > c->cand_cap) {
+      const int64_t cap = (int64_t)h.n_cand + (int64_t)h.n_cand / 4 + 1024;
+      HIP_OK(c, dev_alloc(c->cands, cap));
+      c->cand_cap = cap;
+    }
+  }
+  return P3T_OK;
+}
+
 p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
   if (!c) return P3T_ERR_ARG;
   if (!c->tree_valid) return fail(c, P3T_ERR_STATE, "compute_soft_force: no tree (call p3t_build_tree)");
@@ -393,34 +460,7 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
     if ((st = sync_counters(c, &h)) != P3T_OK) return st;
     const unsigned retry = h.status & RETRY_BITS;
     if (retry) {
-      hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, RETRY_BITS);
-      if (retry & P3T_FLAG_LIST_OVERFLOW) {
-        if ((int64_t)h.pool_cursor > c->pool_cap) {
-          const int64_t cap = (int64_t)h.pool_cursor + (int64_t)h.pool_cursor / 4 + 1024;
-          HIP_OK(c, dev_alloc(c->pool, cap));
-          c->pool_cap = cap;
-        } else {
-          c->slot_cap_list *= 2;
-          HIP_OK(c, dev_alloc(c->slot_lists, (int64_t)c->walk_slots * 3 * c->slot_cap_list));
-        }
-      }
-      if (retry & P3T_FLAG_STACK_OVERFLOW) {
-        c->slot_cap_stack *= 2;
-        HIP_OK(c, dev_alloc(c->slot_stack, (int64_t)c->walk_slots * c->slot_cap_stack));
-      }
-      if (retry & P3T_FLAG_PAIR_OVERFLOW) {
-        if ((int64_t)h.n_pairs > c->pair_cap) {
-          const int64_t cap = (int64_t)h.n_pairs + (int64_t)h.n_pairs / 4 + 1024;
-          HIP_OK(c, dev_alloc(c->pairs, cap));
-          HIP_OK(c, dev_alloc(c->csr_col, cap));
-          c->pair_cap = cap;
-        }
-        if ((int64_t)h.n_cand > c->cand_cap) {
-          const int64_t cap = (int64_t)h.n_cand + (int64_t)h.n_cand / 4 + 1024;
-          HIP_OK(c, dev_alloc(c->cands, cap));
-          c->cand_cap = cap;
-        }
-      }
+      if ((st = grow_for_retry(c, h)) != P3T_OK) return st;
       continue;
     }
     c->n_pairs = (int64_t)h.n_pairs;
@@ -450,6 +490,87 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
     return P3T_OK;
   }
   return fail(c, P3T_ERR_CAPACITY, "compute_soft_force: scratch still too small after repeated growth");
+}
+
+p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                        const double *r_out, const double *r_search, double *acc3, int32_t use_graph) {
+  if (!c) return P3T_ERR_ARG;
+  if (!use_graph || n == 0) {
+    p3t_status st = p3t_build_tree(c, n, pos3, vel3, mass, r_out, r_search);
+    if (st != P3T_OK) return st;
+    return p3t_compute_soft_force(c, acc3);
+  }
+  if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "evaluate: n out of range");
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(r_search, n) ||
+      bad_ptr(acc3, n))
+    return fail(c, P3T_ERR_ARG, "evaluate: null pointer");
+  c->tree_valid = c->force_valid = false;
+  c->n = n;
+  p3t_status st = ensure_n(c, n);
+  if (st != P3T_OK) return st;
+  if ((st = ensure_lists(c, n)) != P3T_OK) return st;
+  const void *ptrs[] = {pos3, vel3, mass, r_out, r_search, acc3};
+  const uint64_t key = graph_key(c, n, ptrs, 6);
+  if (!c->g_exec || key != c->g_key) {
+    drop_graph(c);
+    if (!c->cap_stream) HIP_OK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    const hipStream_t user = c->stream;
+    const int timing = c->timing;
+    c->stream = c->cap_stream;
+    c->timing = 0;  // no event records inside the graph
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      // n bounds the group count; every group-sized loop reads the count on the device
+      hipError_t e1 = build_tree(c, n, pos3, vel3, mass, r_out, r_search);
+      if (e1 == hipSuccess) e1 = walk_groups(c, n);
+      if (e1 == hipSuccess) e1 = soft_force(c, n, acc3);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(c->cap_stream, &g);
+      if (e == hipSuccess) e = e1;
+      c->g_graph = g;
+      if (e == hipSuccess) e = hipGraphInstantiate(&c->g_exec, c->g_graph, nullptr, nullptr, 0);
+    }
+    c->stream = user;
+    c->timing = timing;
+    if (e != hipSuccess) {
+      drop_graph(c);
+      return fail(c, P3T_ERR_HIP, "evaluate: graph capture failed: %s", hipGetErrorString(e));
+    }
+    c->g_key = key;
+  }
+  ev_record(c, 2);
+  HIP_OK(c, hipGraphLaunch(c->g_exec, c->stream));
+  ev_record(c, 6);
+  DevCounters h;
+  if ((st = sync_counters(c, &h)) != P3T_OK) return st;
+  c->n_groups = (int64_t)h.n_groups;
+  c->tree_valid = true;
+  c->stats.n = n;
+  c->stats.n_nodes = 2 * n - 1;
+  c->stats.n_groups = c->n_groups;
+  if (h.status & RETRY_BITS) {
+    // a buffer overflowed: grow it (the key changes with it) and finish eagerly
+    if ((st = grow_for_retry(c, h)) != P3T_OK) return st;
+    return p3t_compute_soft_force(c, acc3);
+  }
+  c->n_pairs = (int64_t)h.n_pairs;
+  c->stats.n_near = (int64_t)h.n_near;
+  c->stats.n_far = (int64_t)h.n_far;
+  c->stats.n_cell = (int64_t)h.n_cell;
+  c->stats.n_pairs = c->n_pairs;
+  c->stats.list_entries = (int64_t)h.pool_cursor;
+  if (c->timing) {
+    c->stats.ms_tree = c->stats.ms_walk = 0.0;
+    c->stats.ms_force = ev_ms(c, 2, 6);  // the whole captured evaluation
+    c->stats.ms_near = c->stats.ms_far = c->stats.ms_cell = c->stats.ms_cand = 0.0;
+  }
+  const unsigned num = h.status & NUMERIC_BITS;
+  c->host_status |= h.status;
+  if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
+  c->force_valid = true;
+  if (num) return fail(c, P3T_ERR_NUMERIC, "evaluate: device status 0x%x (coincident particles or NaN)", num);
+  return P3T_OK;
 }
 
 p3t_status p3t_neighbour_list(p3t_ctx *c, int64_t *row_ptr, int32_t *col, int64_t cap, int64_t *nnz_host,

@@ -221,6 +221,11 @@ struct p3t_ctx {
   double *cut_part = nullptr;       // cut-off bin partial sums
   double *tmp_d = nullptr;          // per-particle FP64 scratch (3n)
   double *acc_s = nullptr;          // soft acceleration in sorted order (3n)
+  // captured evaluation graph (p3t_evaluate with use_graph = 1)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t g_graph = nullptr;
+  hipGraphExec_t g_exec = nullptr;
+  uint64_t g_key = 0;
   double *adj_buf = nullptr;        // soft-kick adjoint scratch (adjoint_buf_need(adj_cap))
   int64_t adj_cap = 0;
 };

@@ -201,8 +201,10 @@ hipError_t walk_groups(p3t_ctx *c, int64_t n_groups_max) {
                      c->group_order);
   uint64_t *k = c->gkey, *ka = c->gkey_alt;
   int32_t *v = c->group_order, *va = c->gorder_alt;
-  hipError_t e = radix_sort_pairs(k, v, ka, va, n_groups_max, nullptr, 32, 64, c->radix_hist, c->radix_hist_cap,
-                                  c->scan_tmp, c->scan_tmp_cap, s);
+  // the device-side group count bounds the sort, so n_groups_max may be any
+  // upper bound (a captured graph passes the particle count)
+  hipError_t e = radix_sort_pairs(k, v, ka, va, n_groups_max, &c->cnt->n_groups, 32, 64, c->radix_hist,
+                                  c->radix_hist_cap, c->scan_tmp, c->scan_tmp_cap, s);
   if (e != hipSuccess) return e;
   // 4 passes: the sorted order is back in group_order
   return hipGetLastError();

@@ -21,8 +21,13 @@ from .api import Context, Params
 
 
 class P3TStepper:
-    def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False):
+    """graph=True evaluates tree + force through p3t_evaluate's captured
+    hipGraph (replayed every step: positions, masses, radii and the
+    acceleration live in fixed buffers)."""
+
+    def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False, graph: bool = False):
         self.ctx = ctx
+        self.graph = graph
         self.pos, self.vel, self.mass = pos, vel, mass
         self.n = int(mass.shape[0])
         self.dt = ctx.params.dt_soft
@@ -35,8 +40,11 @@ class P3TStepper:
 
     def _evaluate(self):
         c = self.ctx
-        c.build_tree(self.pos, self.vel, self.mass, self.r_out, self.r_search)
-        c.compute_soft_force(out=self.acc)
+        if self.graph:
+            c.evaluate(self.pos, self.vel, self.mass, self.r_out, self.r_search, out=self.acc, graph=True)
+        else:
+            c.build_tree(self.pos, self.vel, self.mass, self.r_out, self.r_search)
+            c.compute_soft_force(out=self.acc)
         self.row_ptr, self.col, self.label = c.neighbour_list(labels=True)
         self.last = c.stats()
 
@@ -48,7 +56,7 @@ class P3TStepper:
         c.hermite_cluster_step(self.pos, self.vel, self.mass, self.r_out, cl_ptr, members, dt_hard=self.dt_hard,
                                energy=False)
         if self.recompute:
-            self.r_out, self.r_search, self.v_ran = c.compute_cutoffs(self.pos, self.vel, self.mass)
+            c.compute_cutoffs(self.pos, self.vel, self.mass, out=(self.r_out, self.r_search, self.v_ran))
         self._evaluate()
         c.kick(self.acc, self.vel, 0.5 * self.dt)
 

@@ -259,3 +259,28 @@ def test_hermite_matches_oracle(gpu, orc):
         assert dxc.max() < 1e-5
         # energy errors of eq. (hard) per cluster agree
         assert np.all(np.abs(eg - eo) <= np.maximum(0.05 * eo, 1e-13))
+
+
+def test_graph_replays_match_eager(gpu, orc, ring):
+    """The captured evaluation, replayed on moving positions with eager work
+    and synchronisations in between, equals the eager path every time:
+    forces to the bit, neighbour lists and labels exactly."""
+    g = ring.g
+    p = gparams(gpu, ring.p, theta=0.5, multipole=2, precision=1)
+    ce, cg = gpu.Context(p), gpu.Context(p)
+    pos = g["pos"].clone()
+    acc_g = torch.empty_like(pos)
+    for rep in range(4):
+        pos.add_(g["vel"], alpha=1e-4 * rep)  # the same buffer moves
+        junk = (pos * pos).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        ce.build_tree(pos, g["vel"], g["m"], g["ro"], g["rs"])
+        acc_e = ce.compute_soft_force()
+        rp_e, col_e, lab_e = ce.neighbour_list()
+        cg.evaluate(pos, g["vel"], g["m"], g["ro"], g["rs"], out=acc_g, graph=True)
+        rp_g, col_g, lab_g = cg.neighbour_list()
+        torch.cuda.synchronize()
+        assert torch.equal(acc_e, acc_g), rep
+        assert torch.equal(rp_e, rp_g) and torch.equal(col_e, col_g) and torch.equal(lab_e, lab_g), rep
+        assert cg.stats()["n_groups"] == ce.stats()["n_groups"]
+        del junk
