@@ -94,7 +94,7 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     dom = max(ks, key=lambda k: ks[k]["avg_ms"])
     r = dict(ks[dom])
     r["kernel"] = dom
-    r["traffic"] = measured_traffic(dom, precision)
+    r["traffic"] = measured_traffic(dom, precision, kcfg)
     out["roofline"] = r
     out["kernels"] = ks
     out["_acc0"] = acc0.cpu().numpy()
@@ -137,10 +137,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, precision):
+def measured_traffic(kernel, precision, kcfg=None):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, or None if the kernel sources changed since
-    the counters were taken."""
+    WRITE_SIZE counter summary, or None if the kernel sources or the launch
+    shape differ from those the counters were taken with."""
     path = os.path.join(ROOT, "profiles", "traffic_force_disk1m.json")
     try:
         with open(path) as fh:
@@ -149,8 +149,39 @@ def measured_traffic(kernel, precision):
         return None
     if t.get("source_digest") != source_digest():
         return None
+    shape = t.get("shape", {})
+    for k, v in shape.items():
+        if (kcfg or {}).get(k, v) != v:
+            return None
     rec = t.get("kernels", {}).get(f"{kernel}:{'mixed' if precision == 1 else 'fp64'}")
     return None if rec is None else rec.get("bytes_per_launch")
+
+
+def autotune(p3t, torch, disk, n_group, n_leaf):
+    """The project's tuner on this workload (mixed precision, theta 0.5
+    quadrupole).  Group and leaf sizes change the lists, hence the number of
+    interactions and the truncation error, so the measured configuration
+    keeps the stated ones (groups <= n_group, leaves <= n_leaf) and the tuner
+    picks the launch shapes, which change neither.  Its list stage is run
+    over other group / leaf sizes only as a reported sweep."""
+    from paper_2007_15432_amd.autotune import GROUPS, LEAVES, tune
+
+    dev = "cuda:0"
+    params = p3t.Params.defaults().replace(theta=0.5, multipole=2, precision=1)
+    ctx = p3t.Context(params)
+    ctx.reserve(disk.n, 4 * disk.n)
+    pos = torch.tensor(disk.pos, dtype=torch.float64, device=dev)
+    vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
+    m = torch.tensor(disk.mass, dtype=torch.float64, device=dev)
+    ro, rs, _ = ctx.compute_cutoffs(pos, vel, m)
+    sweep = tune(ctx, pos, vel, m, ro, rs, reps=2, group_cap=n_group, groups=GROUPS, leaves=LEAVES, shapes=[],
+                 walk_waves=())
+    ctx.set_params(params)
+    res = tune(ctx, pos, vel, m, ro, rs, reps=3, groups=(n_group,), leaves=(n_leaf,))
+    res.sweep = [dict(n_group_max=t.params["n_group_max"], n_leaf_max=t.params["n_leaf_max"], ms=t.ms,
+                      interactions=t.interactions) for t in sweep.trials]
+    ctx.close()
+    return res
 
 
 def cpu_baseline(disk, results, sample, seed=33):
@@ -191,6 +222,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--paths", default="mixed,fp64")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph run of the mixed path")
+    ap.add_argument("--no-autotune", action="store_true", help="use --n-group / --n-leaf and the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the FETCH/WRITE counters)")
     args = ap.parse_args()
@@ -216,17 +248,24 @@ def main():
     p3t.load()
     disk = diskgen.workload("disk1m_masslaw", args.n)
     print(f"# workload disk1m_masslaw N={disk.n}", file=sys.stderr, flush=True)
+    tuned, kcfg, n_group, n_leaf = None, None, args.n_group, args.n_leaf
+    if not args.no_autotune:
+        tuned = autotune(p3t, torch, disk, args.n_group, args.n_leaf)
+        n_group, n_leaf = tuned.params["n_group_max"], tuned.params["n_leaf_max"]
+        kcfg = tuned.kernel
+        print(f"# autotuned in {tuned.seconds:.1f} s: {tuned.params} {tuned.kernel} ({tuned.ms:.2f} ms per "
+              "tree+walk+force)", file=sys.stderr, flush=True)
     results = {}
     for name in args.paths.split(","):
         prec = 1 if name == "mixed" else 0
-        results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, args.n_group, args.n_leaf)
+        results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, n_group, n_leaf, kcfg=kcfg)
         r = results[name]
         print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
               f"force {r['stages_ms']['force']:.2f} ms, {r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}",
               file=sys.stderr, flush=True)
     graph = None
     if not args.no_graph:
-        g = run_path(p3t, torch, disk, 1, args.steps, args.warmup, args.n_group, args.n_leaf, graph=True)
+        g = run_path(p3t, torch, disk, 1, args.steps, args.warmup, n_group, n_leaf, graph=True, kcfg=kcfg)
         graph = {k: g[k] for k in ("value", "ms_per_step", "interactions_per_step")}
         graph["path"] = "mixed, tree + walk + force replayed from one captured hipGraph per step"
         print(f"# mixed (graph): {g['value']:.4g} interactions/s, {g['ms_per_step']:.2f} ms/step", file=sys.stderr,
@@ -252,7 +291,8 @@ def main():
         "config": {
             "workload": f"disk1m_masslaw: N={disk.n} planetesimals, a in [0.5, 5] au, sigma ~ a^-3/2, "
                         "dN/dm ~ m^-2.5 on [1e-10, 1e-8], rms e = 2 rms i = 2 h(1e-9); theta=0.5 quadrupole; "
-                        f"groups <= {args.n_group}, leaves <= {args.n_leaf}; one P3T soft step per step",
+                        f"groups <= {n_group}, leaves <= {n_leaf}; launch shapes autotuned; one P3T soft step "
+                        "per step",
             "path": head,
         },
         "roofline": {k: v for k, v in h["roofline"].items()},
@@ -270,6 +310,9 @@ def main():
     line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters")}
     if graph:
         line["graph"] = graph
+    if tuned:
+        line["autotune"] = {"params": tuned.params, "kernel": tuned.kernel, "ms_eval": tuned.ms,
+                            "seconds": tuned.seconds, "trials": len(tuned.trials), "list_sweep": tuned.sweep}
     print(json.dumps(line))
 
 

@@ -284,3 +284,24 @@ def test_graph_replays_match_eager(gpu, orc, ring):
         assert torch.equal(rp_e, rp_g) and torch.equal(col_e, col_g) and torch.equal(lab_e, lab_g), rep
         assert cg.stats()["n_groups"] == ce.stats()["n_groups"]
         del junk
+
+
+def test_autotuned_context_matches_oracle(gpu, orc, ring):
+    """The tuner leaves the context in a valid configuration: neighbour
+    lists stay bit-exact and forces within the tree tolerance."""
+    from paper_2007_15432_amd.autotune import tune
+
+    g = ring.g
+    ctx = gpu.Context(gparams(gpu, ring.p, theta=0.5, multipole=2, precision=1))
+    res = tune(ctx, g["pos"], g["vel"], g["m"], g["ro"], g["rs"], reps=1, groups=(64, 128), leaves=(8, 16),
+               shapes=[dict(force_split=1, force_unroll=2, waves_per_cu=16), dict(force_split=0, force_unroll=4)],
+               walk_waves=(2, 4))
+    print("tuned", res.params, res.kernel, f"{res.ms:.3f} ms over {len(res.trials)} trials")
+    assert len(res.trials) == 4 + 2 + 2
+    ctx.build_tree(g["pos"], g["vel"], g["m"], g["ro"], g["rs"])
+    acc = ctx.compute_soft_force().cpu().numpy()
+    rp, col, _ = ctx.neighbour_list(labels=False)
+    rp_o, col_o = ring.nbr(orc)
+    assert np.array_equal(rp.cpu().numpy(), rp_o) and np.array_equal(col.cpu().numpy(), col_o)
+    e = errs(acc, ring.acc(orc))
+    assert e[0] < 2e-3 and e[1] < 1e-3
