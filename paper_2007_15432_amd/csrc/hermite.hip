@@ -40,7 +40,7 @@ struct HermArgs {
   int64_t n;
   double G, GM, gamma, inv1mg, eta, eta0, dt_soft, tick;
   // powers of dt_soft for the corrector (scaled per level by exact powers of two)
-  double inv_dt2, inv_dt3, dt3_6, dt4_24, dt5_120;
+  double inv_dt2, inv_dt3, dt3_6, dt4_24, dt5_120, dt_soft2;
   int k_max, max_iter;
   double wc, wf1, wlog;
   double wp[8];  // f(y) = sum_k wp[k] y^k + wlog y ln y   (eq. (cutfuncW))
@@ -107,6 +107,23 @@ __device__ __forceinline__ int level_for(double dt_soft, double dtc, int kmax) {
 }
 
 __device__ __forceinline__ double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+__device__ __forceinline__ double dot3(const double *a, const double *b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Smallest k >= 0 with P 4^-k <= L (k_max + 1 if none), P = dt_soft^2 den,
+// L = eta num >= 0: the level whose squared step does not exceed the
+// squared Aarseth step.  P = 0 (den = 0) gives level 0, as a step of dt_soft.
+// Started one below the exponent estimate; every comparison is exact.
+__device__ __forceinline__ int level_for_sq(double P, double L, int kmax) {
+  if (!(P > L)) return 0;
+  if (!(L > 0.0)) return kmax + 1;
+  const int e = ilogb(P) - ilogb(L);
+  int k = (e - 1) >> 1;
+  k = k < 0 ? 0 : k;
+  while (k <= kmax && ldexp(P, -2 * k) > L) ++k;
+  return k;
+}
 
 // corrector + new level for one active member; its step is h = dt_soft 2^-lev
 // (h, 1/h^2, 1/h^3, h^3/6, ... are the level-0 powers scaled by exact
@@ -128,11 +145,15 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
     a0[d] = a1[d];
     j0[d] = j1[d];
   }
+  // Aarseth: dt^2 = eta (|a||a2| + |j|^2) / (|j||a3| + |a2|^2), a2 at the
+  // step's end.  The level is the smallest k with (dt_soft 2^-k)^2 <= dt^2,
+  // found without the division and the outer root: dt_soft^2 den 4^-k <=
+  // eta num, with |a||a2| = sqrt(|a|^2 |a2|^2) (two roots instead of four).
   const double a2e[3] = {a2[0] + a3[0] * h, a2[1] + a3[1] * h, a2[2] + a3[2] * h};
-  const double an = norm3(a1), jn = norm3(j1), a2n = norm3(a2e), a3n = norm3(a3);
-  const double den = jn * a3n + a2n * a2n;
-  const double dtc = den > 0.0 ? sqrt(A.eta * (an * a2n + jn * jn) / den) : A.dt_soft;
-  const int knew = level_for(A.dt_soft, dtc, A.k_max);
+  const double an2 = dot3(a1, a1), jn2 = dot3(j1, j1), a2n2 = dot3(a2e, a2e), a3n2 = dot3(a3, a3);
+  const double num = A.eta * (sqrt(an2 * a2n2) + jn2);
+  const double den = sqrt(jn2 * a3n2) + a2n2;
+  const int knew = level_for_sq(A.dt_soft2 * den, num, A.k_max);
   int k = lev;
   if (knew < k) {
     // grow by at most a factor two, and only on a multiple of the doubled step
@@ -173,23 +194,21 @@ __device__ __forceinline__ int64_t dpp_i64(int64_t v) {
 }
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
 
-// minimum over aligned segments of SEG lanes; every lane of the wave must be
-// active
-template <int SEG>
-__device__ __forceinline__ int64_t seg_min(int64_t v) {
+// minimum over aligned segments of 2^sl2 lanes (sl2 wave-uniform); every
+// lane of the wave must be active
+__device__ __forceinline__ int64_t seg_min(int64_t v, int sl2) {
   int64_t t;
-  if (SEG >= 2) { t = dpp_i64<DPP_XOR1>(v); v = t < v ? t : v; }
-  if (SEG >= 4) { t = dpp_i64<DPP_XOR2>(v); v = t < v ? t : v; }
-  if (SEG >= 8) { t = dpp_i64<DPP_HALF_MIRROR>(v); v = t < v ? t : v; }
-  if (SEG >= 16) { t = dpp_i64<DPP_MIRROR>(v); v = t < v ? t : v; }
-  if (SEG >= 32) { t = __shfl_xor(v, 16, WAVE); v = t < v ? t : v; }
-  if (SEG >= 64) { t = __shfl_xor(v, 32, WAVE); v = t < v ? t : v; }
+  if (sl2 >= 1) { t = dpp_i64<DPP_XOR1>(v); v = t < v ? t : v; }
+  if (sl2 >= 2) { t = dpp_i64<DPP_XOR2>(v); v = t < v ? t : v; }
+  if (sl2 >= 3) { t = dpp_i64<DPP_HALF_MIRROR>(v); v = t < v ? t : v; }
+  if (sl2 >= 4) { t = dpp_i64<DPP_MIRROR>(v); v = t < v ? t : v; }
+  if (sl2 >= 5) { t = __shfl_xor(v, 16, WAVE); v = t < v ? t : v; }
+  if (sl2 >= 6) { t = __shfl_xor(v, 32, WAVE); v = t < v ? t : v; }
   return v;
 }
-template <int SEG>
-__device__ __forceinline__ double seg_sum(double v) {
-#pragma unroll
-  for (int o = SEG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SEG);
+// sum over aligned segments of 2^sl2 lanes
+__device__ __forceinline__ double seg_sum(double v, int sl2) {
+  for (int o = 1; o < (1 << sl2); o <<= 1) v += __shfl_xor(v, o, WAVE);
   return v;
 }
 
@@ -209,17 +228,52 @@ struct Lds {
 // ---------------------------------------------------------------- small clusters
 // One wavefront (lanes [wbase, wbase + 64) of the LDS arrays) runs 64/SEG
 // clusters; cluster index ci of bucket bk.
-template <int SEG>
-__device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int ci0, const Lds &L, int wbase) {
-  const int lane = threadIdx.x & (WAVE - 1), seg = lane / SEG, sl = lane % SEG, sb = wbase + seg * SEG;
-  const int ci = ci0 + seg;
+// Lanes of a size bucket bk <= 6: SEG = 2^bk member slots per cluster and
+// LPM = 2^ll2 lanes per member that share the member's pair loop, so a
+// cluster spans 2^(bk + ll2) lanes.  Small clusters (bk <= 1) keep one lane
+// per member and pack many clusters per wavefront; from four members on,
+// the pair loop, which grows with the cluster, is split over up to eight
+// lanes per member (clusters then fill a whole wavefront or a quarter).
+__host__ __device__ constexpr int lanes_per_member_log2(int bk) {
+  return bk < 2 ? 0 : (bk < 6 - bk ? bk : 6 - bk);
+}
+
+// DPP exchange of a double with a fixed lane permutation
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int64_t t = dpp_i64<CTRL>(__double_as_longlong(v));
+  return __longlong_as_double(t);
+}
+// sum over aligned groups of 2^ll2 <= 8 lanes (all lanes active)
+__device__ __forceinline__ double lpm_sum(double v, int ll2) {
+  if (ll2 >= 1) v += dpp_f64<DPP_XOR1>(v);
+  if (ll2 >= 2) v += dpp_f64<DPP_XOR2>(v);
+  if (ll2 >= 3) v += dpp_f64<DPP_HALF_MIRROR>(v);
+  return v;
+}
+
+// One wavefront (lanes [wbase, wbase + 64) of the LDS arrays) runs the
+// clusters ci0, ci0 + 1, ... of bucket bk; one body serves every bucket (a
+// template per bucket would multiply the kernel's code, and all buckets run
+// side by side in the fused launch, sharing the instruction cache).  The
+// LPM lanes of a member hold identical copies of its state; each evaluates
+// every LPM-th partner and the partial sums are added across them.
+__device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int ci0, const Lds &L,
+                                         int wbase, int sl2) {
+  const int ll2 = lanes_per_member_log2(sl2), cl2 = sl2 + ll2;
+  const int SEG = 1 << sl2, LPM = 1 << ll2;
+  const int lane = threadIdx.x & (WAVE - 1), cseg = lane >> cl2, lic = lane & ((1 << cl2) - 1);
+  const int sl = lic >> ll2, sub = lic & (LPM - 1);
+  const int sb = wbase + cseg * SEG;  // LDS slot of the cluster's first member
+  const int ci = ci0 + cseg;
   const int c = ci < count ? blist[ci] : -1;
   const int b = c >= 0 ? A.cl_ptr[c] : 0;
   const int size = c >= 0 ? A.cl_ptr[c + 1] - b : 0;
   const bool mem = sl < size;
+  const bool lead = mem && sub == 0;  // the copy that reads and writes memory
   const int gid = mem ? A.members[b + sl] : 0;
   const int64_t n = A.n;
-  const int me = wbase + lane;
+  const int me = sb + sl;
   double x[3] = {1.0, 0.0, 0.0}, v[3] = {0.0, 1.0, 0.0}, a0[3], j0[3];
   double m = 0.0, ro = 1.0;
   if (mem) {
@@ -234,35 +288,43 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   }
   const double invi = 1.0 / ro;
   wave_sync();
-  L.pgm[me] = A.G * m;
-  L.pinv[me] = invi;
-  L.px[me] = x[0];
-  L.py[me] = x[1];
-  L.pz[me] = x[2];
-  L.pvx[me] = v[0];
-  L.pvy[me] = v[1];
-  L.pvz[me] = v[2];
+  if (lead) {
+    L.pgm[me] = A.G * m;
+    L.pinv[me] = invi;
+    L.px[me] = x[0];
+    L.py[me] = x[1];
+    L.pz[me] = x[2];
+    L.pvx[me] = v[0];
+    L.pvy[me] = v[1];
+    L.pvz[me] = v[2];
+  }
   wave_sync();
   // forces at t = 0 and the initial energy
-  star_term(x, v, A.GM, a0, j0);
-  double e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
-                       A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
-                 : 0.0;
+  double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0};
+  double e = lead ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
+                        A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
+                  : 0.0;
   if (mem) {
-    for (int jj = 0; jj < size; ++jj) {
+    for (int jj = sub; jj < size; jj += LPM) {
       if (jj == sl) continue;
       const int q = sb + jj;
       const double dx = L.px[q] - x[0], dy = L.py[q] - x[1], dz = L.pz[q] - x[2];
       const double invR = fmin(invi, L.pinv[q]);
-      hard_pair(dx, dy, dz, L.pvx[q] - v[0], L.pvy[q] - v[1], L.pvz[q] - v[2], L.pgm[q], invR, A, a0, j0);
+      hard_pair(dx, dy, dz, L.pvx[q] - v[0], L.pvy[q] - v[1], L.pvz[q] - v[2], L.pgm[q], invR, A, pa, pj);
       if (jj > sl) {
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         e -= m * L.pgm[q] * (1.0 - changeover_W(r * invR, A)) / r;
       }
     }
   }
-  const double E0 = seg_sum<SEG>(e);
-  int lev = initial_level(a0, j0, mem, gid, A);
+  star_term(x, v, A.GM, a0, j0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a0[d] += lpm_sum(pa[d], ll2);
+    j0[d] += lpm_sum(pj[d], ll2);
+  }
+  const double E0 = seg_sum(e, cl2);
+  int lev = initial_level(a0, j0, mem, gid, A);  // every copy reads the carried step
   const int64_t T = (int64_t)1 << TICK_BITS;
   int64_t t = 0;
   int nst = 0;  // block steps of this lane's cluster
@@ -271,7 +333,7 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     // every step divides T and each member's time is a multiple of its
     // step, so a cluster is finished exactly when its earliest next time
     // lies beyond T
-    const int64_t tn = seg_min<SEG>(te);
+    const int64_t tn = seg_min(te, cl2);
     const bool done = (size == 0) || (tn > T);
     if (__all(done)) break;
     if (it >= A.max_iter) {
@@ -297,21 +359,39 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
       }
     }
     wave_sync();
-    L.px[me] = xp[0];
-    L.py[me] = xp[1];
-    L.pz[me] = xp[2];
-    L.pvx[me] = vp[0];
-    L.pvy[me] = vp[1];
-    L.pvz[me] = vp[2];
+    if (lead) {
+      L.px[me] = xp[0];
+      L.py[me] = xp[1];
+      L.pz[me] = xp[2];
+      L.pvx[me] = vp[0];
+      L.pvy[me] = vp[1];
+      L.pvz[me] = vp[2];
+    }
     wave_sync();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) pa[d] = pj[d] = 0.0;
     if (active) {
-      double a1[3], j1[3];
-      star_term(xp, vp, A.GM, a1, j1);
-      for (int jj = 0; jj < size; ++jj) {
+      for (int jj = sub; jj < size; jj += LPM) {
         if (jj == sl) continue;
         const int q = sb + jj;
         hard_pair(L.px[q] - xp[0], L.py[q] - xp[1], L.pz[q] - xp[2], L.pvx[q] - vp[0], L.pvy[q] - vp[1],
-                  L.pvz[q] - vp[2], L.pgm[q], fmin(invi, L.pinv[q]), A, a1, j1);
+                  L.pvz[q] - vp[2], L.pgm[q], fmin(invi, L.pinv[q]), A, pa, pj);
+      }
+    }
+    if (ll2 > 0) {  // partial sums of the member's copies (all lanes take part)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        pa[d] = lpm_sum(pa[d], ll2);
+        pj[d] = lpm_sum(pj[d], ll2);
+      }
+    }
+    if (active) {
+      double a1[3], j1[3];
+      star_term(xp, vp, A.GM, a1, j1);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a1[d] += pa[d];
+        j1[d] += pj[d];
       }
       const double h = (double)(tn - t) * A.tick;
       t = tn;
@@ -320,26 +400,28 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   }
   // final energy
   wave_sync();
-  L.px[me] = x[0];
-  L.py[me] = x[1];
-  L.pz[me] = x[2];
-  L.pvx[me] = v[0];
-  L.pvy[me] = v[1];
-  L.pvz[me] = v[2];
+  if (lead) {
+    L.px[me] = x[0];
+    L.py[me] = x[1];
+    L.pz[me] = x[2];
+    L.pvx[me] = v[0];
+    L.pvy[me] = v[1];
+    L.pvz[me] = v[2];
+  }
   wave_sync();
-  e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
-                A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
-          : 0.0;
+  e = lead ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
+                 A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
+           : 0.0;
   if (mem) {
-    for (int jj = sl + 1; jj < size; ++jj) {
+    for (int jj = sl + 1 + sub; jj < size; jj += LPM) {
       const int q = sb + jj;
       const double dx = L.px[q] - x[0], dy = L.py[q] - x[1], dz = L.pz[q] - x[2];
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       e -= m * L.pgm[q] * (1.0 - changeover_W(r * fmin(invi, L.pinv[q]), A)) / r;
     }
   }
-  const double E1 = seg_sum<SEG>(e);
-  if (mem) {
+  const double E1 = seg_sum(e, cl2);
+  if (lead) {
     A.pos[gid] = x[0];
     A.pos[n + gid] = x[1];
     A.pos[2 * n + gid] = x[2];
@@ -349,8 +431,8 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     if (A.dt_hard) A.dt_hard[gid] = ldexp(A.dt_soft, -lev);
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) set_flag(A.cnt, P3T_FLAG_NAN);
   }
-  if (sl == 0 && c >= 0 && A.e_rel) A.e_rel[c] = fabs(E1 - E0) / fabs(E0);
-  if (sl == 0 && c >= 0 && A.nsteps) A.nsteps[c] = nst;
+  if (lic == 0 && c >= 0 && A.e_rel) A.e_rel[c] = fabs(E1 - E0) / fabs(E0);
+  if (lic == 0 && c >= 0 && A.nsteps) A.nsteps[c] = nst;
 }
 
 // ---------------------------------------------------------------- big clusters
@@ -560,17 +642,13 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   }
   const int w = threadIdx.x / WAVE;
   const int wbase = w * WAVE;
-  const int per_wave = WAVE >> bk;  // clusters per wavefront
+  const int per_wave = WAVE >> (bk + lanes_per_member_log2(bk));  // clusters per wavefront
   const int ci0 = (local * (BIG_T / WAVE) + w) * per_wave;
-  switch (bk) {
-    case 0: seg_body<1>(A, blist, A.bcount[0], ci0, L, wbase); break;
-    case 1: seg_body<2>(A, blist, A.bcount[1], ci0, L, wbase); break;
-    case 2: seg_body<4>(A, blist, A.bcount[2], ci0, L, wbase); break;
-    case 3: seg_body<8>(A, blist, A.bcount[3], ci0, L, wbase); break;
-    case 4: seg_body<16>(A, blist, A.bcount[4], ci0, L, wbase); break;
-    case 5: seg_body<32>(A, blist, A.bcount[5], ci0, L, wbase); break;
-    default: seg_body<64>(A, blist, A.bcount[6], ci0, L, wbase); break;
-  }
+  int count = 0;
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+    if (q == bk) count = A.bcount[q];  // constant indices only (see above)
+  seg_body(A, blist, count, ci0, L, wbase, bk);
 }
 
 template <int MPT>
@@ -600,35 +678,73 @@ __device__ __forceinline__ int bucket_of(int size) {
 // Bucket the clusters by size with one atomic per bucket per wavefront; also
 // validate the caller's cluster arrays (offsets non-decreasing from >= 0,
 // members in [0, n)); a violation sets bcount[15] and nothing is integrated.
+// Bucket lists.  Each workgroup owns a contiguous range of clusters: it
+// counts its clusters per bucket in LDS, reserves its share of every bucket
+// with one global atomic per bucket, then writes the entries in cluster
+// order.  (One atomic per wavefront and bucket contended on the same eleven
+// counters across the whole grid.)
+__device__ __forceinline__ int cluster_bucket(int64_t c, int64_t n, const int32_t *__restrict__ cl_ptr,
+                                              const int32_t *__restrict__ members, int32_t *__restrict__ bcount) {
+  const int a = cl_ptr[c], b = cl_ptr[c + 1];
+  bool ok = a >= 0 && b >= a;
+  for (int k = a; ok && k < b; ++k) {
+    const int g = members[k];
+    ok = g >= 0 && (int64_t)g < n;
+  }
+  if (!ok) {
+    atomicOr(&bcount[15], 1);
+    return -1;
+  }
+  return b > a ? bucket_of(b - a) : -1;
+}
+
 __global__ __launch_bounds__(256) void k_herm_bucket(int64_t nc, int64_t n, const int32_t *__restrict__ cl_ptr,
                                                      const int32_t *__restrict__ members, int32_t *__restrict__ bcount,
                                                      int32_t *__restrict__ blists) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += stride) {  // uniform loop
-    const int64_t c = base + threadIdx.x;
-    int bk = -1;
-    if (c < nc) {
-      const int a = cl_ptr[c], b = cl_ptr[c + 1];
-      bool ok = a >= 0 && b >= a;
-      for (int k = a; ok && k < b; ++k) {
-        const int g = members[k];
-        ok = g >= 0 && (int64_t)g < n;
-      }
-      if (!ok)
-        atomicOr(&bcount[15], 1);
-      else if (b > a)
-        bk = bucket_of(b - a);
-    }
+  __shared__ int cnt[N_BUCKETS], base[N_BUCKETS];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+  const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
+  if (tid < N_BUCKETS) cnt[tid] = 0;
+  __syncthreads();
+  for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {
+    const int64_t c = b0 + tid;
+    const int bk = c < c1 ? cluster_bucket(c, n, cl_ptr, members, bcount) : -1;
     for (int q = 0; q < N_BUCKETS; ++q) {
       const unsigned long long mask = __ballot(bk == q);
-      if (mask == 0ull) continue;
-      // every lane executes the atomic, only the lowest lane of the bucket adds
-      const int leader = __ffsll((long long)mask) - 1;
-      const int start =
-          __builtin_amdgcn_readlane(atomicAdd(&bcount[q], lane == leader ? (int)__popcll(mask) : 0), leader);
-      if (bk == q) blists[(int64_t)q * nc + start + popc_below(mask)] = (int32_t)c;
+      if (mask != 0ull && lane == __ffsll((long long)mask) - 1) atomicAdd(&cnt[q], (int)__popcll(mask));
     }
+  }
+  __syncthreads();
+  if (tid < N_BUCKETS) {
+    base[tid] = cnt[tid] > 0 ? atomicAdd(&bcount[tid], cnt[tid]) : 0;
+    cnt[tid] = 0;
+  }
+  __syncthreads();
+  __shared__ int wofs[BIG_T / WAVE][N_BUCKETS];
+  const int w = tid / WAVE;
+  for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {  // uniform over the workgroup
+    const int64_t c = b0 + tid;
+    const int bk = c < c1 ? cluster_bucket(c, n, cl_ptr, members, bcount) : -1;  // as counted above
+    unsigned long long mine = 0ull;
+    for (int q = 0; q < N_BUCKETS; ++q) {
+      const unsigned long long mask = __ballot(bk == q);
+      if (lane == 0) wofs[w][q] = (int)__popcll(mask);
+      if (q == bk) mine = mask;
+    }
+    __syncthreads();
+    if (bk >= 0) {
+      int off = 0;
+      for (int u = 0; u < w; ++u) off += wofs[u][bk];  // wavefronts take their slots in order
+      blists[(int64_t)bk * nc + base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
+    }
+    __syncthreads();
+    if (tid < N_BUCKETS) {
+      int tot = 0;
+      for (int u = 0; u < BIG_T / WAVE; ++u) tot += wofs[u][tid];
+      cnt[tid] += tot;
+    }
+    __syncthreads();
   }
 }
 
@@ -660,7 +776,7 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   int32_t *bcount = c->herm_bcount;
   int32_t *blists = c->herm_blists;
   if ((e = fill_i32(bcount, 0, 16, s)) != hipSuccess) return e;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nc + 255) / 256));
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
   hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, nc, n, cl_ptr, cl_members, bcount, blists);
   int32_t hc[16];
   if ((e = hipMemcpyAsync(hc, bcount, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
@@ -696,6 +812,7 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
     A.dt3_6 = h3 / 6.0;
     A.dt4_24 = h4 / 24.0;
     A.dt5_120 = h5 / 120.0;
+    A.dt_soft2 = h2;
   }
   A.k_max = P.k_max;
   A.max_iter = 1 << 22;
@@ -706,7 +823,7 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   int blocks = 0;
   for (int bk = 0; bk < 8; ++bk) {
     A.boff[bk] = blocks;
-    const int per_block = bk < 7 ? (BIG_T / WAVE) * (WAVE >> bk) : 1;
+    const int per_block = bk < 7 ? (BIG_T / WAVE) * (WAVE >> (bk + lanes_per_member_log2(bk))) : 1;
     blocks += (hc[bk] + per_block - 1) / per_block;
   }
   for (int bk = 8; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
