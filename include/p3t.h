@@ -174,6 +174,22 @@ p3t_status p3t_hermite_cluster_step(p3t_ctx *ctx, int64_t n, int64_t n_clusters,
 /* Soft kick, eq. (HamiltonSol): vel3 += h * acc3 (3n each). */
 p3t_status p3t_kick(p3t_ctx *ctx, int64_t n, double h, const double *acc3, double *vel3);
 
+/* The hard part of a soft step (Section 2.2, steps (4)-(5)) in one call,
+ * from the neighbour pairs of the last p3t_compute_soft_force (or
+ * p3t_evaluate): cluster labels (minimum index per connected component,
+ * Section 2.3), the cluster CSR, and the Hermite integration of every
+ * cluster over dt_soft (as p3t_hermite_cluster_step), all on the device with
+ * one host synchronisation (the cluster-size buckets).  pos3, vel3 (3n) are
+ * updated in place; mass, r_out (n) as for p3t_hermite_cluster_step; dt_hard
+ * (n, nullable) carries each particle's hard step.  *n_clusters_host
+ * (nullable) receives the number of clusters.  Conditions detected on the
+ * device during the integration (P3T_FLAG_KMAX, P3T_FLAG_NSTEPS,
+ * P3T_FLAG_NAN) are left in the status word for p3t_get_status or the next
+ * synchronising call.  P3T_ERR_STATE without a prior force evaluation,
+ * P3T_ERR_CLUSTER for a cluster above 1024 members. */
+p3t_status p3t_hard_step(p3t_ctx *ctx, double *pos3, double *vel3, const double *mass, const double *r_out,
+                         double *dt_hard, int64_t *n_clusters_host);
+
 /* p3t_build_tree followed by p3t_compute_soft_force in one call.  With
  * use_graph = 1 the whole device sequence (bounding box, Morton keys, radix
  * sort, gather, radix tree, moments, groups, walk, longest-first group order,

@@ -214,6 +214,22 @@ class Context:
         self.n = n
         return acc
 
+    def hard_step(self, pos, vel, mass, r_out, dt_hard=None) -> int:
+        """Clusters from the last evaluation's neighbour pairs and their
+        Hermite integration over dt_soft, in place; returns the cluster count."""
+        n = self.n
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        self._vec(mass, n, "mass")
+        self._vec(r_out, n, "r_out")
+        if dt_hard is not None:
+            self._vec(dt_hard, n, "dt_hard")
+        nc = C.c_int64(0)
+        self._bind()
+        self._check(self.L.p3t_hard_step(self._h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(r_out), _ptr(dt_hard),
+                                         C.byref(nc)), "hard_step")
+        return int(nc.value)
+
     def soft_force_frozen(self, pos, mass, out=None):
         """Soft force at new positions / masses over the current tree topology
         and interaction lists (the function the adjoint differentiates)."""

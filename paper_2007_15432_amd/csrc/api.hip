@@ -96,6 +96,7 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   total += bytes(cut_part_need(n_cap), sizeof(double));
   total += 2 * bytes(3 * n_cap, sizeof(double));
   total += bytes(16, sizeof(int32_t)) + bytes(11 * n_cap, sizeof(int32_t));  // hermite buckets
+  total += 3 * bytes(n_cap + 1, sizeof(int32_t));                             // hard-step labels, clusters
   total += 4096;
   if (c->arena.base) {
     HIP_OK(c, hipFree(c->arena.base));
@@ -141,6 +142,9 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   c->acc_s = A.take<double>(3 * n_cap);
   c->herm_bcount = A.take<int32_t>(16);
   c->herm_blists = A.take<int32_t>(11 * n_cap);
+  c->hs_label = A.take<int32_t>(n_cap + 1);
+  c->hs_cl_ptr = A.take<int32_t>(n_cap + 1);
+  c->hs_cl_mem = A.take<int32_t>(n_cap + 1);
   if (!c->herm_blists) return fail(c, P3T_ERR_HIP, "arena layout overflow (internal)");
   HIP_OK(c, hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream));
   c->n_cap = n_cap;
@@ -648,6 +652,34 @@ p3t_status p3t_kick(p3t_ctx *c, int64_t n, double h, const double *acc3, double 
   if (!c) return P3T_ERR_ARG;
   if (n < 0 || bad_ptr(acc3, n) || bad_ptr(vel3, n) || !std::isfinite(h)) return fail(c, P3T_ERR_ARG, "kick: bad argument");
   HIP_OK(c, kick(n, h, acc3, vel3, c->stream));
+  return P3T_OK;
+}
+
+p3t_status p3t_hard_step(p3t_ctx *c, double *pos3, double *vel3, const double *mass, const double *r_out,
+                         double *dt_hard, int64_t *n_clusters_host) {
+  if (!c) return P3T_ERR_ARG;
+  if (!c->force_valid) return fail(c, P3T_ERR_STATE, "hard_step: no neighbour pairs (call p3t_compute_soft_force)");
+  const int64_t n = c->n;
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n))
+    return fail(c, P3T_ERR_ARG, "hard_step: null pointer");
+  if (n_clusters_host) *n_clusters_host = 0;
+  if (n == 0) return P3T_OK;
+  ev_record(c, 9);
+  HIP_OK(c, build_csr(c, n, c->n_pairs));
+  HIP_OK(c, labels_cc(c, n, c->hs_label));
+  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  int64_t nc = 0;
+  hipError_t e = hermite_clusters(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr,
+                                  nullptr, c->node_scan + n, &nc);
+  if (e == hipErrorInvalidValue)
+    return fail(c, P3T_ERR_CLUSTER, "hard_step: a cluster exceeds 1024 members (percolation)");
+  HIP_OK(c, e);
+  ev_record(c, 10);
+  if (n_clusters_host) *n_clusters_host = nc;
+  if (c->timing) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->stats.ms_hermite = ev_ms(c, 9, 10);
+  }
   return P3T_OK;
 }
 

@@ -8,7 +8,9 @@
 //            rounding of r^2) and appends them after the tile to a candidate
 //            buffer.  Writes the sorted-order accumulator (=).
 //   k_cand_test  the exact neighbour test of Section 2.3 on every candidate,
-//            one thread each; neighbours go to the pair buffer.
+//            one thread each; neighbours go to the pair buffer.  Coincident
+//            pairs (r = 0, i != j) are always candidates and are reported
+//            here.
 //   k_far    K = 1 particles, FP64 or (mixed) FP32 offsets from the group
 //            centre with compensated accumulation.  Adds (+=).
 //   k_cell   monopole or traceless-quadrupole cells, FP64 or FP32.  Adds.
@@ -56,6 +58,10 @@ __device__ __forceinline__ int next_gi(const ForceArgs &A, int lane, int iter, i
 }
 
 constexpr double kDummyOffset = 1.0e3;  // distance of padding entries from the group centre
+constexpr double kTinyR2 = 1.0e-150;     // floor of r^2 in the near kernel (see there)
+// relative margin on reach^2 for neighbour candidates: it covers the rounding
+// of r^2 as computed here, so no pair the exact test keeps is missed
+constexpr double kCandMargin = 1.0 + 1.0e-12;
 
 // ------------------------------------------------------------------ near
 struct NearTile {
@@ -78,10 +84,9 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
     yi[s] = A.sy[i];
     zi[s] = A.sz[i];
     invi[s] = A.sinv[i];
-    rch2[s] = A.sreach[i] * A.sreach[i];
+    rch2[s] = A.sreach[i] * A.sreach[i] * kCandMargin;
     ax[s] = ay[s] = az[s] = 0.0;
   }
-  bool coincident = false;
   const int32_t *Ln = A.pool + h.off + h.n_cell;
   for (int t0 = 0; t0 < h.n_near; t0 += WAVE) {
     const int nt = min(WAVE, h.n_near - t0);
@@ -91,7 +96,7 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
       const int j = Ln[t0 + lane];
       const double r = A.sreach[j];
       T.a[lane] = make_double4(A.sx[j], A.sy[j], A.sz[j], A.G * A.sm[j]);
-      T.b[lane] = make_double2(A.sinv[j], r * r);
+      T.b[lane] = make_double2(A.sinv[j], r * r * kCandMargin);
       T.j[lane] = j;
     } else if (lane < ntp) {
       T.a[lane] = make_double4(h.cx + kDummyOffset, h.cy, h.cz, 0.0);
@@ -116,21 +121,21 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
           for (int s = 0; s < IPL; ++s) {
             const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const bool other = jidx != ii[s];
-            const bool ok = other && (r2 > 0.0);
-            coincident |= other && !(r2 > 0.0);
-            const double r2s = ok ? r2 : 1.0;
+            // r = 0 (the particle itself, or a coincident pair, which the
+            // candidate test reports) gives y ~ 0 < gamma, so K = 0 and the
+            // term vanishes exactly: rinv^3 = 1e225 stays finite
+            const double r2s = fmax(r2, kTinyR2);
             const double rinv = rsqrt(r2s);
             const double y = r2s * rinv * fmin(invi[s], b.x);
             const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
             const double x2 = x * x;
             const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
-            const double f = ok ? a.w * K * rinv * rinv * rinv : 0.0;
+            const double f = a.w * K * rinv * rinv * rinv;
             ax[s] += f * dx;
             ay[s] += f * dy;
             az[s] += f * dz;
-            const bool cand = other && r2 <= fmax(rch2[s], b.y) * (1.0 + 1e-12);
-            cm[half][s] |= cand ? bit : 0u;
+            // reach^2 of both sides carry the candidate margin already
+            if (jidx != ii[s] && (r2 <= rch2[s] || r2 <= b.y)) cm[half][s] |= bit;
           }
         }
       }
@@ -173,7 +178,6 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
       acc[2 * A.n + ii[s]] = az[s];
     }
   }
-  if (__ballot(coincident) != 0ull && lane == 0) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
 }
 
 template <int UNR>
@@ -542,6 +546,7 @@ __global__ void k_cand_test(ForceArgs A) {
       const int2 c = A.cands[p];
       i = c.x;
       j = c.y;
+      if (A.sx[i] == A.sx[j] && A.sy[i] == A.sy[j] && A.sz[i] == A.sz[j]) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
       nb = neighbour_test(A.sx[i], A.sy[i], A.sz[i], A.svx[i], A.svy[i], A.svz[i], A.sm[i], A.sro[i], A.srs[i],
                           A.sx[j], A.sy[j], A.sz[j], A.svx[j], A.svy[j], A.svz[j], A.sm[j], A.sro[j], A.srs[j], A.G,
                           A.rsch2, A.rsch3, A.dt);

@@ -698,11 +698,14 @@ __device__ __forceinline__ int cluster_bucket(int64_t c, int64_t n, const int32_
   return b > a ? bucket_of(b - a) : -1;
 }
 
-__global__ __launch_bounds__(256) void k_herm_bucket(int64_t nc, int64_t n, const int32_t *__restrict__ cl_ptr,
+__global__ __launch_bounds__(256) void k_herm_bucket(int64_t nc_host, const int64_t *__restrict__ nc_dev,
+                                                     int64_t stride, int64_t n, const int32_t *__restrict__ cl_ptr,
                                                      const int32_t *__restrict__ members, int32_t *__restrict__ bcount,
                                                      int32_t *__restrict__ blists) {
   __shared__ int cnt[N_BUCKETS], base[N_BUCKETS];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+  const int64_t nc = nc_dev ? *nc_dev : nc_host;  // clusters (at most stride)
+  if (blockIdx.x == 0 && tid == 0) bcount[14] = (int32_t)nc;
   const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
   if (tid < N_BUCKETS) cnt[tid] = 0;
@@ -736,7 +739,7 @@ __global__ __launch_bounds__(256) void k_herm_bucket(int64_t nc, int64_t n, cons
     if (bk >= 0) {
       int off = 0;
       for (int u = 0; u < w; ++u) off += wofs[u][bk];  // wavefronts take their slots in order
-      blists[(int64_t)bk * nc + base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
+      blists[(int64_t)bk * stride + base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
     }
     __syncthreads();
     if (tid < N_BUCKETS) {
@@ -769,18 +772,20 @@ static void host_changeover_coeffs(double g, HermArgs &A) {
 
 hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                             double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
-                            double *e_rel_err, int32_t *n_steps) {
+                            double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev, int64_t *nc_out) {
   hipStream_t s = c->stream;
   hipError_t e;
-  if (nc <= 0) return hipSuccess;
+  if (nc_out) *nc_out = 0;
+  if (nc <= 0) return hipSuccess;  // with nc_dev, nc is an upper bound (the particle count)
   int32_t *bcount = c->herm_bcount;
   int32_t *blists = c->herm_blists;
   if ((e = fill_i32(bcount, 0, 16, s)) != hipSuccess) return e;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
-  hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, nc, n, cl_ptr, cl_members, bcount, blists);
+  hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, nc, nc_dev, nc, n, cl_ptr, cl_members, bcount, blists);
   int32_t hc[16];
   if ((e = hipMemcpyAsync(hc, bcount, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  if (nc_out) *nc_out = hc[14];
   if (hc[15]) return hipErrorInvalidDevicePointer;  // malformed cluster arrays
   if (hc[10] > 0) return hipErrorInvalidValue;       // cluster above the largest supported size
   const p3t_params &P = c->P;

@@ -140,6 +140,19 @@ __global__ void k_cl_ptr(int64_t n, const int32_t *__restrict__ flag, const int6
 
 hipError_t clusters_csr(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
                         int64_t *n_clusters) {
+  hipError_t e = clusters_csr_dev(c, n, label, cl_ptr, cl_members);
+  if (e != hipSuccess) return e;
+  int64_t nc = 0;
+  if ((e = hipMemcpyAsync(&nc, c->node_scan + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  *n_clusters = nc;
+  return hipSuccess;
+}
+
+// The same without the host round trip: the cluster count is left at
+// node_scan[n] on the device.
+hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members) {
   hipStream_t s = c->stream;
   hipError_t e;
   hipLaunchKernelGGL(k_cl_keys, dim3(g1d(n)), dim3(256), 0, s, n, label, c->cl_keys);
@@ -156,11 +169,7 @@ hipError_t clusters_csr(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl
   // (the node-scan buffer is free here; the neighbour CSR stays intact)
   if ((e = scan_i32_to_i64(c->row_cnt, c->node_scan, n, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cl_ptr, dim3(g1d(n)), dim3(256), 0, s, n, c->row_cnt, c->node_scan, cl_ptr);
-  int64_t nc = 0;
-  if ((e = hipMemcpyAsync(&nc, c->node_scan + n, sizeof(int64_t), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  *n_clusters = nc;
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 }  // namespace p3t

@@ -226,6 +226,9 @@ struct p3t_ctx {
   hipGraph_t g_graph = nullptr;
   hipGraphExec_t g_exec = nullptr;
   uint64_t g_key = 0;
+  int32_t *hs_label = nullptr;      // p3t_hard_step: labels (n), cluster CSR (n + 1, n)
+  int32_t *hs_cl_ptr = nullptr;
+  int32_t *hs_cl_mem = nullptr;
   double *adj_buf = nullptr;        // soft-kick adjoint scratch (adjoint_buf_need(adj_cap))
   int64_t adj_cap = 0;
 };
@@ -277,10 +280,13 @@ hipError_t build_csr(p3t_ctx *c, int64_t n, int64_t n_pairs);
 hipError_t labels_cc(p3t_ctx *c, int64_t n, int32_t *label);
 hipError_t clusters_csr(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
                         int64_t *n_clusters);
+hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members);
 
 // hermite.hip
-hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t n_clusters, const int32_t *cl_ptr,
-                            const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
-                            const double *r_out, double *dt_hard, double *e_rel_err, int32_t *n_steps);
+// nc_dev (nullable): the cluster count on the device, nc then only bounds it
+hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
+                            double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
+                            double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev = nullptr,
+                            int64_t *nc_out = nullptr);
 
 }  // namespace p3t

@@ -6,6 +6,7 @@ libp3t's kernels.
     step:  v += a_soft dt/2                                           (3)
            neighbour clusters from the lists of the last evaluation   (4)
            Hermite integration of every cluster over dt               (5)
+           ((4)-(5) in one library call, p3t_hard_step, by default)
            tree; soft force and neighbour lists at the new state      (7)
            v += a_soft dt/2                                           (8)
 
@@ -25,9 +26,11 @@ class P3TStepper:
     hipGraph (replayed every step: positions, masses, radii and the
     acceleration live in fixed buffers)."""
 
-    def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False, graph: bool = False):
+    def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False, graph: bool = False,
+                 fused_hard: bool = True):
         self.ctx = ctx
         self.graph = graph
+        self.fused_hard = fused_hard
         self.pos, self.vel, self.mass = pos, vel, mass
         self.n = int(mass.shape[0])
         self.dt = ctx.params.dt_soft
@@ -35,7 +38,7 @@ class P3TStepper:
         self.r_out, self.r_search, self.v_ran = ctx.compute_cutoffs(pos, vel, mass)
         self.dt_hard = torch.zeros(self.n, dtype=torch.float64, device=pos.device)
         self.acc = torch.empty((3, self.n), dtype=torch.float64, device=pos.device)
-        self.last = {}
+        self.n_clusters = 0
         self._evaluate()
 
     def _evaluate(self):
@@ -45,16 +48,24 @@ class P3TStepper:
         else:
             c.build_tree(self.pos, self.vel, self.mass, self.r_out, self.r_search)
             c.compute_soft_force(out=self.acc)
-        self.row_ptr, self.col, self.label = c.neighbour_list(labels=True)
-        self.last = c.stats()
+        if not self.fused_hard:
+            self.row_ptr, self.col, self.label = c.neighbour_list(labels=True)
+
+    @property
+    def last(self) -> dict:
+        """Counters of the last evaluation (synchronises)."""
+        return self.ctx.stats()
 
     def step(self):
         c = self.ctx
         c.kick(self.acc, self.vel, 0.5 * self.dt)
-        cl_ptr, members = c.clusters(self.label)
-        self.n_clusters = int(cl_ptr.shape[0]) - 1
-        c.hermite_cluster_step(self.pos, self.vel, self.mass, self.r_out, cl_ptr, members, dt_hard=self.dt_hard,
-                               energy=False)
+        if self.fused_hard:
+            self.n_clusters = c.hard_step(self.pos, self.vel, self.mass, self.r_out, dt_hard=self.dt_hard)
+        else:
+            cl_ptr, members = c.clusters(self.label)
+            self.n_clusters = int(cl_ptr.shape[0]) - 1
+            c.hermite_cluster_step(self.pos, self.vel, self.mass, self.r_out, cl_ptr, members, dt_hard=self.dt_hard,
+                                   energy=False)
         if self.recompute:
             c.compute_cutoffs(self.pos, self.vel, self.mass, out=(self.r_out, self.r_search, self.v_ran))
         self._evaluate()

@@ -383,3 +383,46 @@ def test_full_size_sampled(gpu, orc, precision):
     rows = np.repeat(np.arange(d.n), np.diff(rp))
     fwd = set(zip(rows.tolist(), col.tolist()))
     assert all((j, i) in fwd for i, j in fwd)
+
+
+def test_coincident_pair_is_reported(gpu, orc):
+    """Two distinct particles at the same position: the force call reports a
+    numeric error (P3T_FLAG_COINCIDENT) instead of returning a force."""
+    d = diskgen.make_disk(200, 0.999, 1.001, seed=5, m_equal=1e-9)
+    pos = d.pos.copy()
+    pos[:, 7] = pos[:, 3]
+    p = orc.Params()
+    ro, rs, _ = orc.cutoffs(pos, d.vel, d.mass, p)
+    ctx = gpu.Context(gparams(gpu, p, theta=0.5))
+    ctx.build_tree(T(pos), T(d.vel), T(d.mass), T(ro), T(rs))
+    with pytest.raises(gpu.P3TError) as ei:
+        ctx.compute_soft_force()
+    assert ei.value.status == 5  # P3T_ERR_NUMERIC
+
+
+def test_hard_step_equals_separate_calls(gpu, orc, ring):
+    """p3t_hard_step (labels, cluster CSR and Hermite in one call) gives the
+    same states, bit for bit, as neighbour_list + clusters +
+    hermite_cluster_step."""
+    g = ring.g
+    p = gparams(gpu, ring.p, theta=0.5, multipole=2)
+    out = []
+    for fused in (False, True):
+        ctx = gpu.Context(p)
+        pos, vel = g["pos"].clone(), g["vel"].clone()
+        dth = torch.zeros_like(g["m"])
+        ctx.build_tree(pos, vel, g["m"], g["ro"], g["rs"])
+        ctx.compute_soft_force()
+        if fused:
+            nc = ctx.hard_step(pos, vel, g["m"], g["ro"], dt_hard=dth)
+        else:
+            _, _, lab = ctx.neighbour_list(labels=True)
+            cl_ptr, members = ctx.clusters(lab)
+            nc = int(cl_ptr.shape[0]) - 1
+            ctx.hermite_cluster_step(pos, vel, g["m"], g["ro"], cl_ptr, members, dt_hard=dth, energy=False)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        out.append((nc, pos, vel, dth))
+    assert out[0][0] == out[1][0] and out[0][0] < ring.d.n
+    for a, b in zip(out[0][1:], out[1][1:]):
+        assert torch.equal(a, b)
