@@ -317,6 +317,10 @@ p3t_status p3t_destroy(p3t_ctx *c) {
   hipStreamSynchronize(c->stream);
   drop_graph(c);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  if (c->aux_stream) hipStreamSynchronize(c->aux_stream);
+  if (c->aux_stream) hipStreamDestroy(c->aux_stream);
+  for (auto &ev : c->aux_ev)
+    if (ev) hipEventDestroy(ev);
   void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col, c->cands, c->adj_buf};
   for (void *b : bufs)
     if (b) hipFree(b);

@@ -223,7 +223,10 @@ __device__ __forceinline__ void wave_sync() {
 
 struct Lds {
   double *px, *py, *pz, *pvx, *pvy, *pvz, *pgm, *pinv;
+  int *act;     // big clusters: active members of the step (BIG_ACT)
+  double *res;  // big clusters: their reduced partner sums (6 BIG_ACT)
 };
+constexpr int BIG_ACT = 128;  // most active members handled lane-parallel
 
 // ---------------------------------------------------------------- small clusters
 // One wavefront (lanes [wbase, wbase + 64) of the LDS arrays) runs 64/SEG
@@ -457,6 +460,23 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// exclusive scan of one int per thread over the workgroup; returns the total
+__device__ __forceinline__ int block_excl_scan_i32(int v, int &excl, int64_t *sh) {
+  const int w = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+  const int incl = wave_incl_scan(v);
+  __syncthreads();
+  if (l == WAVE - 1) sh[w] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int q = 0; q < BIG_T / WAVE; ++q) {
+    const int s = (int)sh[q];
+    off += q < w ? s : 0;
+    tot += s;
+  }
+  excl = off + incl - v;
+  return tot;
+}
+
 // One 256-thread workgroup per cluster c, MPT members per thread.
 template <int MPT>
 __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L, int64_t *shi, double *shd) {
@@ -560,16 +580,73 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L,
       L.pvz[k] = vp[u][2];
     }
     __syncthreads();
+    // Active members (due at tn).  With few of them, each active member's
+    // partner loop is spread over the 64 lanes of a wavefront (wavefronts
+    // take active members in turn) and reduced; otherwise every thread
+    // loops over all partners of its own members.
+    bool act[MPT];
+    int slot[MPT];
+    int na_me = 0;
+#pragma unroll
+    for (int u = 0; u < MPT; ++u) {
+      act[u] = mem[u] && t[u] + ((int64_t)1 << (TICK_BITS - lev[u])) == tn;
+      na_me += act[u] ? 1 : 0;
+    }
+    int base_me = 0;
+    const int na = block_excl_scan_i32(na_me, base_me, shi);
+    const bool spread = L.act != nullptr && na <= BIG_ACT && 2 * na <= size;
+    if (spread) {
+      int q = base_me;
+#pragma unroll
+      for (int u = 0; u < MPT; ++u) {
+        slot[u] = act[u] ? q : -1;
+        if (act[u]) L.act[q++] = tid + BIG_T * u;
+      }
+      __syncthreads();
+      const int w = tid / WAVE, lane = tid & (WAVE - 1);
+      for (int a = w; a < na; a += BIG_T / WAVE) {  // uniform per wavefront
+        const int k = L.act[a];
+        const double xk = L.px[k], yk = L.py[k], zk = L.pz[k], vxk = L.pvx[k], vyk = L.pvy[k], vzk = L.pvz[k];
+        const double ik = L.pinv[k];
+        double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0};
+        for (int qq = lane; qq < size; qq += WAVE) {
+          if (qq == k) continue;
+          hard_pair(L.px[qq] - xk, L.py[qq] - yk, L.pz[qq] - zk, L.pvx[qq] - vxk, L.pvy[qq] - vyk, L.pvz[qq] - vzk,
+                    L.pgm[qq], fmin(ik, L.pinv[qq]), A, pa, pj);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          pa[d] = wave_sum(pa[d]);
+          pj[d] = wave_sum(pj[d]);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            L.res[6 * a + d] = pa[d];
+            L.res[6 * a + 3 + d] = pj[d];
+          }
+        }
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
       const int k = tid + BIG_T * u;
-      if (!mem[u] || t[u] + ((int64_t)1 << (TICK_BITS - lev[u])) != tn) continue;
+      if (!act[u]) continue;
       double a1[3], j1[3];
       star_term(xp[u], vp[u], A.GM, a1, j1);
-      for (int q = 0; q < size; ++q) {
-        if (q == k) continue;
-        hard_pair(L.px[q] - xp[u][0], L.py[q] - xp[u][1], L.pz[q] - xp[u][2], L.pvx[q] - vp[u][0],
-                  L.pvy[q] - vp[u][1], L.pvz[q] - vp[u][2], L.pgm[q], fmin(invi[u], L.pinv[q]), A, a1, j1);
+      if (spread) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a1[d] += L.res[6 * slot[u] + d];
+          j1[d] += L.res[6 * slot[u] + 3 + d];
+        }
+      } else {
+        for (int q = 0; q < size; ++q) {
+          if (q == k) continue;
+          hard_pair(L.px[q] - xp[u][0], L.py[q] - xp[u][1], L.pz[q] - xp[u][2], L.pvx[q] - vp[u][0],
+                    L.pvy[q] - vp[u][1], L.pvz[q] - vp[u][2], L.pgm[q], fmin(invi[u], L.pinv[q]), A, a1, j1);
+        }
       }
       const double h = (double)(tn - t[u]) * A.tick;
       t[u] = tn;
@@ -616,13 +693,15 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L,
   if (tid == 0 && A.nsteps) A.nsteps[c] = it;
 }
 
-// Buckets 0..7 (sizes 1..256) in one launch of 256-thread workgroups; the
+// Buckets 0..6 (sizes 1..64) in one launch of 256-thread workgroups; the
 // block index selects the bucket (uniform per workgroup).
 __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   __shared__ double lds[8][BIG_T];
   __shared__ int64_t shi[BIG_T / WAVE];
   __shared__ double shd[BIG_T / WAVE];
-  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7]};
+  __shared__ int act[BIG_ACT];
+  __shared__ double res[6 * BIG_ACT];
+  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7], act, res};
   const int blk = blockIdx.x;
   // bucket of this workgroup (boff is non-decreasing).  Only constant
   // indices into the argument struct: a run-time index would make the
@@ -636,10 +715,6 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
     }
   const int local = blk - first;
   const int32_t *blist = A.blists + (int64_t)bk * A.nc;
-  if (bk == 7) {
-    big_body<1>(A, blist[local], L, shi, shd);
-    return;
-  }
   const int w = threadIdx.x / WAVE;
   const int wbase = w * WAVE;
   const int per_wave = WAVE >> (bk + lanes_per_member_log2(bk));  // clusters per wavefront
@@ -656,7 +731,12 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A, int bk) {
   __shared__ double lds[8][BIG_T * MPT];
   __shared__ int64_t shi[BIG_T / WAVE];
   __shared__ double shd[BIG_T / WAVE];
-  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7]};
+  // the lane-parallel partner loop needs 6.6 KB more LDS, which the
+  // 1024-member variant does not have within 64 KB per workgroup
+  constexpr int NACT = MPT <= 2 ? BIG_ACT : 1;
+  __shared__ int act[NACT];
+  __shared__ double res[6 * NACT];
+  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7], MPT <= 2 ? act : nullptr, res};
   big_body<MPT>(A, A.blists[(int64_t)bk * A.nc + blockIdx.x], L, shi, shd);
 }
 
@@ -824,17 +904,36 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
   for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = hc[bk];
-  // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG), bucket 7 (one per block)
+  // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG /
+  // lanes per member); the clusters of 65 members and more run at the same
+  // time in their own launches on a second stream (one workgroup each)
   int blocks = 0;
-  for (int bk = 0; bk < 8; ++bk) {
+  for (int bk = 0; bk < 7; ++bk) {
     A.boff[bk] = blocks;
-    const int per_block = bk < 7 ? (BIG_T / WAVE) * (WAVE >> (bk + lanes_per_member_log2(bk))) : 1;
+    const int per_block = (BIG_T / WAVE) * (WAVE >> (bk + lanes_per_member_log2(bk)));
     blocks += (hc[bk] + per_block - 1) / per_block;
   }
-  for (int bk = 8; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
+  for (int bk = 7; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
+  const bool big = hc[7] > 0 || hc[8] > 0 || hc[9] > 0;
+  hipStream_t s2 = s;
+  if (big && blocks > 0) {
+    if (!c->aux_stream && (e = hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+    if (!c->aux_ev[0]) {
+      for (auto &ev : c->aux_ev)
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    s2 = c->aux_stream;
+    if ((e = hipEventRecord(c->aux_ev[0], s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s2, c->aux_ev[0], 0)) != hipSuccess) return e;
+  }
+  if (hc[7] > 0) hipLaunchKernelGGL(k_herm_big<1>, dim3(hc[7]), dim3(BIG_T), 0, s2, A, 7);
+  if (hc[8] > 0) hipLaunchKernelGGL(k_herm_big<2>, dim3(hc[8]), dim3(BIG_T), 0, s2, A, 8);
+  if (hc[9] > 0) hipLaunchKernelGGL(k_herm_big<4>, dim3(hc[9]), dim3(BIG_T), 0, s2, A, 9);
   if (blocks > 0) hipLaunchKernelGGL(k_herm_fused, dim3(blocks), dim3(BIG_T), 0, s, A);
-  if (hc[8] > 0) hipLaunchKernelGGL(k_herm_big<2>, dim3(hc[8]), dim3(BIG_T), 0, s, A, 8);
-  if (hc[9] > 0) hipLaunchKernelGGL(k_herm_big<4>, dim3(hc[9]), dim3(BIG_T), 0, s, A, 9);
+  if (s2 != s) {  // join
+    if ((e = hipEventRecord(c->aux_ev[1], s2)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, c->aux_ev[1], 0)) != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

@@ -221,6 +221,9 @@ struct p3t_ctx {
   double *cut_part = nullptr;       // cut-off bin partial sums
   double *tmp_d = nullptr;          // per-particle FP64 scratch (3n)
   double *acc_s = nullptr;          // soft acceleration in sorted order (3n)
+  // second stream for the big Hermite clusters, fork / join events
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t aux_ev[2] = {};
   // captured evaluation graph (p3t_evaluate with use_graph = 1)
   hipStream_t cap_stream = nullptr;
   hipGraph_t g_graph = nullptr;
