@@ -33,7 +33,7 @@ GROUPS = (64, 96, 128)
 LEAVES = (8, 16, 32)
 SHAPES = [dict(force_split=0, force_unroll=4)] + [
     dict(force_split=1, force_unroll=u, waves_per_cu=w) for u in (1, 2, 4, 8) for w in (8, 16, 32)]
-WALK_WAVES = (2, 4, 8)
+WALK_WAVES = (2, 4, 8, 16)
 
 
 @dataclass
@@ -59,16 +59,21 @@ class TuneResult:
                            "trials": [asdict(t) for t in self.trials]})
 
 
-def _best(trials):
-    return min(trials, key=lambda t: t.ms)
+def _best(trials, incumbent=None, margin: float = 0.03):
+    """Fastest trial; the incumbent stays unless beaten by more than
+    `margin` (timing noise would otherwise flip between equal shapes)."""
+    b = min(trials, key=lambda t: t.ms)
+    if incumbent is not None and incumbent.ms <= b.ms * (1.0 + margin):
+        return incumbent
+    return b
 
 
 def search(measure, group_cap: int = 128, groups=GROUPS, leaves=LEAVES, shapes=SHAPES, walk_waves=WALK_WAVES,
            default_kernel=None) -> TuneResult:
     """Coordinate search driven by measure(params: dict, kernel: dict) ->
     (ms, interactions).  Host logic only; see tune() for the GPU measure."""
-    kernel0 = dict(default_kernel or dict(force_split=1, force_unroll=4, force_persistent=1, waves_per_cu=32,
-                                          walk_waves_per_cu=4))
+    kernel0 = dict(default_kernel or dict(force_split=1, force_unroll=4, force_persistent=1, waves_per_cu=8,
+                                          walk_waves_per_cu=8))
     trials = []
     s1 = []
     for g, l in itertools.product(groups, leaves):
@@ -88,14 +93,14 @@ def search(measure, group_cap: int = 128, groups=GROUPS, leaves=LEAVES, shapes=S
         k.update(sh)
         ms, inter = measure(b1.params, k)
         s2.append(Trial(2, dict(b1.params), k, ms, inter))
-    b2 = _best(s2 + [b1])
+    b2 = _best(s2, incumbent=b1)
     s3 = []
     for w in walk_waves:
         k = dict(b2.kernel)
         k["walk_waves_per_cu"] = w
         ms, inter = measure(b2.params, k)
         s3.append(Trial(3, dict(b2.params), k, ms, inter))
-    b3 = _best(s3 + [b2])
+    b3 = _best(s3, incumbent=b2)
     trials = s1 + s2 + s3
     return TuneResult(params=dict(b3.params), kernel=dict(b3.kernel), ms=b3.ms, trials=trials)
 

@@ -180,11 +180,11 @@ struct p3t_ctx {
   unsigned host_status = 0;   // accumulated device status bits (cleared by p3t_get_status)
   int force_slots = 0;        // persistent force grid
   int force_persistent = 1;
-  int walk_waves_per_cu = 4;  // persistent walk grid
+  int walk_waves_per_cu = 8;  // persistent walk grid
   struct {
     int split = 1;         // 1: one kernel per interaction class, 0: the fused kernel
     int unroll = 4;        // j-loop unroll of the split kernels (1, 2, 4, 8)
-    int waves_per_cu = 32; // persistent grid of the split kernels: waves per CU (capped by occupancy)
+    int waves_per_cu = 8;  // persistent grid of the split kernels: waves per CU (capped by occupancy)
   } fcfg;
   int32_t *herm_bcount = nullptr;  // Hermite bucket counts (16)
   int32_t *herm_blists = nullptr;  // Hermite bucket lists (11 * n_cap)
