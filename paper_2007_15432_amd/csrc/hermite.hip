@@ -188,8 +188,10 @@ __device__ __forceinline__ int initial_level(const double *a0, const double *j0,
 // the quad steps brings the other half's minimum to every lane.
 template <int CTRL>
 __device__ __forceinline__ int64_t dpp_i64(int64_t v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(uint64_t)v, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xF, 0xF, false);
+  // every lane is written (the permutations stay inside each row), so no
+  // "old" value is needed
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)(uint64_t)v, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xF, 0xF, true);
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
@@ -329,6 +331,8 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   const double E0 = seg_sum(e, cl2);
   int lev = initial_level(a0, j0, mem, gid, A);  // every copy reads the carried step
   const int64_t T = (int64_t)1 << TICK_BITS;
+  const int max_iter = A.max_iter;
+  const double tick = A.tick, GM = A.GM;
   int64_t t = 0;
   int nst = 0;  // block steps of this lane's cluster
   for (int it = 0;; ++it) {
@@ -339,7 +343,7 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     const int64_t tn = seg_min(te, cl2);
     const bool done = (size == 0) || (tn > T);
     if (__all(done)) break;
-    if (it >= A.max_iter) {
+    if (it >= max_iter) {
       if (lane == 0) set_flag(A.cnt, P3T_FLAG_NSTEPS);
       break;
     }
@@ -347,7 +351,7 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     nst += done ? 0 : 1;
     double xp[3], vp[3];
     if (mem && !done) {
-      const double dl = (double)(tn - t) * A.tick;
+      const double dl = (double)(tn - t) * tick;
       const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -390,13 +394,13 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     }
     if (active) {
       double a1[3], j1[3];
-      star_term(xp, vp, A.GM, a1, j1);
+      star_term(xp, vp, GM, a1, j1);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         a1[d] += pa[d];
         j1[d] += pj[d];
       }
-      const double h = (double)(tn - t) * A.tick;
+      const double h = (double)(tn - t) * tick;
       t = tn;
       correct(x, v, a0, j0, xp, vp, a1, j1, h, t, lev, A);
     }

@@ -426,3 +426,61 @@ def test_hard_step_equals_separate_calls(gpu, orc, ring):
     assert out[0][0] == out[1][0] and out[0][0] < ring.d.n
     for a, b in zip(out[0][1:], out[1][1:]):
         assert torch.equal(a, b)
+
+
+def test_empty_input_is_a_no_op(gpu, orc):
+    """n = 0 is valid for every entry point and produces nothing."""
+    ctx = gpu.Context(gparams(gpu, orc.Params()))
+    z3 = torch.zeros((3, 0), dtype=torch.float64, device=DEV)
+    z = torch.zeros(0, dtype=torch.float64, device=DEV)
+    ro, rs, vr = ctx.compute_cutoffs(z3, z3, z)
+    assert ro.numel() == 0
+    ctx.build_tree(z3, z3, z, z, z)
+    assert ctx.compute_soft_force().numel() == 0
+    rp, col, lab = ctx.neighbour_list()
+    assert rp.cpu().tolist() == [0] and col.numel() == 0
+    assert ctx.hard_step(z3, z3, z, z) == 0
+    assert ctx.evaluate(z3, z3, z, z, z, graph=True).numel() == 0
+    gx, gm = ctx.soft_kick_adjoint(z3, 1.0)
+    assert gx.numel() == 0 and gm.numel() == 0
+
+
+def test_buffer_growth_keeps_results_exact(gpu, orc):
+    """A dense ring with a large cut-off overflows the default list pool, pair
+    and candidate buffers; the library grows them and redoes the evaluation,
+    and the neighbour rows still match the oracle bit for bit."""
+    d = diskgen.dense_ring(4096, seed=11)
+    case = Case(orc, d, orc.Params(r_cut0=30.0))
+    ctx, acc = run_force(gpu, case, theta=0.5, multipole=2)
+    rp, col, _ = ctx.neighbour_list(labels=False)
+    rp_o, col_o = case.nbr(orc)
+    print("ring r_cut0=30: nnz", int(rp_o[-1]), "list entries", ctx.stats()["list_entries"])
+    assert int(rp_o[-1]) > 65536  # more pairs than the initial pair buffer holds
+    assert np.array_equal(rp.cpu().numpy(), rp_o) and np.array_equal(col.cpu().numpy(), col_o)
+    # the same context again, now with grown buffers and no retry: same bits
+    acc2 = ctx.compute_soft_force().cpu().numpy()
+    assert np.array_equal(acc, acc2)
+    e = errs(acc, case.acc(orc))
+    print("ring r_cut0=30 eps", e)
+    assert e[0] < 1e-2 and e[1] < 1e-2
+
+
+def test_hermite_rejects_bad_clusters(gpu, orc):
+    """A cluster above 1024 members is P3T_ERR_CLUSTER; cluster pointers
+    that decrease are P3T_ERR_ARG; nothing is integrated in either case."""
+    d = diskgen.workload("disk2k_equal")
+    p = orc.Params()
+    ro, _, _ = orc.cutoffs(d.pos, d.vel, d.mass, p)
+    ctx = gpu.Context(gparams(gpu, p))
+    pos, vel = T(d.pos), T(d.vel)
+    members = torch.arange(d.n, dtype=torch.int32, device=DEV)
+    big = torch.tensor([0, 1100, d.n], dtype=torch.int32, device=DEV)
+    with pytest.raises(gpu.P3TError) as ei:
+        ctx.hermite_cluster_step(pos, vel, T(d.mass), T(ro), big, members)
+    assert ei.value.status == 6
+    bad = torch.tensor([0, 10, 5, d.n], dtype=torch.int32, device=DEV)
+    with pytest.raises(gpu.P3TError) as ei:
+        ctx.hermite_cluster_step(pos, vel, T(d.mass), T(ro), bad, members)
+    assert ei.value.status == 1
+    torch.cuda.synchronize()
+    assert torch.equal(pos, T(d.pos)) and torch.equal(vel, T(d.vel))
