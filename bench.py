@@ -43,7 +43,7 @@ PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published, packed)
 METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force error"
 
 
-def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None):
+def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None, overlap=False):
     from paper_2007_15432_amd.driver import P3TStepper
 
     dev = "cuda:0"
@@ -57,7 +57,7 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
     m = torch.tensor(disk.mass, dtype=torch.float64, device=dev)
     # force at the initial state, kept for the error measurement
-    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph)
+    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph, overlap=overlap)
     acc0 = st.acc.clone()
     r_out0 = st.r_out.clone()
     for _ in range(warmup):
@@ -67,7 +67,8 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     t0 = time.perf_counter()
     inter = near = far = cell = 0
     stage = {k: 0.0 for k in ("ms_cutoffs", "ms_tree", "ms_walk", "ms_force", "ms_neighbour", "ms_hermite",
-                              "ms_near", "ms_far", "ms_cell", "ms_cand")}
+                              "ms_near", "ms_far", "ms_cell", "ms_cand", "ms_direct")}
+    n_slow = 0
     for _ in range(steps):
         st.step()
         s = ctx.stats()
@@ -76,6 +77,7 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
         cell += s["n_cell"]
         for k in stage:
             stage[k] += s[k]
+        n_slow += st.n_slow
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_timing(False)
@@ -84,7 +86,7 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     s = ctx.stats()
     out = dict(value=inter / steps / sec, ms_per_step=1e3 * sec, interactions_per_step=inter // steps,
                n_near=near // steps, n_far=far // steps, n_cell=cell // steps, n_groups=s["n_groups"],
-               n_pairs=s["n_pairs"], n_clusters=st.n_clusters,
+               n_pairs=s["n_pairs"], n_clusters=st.n_clusters, n_slow=n_slow / steps,
                stages_ms={k[3:]: v / steps for k, v in stage.items()})
     if graph:  # kernels inside the graph are not timed one by one
         ctx.close()
@@ -220,7 +222,9 @@ def main():
     ap.add_argument("--n-leaf", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--paths", default="mixed,fp64")
+    ap.add_argument("--paths", default="mixed,fp64,mixed_serial",
+                    help="mixed: FP32 bulk / FP64 near, slow clusters overlapped with the tree; fp64: plain FP64, "
+                         "hard part then tree; mixed_serial: mixed precision, hard part then tree")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph run of the mixed path")
     ap.add_argument("--no-autotune", action="store_true", help="use --n-group / --n-leaf and the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -257,17 +261,20 @@ def main():
               "tree+walk+force)", file=sys.stderr, flush=True)
     results = {}
     for name in args.paths.split(","):
-        prec = 1 if name == "mixed" else 0
-        results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, n_group, n_leaf, kcfg=kcfg)
+        prec = 1 if name.startswith("mixed") else 0
+        results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, n_group, n_leaf, kcfg=kcfg,
+                                 overlap=name == "mixed")
         r = results[name]
         print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
               f"force {r['stages_ms']['force']:.2f} ms, {r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}",
               file=sys.stderr, flush=True)
     graph = None
     if not args.no_graph:
-        g = run_path(p3t, torch, disk, 1, args.steps, args.warmup, n_group, n_leaf, graph=True, kcfg=kcfg)
+        g = run_path(p3t, torch, disk, 1, args.steps, args.warmup, n_group, n_leaf, graph=True, kcfg=kcfg,
+                     overlap=True)
         graph = {k: g[k] for k in ("value", "ms_per_step", "interactions_per_step")}
-        graph["path"] = "mixed, tree + walk + force replayed from one captured hipGraph per step"
+        graph["path"] = "mixed with the slow clusters overlapped, tree + walk + force replayed from one captured " \
+                        "hipGraph per step"
         print(f"# mixed (graph): {g['value']:.4g} interactions/s, {g['ms_per_step']:.2f} ms/step", file=sys.stderr,
               flush=True)
     head = "mixed" if "mixed" in results else next(iter(results))
@@ -307,7 +314,7 @@ def main():
             line[name] = {k: r[k] for k in ("value", "ms_per_step", "interactions_per_step", "stages_ms", "roofline",
                                             "kernels")}
             line[name]["force_error"] = errs.get(name)
-    line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters")}
+    line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters", "n_slow")}
     if graph:
         line["graph"] = graph
     if tuned:

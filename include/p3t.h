@@ -90,7 +90,8 @@ typedef struct {
      neighbour test of the candidates */
   double ms_near, ms_far, ms_cell, ms_cand;
   int32_t timing;       /* 1 if the phase times above were measured */
-  int32_t reserved;
+  int32_t n_slow;       /* members of slow clusters in the last p3t_hard_evaluate */
+  double ms_direct;     /* p3t_hard_evaluate: the direct terms of the slow members */
 } p3t_stats;
 
 /* Fill *p_host with the defaults described above. */
@@ -204,6 +205,38 @@ p3t_status p3t_hard_step(p3t_ctx *ctx, double *pos3, double *vel3, const double 
  * as the two calls it replaces; with use_graph = 0 it is exactly those. */
 p3t_status p3t_evaluate(p3t_ctx *ctx, int64_t n, const double *pos3, const double *vel3, const double *mass,
                         const double *r_out, const double *r_search, double *acc3, int32_t use_graph);
+
+/* p3t_hard_step followed by p3t_evaluate (Section 2.2, steps (4)-(7)), with
+ * the clusters that will run long taken off the critical path.  A cluster is
+ * slow when one of its members carries a hard step dt_hard <= dt_soft *
+ * 2^-slow_log2 from its last integration (it will take about 2^slow_log2
+ * block steps or more); the members of slow clusters, at most 1024 in one
+ * call (clusters that do not fit stay in the ordinary set), form S.  The slow
+ * clusters integrate on a second stream into copies of the state while the
+ * others integrate in place and the tree, walk and soft force of Section 2.2
+ * run at the new state with the members of S given zero mass; after both
+ * finish, the copies go back into pos3 and vel3 and the soft terms between S
+ * and every particle (eq. (softforce) with the changeover at the pair
+ * cut-off, eq. (rout2)) are summed directly in FP64, with the neighbour test
+ * of Section 2.3 for every pair that involves S.
+ *   pos3, vel3 (3n, in/out), mass (n): as for p3t_hard_step; the state
+ *     after the call is the one p3t_hard_step leaves, bit for bit.
+ *   r_out_hard (n): the cut-offs of the hard part (those of the evaluation
+ *     whose pairs form the clusters); r_out, r_search (n): those of the new
+ *     evaluation (they may be the same arrays).
+ *   dt_hard (n, in/out, nullable): carried hard steps, as for p3t_hard_step;
+ *     NULL or slow_log2 <= 0 disables the split.
+ *   acc3 (3n, out): the soft acceleration at the new state.  The neighbour
+ *     pairs (p3t_neighbour_list) equal those of p3t_evaluate bit for bit; the
+ *     forces differ from it only in that the terms involving S are exact
+ *     rather than tree terms.
+ *   use_graph: as for p3t_evaluate.  *n_clusters_host, *n_slow_host
+ *     (nullable) receive the cluster count and |S|.
+ * Errors as p3t_hard_step and p3t_evaluate; the state is advanced whenever
+ * the hard part succeeded.  n is that of the last evaluation. */
+p3t_status p3t_hard_evaluate(p3t_ctx *ctx, double *pos3, double *vel3, const double *mass, const double *r_out_hard,
+                             double *dt_hard, const double *r_out, const double *r_search, double *acc3,
+                             int32_t slow_log2, int32_t use_graph, int64_t *n_clusters_host, int64_t *n_slow_host);
 
 /* Soft force over the CURRENT tree topology and interaction lists at new
  * positions pos3 (3n) and masses mass (n), in the caller's order, with the

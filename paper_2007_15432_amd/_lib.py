@@ -45,7 +45,7 @@ class CStats(C.Structure):
         ("ms_cutoffs", C.c_double), ("ms_tree", C.c_double), ("ms_walk", C.c_double), ("ms_force", C.c_double),
         ("ms_neighbour", C.c_double), ("ms_hermite", C.c_double),
         ("ms_near", C.c_double), ("ms_far", C.c_double), ("ms_cell", C.c_double), ("ms_cand", C.c_double),
-        ("timing", C.c_int32), ("reserved", C.c_int32),
+        ("timing", C.c_int32), ("n_slow", C.c_int32), ("ms_direct", C.c_double),
     ]
 
 
@@ -75,6 +75,8 @@ SIGNATURES = {
     "p3t_kick": (C.c_int, [_vp, _i64, _d, _vp, _vp]),
     "p3t_evaluate": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i32]),
     "p3t_hard_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)]),
+    "p3t_hard_evaluate": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, C.POINTER(_i64),
+                                    C.POINTER(_i64)]),
     "p3t_soft_force_frozen": (C.c_int, [_vp, _vp, _vp, _vp]),
     "p3t_soft_kick_adjoint": (C.c_int, [_vp, _d, _vp, _vp, _vp]),
     "p3t_set_timing": (C.c_int, [_vp, _i32]),

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libp3t.so")
 ARCH = os.environ.get("P3T_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["util.hip", "cutoff.hip", "tree.hip", "walk.hip", "force.hip", "force_split.hip", "nbr.hip", "hermite.hip", "adjoint.hip",
+SOURCES = ["util.hip", "cutoff.hip", "tree.hip", "walk.hip", "force.hip", "force_split.hip", "nbr.hip", "hermite.hip", "adjoint.hip", "slow.hip",
            "api.hip"]
 
 CFLAGS = [

@@ -95,7 +95,8 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   total += bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));      // uf, cl keys
   total += bytes(cut_part_need(n_cap), sizeof(double));
   total += 2 * bytes(3 * n_cap, sizeof(double));
-  total += bytes(16, sizeof(int32_t)) + bytes(11 * n_cap, sizeof(int32_t));  // hermite buckets
+  total += bytes(HERM_BC_WORDS, sizeof(int32_t)) + bytes(HERM_N_BUCKETS * n_cap, sizeof(int32_t));  // buckets
+  total += bytes(n_cap, sizeof(int32_t)) + bytes(n_cap, sizeof(uint8_t));  // cluster buckets, slow flags
   total += 3 * bytes(n_cap + 1, sizeof(int32_t));                             // hard-step labels, clusters
   total += 4096;
   if (c->arena.base) {
@@ -140,12 +141,14 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   c->cut_part = A.take<double>(cut_part_need(n_cap));
   c->tmp_d = A.take<double>(3 * n_cap);
   c->acc_s = A.take<double>(3 * n_cap);
-  c->herm_bcount = A.take<int32_t>(16);
-  c->herm_blists = A.take<int32_t>(11 * n_cap);
+  c->herm_bcount = A.take<int32_t>(HERM_BC_WORDS);
+  c->herm_blists = A.take<int32_t>(HERM_N_BUCKETS * n_cap);
+  c->herm_clbk = A.take<int32_t>(n_cap);
+  c->slow_flag = A.take<uint8_t>(n_cap);
   c->hs_label = A.take<int32_t>(n_cap + 1);
   c->hs_cl_ptr = A.take<int32_t>(n_cap + 1);
   c->hs_cl_mem = A.take<int32_t>(n_cap + 1);
-  if (!c->herm_blists) return fail(c, P3T_ERR_HIP, "arena layout overflow (internal)");
+  if (!c->hs_cl_mem) return fail(c, P3T_ERR_HIP, "arena layout overflow (internal)");
   HIP_OK(c, hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream));
   c->n_cap = n_cap;
   c->tree_valid = c->force_valid = false;
@@ -190,7 +193,8 @@ p3t_status sync_counters(p3t_ctx *c, DevCounters *h) {
   return P3T_OK;
 }
 
-__global__ void k_clear_bits(DevCounters *cnt, unsigned bits) { cnt->status &= ~bits; }
+// atomic: a kernel on another stream may be setting bits at the same time
+__global__ void k_clear_bits(DevCounters *cnt, unsigned bits) { atomicAnd(&cnt->status, ~bits); }
 
 // move numeric bits from the device word into the host-side word
 p3t_status harvest_status(p3t_ctx *c, unsigned *new_bits) {
@@ -274,6 +278,7 @@ uint64_t graph_key(const p3t_ctx *c, int64_t n, const void *const *ptrs, int np)
   const int64_t caps[] = {c->n_cap, c->pool_cap, c->slot_cap_list, c->slot_cap_stack, c->pair_cap, c->cand_cap,
                           c->walk_slots, c->fcfg.split, c->fcfg.unroll, c->fcfg.waves_per_cu, c->force_persistent};
   for (int64_t v : caps) h = mix(h, (uint64_t)v);
+  h = mix(h, (uint64_t)c->slow_active);
   const unsigned char *pb = reinterpret_cast<const unsigned char *>(&c->P);
   for (size_t k = 0; k < sizeof(p3t_params); ++k) h = mix(h, pb[k]);
   return h;
@@ -321,7 +326,12 @@ p3t_status p3t_destroy(p3t_ctx *c) {
   if (c->aux_stream) hipStreamDestroy(c->aux_stream);
   for (auto &ev : c->aux_ev)
     if (ev) hipEventDestroy(ev);
-  void *bufs[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->csr_col, c->cands, c->adj_buf};
+  if (c->slow_stream) hipStreamSynchronize(c->slow_stream);
+  if (c->slow_stream) hipStreamDestroy(c->slow_stream);
+  for (auto &ev : c->slow_ev)
+    if (ev) hipEventDestroy(ev);
+  void *bufs[] = {c->arena.base, c->pool,     c->slot_lists, c->slot_stack, c->pairs,
+                  c->csr_col,    c->cands,    c->adj_buf,    c->ov_buf};
   for (void *b : bufs)
     if (b) hipFree(b);
   for (auto &e : c->ev)
@@ -685,6 +695,127 @@ p3t_status p3t_hard_step(p3t_ctx *c, double *pos3, double *vel3, const double *m
     c->stats.ms_hermite = ev_ms(c, 9, 10);
   }
   return P3T_OK;
+}
+
+namespace {
+
+// buffers of p3t_hard_evaluate's slow split, sized for n_cap particles
+p3t_status ensure_overlap(p3t_ctx *c) {
+  if (!c->slow_ev[0])
+    for (auto &ev : c->slow_ev) HIP_OK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  if (c->ov_buf && c->ov_n_cap >= c->n_cap) return P3T_OK;
+  const int64_t nc = c->n_cap;
+  auto bytes = [](int64_t count, size_t sz) { return ((size_t)count * sz + 255) & ~size_t(255); };
+  const size_t total = 2 * bytes(3 * nc, sizeof(double)) + bytes(nc, sizeof(double)) +
+                       bytes(SLOW_CAP, sizeof(int32_t)) + bytes(HERM_N_BUCKETS * SLOW_CAP, sizeof(int32_t)) +
+                       bytes((int64_t)SLOW_CAP * SLOW_CHUNKS * 3, sizeof(double));
+  c->ov_n_cap = 0;
+  c->slow_list = nullptr;
+  HIP_OK(c, dev_alloc(c->ov_buf, (int64_t)total));
+  Arena A;
+  A.base = c->ov_buf;
+  A.size = total;
+  c->sh_pos = A.take<double>(3 * nc);
+  c->sh_vel = A.take<double>(3 * nc);
+  c->m_eff = A.take<double>(nc);
+  c->slow_list = A.take<int32_t>(SLOW_CAP);
+  c->slow_blists = A.take<int32_t>(HERM_N_BUCKETS * SLOW_CAP);
+  c->slow_part = A.take<double>((int64_t)SLOW_CAP * SLOW_CHUNKS * 3);
+  if (!c->slow_part) return fail(c, P3T_ERR_HIP, "overlap buffer layout overflow (internal)");
+  c->ov_n_cap = nc;
+  return P3T_OK;
+}
+
+}  // namespace
+
+p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const double *mass, const double *r_out_hard,
+                             double *dt_hard, const double *r_out, const double *r_search, double *acc3,
+                             int32_t slow_log2, int32_t use_graph, int64_t *n_clusters_host, int64_t *n_slow_host) {
+  if (!c) return P3T_ERR_ARG;
+  if (n_clusters_host) *n_clusters_host = 0;
+  if (n_slow_host) *n_slow_host = 0;
+  if (!c->force_valid)
+    return fail(c, P3T_ERR_STATE, "hard_evaluate: no neighbour pairs (call p3t_compute_soft_force)");
+  const int64_t n = c->n;
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out_hard, n) || bad_ptr(r_out, n) ||
+      bad_ptr(r_search, n) || bad_ptr(acc3, n))
+    return fail(c, P3T_ERR_ARG, "hard_evaluate: null pointer");
+  c->stats.n_slow = 0;
+  c->stats.ms_direct = 0.0;
+  if (n == 0) return p3t_evaluate(c, 0, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
+  const bool split = slow_log2 > 0 && dt_hard != nullptr;
+  p3t_status st;
+  if (split && (st = ensure_overlap(c)) != P3T_OK) return st;
+  ev_record(c, 9);
+  HIP_OK(c, build_csr(c, n, c->n_pairs));
+  HIP_OK(c, labels_cc(c, n, c->hs_label));
+  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  int32_t hc[HERM_BC_WORDS];
+  hipError_t e = herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, split ? dt_hard : nullptr,
+                             split ? slow_log2 : 0, hc);
+  if (n_clusters_host) *n_clusters_host = hc[HERM_BC_NC];
+  if (e == hipErrorInvalidValue)
+    return fail(c, P3T_ERR_CLUSTER, "hard_evaluate: a cluster exceeds 1024 members (percolation)");
+  HIP_OK(c, e);
+  HIP_OK(c, aux_streams(c));
+  const int ns = split ? hc[HERM_BC_SLOW] : 0;
+  if (ns > 0) {
+    // the slow clusters integrate copies of the state on their own stream
+    HIP_OK(c, hipMemcpyAsync(c->sh_pos, pos3, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->sh_vel, vel3, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
+    HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
+    HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->sh_pos, c->sh_vel, mass, r_out_hard, dt_hard,
+                          nullptr, nullptr, hc, 1, c->slow_stream, c->slow_stream, nullptr, nullptr));
+    HIP_OK(c, hipEventRecord(c->slow_ev[1], c->slow_stream));
+  }
+  HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
+                        hc, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
+  ev_record(c, 10);
+  if (!split) {
+    st = p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
+    if (c->timing) c->stats.ms_hermite = ev_ms(c, 9, 10);
+    return st;
+  }
+  // everyone else: tree, walk and force at the new state, S massless (with
+  // S empty too, so that a captured evaluation keeps its arguments)
+  HIP_OK(c, slow_prepare(c, mass, ns));
+  c->slow_active = 1;
+  st = p3t_evaluate(c, n, pos3, vel3, c->m_eff, r_out, r_search, acc3, use_graph);
+  c->slow_active = 0;
+  // join; S's new state goes back into pos3 / vel3 inside slow_direct
+  if (ns > 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slow_ev[1], 0));
+  ev_record(c, 15);
+  if (ns > 0) HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, acc3, ns));
+  if (st != P3T_OK && st != P3T_ERR_NUMERIC) {
+    // the state is still that of p3t_hard_step; the force is not
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->force_valid = false;
+    return st;
+  }
+  const p3t_status st_eval = st;  // P3T_ERR_NUMERIC: flagged, but complete
+  ev_record(c, 16);
+  DevCounters h;
+  if ((st = sync_counters(c, &h)) != P3T_OK) return st;
+  if (c->timing) {
+    c->stats.ms_hermite = ev_ms(c, 9, 10);
+    c->stats.ms_direct = ev_ms(c, 15, 16);
+  }
+  c->stats.n_slow = ns;
+  if (n_slow_host) *n_slow_host = ns;
+  if (h.status & RETRY_BITS) {
+    // the direct pairs did not fit: grow, and evaluate again at the final state
+    if ((st = grow_for_retry(c, h)) != P3T_OK) return st;
+    return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, 0);
+  }
+  c->n_pairs = (int64_t)h.n_pairs;
+  c->stats.n_pairs = c->n_pairs;
+  const unsigned num = h.status & NUMERIC_BITS;
+  c->host_status |= h.status;
+  if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
+  if (num)
+    return fail(c, P3T_ERR_NUMERIC, "hard_evaluate: device status 0x%x (coincident particles or NaN)", num);
+  return st_eval;
 }
 
 p3t_status p3t_soft_force_frozen(p3t_ctx *c, const double *pos3, const double *mass, double *acc3) {

@@ -127,7 +127,8 @@ __global__ __launch_bounds__(WAVE) void k_force(ForceArgs A) {
           const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
           const double r2 = dx * dx + dy * dy + dz * dz;
           const double rr = fmax(reachi[s], reachj);
-          if (ii[s] >= 0 && jidx != ii[s] && r2 <= rr * rr * (1.0 + 1e-12)) {
+          if (ii[s] >= 0 && jidx != ii[s] && r2 <= rr * rr * (1.0 + 1e-12) &&
+              !(A.slow && (A.slow[A.sid[ii[s]]] | A.slow[A.sid[jidx]]))) {
             const int i = ii[s], j = jidx;
             if (pair_is_neighbour(A.sx[i], A.sy[i], A.sz[i], A.svx[i], A.svy[i], A.svz[i], A.sm[i], A.sro[i],
                                   A.srs[i], A.sx[j], A.sy[j], A.sz[j], A.svx[j], A.svy[j], A.svz[j], A.sm[j],
@@ -395,6 +396,7 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3, bool froze
   A.pair_cap = c->pair_cap;
   A.cands = c->cands;
   A.cand_cap = c->cand_cap;
+  A.slow = c->slow_active ? c->slow_flag : nullptr;
   if (frozen) A.pair_cap = A.cand_cap = 0;
   A.acc = acc3;
   A.n = c->n;

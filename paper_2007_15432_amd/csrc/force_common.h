@@ -17,6 +17,7 @@ struct ForceArgs {
   int2 *pairs;
   int64_t pair_cap;
   int2 *cands;  // neighbour candidates (sorted indices), split form
+  const uint8_t *slow;  // caller's order: pairs with a flagged member are not reported (nullable)
   int64_t cand_cap;
   double *acc;
   int64_t n;

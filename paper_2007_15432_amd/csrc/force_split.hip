@@ -546,8 +546,11 @@ __global__ void k_cand_test(ForceArgs A) {
       const int2 c = A.cands[p];
       i = c.x;
       j = c.y;
-      if (A.sx[i] == A.sx[j] && A.sy[i] == A.sy[j] && A.sz[i] == A.sz[j]) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
-      nb = neighbour_test(A.sx[i], A.sy[i], A.sz[i], A.svx[i], A.svy[i], A.svz[i], A.sm[i], A.sro[i], A.srs[i],
+      // a slow member sits at its pre-drift position here; its pairs are
+      // tested once its integration has finished
+      const bool skip = A.slow && (A.slow[A.sid[i]] | A.slow[A.sid[j]]);
+      if (!skip && A.sx[i] == A.sx[j] && A.sy[i] == A.sy[j] && A.sz[i] == A.sz[j]) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
+      nb = !skip && neighbour_test(A.sx[i], A.sy[i], A.sz[i], A.svx[i], A.svy[i], A.svz[i], A.sm[i], A.sro[i], A.srs[i],
                           A.sx[j], A.sy[j], A.sz[j], A.svx[j], A.svy[j], A.svz[j], A.sm[j], A.sro[j], A.srs[j], A.G,
                           A.rsch2, A.rsch3, A.dt);
     }

@@ -26,7 +26,8 @@ namespace p3t {
 
 constexpr int TICK_BITS = 40;
 constexpr int BIG_T = 256;
-constexpr int N_BUCKETS = 11;  // SEG 1..64 (7), 256-thread MPT 1, 2, 4 (3), too big (1)
+constexpr int N_BUCKETS = HERM_N_BUCKETS;  // SEG 1..64 (7), 256-thread MPT 1, 2, 4 (3), too big (1)
+constexpr int BC_NC = HERM_BC_NC, BC_BAD = HERM_BC_BAD, BC_SLOW = HERM_BC_SLOW, BC_WORDS = HERM_BC_WORDS;
 
 struct HermArgs {
   const int32_t *cl_ptr, *members, *blists;
@@ -374,6 +375,11 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
       L.pvy[me] = vp[1];
       L.pvz[me] = vp[2];
     }
+    // the star's term needs only the own predicted state: computed while the
+    // exchange through LDS is in flight (one wavefront runs this chain alone,
+    // so independent work is what hides the FP64 latency)
+    double a1[3], j1[3];
+    star_term(xp, vp, GM, a1, j1);
     wave_sync();
 #pragma unroll
     for (int d = 0; d < 3; ++d) pa[d] = pj[d] = 0.0;
@@ -393,8 +399,6 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
       }
     }
     if (active) {
-      double a1[3], j1[3];
-      star_term(xp, vp, GM, a1, j1);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         a1[d] += pa[d];
@@ -761,7 +765,7 @@ __device__ __forceinline__ int bucket_of(int size) {
 
 // Bucket the clusters by size with one atomic per bucket per wavefront; also
 // validate the caller's cluster arrays (offsets non-decreasing from >= 0,
-// members in [0, n)); a violation sets bcount[15] and nothing is integrated.
+// members in [0, n)); a violation sets bcount[BC_BAD] and nothing is integrated.
 // Bucket lists.  Each workgroup owns a contiguous range of clusters: it
 // counts its clusters per bucket in LDS, reserves its share of every bucket
 // with one global atomic per bucket, then writes the entries in cluster
@@ -776,45 +780,103 @@ __device__ __forceinline__ int cluster_bucket(int64_t c, int64_t n, const int32_
     ok = g >= 0 && (int64_t)g < n;
   }
   if (!ok) {
-    atomicOr(&bcount[15], 1);
+    atomicOr(&bcount[BC_BAD], 1);
     return -1;
   }
   return b > a ? bucket_of(b - a) : -1;
 }
 
-__global__ __launch_bounds__(256) void k_herm_bucket(int64_t nc_host, const int64_t *__restrict__ nc_dev,
-                                                     int64_t stride, int64_t n, const int32_t *__restrict__ cl_ptr,
-                                                     const int32_t *__restrict__ members, int32_t *__restrict__ bcount,
-                                                     int32_t *__restrict__ blists) {
-  __shared__ int cnt[N_BUCKETS], base[N_BUCKETS];
+// Slow split (optional): a cluster whose members carry hard steps of
+// dt_soft 2^-k with k >= slow_log2 (it will take >= 2^slow_log2 block steps)
+// goes to bucket + N_BUCKETS as long as its members still fit in SLOW_CAP;
+// its members are listed in slow_list and flagged in slow_flag, its index
+// goes to slow_blists (stride SLOW_CAP) instead of blists (stride `stride`).
+struct BucketArgs {
+  int64_t nc_host;
+  const int64_t *nc_dev;
+  int64_t stride, n;
+  const int32_t *cl_ptr, *members;
+  int32_t *bcount, *blists, *slow_blists;
+  int32_t *cl_bk;                // bucket chosen per cluster (between the sweeps)
+  const double *dt_hard;         // carried hard steps, nullable
+  double dt_soft;
+  int slow_log2;                 // <= 0: no split
+  uint8_t *slow_flag;            // written for every member when slow_log2 > 0
+  int32_t *slow_list;            // SLOW_CAP entries
+};
+
+// reserve k slots of a capped counter; false (nothing reserved) if they do
+// not fit.  Each failed exchange means another reservation went through, and
+// the counter never passes the cap, so the loop ends.
+__device__ __forceinline__ bool reserve_capped(int32_t *ctr, int k, int cap, int &at) {
+  int old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (old + k <= cap) {
+    const int prev = atomicCAS(ctr, old, old + k);
+    if (prev == old) {
+      at = old;
+      return true;
+    }
+    old = prev;
+  }
+  return false;
+}
+
+__device__ __forceinline__ int slow_level(int a, int b, const BucketArgs &B) {
+  int lv = 0;
+  for (int k = a; k < b; ++k) {
+    const double d = B.dt_hard[B.members[k]];
+    if (d > 0.0) {
+      const int l = ilogb(B.dt_soft) - ilogb(d);
+      lv = l > lv ? l : lv;
+    }
+  }
+  return lv;
+}
+
+__global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
+  __shared__ int cnt[2 * N_BUCKETS], base[2 * N_BUCKETS];
+  constexpr int NB2 = 2 * N_BUCKETS;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
-  const int64_t nc = nc_dev ? *nc_dev : nc_host;  // clusters (at most stride)
-  if (blockIdx.x == 0 && tid == 0) bcount[14] = (int32_t)nc;
+  const int64_t nc = B.nc_dev ? *B.nc_dev : B.nc_host;  // clusters (at most stride)
+  int32_t *bcount = B.bcount;
+  if (blockIdx.x == 0 && tid == 0) bcount[BC_NC] = (int32_t)nc;
   const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
-  if (tid < N_BUCKETS) cnt[tid] = 0;
+  if (tid < NB2) cnt[tid] = 0;
   __syncthreads();
   for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {
     const int64_t c = b0 + tid;
-    const int bk = c < c1 ? cluster_bucket(c, n, cl_ptr, members, bcount) : -1;
-    for (int q = 0; q < N_BUCKETS; ++q) {
+    int bk = c < c1 ? cluster_bucket(c, B.n, B.cl_ptr, B.members, bcount) : -1;
+    if (bk >= 0 && B.slow_log2 > 0) {
+      const int a = B.cl_ptr[c], b = B.cl_ptr[c + 1];
+      int at = 0;
+      const bool slow = B.dt_hard && slow_level(a, b, B) >= B.slow_log2 &&
+                        reserve_capped(&bcount[BC_SLOW], b - a, SLOW_CAP, at);
+      if (slow) {
+        bk += N_BUCKETS;
+        for (int k = a; k < b; ++k) B.slow_list[at + k - a] = B.members[k];
+      }
+      for (int k = a; k < b; ++k) B.slow_flag[B.members[k]] = slow ? 1 : 0;
+    }
+    if (c < c1) B.cl_bk[c] = bk;
+    for (int q = 0; q < NB2; ++q) {
       const unsigned long long mask = __ballot(bk == q);
       if (mask != 0ull && lane == __ffsll((long long)mask) - 1) atomicAdd(&cnt[q], (int)__popcll(mask));
     }
   }
   __syncthreads();
-  if (tid < N_BUCKETS) {
+  if (tid < NB2) {
     base[tid] = cnt[tid] > 0 ? atomicAdd(&bcount[tid], cnt[tid]) : 0;
     cnt[tid] = 0;
   }
   __syncthreads();
-  __shared__ int wofs[BIG_T / WAVE][N_BUCKETS];
+  __shared__ int wofs[BIG_T / WAVE][NB2];
   const int w = tid / WAVE;
   for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {  // uniform over the workgroup
     const int64_t c = b0 + tid;
-    const int bk = c < c1 ? cluster_bucket(c, n, cl_ptr, members, bcount) : -1;  // as counted above
+    const int bk = c < c1 ? B.cl_bk[c] : -1;  // as decided above
     unsigned long long mine = 0ull;
-    for (int q = 0; q < N_BUCKETS; ++q) {
+    for (int q = 0; q < NB2; ++q) {
       const unsigned long long mask = __ballot(bk == q);
       if (lane == 0) wofs[w][q] = (int)__popcll(mask);
       if (q == bk) mine = mask;
@@ -823,10 +885,12 @@ __global__ __launch_bounds__(256) void k_herm_bucket(int64_t nc_host, const int6
     if (bk >= 0) {
       int off = 0;
       for (int u = 0; u < w; ++u) off += wofs[u][bk];  // wavefronts take their slots in order
-      blists[(int64_t)bk * stride + base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
+      int32_t *dst = bk < N_BUCKETS ? B.blists + (int64_t)bk * B.stride
+                                    : B.slow_blists + (int64_t)(bk - N_BUCKETS) * SLOW_CAP;
+      dst[base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
     }
     __syncthreads();
-    if (tid < N_BUCKETS) {
+    if (tid < NB2) {
       int tot = 0;
       for (int u = 0; u < BIG_T / WAVE; ++u) tot += wofs[u][tid];
       cnt[tid] += tot;
@@ -854,30 +918,55 @@ static void host_changeover_coeffs(double g, HermArgs &A) {
   A.wf1 = f1;
 }
 
-hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
-                            double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
-                            double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev, int64_t *nc_out) {
+// Bucket lists and counts (one host synchronisation); hc receives
+// BC_WORDS words.  slow_log2 > 0 splits off the slow clusters (see
+// k_herm_bucket).
+hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
+                       const int64_t *nc_dev, const double *dt_hard, int slow_log2, int32_t *hc) {
   hipStream_t s = c->stream;
   hipError_t e;
-  if (nc_out) *nc_out = 0;
-  if (nc <= 0) return hipSuccess;  // with nc_dev, nc is an upper bound (the particle count)
-  int32_t *bcount = c->herm_bcount;
-  int32_t *blists = c->herm_blists;
-  if ((e = fill_i32(bcount, 0, 16, s)) != hipSuccess) return e;
+  if ((e = fill_i32(c->herm_bcount, 0, BC_WORDS, s)) != hipSuccess) return e;
+  BucketArgs B;
+  B.nc_host = nc;
+  B.nc_dev = nc_dev;
+  B.stride = nc;
+  B.n = n;
+  B.cl_ptr = cl_ptr;
+  B.members = cl_members;
+  B.bcount = c->herm_bcount;
+  B.blists = c->herm_blists;
+  B.slow_blists = c->slow_blists;
+  B.cl_bk = c->herm_clbk;
+  B.dt_hard = dt_hard;
+  B.dt_soft = c->P.dt_soft;
+  B.slow_log2 = slow_log2 > 0 && c->slow_list ? slow_log2 : 0;
+  B.slow_flag = c->slow_flag;
+  B.slow_list = c->slow_list;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
-  hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, nc, nc_dev, nc, n, cl_ptr, cl_members, bcount, blists);
-  int32_t hc[16];
-  if ((e = hipMemcpyAsync(hc, bcount, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, B);
+  if ((e = hipMemcpyAsync(hc, c->herm_bcount, sizeof(int32_t) * BC_WORDS, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  if (nc_out) *nc_out = hc[14];
-  if (hc[15]) return hipErrorInvalidDevicePointer;  // malformed cluster arrays
-  if (hc[10] > 0) return hipErrorInvalidValue;       // cluster above the largest supported size
+  if (hc[BC_BAD]) return hipErrorInvalidDevicePointer;                 // malformed cluster arrays
+  if (hc[10] > 0 || hc[10 + N_BUCKETS] > 0) return hipErrorInvalidValue;  // a cluster above 1024 members
+  return hipSuccess;
+}
+
+// Integrates the clusters of one bucket set (set 0: the ordinary buckets,
+// set 1: the slow ones) on stream s; clusters of 65 members and more go to
+// stream s_big (which may be s), joined back into s at the end.
+hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
+                       double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
+                       double *e_rel_err, int32_t *n_steps, const int32_t *hc, int set, hipStream_t s,
+                       hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join) {
+  hipError_t e;
   const p3t_params &P = c->P;
+  const int o = set * N_BUCKETS;
   HermArgs A;
   A.cl_ptr = cl_ptr;
   A.members = cl_members;
-  A.blists = blists;
-  A.nc = nc;
+  A.blists = set == 0 ? c->herm_blists : c->slow_blists;
+  A.nc = set == 0 ? stride : SLOW_CAP;
   A.pos = pos3;
   A.vel = vel3;
   A.mass = mass;
@@ -907,38 +996,58 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   A.max_iter = 1 << 22;
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
-  for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = hc[bk];
+  for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = hc[o + bk];
   // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG /
   // lanes per member); the clusters of 65 members and more run at the same
-  // time in their own launches on a second stream (one workgroup each)
+  // time in their own launches (one workgroup each)
   int blocks = 0;
   for (int bk = 0; bk < 7; ++bk) {
     A.boff[bk] = blocks;
     const int per_block = (BIG_T / WAVE) * (WAVE >> (bk + lanes_per_member_log2(bk)));
-    blocks += (hc[bk] + per_block - 1) / per_block;
+    blocks += (A.bcount[bk] + per_block - 1) / per_block;
   }
   for (int bk = 7; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
-  const bool big = hc[7] > 0 || hc[8] > 0 || hc[9] > 0;
+  const bool big = A.bcount[7] > 0 || A.bcount[8] > 0 || A.bcount[9] > 0;
   hipStream_t s2 = s;
-  if (big && blocks > 0) {
-    if (!c->aux_stream && (e = hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking)) != hipSuccess) return e;
-    if (!c->aux_ev[0]) {
-      for (auto &ev : c->aux_ev)
-        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
-    }
-    s2 = c->aux_stream;
-    if ((e = hipEventRecord(c->aux_ev[0], s)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s2, c->aux_ev[0], 0)) != hipSuccess) return e;
+  if (big && blocks > 0 && s_big != s) {
+    s2 = s_big;
+    if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s2, ev_fork, 0)) != hipSuccess) return e;
   }
-  if (hc[7] > 0) hipLaunchKernelGGL(k_herm_big<1>, dim3(hc[7]), dim3(BIG_T), 0, s2, A, 7);
-  if (hc[8] > 0) hipLaunchKernelGGL(k_herm_big<2>, dim3(hc[8]), dim3(BIG_T), 0, s2, A, 8);
-  if (hc[9] > 0) hipLaunchKernelGGL(k_herm_big<4>, dim3(hc[9]), dim3(BIG_T), 0, s2, A, 9);
+  if (A.bcount[7] > 0) hipLaunchKernelGGL(k_herm_big<1>, dim3(A.bcount[7]), dim3(BIG_T), 0, s2, A, 7);
+  if (A.bcount[8] > 0) hipLaunchKernelGGL(k_herm_big<2>, dim3(A.bcount[8]), dim3(BIG_T), 0, s2, A, 8);
+  if (A.bcount[9] > 0) hipLaunchKernelGGL(k_herm_big<4>, dim3(A.bcount[9]), dim3(BIG_T), 0, s2, A, 9);
   if (blocks > 0) hipLaunchKernelGGL(k_herm_fused, dim3(blocks), dim3(BIG_T), 0, s, A);
   if (s2 != s) {  // join
-    if ((e = hipEventRecord(c->aux_ev[1], s2)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, c->aux_ev[1], 0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_join, s2)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, ev_join, 0)) != hipSuccess) return e;
   }
   return hipGetLastError();
+}
+
+hipError_t aux_streams(p3t_ctx *c) {
+  hipError_t e;
+  if (!c->aux_stream && (e = hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+  if (!c->slow_stream && (e = hipStreamCreateWithFlags(&c->slow_stream, hipStreamNonBlocking)) != hipSuccess)
+    return e;
+  if (!c->aux_ev[0])
+    for (auto &ev : c->aux_ev)
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
+                            double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
+                            double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev, int64_t *nc_out) {
+  if (nc_out) *nc_out = 0;
+  if (nc <= 0) return hipSuccess;  // with nc_dev, nc is an upper bound (the particle count)
+  int32_t hc[BC_WORDS];
+  hipError_t e = herm_bucket(c, n, nc, cl_ptr, cl_members, nc_dev, nullptr, 0, hc);
+  if (nc_out) *nc_out = hc[BC_NC];
+  if (e != hipSuccess) return e;
+  if ((e = aux_streams(c)) != hipSuccess) return e;
+  return herm_launch(c, n, nc, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps, hc, 0,
+                     c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]);
 }
 
 }  // namespace p3t

@@ -1,0 +1,273 @@
+// slow.hip -- the soft interactions of the members of slow clusters, summed
+// directly once their Hermite integration has finished.
+//
+// p3t_hard_evaluate integrates the clusters that will take many block steps
+// (the set S of their members) on a second stream, on copies of the state,
+// while the tree of the other particles is built, walked and evaluated at
+// the post-drift state.  In that tree the members of S carry zero mass
+// (their pre-drift positions only shape the boxes), and the force kernels
+// report no neighbour pair that involves them.  After the join:
+//   - the copies of S's positions and velocities go back into the state;
+//   - every particle i outside S adds sum_{s in S} of the soft pair term of
+//     Section 2.2 (eq. of the P3T split, changeover K at the larger cut-off),
+//     and every (i, s) that passes the neighbour test of Section 2.3 is
+//     reported in both directions;
+//   - every s in S gets sum_{j != s} over all particles, directly (partial
+//     sums over SLOW_CHUNKS ranges of j, added in order), and the pairs
+//     (s, s') with s' in S are reported from both sides.
+// Sums are in FP64 and in a fixed order, so the result is reproducible; the
+// pairs arrive in any order (the CSR build sorts every row).
+#include "force_common.h"
+
+namespace p3t {
+
+namespace {
+
+constexpr double kTinyR2s = 1e-150;  // r = 0 gives y ~ 0 < gamma: K = 0, the term vanishes
+
+struct SoftPair {
+  double G, gamma, inv1mg;
+};
+
+// soft pair term: G m_j K(r / max(r_out,i, r_out,j)) (x_j - x_i) / r^3
+__device__ __forceinline__ void soft_term(const SoftPair &P, double dx, double dy, double dz, double gm, double invi,
+                                          double invj, double &ax, double &ay, double &az) {
+  const double r2s = fmax(dx * dx + dy * dy + dz * dz, kTinyR2s);
+  const double rinv = rsqrt(r2s);
+  const double y = r2s * rinv * fmin(invi, invj);
+  const double x = fmin(fmax((y - P.gamma) * P.inv1mg, 0.0), 1.0);
+  const double x2 = x * x;
+  const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+  const double f = gm * K * rinv * rinv * rinv;
+  ax += f * dx;
+  ay += f * dy;
+  az += f * dz;
+}
+
+__device__ __forceinline__ void push_pair(DevCounters *cnt, int2 *pairs, int64_t cap, int a, int b) {
+  const unsigned long long q = atomicAdd(&cnt->n_pairs, 1ull);
+  if ((int64_t)q < cap)
+    pairs[q] = make_int2(a, b);
+  else
+    set_flag(cnt, P3T_FLAG_PAIR_OVERFLOW);
+}
+
+struct SlowArgs {
+  const double *pos, *vel, *mass, *ro, *rs;
+  const uint8_t *slow;
+  const int32_t *list;
+  int ns;
+  int64_t n;
+  double *acc;
+  double *part;
+  DevCounters *cnt;
+  int2 *pairs;
+  int64_t pair_cap;
+  SoftPair P;
+  double rsch2, rsch3, dt;
+};
+
+constexpr int ST = 256;  // threads per block of the direct kernels
+
+// bitonic sort of the slow list (at most SLOW_CAP entries) in one workgroup,
+// so that the direct sums run in ascending member order
+__global__ __launch_bounds__(SLOW_CAP) void k_sort_list(int32_t *a, int n) {
+  __shared__ int32_t v[SLOW_CAP];
+  const int t = threadIdx.x;
+  v[t] = t < n ? a[t] : 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= SLOW_CAP; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int p = t ^ j;
+      if (p > t) {
+        const bool up = (t & k) == 0;
+        const int x = v[t], y = v[p];
+        if ((x > y) == up) {
+          v[t] = y;
+          v[p] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (t < n) a[t] = v[t];
+}
+
+__global__ void k_mask_mass(int64_t n, const double *__restrict__ mass, const uint8_t *__restrict__ slow,
+                            double *__restrict__ m_eff) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m_eff[i] = slow[i] ? 0.0 : mass[i];
+}
+
+__global__ void k_slow_scatter(int64_t n, int ns, const int32_t *__restrict__ list, const double *__restrict__ sp,
+                               const double *__restrict__ sv, double *__restrict__ pos, double *__restrict__ vel) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += gridDim.x * blockDim.x) {
+    const int64_t i = list[s];
+    for (int d = 0; d < 3; ++d) {
+      pos[d * n + i] = sp[d * n + i];
+      vel[d * n + i] = sv[d * n + i];
+    }
+  }
+}
+
+// every particle outside S: add the terms of S, report its pairs with S
+__global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
+  __shared__ double tx[ST], ty[ST], tz[ST], tvx[ST], tvy[ST], tvz[ST], tm[ST], tro[ST], trs[ST], tinv[ST];
+  __shared__ int32_t tid_[ST];
+  const int t = threadIdx.x;
+  const int64_t n = A.n;
+  for (int64_t b0 = (int64_t)blockIdx.x * ST; b0 < n; b0 += (int64_t)gridDim.x * ST) {  // uniform per block
+    const int64_t i = b0 + t;
+    const bool act = i < n && !A.slow[i];
+    const int64_t ic = act ? i : 0;
+    const double xi = A.pos[ic], yi = A.pos[n + ic], zi = A.pos[2 * n + ic];
+    const double vxi = A.vel[ic], vyi = A.vel[n + ic], vzi = A.vel[2 * n + ic];
+    const double mi = A.mass[ic], roi = A.ro[ic], rsi = A.rs[ic], invi = 1.0 / roi;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    bool coincident = false;
+    for (int s0 = 0; s0 < A.ns; s0 += ST) {
+      const int m = min(ST, A.ns - s0);
+      __syncthreads();
+      if (t < m) {
+        const int64_t j = A.list[s0 + t];
+        tx[t] = A.pos[j];
+        ty[t] = A.pos[n + j];
+        tz[t] = A.pos[2 * n + j];
+        tvx[t] = A.vel[j];
+        tvy[t] = A.vel[n + j];
+        tvz[t] = A.vel[2 * n + j];
+        tm[t] = A.mass[j];
+        tro[t] = A.ro[j];
+        tinv[t] = 1.0 / A.ro[j];
+        trs[t] = A.rs[j];
+        tid_[t] = (int32_t)j;
+      }
+      __syncthreads();
+      if (act) {
+        for (int k = 0; k < m; ++k) {
+          soft_term(A.P, tx[k] - xi, ty[k] - yi, tz[k] - zi, A.P.G * tm[k], invi, tinv[k], ax, ay, az);
+          if (tx[k] == xi && ty[k] == yi && tz[k] == zi) coincident = true;
+          if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, tx[k], ty[k], tz[k], tvx[k], tvy[k], tvz[k],
+                             tm[k], tro[k], trs[k], A.P.G, A.rsch2, A.rsch3, A.dt)) {
+            push_pair(A.cnt, A.pairs, A.pair_cap, (int32_t)i, tid_[k]);
+            push_pair(A.cnt, A.pairs, A.pair_cap, tid_[k], (int32_t)i);
+          }
+        }
+      }
+    }
+    if (act) {
+      const double nx = A.acc[i] + ax, ny = A.acc[n + i] + ay, nz = A.acc[2 * n + i] + az;
+      A.acc[i] = nx;
+      A.acc[n + i] = ny;
+      A.acc[2 * n + i] = nz;
+      if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) set_flag(A.cnt, P3T_FLAG_NAN);
+      if (coincident) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
+    }
+  }
+}
+
+// member s of S against the particles of chunk blockIdx.x: partial sums, and
+// the pairs (s, s') with s' in S
+__global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
+  __shared__ double red[3][ST / WAVE];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+  const int s = blockIdx.y;
+  const int64_t n = A.n;
+  const int64_t i = A.list[s];
+  const double xi = A.pos[i], yi = A.pos[n + i], zi = A.pos[2 * n + i];
+  const double vxi = A.vel[i], vyi = A.vel[n + i], vzi = A.vel[2 * n + i];
+  const double mi = A.mass[i], roi = A.ro[i], rsi = A.rs[i], invi = 1.0 / roi;
+  const int64_t chunk = (n + SLOW_CHUNKS - 1) / SLOW_CHUNKS;
+  const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  bool coincident = false;
+  for (int64_t j = j0 + t; j < j1; j += ST) {
+    if (j == i) continue;
+    const double xj = A.pos[j], yj = A.pos[n + j], zj = A.pos[2 * n + j];
+    const double mj = A.mass[j], roj = A.ro[j];
+    soft_term(A.P, xj - xi, yj - yi, zj - zi, A.P.G * mj, invi, 1.0 / roj, ax, ay, az);
+    if (A.slow[j]) {
+      if (xj == xi && yj == yi && zj == zi) coincident = true;
+      if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, xj, yj, zj, A.vel[j], A.vel[n + j], A.vel[2 * n + j],
+                         mj, roj, A.rs[j], A.P.G, A.rsch2, A.rsch3, A.dt))
+        push_pair(A.cnt, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
+    }
+  }
+  if (coincident) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
+  ax = wave_sum(ax);
+  ay = wave_sum(ay);
+  az = wave_sum(az);
+  if (lane == 0) {
+    red[0][w] = ax;
+    red[1][w] = ay;
+    red[2][w] = az;
+  }
+  __syncthreads();
+  if (t < 3) {
+    double v = 0.0;
+    for (int q = 0; q < ST / WAVE; ++q) v += red[t][q];
+    A.part[((int64_t)s * SLOW_CHUNKS + blockIdx.x) * 3 + t] = v;
+  }
+}
+
+__global__ void k_slow_reduce(SlowArgs A) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < A.ns; s += gridDim.x * blockDim.x) {
+    const int64_t i = A.list[s];
+    double a[3];
+    for (int d = 0; d < 3; ++d) {
+      double v = 0.0;
+      for (int p = 0; p < SLOW_CHUNKS; ++p) v += A.part[((int64_t)s * SLOW_CHUNKS + p) * 3 + d];
+      a[d] = v;
+      A.acc[d * A.n + i] = v;
+    }
+    if (!(isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]))) set_flag(A.cnt, P3T_FLAG_NAN);
+  }
+}
+
+}  // namespace
+
+hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns) {
+  hipStream_t s = c->stream;
+  if (ns > 1) hipLaunchKernelGGL(k_sort_list, dim3(1), dim3(SLOW_CAP), 0, s, c->slow_list, ns);
+  const int64_t n = c->n;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256));
+  hipLaunchKernelGGL(k_mask_mass, dim3(g), dim3(256), 0, s, n, mass, (const uint8_t *)c->slow_flag, c->m_eff);
+  return hipGetLastError();
+}
+
+hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const double *mass, const double *r_out,
+                       const double *r_search, double *acc3, int ns) {
+  hipStream_t s = c->stream;
+  const int64_t n = c->n;
+  hipLaunchKernelGGL(k_slow_scatter, dim3((ns + 255) / 256), dim3(256), 0, s, n, ns, (const int32_t *)c->slow_list,
+                     (const double *)c->sh_pos, (const double *)c->sh_vel, const_cast<double *>(pos3),
+                     const_cast<double *>(vel3));
+  SlowArgs A;
+  A.pos = pos3;
+  A.vel = vel3;
+  A.mass = mass;
+  A.ro = r_out;
+  A.rs = r_search;
+  A.slow = c->slow_flag;
+  A.list = c->slow_list;
+  A.ns = ns;
+  A.n = n;
+  A.acc = acc3;
+  A.part = c->slow_part;
+  A.cnt = c->cnt;
+  A.pairs = c->pairs;
+  A.pair_cap = c->pair_cap;
+  A.P.G = c->P.G;
+  A.P.gamma = c->P.gamma;
+  A.P.inv1mg = 1.0 / (1.0 - c->P.gamma);
+  A.rsch2 = c->P.r_search2;
+  A.rsch3 = c->P.r_search3;
+  A.dt = c->P.dt_soft;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + ST - 1) / ST));
+  hipLaunchKernelGGL(k_slow_into, dim3(g), dim3(ST), 0, s, A);
+  hipLaunchKernelGGL(k_slow_from, dim3(SLOW_CHUNKS, ns), dim3(ST), 0, s, A);
+  hipLaunchKernelGGL(k_slow_reduce, dim3((ns + 255) / 256), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+}  // namespace p3t

@@ -13,6 +13,15 @@ libp3t's kernels.
 The cut-off radii are fixed between collisions (Section 2.4: they are
 recomputed after a merger); `recompute_cutoffs` recomputes them every step
 instead (used to time the cut-off stage as part of the step).
+
+overlap=True runs (4)-(7) as one p3t_hard_evaluate call: clusters whose
+members took hard steps of dt_soft 2^-slow_log2 or less in their last
+integration run on a second stream while the tree of everyone else is
+evaluated, and their soft terms are summed directly afterwards.  With
+recompute_cutoffs the evaluation of step k then uses the radii computed from
+the state of evaluation k-1 (the hard part of step k still uses the radii of
+evaluation k-1, as the P3T split requires): the radii lag one step, because
+the slow members' new state is not known when the tree is built.
 """
 from __future__ import annotations
 
@@ -27,10 +36,13 @@ class P3TStepper:
     acceleration live in fixed buffers)."""
 
     def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False, graph: bool = False,
-                 fused_hard: bool = True):
+                 fused_hard: bool = True, overlap: bool = False, slow_log2: int = 7):
         self.ctx = ctx
         self.graph = graph
         self.fused_hard = fused_hard
+        self.overlap = overlap
+        self.slow_log2 = slow_log2
+        self.n_slow = 0
         self.pos, self.vel, self.mass = pos, vel, mass
         self.n = int(mass.shape[0])
         self.dt = ctx.params.dt_soft
@@ -40,6 +52,11 @@ class P3TStepper:
         self.acc = torch.empty((3, self.n), dtype=torch.float64, device=pos.device)
         self.n_clusters = 0
         self._evaluate()
+        # radii of the next evaluation (the same buffers unless they lag)
+        self.r_out_next, self.r_search_next = self.r_out, self.r_search
+        if overlap and recompute_cutoffs:
+            self.r_out_next, self.r_search_next = self.r_out.clone(), self.r_search.clone()
+            self.v_ran_next = self.v_ran.clone()
 
     def _evaluate(self):
         c = self.ctx
@@ -59,6 +76,20 @@ class P3TStepper:
     def step(self):
         c = self.ctx
         c.kick(self.acc, self.vel, 0.5 * self.dt)
+        if self.overlap:
+            _, self.n_clusters, self.n_slow = c.hard_evaluate(
+                self.pos, self.vel, self.mass, self.r_out, self.dt_hard, self.r_out_next, self.r_search_next,
+                out=self.acc, slow_log2=self.slow_log2, graph=self.graph)
+            if self.recompute:
+                # the radii just used become those of the next hard part;
+                # the next evaluation's come from the state at hand
+                self.r_out.copy_(self.r_out_next)
+                self.r_search.copy_(self.r_search_next)
+                self.v_ran.copy_(self.v_ran_next)
+                c.compute_cutoffs(self.pos, self.vel, self.mass,
+                                  out=(self.r_out_next, self.r_search_next, self.v_ran_next))
+            c.kick(self.acc, self.vel, 0.5 * self.dt)
+            return
         if self.fused_hard:
             self.n_clusters = c.hard_step(self.pos, self.vel, self.mass, self.r_out, dt_hard=self.dt_hard)
         else:
