@@ -101,6 +101,8 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     out["kernels"] = ks
     out["_acc0"] = acc0.cpu().numpy()
     out["_r_out0"] = r_out0.cpu().numpy()
+    if overlap:  # the last overlapped evaluation, for its own error
+        out["_final"] = (st.pos.cpu().numpy(), st.acc.cpu().numpy(), st.r_out.cpu().numpy())
     ctx.close()
     return out
 
@@ -207,6 +209,19 @@ def cpu_baseline(disk, results, sample, seed=33):
         den = (ref ** 2).sum(0)
         errs[name] = dict(eps_rms=float(np.sqrt(np.mean(num / den))), eps_global=float(np.sqrt(num.sum() / den.sum())),
                           eps_max=float(np.sqrt((num / den).max())))
+    for name, r in results.items():
+        if "_final" not in r:
+            continue
+        # the overlapped evaluation after the timed steps (slow members' terms
+        # exact), on a smaller sample at that state
+        pos_f, acc_f, ro_f = r["_final"]
+        idx_f = diskgen.sample_indices(disk.n, 2048, seed + 1)
+        ref_f = oracle.soft_acc(pos_f, disk.mass, ro_f, p, idx=idx_f)
+        a = acc_f[:, idx_f]
+        num = ((a - ref_f) ** 2).sum(0)
+        den = (ref_f ** 2).sum(0)
+        errs[name]["after_steps"] = dict(eps_rms=float(np.sqrt(np.mean(num / den))),
+                                         eps_global=float(np.sqrt(num.sum() / den.sum())), sample=len(idx_f))
     base = dict(value=len(idx) * (disk.n - 1) / dt, unit="interactions/s", cores=oracle.num_threads(), kind="oracle",
                 sample=f"{len(idx)} i-particles (seed {seed}) x all {disk.n} j, direct FP64 sum, {dt:.1f} s")
     return base, errs

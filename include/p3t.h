@@ -207,36 +207,38 @@ p3t_status p3t_evaluate(p3t_ctx *ctx, int64_t n, const double *pos3, const doubl
                         const double *r_out, const double *r_search, double *acc3, int32_t use_graph);
 
 /* p3t_hard_step followed by p3t_evaluate (Section 2.2, steps (4)-(7)), with
- * the clusters that will run long taken off the critical path.  A cluster is
- * slow when one of its members carries a hard step dt_hard <= dt_soft *
- * 2^-slow_log2 from its last integration (it will take about 2^slow_log2
- * block steps or more); the members of slow clusters, at most 1024 in one
- * call (clusters that do not fit stay in the ordinary set), form S.  The slow
- * clusters integrate on a second stream into copies of the state while the
- * others integrate in place and the tree, walk and soft force of Section 2.2
- * run at the new state with the members of S given zero mass; after both
- * finish, the copies go back into pos3 and vel3 and the soft terms between S
- * and every particle (eq. (softforce) with the changeover at the pair
- * cut-off, eq. (rout2)) are summed directly in FP64, with the neighbour test
- * of Section 2.3 for every pair that involves S.
+ * the long-running clusters taken off the critical path.  Every cluster of
+ * 1..64 members that is still running after 2^slow_log2 block steps saves
+ * its block-step state and stops ("parks"), as long as the parked members
+ * fit in 1024 (the others run to the end); the parked members form S.  The
+ * parked clusters then finish on a second stream, continuing exactly where
+ * they stopped, while the tree, walk and soft force of Section 2.2 run at
+ * the new state with the members of S given zero mass; after both finish,
+ * S's final positions and velocities go into pos3 and vel3 and the soft
+ * terms between S and every particle (eq. (softforce) with the changeover
+ * at the pair cut-off, eq. (rout2)) are summed directly in FP64, with the
+ * neighbour test of Section 2.3 for every pair that involves S.
  *   pos3, vel3 (3n, in/out), mass (n): as for p3t_hard_step; the state
  *     after the call is the one p3t_hard_step leaves, bit for bit.
  *   r_out_hard (n): the cut-offs of the hard part (those of the evaluation
  *     whose pairs form the clusters); r_out, r_search (n): those of the new
  *     evaluation (they may be the same arrays).
- *   dt_hard (n, in/out, nullable): carried hard steps, as for p3t_hard_step;
- *     NULL or slow_log2 <= 0 disables the split.
+ *   dt_hard (n, in/out, nullable): carried hard steps, as for p3t_hard_step.
+ *   steps (n, int32, out, nullable): block steps taken by each particle's
+ *     cluster.
  *   acc3 (3n, out): the soft acceleration at the new state.  The neighbour
  *     pairs (p3t_neighbour_list) equal those of p3t_evaluate bit for bit; the
  *     forces differ from it only in that the terms involving S are exact
  *     rather than tree terms.
+ *   slow_log2 <= 0: no budget, exactly p3t_hard_step + p3t_evaluate.
  *   use_graph: as for p3t_evaluate.  *n_clusters_host, *n_slow_host
  *     (nullable) receive the cluster count and |S|.
  * Errors as p3t_hard_step and p3t_evaluate; the state is advanced whenever
  * the hard part succeeded.  n is that of the last evaluation. */
 p3t_status p3t_hard_evaluate(p3t_ctx *ctx, double *pos3, double *vel3, const double *mass, const double *r_out_hard,
-                             double *dt_hard, const double *r_out, const double *r_search, double *acc3,
-                             int32_t slow_log2, int32_t use_graph, int64_t *n_clusters_host, int64_t *n_slow_host);
+                             double *dt_hard, int32_t *steps, const double *r_out, const double *r_search,
+                             double *acc3, int32_t slow_log2, int32_t use_graph, int64_t *n_clusters_host,
+                             int64_t *n_slow_host);
 
 /* Soft force over the CURRENT tree topology and interaction lists at new
  * positions pos3 (3n) and masses mass (n), in the caller's order, with the

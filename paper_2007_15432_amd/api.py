@@ -230,12 +230,13 @@ class Context:
                                          C.byref(nc)), "hard_step")
         return int(nc.value)
 
-    def hard_evaluate(self, pos, vel, mass, r_out_hard, dt_hard, r_out, r_search, out=None, slow_log2: int = 7,
-                      graph: bool = True):
-        """hard_step then evaluate in one call, the slow clusters (members
-        with dt_hard <= dt_soft 2^-slow_log2) integrating on a second stream
-        while the tree of the others is evaluated; their soft terms are then
-        summed directly.  Returns (acc (3, n), clusters, slow members)."""
+    def hard_evaluate(self, pos, vel, mass, r_out_hard, dt_hard, steps, r_out, r_search, out=None,
+                      slow_log2: int = 9, graph: bool = True):
+        """hard_step then evaluate in one call.  Clusters still running after
+        2^slow_log2 block steps park and finish on a second stream while the
+        tree of the others is evaluated; their soft terms are then summed
+        directly.  `steps` (int32, nullable) receives each particle's cluster
+        step count.  Returns (acc (3, n), clusters, parked members)."""
         n = self.n
         for a, nm in ((pos, "pos"), (vel, "vel")):
             self._vec3(a, n, nm)
@@ -243,13 +244,16 @@ class Context:
             self._vec(a, n, nm)
         if dt_hard is not None:
             self._vec(dt_hard, n, "dt_hard")
+        if steps is not None:
+            self._vec(steps, n, "steps", dtype=torch.int32)
         acc = out if out is not None else torch.empty((3, n), dtype=torch.float64, device=self.device)
         self._vec3(acc, n, "acc")
         nc, ns = C.c_int64(0), C.c_int64(0)
         self._bind()
         self._check(self.L.p3t_hard_evaluate(self._h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(r_out_hard),
-                                             _ptr(dt_hard), _ptr(r_out), _ptr(r_search), _ptr(acc), int(slow_log2),
-                                             1 if graph else 0, C.byref(nc), C.byref(ns)), "hard_evaluate")
+                                             _ptr(dt_hard), _ptr(steps), _ptr(r_out), _ptr(r_search), _ptr(acc),
+                                             int(slow_log2), 1 if graph else 0, C.byref(nc), C.byref(ns)),
+                    "hard_evaluate")
         return acc, int(nc.value), int(ns.value)
 
     def soft_force_frozen(self, pos, mass, out=None):

@@ -706,20 +706,26 @@ p3t_status ensure_overlap(p3t_ctx *c) {
   if (c->ov_buf && c->ov_n_cap >= c->n_cap) return P3T_OK;
   const int64_t nc = c->n_cap;
   auto bytes = [](int64_t count, size_t sz) { return ((size_t)count * sz + 255) & ~size_t(255); };
-  const size_t total = 2 * bytes(3 * nc, sizeof(double)) + bytes(nc, sizeof(double)) +
-                       bytes(SLOW_CAP, sizeof(int32_t)) + bytes(HERM_N_BUCKETS * SLOW_CAP, sizeof(int32_t)) +
+  const size_t total = 4 * bytes(3 * nc, sizeof(double)) + bytes(nc, sizeof(int64_t)) + 2 * bytes(nc, sizeof(int32_t)) +
+                       2 * bytes(nc, sizeof(double)) + bytes(7 * nc, sizeof(int32_t)) + bytes(nc, sizeof(int32_t)) +
                        bytes((int64_t)SLOW_CAP * SLOW_CHUNKS * 3, sizeof(double));
   c->ov_n_cap = 0;
-  c->slow_list = nullptr;
+  c->pk_x = nullptr;
   HIP_OK(c, dev_alloc(c->ov_buf, (int64_t)total));
   Arena A;
   A.base = c->ov_buf;
   A.size = total;
-  c->sh_pos = A.take<double>(3 * nc);
-  c->sh_vel = A.take<double>(3 * nc);
+  c->pk_x = A.take<double>(3 * nc);
+  c->pk_v = A.take<double>(3 * nc);
+  c->pk_a = A.take<double>(3 * nc);
+  c->pk_j = A.take<double>(3 * nc);
+  c->pk_t = A.take<int64_t>(nc);
+  c->pk_lev = A.take<int32_t>(nc);
+  c->pk_nst = A.take<int32_t>(nc);
+  c->pk_e0 = A.take<double>(nc);
   c->m_eff = A.take<double>(nc);
-  c->slow_list = A.take<int32_t>(SLOW_CAP);
-  c->slow_blists = A.take<int32_t>(HERM_N_BUCKETS * SLOW_CAP);
+  c->pk_lists = A.take<int32_t>(7 * nc);
+  c->slow_list = A.take<int32_t>(nc);
   c->slow_part = A.take<double>((int64_t)SLOW_CAP * SLOW_CHUNKS * 3);
   if (!c->slow_part) return fail(c, P3T_ERR_HIP, "overlap buffer layout overflow (internal)");
   c->ov_n_cap = nc;
@@ -729,7 +735,7 @@ p3t_status ensure_overlap(p3t_ctx *c) {
 }  // namespace
 
 p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const double *mass, const double *r_out_hard,
-                             double *dt_hard, const double *r_out, const double *r_search, double *acc3,
+                             double *dt_hard, int32_t *steps, const double *r_out, const double *r_search, double *acc3,
                              int32_t slow_log2, int32_t use_graph, int64_t *n_clusters_host, int64_t *n_slow_host) {
   if (!c) return P3T_ERR_ARG;
   if (n_clusters_host) *n_clusters_host = 0;
@@ -743,7 +749,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   c->stats.n_slow = 0;
   c->stats.ms_direct = 0.0;
   if (n == 0) return p3t_evaluate(c, 0, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
-  const bool split = slow_log2 > 0 && dt_hard != nullptr;
+  const bool split = slow_log2 > 0;
   p3t_status st;
   if (split && (st = ensure_overlap(c)) != P3T_OK) return st;
   ev_record(c, 9);
@@ -751,31 +757,47 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   HIP_OK(c, labels_cc(c, n, c->hs_label));
   HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
   int32_t hc[HERM_BC_WORDS];
-  hipError_t e = herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, split ? dt_hard : nullptr,
-                             split ? slow_log2 : 0, hc);
+  hipError_t e = herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc);
   if (n_clusters_host) *n_clusters_host = hc[HERM_BC_NC];
   if (e == hipErrorInvalidValue)
     return fail(c, P3T_ERR_CLUSTER, "hard_evaluate: a cluster exceeds 1024 members (percolation)");
   HIP_OK(c, e);
   HIP_OK(c, aux_streams(c));
-  const int ns = split ? hc[HERM_BC_SLOW] : 0;
-  if (ns > 0) {
-    // the slow clusters integrate copies of the state on their own stream
-    HIP_OK(c, hipMemcpyAsync(c->sh_pos, pos3, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c->stream));
-    HIP_OK(c, hipMemcpyAsync(c->sh_vel, vel3, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, c->stream));
-    HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
-    HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
-    HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->sh_pos, c->sh_vel, mass, r_out_hard, dt_hard,
-                          nullptr, nullptr, hc, 1, c->slow_stream, c->slow_stream, nullptr, nullptr));
-    HIP_OK(c, hipEventRecord(c->slow_ev[1], c->slow_stream));
-  }
+  const int budget = split ? (slow_log2 < 30 ? 1 << slow_log2 : 1 << 30) : 0;
+  if (split) HIP_OK(c, hipMemsetAsync(c->slow_flag, 0, (size_t)n, c->stream));
   HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
-                        hc, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
+                        steps, hc, budget, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
   ev_record(c, 10);
   if (!split) {
     st = p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
     if (c->timing) c->stats.ms_hermite = ev_ms(c, 9, 10);
     return st;
+  }
+  // the clusters parked by the step budget finish on their own stream
+  HIP_OK(c, hipMemcpyAsync(hc + HERM_BC_PARK0, c->herm_bcount + HERM_BC_PARK0,
+                           sizeof(int32_t) * (HERM_BC_PARKED + 1 - HERM_BC_PARK0), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  int ns = hc[HERM_BC_PARKED];
+  if (ns > SLOW_CAP) {
+    // too many for the direct sums: finish them here, then evaluate as usual
+    HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr,
+                          nullptr, steps, hc, 0, 1, c->stream, c->stream, nullptr, nullptr));
+    HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, nullptr, ns));  // copies the state back only
+    HIP_OK(c, hipMemsetAsync(c->slow_flag, 0, (size_t)n, c->stream));
+    if (c->timing) {
+      ev_record(c, 10);
+      HIP_OK(c, hipStreamSynchronize(c->stream));
+      c->stats.ms_hermite = ev_ms(c, 9, 10);
+    }
+    c->stats.n_slow = 0;
+    return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
+  }
+  if (ns > 0) {
+    HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
+    HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
+    HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
+                          steps, hc, 0, 1, c->slow_stream, c->slow_stream, nullptr, nullptr));
+    HIP_OK(c, hipEventRecord(c->slow_ev[1], c->slow_stream));
   }
   // everyone else: tree, walk and force at the new state, S massless (with
   // S empty too, so that a captured evaluation keeps its arguments)

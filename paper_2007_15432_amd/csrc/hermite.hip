@@ -27,7 +27,8 @@ namespace p3t {
 constexpr int TICK_BITS = 40;
 constexpr int BIG_T = 256;
 constexpr int N_BUCKETS = HERM_N_BUCKETS;  // SEG 1..64 (7), 256-thread MPT 1, 2, 4 (3), too big (1)
-constexpr int BC_NC = HERM_BC_NC, BC_BAD = HERM_BC_BAD, BC_SLOW = HERM_BC_SLOW, BC_WORDS = HERM_BC_WORDS;
+constexpr int BC_NC = HERM_BC_NC, BC_BAD = HERM_BC_BAD, BC_WORDS = HERM_BC_WORDS;
+constexpr int PK_MEM = HERM_BC_PARKED - HERM_BC_PARK0;  // parked-member word, relative to the park counts
 
 struct HermArgs {
   const int32_t *cl_ptr, *members, *blists;
@@ -38,6 +39,23 @@ struct HermArgs {
   const double *mass, *ro;
   double *dt_hard, *e_rel;
   int32_t *nsteps;
+  int32_t *msteps;  // per particle: block steps of its cluster (nullable)
+  // Parking (clusters of 1..64 members): with budget > 0 a cluster still
+  // running after `budget` block steps saves its state to pk and stops;
+  // resume = 1 continues parked clusters from pk and writes their final
+  // state to pos / vel.
+  int budget, resume;
+  struct {
+    double *x, *v, *a, *j;  // per member (3n each), at the member's own time
+    int64_t *t;             // per member: its time in ticks
+    int32_t *lev;           // per member: its block level
+    int32_t *nst;           // per cluster: block steps so far
+    double *e0;             // per cluster: energy at the start
+    int32_t *count;         // [0, 7) parked clusters per bucket, [PK_MEM] parked members
+    int32_t *lists;         // parked clusters, 7 lists of n
+    int32_t *members;       // parked members (n)
+    uint8_t *flag;          // per particle: 1 if parked (cleared by the caller)
+  } pk;
   int64_t n;
   double G, GM, gamma, inv1mg, eta, eta0, dt_soft, tick;
   // powers of dt_soft for the corrector (scaled per level by exact powers of two)
@@ -264,8 +282,12 @@ __device__ __forceinline__ double lpm_sum(double v, int ll2) {
 // side by side in the fused launch, sharing the instruction cache).  The
 // LPM lanes of a member hold identical copies of its state; each evaluates
 // every LPM-th partner and the partial sums are added across them.
+// MODE 0: plain; 1: park clusters still running after A.budget steps;
+// 2: resume parked clusters
+template <int MODE>
 __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int ci0, const Lds &L,
                                          int wbase, int sl2) {
+  constexpr bool RESUME = MODE == 2, PARK = MODE == 1;
   const int ll2 = lanes_per_member_log2(sl2), cl2 = sl2 + ll2;
   const int SEG = 1 << sl2, LPM = 1 << ll2;
   const int lane = threadIdx.x & (WAVE - 1), cseg = lane >> cl2, lic = lane & ((1 << cl2) - 1);
@@ -282,13 +304,14 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   const int me = sb + sl;
   double x[3] = {1.0, 0.0, 0.0}, v[3] = {0.0, 1.0, 0.0}, a0[3], j0[3];
   double m = 0.0, ro = 1.0;
+  const double *src_x = RESUME ? A.pk.x : A.pos, *src_v = RESUME ? A.pk.v : A.vel;
   if (mem) {
-    x[0] = A.pos[gid];
-    x[1] = A.pos[n + gid];
-    x[2] = A.pos[2 * n + gid];
-    v[0] = A.vel[gid];
-    v[1] = A.vel[n + gid];
-    v[2] = A.vel[2 * n + gid];
+    x[0] = src_x[gid];
+    x[1] = src_x[n + gid];
+    x[2] = src_x[2 * n + gid];
+    v[0] = src_v[gid];
+    v[1] = src_v[n + gid];
+    v[2] = src_v[2 * n + gid];
     m = A.mass[gid];
     ro = A.ro[gid];
   }
@@ -305,12 +328,12 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     L.pvz[me] = v[2];
   }
   wave_sync();
-  // forces at t = 0 and the initial energy
+  // forces at t = 0 and the initial energy (a resumed cluster reads them)
   double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0};
   double e = lead ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
                         A.GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
                   : 0.0;
-  if (mem) {
+  if (mem && !RESUME) {
     for (int jj = sub; jj < size; jj += LPM) {
       if (jj == sl) continue;
       const int q = sb + jj;
@@ -329,21 +352,37 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     a0[d] += lpm_sum(pa[d], ll2);
     j0[d] += lpm_sum(pj[d], ll2);
   }
-  const double E0 = seg_sum(e, cl2);
+  double E0 = seg_sum(e, cl2);
   int lev = initial_level(a0, j0, mem, gid, A);  // every copy reads the carried step
   const int64_t T = (int64_t)1 << TICK_BITS;
   const int max_iter = A.max_iter;
   const double tick = A.tick, GM = A.GM;
   int64_t t = 0;
   int nst = 0;  // block steps of this lane's cluster
+  if (RESUME && mem) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      a0[d] = A.pk.a[d * n + gid];
+      j0[d] = A.pk.j[d * n + gid];
+    }
+    t = A.pk.t[gid];
+    lev = A.pk.lev[gid];
+  }
+  if (RESUME && c >= 0) {
+    nst = A.pk.nst[c];
+    E0 = A.pk.e0[c];
+  }
+  bool parked = false;
+  const int budget = PARK ? A.budget : INT_MAX;
   for (int it = 0;; ++it) {
     const int64_t te = mem ? t + ((int64_t)1 << (TICK_BITS - lev)) : LLONG_MAX;
     // every step divides T and each member's time is a multiple of its
     // step, so a cluster is finished exactly when its earliest next time
     // lies beyond T
     const int64_t tn = seg_min(te, cl2);
-    const bool done = (size == 0) || (tn > T);
+    const bool done = (size == 0) || (tn > T) || parked;
     if (__all(done)) break;
+    if (it == budget) break;  // uniform
     if (it >= max_iter) {
       if (lane == 0) set_flag(A.cnt, P3T_FLAG_NSTEPS);
       break;
@@ -409,6 +448,35 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
       correct(x, v, a0, j0, xp, vp, a1, j1, h, t, lev, A);
     }
   }
+  if (PARK) {
+    // park the clusters still running: their first lane takes the slots
+    const int64_t te = mem ? t + ((int64_t)1 << (TICK_BITS - lev)) : LLONG_MAX;
+    const int64_t tmin = seg_min(te, cl2);  // every lane takes part
+    const bool fin = (size == 0) || (tmin > T);
+    int64_t slot = LLONG_MAX;
+    if (!fin && lic == 0) {
+      const int k = atomicAdd(&A.pk.count[sl2], 1);
+      A.pk.lists[(int64_t)sl2 * A.n + k] = c;
+      A.pk.nst[c] = nst;
+      A.pk.e0[c] = E0;
+      slot = atomicAdd(&A.pk.count[PK_MEM], size);
+    }
+    slot = seg_min(slot, cl2);
+    parked = slot != LLONG_MAX;
+    if (parked && lead) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        A.pk.x[d * n + gid] = x[d];
+        A.pk.v[d * n + gid] = v[d];
+        A.pk.a[d * n + gid] = a0[d];
+        A.pk.j[d * n + gid] = j0[d];
+      }
+      A.pk.t[gid] = t;
+      A.pk.lev[gid] = lev;
+      A.pk.members[slot + sl] = gid;
+      A.pk.flag[gid] = 1;
+    }
+  }
   // final energy
   wave_sync();
   if (lead) {
@@ -432,6 +500,7 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     }
   }
   const double E1 = seg_sum(e, cl2);
+  if (PARK && parked) return;  // finished by the resume launch
   if (lead) {
     A.pos[gid] = x[0];
     A.pos[n + gid] = x[1];
@@ -444,6 +513,7 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   }
   if (lic == 0 && c >= 0 && A.e_rel) A.e_rel[c] = fabs(E1 - E0) / fabs(E0);
   if (lic == 0 && c >= 0 && A.nsteps) A.nsteps[c] = nst;
+  if (lead && A.msteps) A.msteps[gid] = nst;
 }
 
 // ---------------------------------------------------------------- big clusters
@@ -699,10 +769,14 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L,
   }
   if (tid == 0 && A.e_rel) A.e_rel[c] = fabs(E1 - E0) / fabs(E0);
   if (tid == 0 && A.nsteps) A.nsteps[c] = it;
+  if (A.msteps)
+    for (int u = 0; u < MPT; ++u)
+      if (mem[u]) A.msteps[gid[u]] = it;
 }
 
 // Buckets 0..6 (sizes 1..64) in one launch of 256-thread workgroups; the
 // block index selects the bucket (uniform per workgroup).
+template <int MODE>
 __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   __shared__ double lds[8][BIG_T];
   __shared__ int64_t shi[BIG_T / WAVE];
@@ -731,7 +805,7 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
 #pragma unroll
   for (int q = 0; q < 7; ++q)
     if (q == bk) count = A.bcount[q];  // constant indices only (see above)
-  seg_body(A, blist, count, ci0, L, wbase, bk);
+  seg_body<MODE>(A, blist, count, ci0, L, wbase, bk);
 }
 
 template <int MPT>
@@ -749,14 +823,16 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A, int bk) {
 }
 
 // ---------------------------------------------------------------- bucketing
+// Clusters above 16 members take the one-workgroup path: in a block step
+// usually only a few of their members are active, and that path spreads an
+// active member's partner loop over a whole wavefront, where the wavefront
+// segment path would walk it serially in one lane.
 __device__ __forceinline__ int bucket_of(int size) {
   if (size <= 1) return 0;
   if (size <= 2) return 1;
   if (size <= 4) return 2;
   if (size <= 8) return 3;
   if (size <= 16) return 4;
-  if (size <= 32) return 5;
-  if (size <= 64) return 6;
   if (size <= 256) return 7;
   if (size <= 512) return 8;
   if (size <= 1024) return 9;
@@ -786,97 +862,47 @@ __device__ __forceinline__ int cluster_bucket(int64_t c, int64_t n, const int32_
   return b > a ? bucket_of(b - a) : -1;
 }
 
-// Slow split (optional): a cluster whose members carry hard steps of
-// dt_soft 2^-k with k >= slow_log2 (it will take >= 2^slow_log2 block steps)
-// goes to bucket + N_BUCKETS as long as its members still fit in SLOW_CAP;
-// its members are listed in slow_list and flagged in slow_flag, its index
-// goes to slow_blists (stride SLOW_CAP) instead of blists (stride `stride`).
 struct BucketArgs {
   int64_t nc_host;
   const int64_t *nc_dev;
   int64_t stride, n;
   const int32_t *cl_ptr, *members;
-  int32_t *bcount, *blists, *slow_blists;
-  int32_t *cl_bk;                // bucket chosen per cluster (between the sweeps)
-  const double *dt_hard;         // carried hard steps, nullable
-  double dt_soft;
-  int slow_log2;                 // <= 0: no split
-  uint8_t *slow_flag;            // written for every member when slow_log2 > 0
-  int32_t *slow_list;            // SLOW_CAP entries
+  int32_t *bcount, *blists;
+  int32_t *cl_bk;  // bucket chosen per cluster (between the sweeps)
 };
 
-// reserve k slots of a capped counter; false (nothing reserved) if they do
-// not fit.  Each failed exchange means another reservation went through, and
-// the counter never passes the cap, so the loop ends.
-__device__ __forceinline__ bool reserve_capped(int32_t *ctr, int k, int cap, int &at) {
-  int old = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  while (old + k <= cap) {
-    const int prev = atomicCAS(ctr, old, old + k);
-    if (prev == old) {
-      at = old;
-      return true;
-    }
-    old = prev;
-  }
-  return false;
-}
-
-__device__ __forceinline__ int slow_level(int a, int b, const BucketArgs &B) {
-  int lv = 0;
-  for (int k = a; k < b; ++k) {
-    const double d = B.dt_hard[B.members[k]];
-    if (d > 0.0) {
-      const int l = ilogb(B.dt_soft) - ilogb(d);
-      lv = l > lv ? l : lv;
-    }
-  }
-  return lv;
-}
-
 __global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
-  __shared__ int cnt[2 * N_BUCKETS], base[2 * N_BUCKETS];
-  constexpr int NB2 = 2 * N_BUCKETS;
+  __shared__ int cnt[N_BUCKETS], base[N_BUCKETS];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
   const int64_t nc = B.nc_dev ? *B.nc_dev : B.nc_host;  // clusters (at most stride)
   int32_t *bcount = B.bcount;
   if (blockIdx.x == 0 && tid == 0) bcount[BC_NC] = (int32_t)nc;
   const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
-  if (tid < NB2) cnt[tid] = 0;
+  if (tid < N_BUCKETS) cnt[tid] = 0;
   __syncthreads();
   for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {
     const int64_t c = b0 + tid;
-    int bk = c < c1 ? cluster_bucket(c, B.n, B.cl_ptr, B.members, bcount) : -1;
-    if (bk >= 0 && B.slow_log2 > 0) {
-      const int a = B.cl_ptr[c], b = B.cl_ptr[c + 1];
-      int at = 0;
-      const bool slow = B.dt_hard && slow_level(a, b, B) >= B.slow_log2 &&
-                        reserve_capped(&bcount[BC_SLOW], b - a, SLOW_CAP, at);
-      if (slow) {
-        bk += N_BUCKETS;
-        for (int k = a; k < b; ++k) B.slow_list[at + k - a] = B.members[k];
-      }
-      for (int k = a; k < b; ++k) B.slow_flag[B.members[k]] = slow ? 1 : 0;
-    }
+    const int bk = c < c1 ? cluster_bucket(c, B.n, B.cl_ptr, B.members, bcount) : -1;
     if (c < c1) B.cl_bk[c] = bk;
-    for (int q = 0; q < NB2; ++q) {
+    for (int q = 0; q < N_BUCKETS; ++q) {
       const unsigned long long mask = __ballot(bk == q);
       if (mask != 0ull && lane == __ffsll((long long)mask) - 1) atomicAdd(&cnt[q], (int)__popcll(mask));
     }
   }
   __syncthreads();
-  if (tid < NB2) {
+  if (tid < N_BUCKETS) {
     base[tid] = cnt[tid] > 0 ? atomicAdd(&bcount[tid], cnt[tid]) : 0;
     cnt[tid] = 0;
   }
   __syncthreads();
-  __shared__ int wofs[BIG_T / WAVE][NB2];
+  __shared__ int wofs[BIG_T / WAVE][N_BUCKETS];
   const int w = tid / WAVE;
   for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {  // uniform over the workgroup
     const int64_t c = b0 + tid;
     const int bk = c < c1 ? B.cl_bk[c] : -1;  // as decided above
     unsigned long long mine = 0ull;
-    for (int q = 0; q < NB2; ++q) {
+    for (int q = 0; q < N_BUCKETS; ++q) {
       const unsigned long long mask = __ballot(bk == q);
       if (lane == 0) wofs[w][q] = (int)__popcll(mask);
       if (q == bk) mine = mask;
@@ -885,12 +911,10 @@ __global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
     if (bk >= 0) {
       int off = 0;
       for (int u = 0; u < w; ++u) off += wofs[u][bk];  // wavefronts take their slots in order
-      int32_t *dst = bk < N_BUCKETS ? B.blists + (int64_t)bk * B.stride
-                                    : B.slow_blists + (int64_t)(bk - N_BUCKETS) * SLOW_CAP;
-      dst[base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
+      B.blists[(int64_t)bk * B.stride + base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
     }
     __syncthreads();
-    if (tid < NB2) {
+    if (tid < N_BUCKETS) {
       int tot = 0;
       for (int u = 0; u < BIG_T / WAVE; ++u) tot += wofs[u][tid];
       cnt[tid] += tot;
@@ -918,11 +942,10 @@ static void host_changeover_coeffs(double g, HermArgs &A) {
   A.wf1 = f1;
 }
 
-// Bucket lists and counts (one host synchronisation); hc receives
-// BC_WORDS words.  slow_log2 > 0 splits off the slow clusters (see
-// k_herm_bucket).
+// Bucket lists and counts (one host synchronisation); hc receives the
+// BC_WORDS words (the park counts are zero).
 hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
-                       const int64_t *nc_dev, const double *dt_hard, int slow_log2, int32_t *hc) {
+                       const int64_t *nc_dev, int32_t *hc) {
   hipStream_t s = c->stream;
   hipError_t e;
   if ((e = fill_i32(c->herm_bcount, 0, BC_WORDS, s)) != hipSuccess) return e;
@@ -935,45 +958,58 @@ hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr,
   B.members = cl_members;
   B.bcount = c->herm_bcount;
   B.blists = c->herm_blists;
-  B.slow_blists = c->slow_blists;
   B.cl_bk = c->herm_clbk;
-  B.dt_hard = dt_hard;
-  B.dt_soft = c->P.dt_soft;
-  B.slow_log2 = slow_log2 > 0 && c->slow_list ? slow_log2 : 0;
-  B.slow_flag = c->slow_flag;
-  B.slow_list = c->slow_list;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
   hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, B);
   if ((e = hipMemcpyAsync(hc, c->herm_bcount, sizeof(int32_t) * BC_WORDS, hipMemcpyDeviceToHost, s)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   if (hc[BC_BAD]) return hipErrorInvalidDevicePointer;                 // malformed cluster arrays
-  if (hc[10] > 0 || hc[10 + N_BUCKETS] > 0) return hipErrorInvalidValue;  // a cluster above 1024 members
+  if (hc[10] > 0) return hipErrorInvalidValue;  // a cluster above 1024 members
   return hipSuccess;
 }
 
-// Integrates the clusters of one bucket set (set 0: the ordinary buckets,
-// set 1: the slow ones) on stream s; clusters of 65 members and more go to
-// stream s_big (which may be s), joined back into s at the end.
+// Integrates the clusters of the buckets (counts in hc[0, 11)) on stream s;
+// clusters of 65 members and more go to stream s_big (which may be s),
+// joined back into s at the end.  budget > 0 parks the clusters of 1..64
+// members still running after `budget` block steps (their counts land in
+// the park words of herm_bcount).  resume = 1 continues the parked clusters
+// (counts in hc[HERM_BC_PARK0, + 7)) and writes their final state into the
+// park buffers' x and v.
 hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
                        double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
-                       double *e_rel_err, int32_t *n_steps, const int32_t *hc, int set, hipStream_t s,
-                       hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join) {
+                       double *e_rel_err, int32_t *n_steps, int32_t *steps_out, const int32_t *hc, int budget,
+                       int resume, hipStream_t s, hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join) {
   hipError_t e;
   const p3t_params &P = c->P;
-  const int o = set * N_BUCKETS;
   HermArgs A;
   A.cl_ptr = cl_ptr;
   A.members = cl_members;
-  A.blists = set == 0 ? c->herm_blists : c->slow_blists;
-  A.nc = set == 0 ? stride : SLOW_CAP;
-  A.pos = pos3;
-  A.vel = vel3;
+  A.blists = resume ? c->pk_lists : c->herm_blists;
+  A.nc = resume ? n : stride;
+  A.pos = resume ? c->pk_x : pos3;
+  A.vel = resume ? c->pk_v : vel3;
   A.mass = mass;
   A.ro = r_out;
   A.dt_hard = dt_hard;
   A.e_rel = e_rel_err;
   A.nsteps = n_steps;
+  A.msteps = steps_out;
+  A.budget = budget;
+  A.resume = resume;
+  A.pk.x = c->pk_x;
+  A.pk.v = c->pk_v;
+  A.pk.a = c->pk_a;
+  A.pk.j = c->pk_j;
+  A.pk.t = c->pk_t;
+  A.pk.lev = c->pk_lev;
+  A.pk.nst = c->pk_nst;
+  A.pk.e0 = c->pk_e0;
+  A.pk.count = c->herm_bcount + HERM_BC_PARK0;
+  A.pk.lists = c->pk_lists;
+  A.pk.members = c->slow_list;
+  A.pk.flag = c->slow_flag;
+  if ((budget > 0 || resume) && !c->pk_x) return hipErrorInvalidValue;  // park buffers not allocated
   A.n = n;
   A.G = P.G;
   A.GM = P.G * P.m_star;
@@ -996,7 +1032,7 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   A.max_iter = 1 << 22;
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
-  for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = hc[o + bk];
+  for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = resume ? (bk < 7 ? hc[HERM_BC_PARK0 + bk] : 0) : hc[bk];
   // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG /
   // lanes per member); the clusters of 65 members and more run at the same
   // time in their own launches (one workgroup each)
@@ -1017,7 +1053,14 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   if (A.bcount[7] > 0) hipLaunchKernelGGL(k_herm_big<1>, dim3(A.bcount[7]), dim3(BIG_T), 0, s2, A, 7);
   if (A.bcount[8] > 0) hipLaunchKernelGGL(k_herm_big<2>, dim3(A.bcount[8]), dim3(BIG_T), 0, s2, A, 8);
   if (A.bcount[9] > 0) hipLaunchKernelGGL(k_herm_big<4>, dim3(A.bcount[9]), dim3(BIG_T), 0, s2, A, 9);
-  if (blocks > 0) hipLaunchKernelGGL(k_herm_fused, dim3(blocks), dim3(BIG_T), 0, s, A);
+  if (blocks > 0) {
+    if (resume)
+      hipLaunchKernelGGL(k_herm_fused<2>, dim3(blocks), dim3(BIG_T), 0, s, A);
+    else if (budget > 0)
+      hipLaunchKernelGGL(k_herm_fused<1>, dim3(blocks), dim3(BIG_T), 0, s, A);
+    else
+      hipLaunchKernelGGL(k_herm_fused<0>, dim3(blocks), dim3(BIG_T), 0, s, A);
+  }
   if (s2 != s) {  // join
     if ((e = hipEventRecord(ev_join, s2)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s, ev_join, 0)) != hipSuccess) return e;
@@ -1042,12 +1085,12 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   if (nc_out) *nc_out = 0;
   if (nc <= 0) return hipSuccess;  // with nc_dev, nc is an upper bound (the particle count)
   int32_t hc[BC_WORDS];
-  hipError_t e = herm_bucket(c, n, nc, cl_ptr, cl_members, nc_dev, nullptr, 0, hc);
+  hipError_t e = herm_bucket(c, n, nc, cl_ptr, cl_members, nc_dev, hc);
   if (nc_out) *nc_out = hc[BC_NC];
   if (e != hipSuccess) return e;
   if ((e = aux_streams(c)) != hipSuccess) return e;
-  return herm_launch(c, n, nc, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps, hc, 0,
-                     c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]);
+  return herm_launch(c, n, nc, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps, nullptr, hc, 0,
+                     0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]);
 }
 
 }  // namespace p3t

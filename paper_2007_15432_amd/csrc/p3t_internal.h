@@ -129,13 +129,13 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Hermite bucket-count words (hermite.hip): [0, 11) the buckets, [11, 22)
-// the buckets of slow clusters, then the cluster count, the malformed-input
-// flag and the slow member count.
-constexpr int HERM_BC_NC = 28, HERM_BC_BAD = 29, HERM_BC_SLOW = 30, HERM_BC_WORDS = 32;
+// Hermite bucket-count words (hermite.hip): [0, 11) the buckets, [11, 18)
+// the parked clusters of buckets 0..6, the parked member count, then the
+// cluster count and the malformed-input flag.
+constexpr int HERM_BC_PARK0 = 11, HERM_BC_PARKED = 18, HERM_BC_NC = 28, HERM_BC_BAD = 29, HERM_BC_WORDS = 32;
 constexpr int HERM_N_BUCKETS = 11;
-// slow members of one p3t_hard_evaluate call at most, and the chunks of the
-// direct sum over all particles for each of them
+// parked members of one p3t_hard_evaluate call at most, and the chunks of
+// the direct sum over all particles for each of them
 constexpr int SLOW_CAP = 1024, SLOW_CHUNKS = 64;
 
 // ---------------------------------------------------------------- context
@@ -245,18 +245,22 @@ struct p3t_ctx {
   int32_t *hs_cl_mem = nullptr;
   double *adj_buf = nullptr;        // soft-kick adjoint scratch (adjoint_buf_need(adj_cap))
   int64_t adj_cap = 0;
-  // p3t_hard_evaluate: slow clusters integrate on slow_stream into copies of
-  // the state while the tree of everyone else is evaluated on the main stream
-  int slow_active = 0;              // force kernels leave pairs with a slow member alone
+  // p3t_hard_evaluate: clusters parked by the step budget finish on
+  // slow_stream while the tree of everyone else is evaluated on the main stream
+  int slow_active = 0;              // force kernels leave pairs with a parked member alone
   hipStream_t slow_stream = nullptr;
   hipEvent_t slow_ev[2] = {};
   char *ov_buf = nullptr;           // one allocation for the pointers below
   int64_t ov_n_cap = 0;
-  double *sh_pos = nullptr, *sh_vel = nullptr;  // state copies (3 n_cap each)
-  double *m_eff = nullptr;          // masses with the slow members at zero (n_cap)
-  int32_t *slow_list = nullptr;     // slow members (SLOW_CAP)
-  int32_t *slow_blists = nullptr;   // bucket lists of the slow clusters (11 * SLOW_CAP)
-  double *slow_part = nullptr;      // partial sums of the forces on the slow members
+  double *pk_x = nullptr, *pk_v = nullptr, *pk_a = nullptr, *pk_j = nullptr;  // parked state (3 n_cap each)
+  int64_t *pk_t = nullptr;          // parked members' times (n_cap)
+  int32_t *pk_lev = nullptr;        // parked members' levels (n_cap)
+  int32_t *pk_nst = nullptr;        // parked clusters' step counts (n_cap)
+  double *pk_e0 = nullptr;          // parked clusters' initial energies (n_cap)
+  int32_t *pk_lists = nullptr;      // parked clusters per bucket (7 * SLOW_CAP)
+  double *m_eff = nullptr;          // masses with the parked members at zero (n_cap)
+  int32_t *slow_list = nullptr;     // parked members (SLOW_CAP)
+  double *slow_part = nullptr;      // partial sums of the forces on the parked members
 };
 
 // ---------------------------------------------------------------- launchers
@@ -311,13 +315,13 @@ hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t
 // hermite.hip
 // nc_dev (nullable): the cluster count on the device, nc then only bounds it
 hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
-                       const int64_t *nc_dev, const double *dt_hard, int slow_log2, int32_t *hc);
+                       const int64_t *nc_dev, int32_t *hc);
 hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
                        double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
-                       double *e_rel_err, int32_t *n_steps, const int32_t *hc, int set, hipStream_t s,
-                       hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join);
+                       double *e_rel_err, int32_t *n_steps, int32_t *steps_out, const int32_t *hc, int budget,
+                       int resume, hipStream_t s, hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join);
 hipError_t aux_streams(p3t_ctx *c);
-// slow.hip: the direct terms of the slow members after their integration
+// slow.hip: the direct terms of the parked members after their integration
 hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const double *mass, const double *r_out,
                        const double *r_search, double *acc3, int ns);
 hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns);

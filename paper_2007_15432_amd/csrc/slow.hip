@@ -166,47 +166,67 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
   }
 }
 
-// member s of S against the particles of chunk blockIdx.x: partial sums, and
-// the pairs (s, s') with s' in S
+// members s0 .. s0 + SG - 1 of S (s0 = SG blockIdx.y) against the particles
+// of chunk blockIdx.x: partial sums, and the pairs (s, s') with s' in S.
+// Each particle of the chunk is loaded once for SG members.
+constexpr int SG = 8;
+
 __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
-  __shared__ double red[3][ST / WAVE];
+  __shared__ double red[3 * SG][ST / WAVE];
   const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
-  const int s = blockIdx.y;
+  const int s0 = blockIdx.y * SG;
+  const int gc = min(SG, A.ns - s0);  // members in this block, uniform
   const int64_t n = A.n;
-  const int64_t i = A.list[s];
-  const double xi = A.pos[i], yi = A.pos[n + i], zi = A.pos[2 * n + i];
-  const double vxi = A.vel[i], vyi = A.vel[n + i], vzi = A.vel[2 * n + i];
-  const double mi = A.mass[i], roi = A.ro[i], rsi = A.rs[i], invi = 1.0 / roi;
+  int64_t ig[SG];
+  double xi[SG], yi[SG], zi[SG], invi[SG], ax[SG], ay[SG], az[SG];
+#pragma unroll
+  for (int g = 0; g < SG; ++g) {
+    ig[g] = A.list[s0 + (g < gc ? g : gc - 1)];
+    xi[g] = A.pos[ig[g]];
+    yi[g] = A.pos[n + ig[g]];
+    zi[g] = A.pos[2 * n + ig[g]];
+    invi[g] = 1.0 / A.ro[ig[g]];
+    ax[g] = ay[g] = az[g] = 0.0;
+  }
   const int64_t chunk = (n + SLOW_CHUNKS - 1) / SLOW_CHUNKS;
   const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
-  double ax = 0.0, ay = 0.0, az = 0.0;
   bool coincident = false;
   for (int64_t j = j0 + t; j < j1; j += ST) {
-    if (j == i) continue;
     const double xj = A.pos[j], yj = A.pos[n + j], zj = A.pos[2 * n + j];
-    const double mj = A.mass[j], roj = A.ro[j];
-    soft_term(A.P, xj - xi, yj - yi, zj - zi, A.P.G * mj, invi, 1.0 / roj, ax, ay, az);
-    if (A.slow[j]) {
-      if (xj == xi && yj == yi && zj == zi) coincident = true;
-      if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, xj, yj, zj, A.vel[j], A.vel[n + j], A.vel[2 * n + j],
-                         mj, roj, A.rs[j], A.P.G, A.rsch2, A.rsch3, A.dt))
-        push_pair(A.cnt, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
+    const double mj = A.mass[j], roj = A.ro[j], gmj = A.P.G * mj, invj = 1.0 / roj;
+    // j = s itself gives r = 0, hence K = 0 and an exact zero term
+#pragma unroll
+    for (int g = 0; g < SG; ++g)
+      if (g < gc) soft_term(A.P, xj - xi[g], yj - yi[g], zj - zi[g], gmj, invi[g], invj, ax[g], ay[g], az[g]);
+    if (A.slow[j]) {  // pairs within S (rare)
+      for (int g = 0; g < gc; ++g) {
+        const int64_t i = ig[g];
+        if (j == i) continue;
+        if (xj == xi[g] && yj == yi[g] && zj == zi[g]) coincident = true;
+        if (neighbour_test(xi[g], yi[g], zi[g], A.vel[i], A.vel[n + i], A.vel[2 * n + i], A.mass[i], A.ro[i], A.rs[i],
+                           xj, yj, zj, A.vel[j], A.vel[n + j], A.vel[2 * n + j], mj, roj, A.rs[j], A.P.G, A.rsch2,
+                           A.rsch3, A.dt))
+          push_pair(A.cnt, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
+      }
     }
   }
   if (coincident) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
-  ax = wave_sum(ax);
-  ay = wave_sum(ay);
-  az = wave_sum(az);
-  if (lane == 0) {
-    red[0][w] = ax;
-    red[1][w] = ay;
-    red[2][w] = az;
+#pragma unroll
+  for (int g = 0; g < SG; ++g) {
+    if (g < gc) {
+      const double sx = wave_sum(ax[g]), sy = wave_sum(ay[g]), sz = wave_sum(az[g]);
+      if (lane == 0) {
+        red[3 * g][w] = sx;
+        red[3 * g + 1][w] = sy;
+        red[3 * g + 2][w] = sz;
+      }
+    }
   }
   __syncthreads();
-  if (t < 3) {
+  if (t < 3 * gc) {
     double v = 0.0;
     for (int q = 0; q < ST / WAVE; ++q) v += red[t][q];
-    A.part[((int64_t)s * SLOW_CHUNKS + blockIdx.x) * 3 + t] = v;
+    A.part[((int64_t)(s0 + t / 3) * SLOW_CHUNKS + blockIdx.x) * 3 + t % 3] = v;
   }
 }
 
@@ -228,7 +248,7 @@ __global__ void k_slow_reduce(SlowArgs A) {
 
 hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns) {
   hipStream_t s = c->stream;
-  if (ns > 1) hipLaunchKernelGGL(k_sort_list, dim3(1), dim3(SLOW_CAP), 0, s, c->slow_list, ns);
+  if (ns > 1 && ns <= SLOW_CAP) hipLaunchKernelGGL(k_sort_list, dim3(1), dim3(SLOW_CAP), 0, s, c->slow_list, ns);
   const int64_t n = c->n;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256));
   hipLaunchKernelGGL(k_mask_mass, dim3(g), dim3(256), 0, s, n, mass, (const uint8_t *)c->slow_flag, c->m_eff);
@@ -239,9 +259,11 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
                        const double *r_search, double *acc3, int ns) {
   hipStream_t s = c->stream;
   const int64_t n = c->n;
-  hipLaunchKernelGGL(k_slow_scatter, dim3((ns + 255) / 256), dim3(256), 0, s, n, ns, (const int32_t *)c->slow_list,
-                     (const double *)c->sh_pos, (const double *)c->sh_vel, const_cast<double *>(pos3),
+  const unsigned gs = (unsigned)std::min<int64_t>(65536, (ns + 255) / 256);
+  hipLaunchKernelGGL(k_slow_scatter, dim3(gs), dim3(256), 0, s, n, ns, (const int32_t *)c->slow_list,
+                     (const double *)c->pk_x, (const double *)c->pk_v, const_cast<double *>(pos3),
                      const_cast<double *>(vel3));
+  if (!acc3) return hipGetLastError();  // state only
   SlowArgs A;
   A.pos = pos3;
   A.vel = vel3;
@@ -265,7 +287,7 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
   A.dt = c->P.dt_soft;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + ST - 1) / ST));
   hipLaunchKernelGGL(k_slow_into, dim3(g), dim3(ST), 0, s, A);
-  hipLaunchKernelGGL(k_slow_from, dim3(SLOW_CHUNKS, ns), dim3(ST), 0, s, A);
+  hipLaunchKernelGGL(k_slow_from, dim3(SLOW_CHUNKS, (ns + SG - 1) / SG), dim3(ST), 0, s, A);
   hipLaunchKernelGGL(k_slow_reduce, dim3((ns + 255) / 256), dim3(256), 0, s, A);
   return hipGetLastError();
 }

@@ -14,10 +14,10 @@ The cut-off radii are fixed between collisions (Section 2.4: they are
 recomputed after a merger); `recompute_cutoffs` recomputes them every step
 instead (used to time the cut-off stage as part of the step).
 
-overlap=True runs (4)-(7) as one p3t_hard_evaluate call: clusters whose
-members took hard steps of dt_soft 2^-slow_log2 or less in their last
-integration run on a second stream while the tree of everyone else is
-evaluated, and their soft terms are summed directly afterwards.  With
+overlap=True runs (4)-(7) as one p3t_hard_evaluate call: clusters still
+running after 2^slow_log2 block steps park and finish on a second stream
+while the tree of everyone else is evaluated, and their soft terms are
+summed directly afterwards.  With
 recompute_cutoffs the evaluation of step k then uses the radii computed from
 the state of evaluation k-1 (the hard part of step k still uses the radii of
 evaluation k-1, as the P3T split requires): the radii lag one step, because
@@ -36,7 +36,7 @@ class P3TStepper:
     acceleration live in fixed buffers)."""
 
     def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False, graph: bool = False,
-                 fused_hard: bool = True, overlap: bool = False, slow_log2: int = 7):
+                 fused_hard: bool = True, overlap: bool = False, slow_log2: int = 9):
         self.ctx = ctx
         self.graph = graph
         self.fused_hard = fused_hard
@@ -49,6 +49,7 @@ class P3TStepper:
         self.recompute = recompute_cutoffs
         self.r_out, self.r_search, self.v_ran = ctx.compute_cutoffs(pos, vel, mass)
         self.dt_hard = torch.zeros(self.n, dtype=torch.float64, device=pos.device)
+        self.steps = torch.zeros(self.n, dtype=torch.int32, device=pos.device)  # block steps of each cluster
         self.acc = torch.empty((3, self.n), dtype=torch.float64, device=pos.device)
         self.n_clusters = 0
         self._evaluate()
@@ -78,8 +79,8 @@ class P3TStepper:
         c.kick(self.acc, self.vel, 0.5 * self.dt)
         if self.overlap:
             _, self.n_clusters, self.n_slow = c.hard_evaluate(
-                self.pos, self.vel, self.mass, self.r_out, self.dt_hard, self.r_out_next, self.r_search_next,
-                out=self.acc, slow_log2=self.slow_log2, graph=self.graph)
+                self.pos, self.vel, self.mass, self.r_out, self.dt_hard, self.steps, self.r_out_next,
+                self.r_search_next, out=self.acc, slow_log2=self.slow_log2, graph=self.graph)
             if self.recompute:
                 # the radii just used become those of the next hard part;
                 # the next evaluation's come from the state at hand

@@ -1,6 +1,7 @@
 """GPU parity of p3t_hard_evaluate: the hard part and the next evaluation in
-one call, the slow clusters integrating on a second stream while the tree of
-everyone else is evaluated, their soft terms then summed directly.
+one call.  Clusters still running after 2^slow_log2 block steps park and
+finish on a second stream while the tree of everyone else is evaluated;
+their soft terms are then summed directly.
 
 Against p3t_hard_step followed by p3t_evaluate from the same state:
   * positions, velocities and carried hard steps: bit for bit (the same
@@ -13,8 +14,6 @@ Against p3t_hard_step followed by p3t_evaluate from the same state:
     evaluation at this angle;
   * the captured-graph form equals the eager form bit for bit.
 """
-import math
-
 import numpy as np
 import pytest
 import torch
@@ -44,18 +43,12 @@ def params(gpu, orc, **kw):
     return gp.replace(**kw)
 
 
-def levels(dt_hard, dt_soft):
-    d = dt_hard.cpu().numpy()
-    lv = np.zeros(d.shape[0], dtype=np.int64)
-    pos = d > 0
-    lv[pos] = np.rint(np.log2(dt_soft / d[pos])).astype(np.int64)
-    return lv
-
-
-def pick_slow_log2(lv, lo, hi):
-    """Smallest level threshold with between lo and hi particles at or above it."""
-    for L in range(1, 41):
-        k = int((lv >= L).sum())
+def pick_slow_log2(steps, lo, hi):
+    """Smallest budget 2^L with between lo and hi particles whose cluster
+    took more than 2^L block steps (in the integration `steps` records)."""
+    st = steps.cpu().numpy()
+    for L in range(1, 31):
+        k = int((st > (1 << L)).sum())
         if lo <= k <= hi:
             return L
     return None
@@ -63,20 +56,21 @@ def pick_slow_log2(lv, lo, hi):
 
 @pytest.fixture(scope="module")
 def stepped(gpu, orc):
-    """disk64k after two plain P3T steps (theta 0.5, quadrupole, mixed
-    precision), so that every particle carries the hard step of its last
-    integration."""
+    """disk64k after two P3T steps (theta 0.5, quadrupole, mixed precision,
+    no budget), so that every particle carries its hard step and the
+    block-step count of its last cluster."""
     from paper_2007_15432_amd.driver import P3TStepper
 
     d = diskgen.workload("disk64k_masslaw")
     p = params(gpu, orc, theta=0.5, multipole=2, precision=1)
     ctx = gpu.Context(p)
-    st = P3TStepper(ctx, T(d.pos), T(d.vel), T(d.mass))
+    st = P3TStepper(ctx, T(d.pos), T(d.vel), T(d.mass), overlap=True, slow_log2=29)
     for _ in range(2):
         st.step()
     torch.cuda.synchronize()
+    assert st.n_slow == 0 and int(st.steps.max().item()) > 0
     return dict(d=d, p=p, pos=st.pos.clone(), vel=st.vel.clone(), m=st.mass.clone(), ro=st.r_out.clone(),
-                rs=st.r_search.clone(), dt=st.dt_hard.clone())
+                rs=st.r_search.clone(), dt=st.dt_hard.clone(), steps=st.steps.clone())
 
 
 def serial(gpu, s):
@@ -93,50 +87,52 @@ def overlapped(gpu, s, slow_log2, graph=False, reps=1):
     ctx = gpu.Context(s["p"])
     outs = []
     for _ in range(reps):
-        pos, vel, dt = s["pos"].clone(), s["vel"].clone(), s["dt"].clone()
+        pos, vel, dt, steps = s["pos"].clone(), s["vel"].clone(), s["dt"].clone(), s["steps"].clone()
         ctx.evaluate(pos, vel, s["m"], s["ro"], s["rs"])
-        acc, nc, ns = ctx.hard_evaluate(pos, vel, s["m"], s["ro"], dt, s["ro"], s["rs"], slow_log2=slow_log2,
-                                        graph=graph)
+        acc, nc, ns = ctx.hard_evaluate(pos, vel, s["m"], s["ro"], dt, steps, s["ro"], s["rs"],
+                                        slow_log2=slow_log2, graph=graph)
         torch.cuda.synchronize()
         assert ctx.status() == 0
         rp, col, _ = ctx.neighbour_list()
         outs.append(dict(pos=pos, vel=vel, dt=dt, acc=acc.clone(), rp=rp, col=col, nc=nc, ns=ns,
-                         stats=ctx.stats()))
+                         stats=ctx.stats(), steps=steps))
     return outs
 
 
 @pytest.mark.parametrize("band", [(8, 300), (1100, 10 ** 9)], ids=["few", "over_cap"])
 def test_hard_evaluate_matches_serial(gpu, orc, stepped, band):
+    """Few parked clusters: overlapped; more than 1024 parked members: they
+    finish before the tree and the call is exactly the serial one."""
     s = stepped
-    lv = levels(s["dt"], s["p"].dt_soft)
-    L = pick_slow_log2(lv, *band)
+    L = pick_slow_log2(s["steps"], *band)
     if L is None:
-        pytest.skip(f"no level threshold puts {band} particles in slow clusters (levels {np.bincount(lv)})")
-    print("levels", np.bincount(lv), "slow_log2", L)
+        pytest.skip(f"no budget puts {band} particles in long clusters (max steps {int(s['steps'].max())})")
     a = serial(gpu, s)
     b = overlapped(gpu, s, L)[0]
-    print("clusters", a["nc"], b["nc"], "slow members", b["ns"], "ms_direct", b["stats"]["ms_direct"])
+    st_b = b["steps"].cpu().numpy()
+    long_ = st_b > (1 << L)  # clusters that ran past the budget (all of 1..64 members here)
+    print("slow_log2", L, "parked", b["ns"], "past the budget", int(long_.sum()), "max steps", int(st_b.max()),
+          "ms_direct", b["stats"]["ms_direct"])
     assert a["nc"] == b["nc"]
-    assert 0 < b["ns"] <= 1024
     for k in ("pos", "vel", "dt", "rp"):
         assert torch.equal(a[k], b[k]), k
     assert torch.equal(a["col"], b["col"])
+    if int(long_.sum()) > 1024:
+        assert b["ns"] == 0
+        assert torch.equal(a["acc"], b["acc"])
+        return
+    assert b["ns"] == int(long_.sum()) > 0
     # forces against the oracle's direct FP64 sum at the new state
     pos = b["pos"].cpu().numpy()
     m = s["m"].cpu().numpy()
     ro = s["ro"].cpu().numpy()
     op = orc.Params()
     n = m.shape[0]
-    flag_slow = np.zeros(n, dtype=bool)
-    dt_new = b["dt"].cpu().numpy()
-    # the slow members are those of the clusters flagged by their carried steps
-    slow_idx = np.nonzero(lv >= L)[0]
-    flag_slow[slow_idx] = True
+    slow_idx = np.nonzero(long_)[0]
     ref_s = orc.soft_acc(pos, m, ro, op, idx=slow_idx)
     e_s = errs(b["acc"].cpu().numpy()[:, slow_idx], ref_s)
-    print("particles at or above the threshold vs oracle", e_s)
-    if band[1] <= 1024:  # all their clusters fit: all of them were summed directly
-        assert e_s[2] < 1e-12
+    print("parked members vs oracle", e_s)
+    assert e_s[2] < 1e-12
     idx = diskgen.sample_indices(n, 2048, 21)
     ref = orc.soft_acc(pos, m, ro, op, idx=idx)
     e_a = errs(a["acc"].cpu().numpy()[:, idx], ref)
@@ -146,23 +142,23 @@ def test_hard_evaluate_matches_serial(gpu, orc, stepped, band):
     # 2e-3, global 5e-4); exact terms in place of tree terms only lower it
     assert e_b[0] < 2e-3 and e_b[1] < 5e-4
     assert e_b[1] <= 1.05 * e_a[1] + 1e-9
-    assert np.isfinite(dt_new).all()
+    assert torch.equal(a["acc"] != a["acc"], b["acc"] != b["acc"])  # no NaN introduced
 
 
 def test_hard_evaluate_graph_equals_eager(gpu, orc, stepped):
     s = stepped
-    L = pick_slow_log2(levels(s["dt"], s["p"].dt_soft), 8, 300)
+    L = pick_slow_log2(s["steps"], 8, 300)
     if L is None:
         pytest.skip("no slow clusters in this state")
     e = overlapped(gpu, s, L)[0]
     g = overlapped(gpu, s, L, graph=True, reps=3)  # capture, then replays
     for r in g:
-        for k in ("pos", "vel", "dt", "acc", "rp", "col"):
+        for k in ("pos", "vel", "dt", "acc", "rp", "col", "steps"):
             assert torch.equal(e[k], r[k]), k
 
 
 def test_hard_evaluate_without_split_is_serial(gpu, orc, stepped):
-    """slow_log2 = 0 (or no carried steps): exactly hard_step + evaluate."""
+    """slow_log2 = 0: exactly hard_step + evaluate."""
     s = stepped
     a = serial(gpu, s)
     b = overlapped(gpu, s, 0)[0]
@@ -179,9 +175,9 @@ def test_overlapped_stepper_tracks_serial(gpu, orc):
 
     d = diskgen.workload("disk64k_masslaw")
     p = params(gpu, orc, theta=0.5, multipole=2, precision=1)
-    probe = P3TStepper(gpu.Context(p), T(d.pos), T(d.vel), T(d.mass))
+    probe = P3TStepper(gpu.Context(p), T(d.pos), T(d.vel), T(d.mass), overlap=True, slow_log2=29)
     probe.step()
-    L = pick_slow_log2(levels(probe.dt_hard, p.dt_soft), 8, 300)
+    L = pick_slow_log2(probe.steps, 8, 300)
     if L is None:
         pytest.skip("no slow clusters after one step")
     runs = []
@@ -206,5 +202,6 @@ def test_hard_evaluate_empty(gpu, orc):
     z3 = torch.zeros((3, 0), dtype=torch.float64, device=DEV)
     z = torch.zeros(0, dtype=torch.float64, device=DEV)
     ctx.evaluate(z3, z3, z, z, z)
-    acc, nc, ns = ctx.hard_evaluate(z3, z3, z, z, z, z, z, slow_log2=3)
+    zi = torch.zeros(0, dtype=torch.int32, device=DEV)
+    acc, nc, ns = ctx.hard_evaluate(z3, z3, z, z, z, zi, z, z, slow_log2=3)
     assert acc.numel() == 0 and nc == 0 and ns == 0
