@@ -8,7 +8,11 @@ A step is one pass of the whole hot path on the GPU (cut-off radii, first
 kick, neighbour clusters, Hermite hard part, tree build, walk, soft force with
 neighbour pairs, neighbour CSR and cluster indices, second kick).  value =
 interactions evaluated per step / wall time per step, inputs resident in HBM.
-The mixed-precision form is the headline; the plain FP64 path runs beside it.
+The mixed-precision batched form is the headline: its hard part parks the
+clusters still running after 2^9 block steps and finishes them on a second
+stream beside the tree (p3t_hard_evaluate), and the interactions counted are
+the tree's (the direct terms of the parked members are not added).  The plain
+FP64 path and the mixed path without the overlap run beside it.
 
 Prints one JSON line.  Only the cpu_baseline leg touches the CPU oracle: it
 times the oracle's direct sum on a sample of i-particles and, with the same
@@ -314,7 +318,7 @@ def main():
             "workload": f"disk1m_masslaw: N={disk.n} planetesimals, a in [0.5, 5] au, sigma ~ a^-3/2, "
                         "dN/dm ~ m^-2.5 on [1e-10, 1e-8], rms e = 2 rms i = 2 h(1e-9); theta=0.5 quadrupole; "
                         f"groups <= {n_group}, leaves <= {n_leaf}; launch shapes autotuned; one P3T soft step "
-                        "per step",
+                        "per step (hard part overlapped with the tree for clusters past 2^9 block steps)",
             "path": head,
         },
         "roofline": {k: v for k, v in h["roofline"].items()},

@@ -707,7 +707,7 @@ p3t_status ensure_overlap(p3t_ctx *c) {
   const int64_t nc = c->n_cap;
   auto bytes = [](int64_t count, size_t sz) { return ((size_t)count * sz + 255) & ~size_t(255); };
   const size_t total = 4 * bytes(3 * nc, sizeof(double)) + bytes(nc, sizeof(int64_t)) + 2 * bytes(nc, sizeof(int32_t)) +
-                       2 * bytes(nc, sizeof(double)) + bytes(7 * nc, sizeof(int32_t)) + bytes(nc, sizeof(int32_t)) +
+                       2 * bytes(nc, sizeof(double)) + bytes(10 * nc, sizeof(int32_t)) + bytes(nc, sizeof(int32_t)) +
                        bytes((int64_t)SLOW_CAP * SLOW_CHUNKS * 3, sizeof(double));
   c->ov_n_cap = 0;
   c->pk_x = nullptr;
@@ -724,7 +724,7 @@ p3t_status ensure_overlap(p3t_ctx *c) {
   c->pk_nst = A.take<int32_t>(nc);
   c->pk_e0 = A.take<double>(nc);
   c->m_eff = A.take<double>(nc);
-  c->pk_lists = A.take<int32_t>(7 * nc);
+  c->pk_lists = A.take<int32_t>(10 * nc);
   c->slow_list = A.take<int32_t>(nc);
   c->slow_part = A.take<double>((int64_t)SLOW_CAP * SLOW_CHUNKS * 3);
   if (!c->slow_part) return fail(c, P3T_ERR_HIP, "overlap buffer layout overflow (internal)");

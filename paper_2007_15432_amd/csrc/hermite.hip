@@ -40,7 +40,7 @@ struct HermArgs {
   double *dt_hard, *e_rel;
   int32_t *nsteps;
   int32_t *msteps;  // per particle: block steps of its cluster (nullable)
-  // Parking (clusters of 1..64 members): with budget > 0 a cluster still
+  // Parking: with budget > 0 a cluster still
   // running after `budget` block steps saves its state to pk and stops;
   // resume = 1 continues parked clusters from pk and writes their final
   // state to pos / vel.
@@ -51,8 +51,8 @@ struct HermArgs {
     int32_t *lev;           // per member: its block level
     int32_t *nst;           // per cluster: block steps so far
     double *e0;             // per cluster: energy at the start
-    int32_t *count;         // [0, 7) parked clusters per bucket, [PK_MEM] parked members
-    int32_t *lists;         // parked clusters, 7 lists of n
+    int32_t *count;         // [0, 10) parked clusters per bucket, [PK_MEM] parked members
+    int32_t *lists;         // parked clusters, 10 lists of n
     int32_t *members;       // parked members (n)
     uint8_t *flag;          // per particle: 1 if parked (cleared by the caller)
   } pk;
@@ -556,8 +556,9 @@ __device__ __forceinline__ int block_excl_scan_i32(int v, int &excl, int64_t *sh
 }
 
 // One 256-thread workgroup per cluster c, MPT members per thread.
-template <int MPT>
-__device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L, int64_t *shi, double *shd) {
+template <int MPT, int MODE>
+__device__ __forceinline__ void big_body(const HermArgs &A, int c, int bk, const Lds &L, int64_t *shi, double *shd) {
+  constexpr bool RESUME = MODE == 2, PARK = MODE == 1;
   const int tid = threadIdx.x;
   const int b = A.cl_ptr[c];
   const int size = A.cl_ptr[c + 1] - b;
@@ -578,9 +579,10 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L,
     m[u] = 0.0;
     double ro = 1.0;
     if (mem[u]) {
+      const double *sx = RESUME ? A.pk.x : A.pos, *sv = RESUME ? A.pk.v : A.vel;
       for (int d = 0; d < 3; ++d) {
-        x[u][d] = A.pos[d * n + gid[u]];
-        v[u][d] = A.vel[d * n + gid[u]];
+        x[u][d] = sx[d * n + gid[u]];
+        v[u][d] = sv[d * n + gid[u]];
       }
       m[u] = A.mass[gid[u]];
       ro = A.ro[gid[u]];
@@ -604,6 +606,15 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L,
     star_term(x[u], v[u], A.GM, a0[u], j0[u]);
     lev[u] = 0;
     if (!mem[u]) continue;
+    if (RESUME) {  // a parked cluster continues from its saved state
+      for (int d = 0; d < 3; ++d) {
+        a0[u][d] = A.pk.a[d * n + gid[u]];
+        j0[u][d] = A.pk.j[d * n + gid[u]];
+      }
+      t[u] = A.pk.t[gid[u]];
+      lev[u] = A.pk.lev[gid[u]];
+      continue;
+    }
     e += 0.5 * m[u] * (v[u][0] * v[u][0] + v[u][1] * v[u][1] + v[u][2] * v[u][2]) -
          A.GM * m[u] * rsqrt(x[u][0] * x[u][0] + x[u][1] * x[u][1] + x[u][2] * x[u][2]);
     for (int q = 0; q < size; ++q) {
@@ -619,10 +630,15 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L,
     }
     lev[u] = initial_level(a0[u], j0[u], true, gid[u], A);
   }
-  const double E0 = block_sum(e, shd);
+  double E0 = block_sum(e, shd);
   const int64_t T = (int64_t)1 << TICK_BITS;
   int it = 0;  // block steps taken
-  for (;; ++it) {
+  if (RESUME) {
+    E0 = A.pk.e0[c];
+    it = A.pk.nst[c];
+  }
+  const int budget = PARK ? A.budget : INT_MAX;
+  for (int its = 0;; ++it, ++its) {
     int64_t tel = LLONG_MAX;
 #pragma unroll
     for (int u = 0; u < MPT; ++u)
@@ -632,6 +648,33 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, const Lds &L,
       }
     const int64_t tn = uniform_first64(block_min_i64(tel, shi));
     if (tn > T) break;  // every member has reached T (see seg_body)
+    if (its == budget) {  // uniform: park the cluster and stop
+      __shared__ int pslot;
+      if (tid == 0) {
+        const int k = atomicAdd(&A.pk.count[bk], 1);
+        A.pk.lists[(int64_t)bk * n + k] = c;
+        A.pk.nst[c] = it;
+        A.pk.e0[c] = E0;
+        pslot = atomicAdd(&A.pk.count[PK_MEM], size);
+      }
+      __syncthreads();
+      const int slot = pslot;
+#pragma unroll
+      for (int u = 0; u < MPT; ++u) {
+        if (!mem[u]) continue;
+        for (int d = 0; d < 3; ++d) {
+          A.pk.x[d * n + gid[u]] = x[u][d];
+          A.pk.v[d * n + gid[u]] = v[u][d];
+          A.pk.a[d * n + gid[u]] = a0[u][d];
+          A.pk.j[d * n + gid[u]] = j0[u][d];
+        }
+        A.pk.t[gid[u]] = t[u];
+        A.pk.lev[gid[u]] = lev[u];
+        A.pk.members[slot + tid + BIG_T * u] = gid[u];
+        A.pk.flag[gid[u]] = 1;
+      }
+      return;  // the whole workgroup: finished by the resume launch
+    }
     if (it >= A.max_iter) {
       if (tid == 0) set_flag(A.cnt, P3T_FLAG_NSTEPS);
       break;
@@ -808,7 +851,7 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   seg_body<MODE>(A, blist, count, ci0, L, wbase, bk);
 }
 
-template <int MPT>
+template <int MPT, int MODE>
 __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A, int bk) {
   __shared__ double lds[8][BIG_T * MPT];
   __shared__ int64_t shi[BIG_T / WAVE];
@@ -819,7 +862,7 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A, int bk) {
   __shared__ int act[NACT];
   __shared__ double res[6 * NACT];
   const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7], MPT <= 2 ? act : nullptr, res};
-  big_body<MPT>(A, A.blists[(int64_t)bk * A.nc + blockIdx.x], L, shi, shd);
+  big_body<MPT, MODE>(A, A.blists[(int64_t)bk * A.nc + blockIdx.x], bk, L, shi, shd);
 }
 
 // ---------------------------------------------------------------- bucketing
@@ -971,10 +1014,10 @@ hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr,
 
 // Integrates the clusters of the buckets (counts in hc[0, 11)) on stream s;
 // clusters of 65 members and more go to stream s_big (which may be s),
-// joined back into s at the end.  budget > 0 parks the clusters of 1..64
-// members still running after `budget` block steps (their counts land in
+// joined back into s at the end.  budget > 0 parks the clusters still
+// running after `budget` block steps (their counts land in
 // the park words of herm_bcount).  resume = 1 continues the parked clusters
-// (counts in hc[HERM_BC_PARK0, + 7)) and writes their final state into the
+// (counts in hc[HERM_BC_PARK0, + 10)) and writes their final state into the
 // park buffers' x and v.
 hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
                        double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
@@ -1032,7 +1075,7 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   A.max_iter = 1 << 22;
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
-  for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = resume ? (bk < 7 ? hc[HERM_BC_PARK0 + bk] : 0) : hc[bk];
+  for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = resume ? (bk < 10 ? hc[HERM_BC_PARK0 + bk] : 0) : hc[bk];
   // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG /
   // lanes per member); the clusters of 65 members and more run at the same
   // time in their own launches (one workgroup each)
@@ -1050,9 +1093,20 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
     if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s2, ev_fork, 0)) != hipSuccess) return e;
   }
-  if (A.bcount[7] > 0) hipLaunchKernelGGL(k_herm_big<1>, dim3(A.bcount[7]), dim3(BIG_T), 0, s2, A, 7);
-  if (A.bcount[8] > 0) hipLaunchKernelGGL(k_herm_big<2>, dim3(A.bcount[8]), dim3(BIG_T), 0, s2, A, 8);
-  if (A.bcount[9] > 0) hipLaunchKernelGGL(k_herm_big<4>, dim3(A.bcount[9]), dim3(BIG_T), 0, s2, A, 9);
+  const int mode = resume ? 2 : (budget > 0 ? 1 : 0);
+#define P3T_LAUNCH_BIG(MPT, BK)                                                                         \
+  if (A.bcount[BK] > 0) {                                                                               \
+    if (mode == 2)                                                                                      \
+      hipLaunchKernelGGL((k_herm_big<MPT, 2>), dim3(A.bcount[BK]), dim3(BIG_T), 0, s2, A, BK);          \
+    else if (mode == 1)                                                                                 \
+      hipLaunchKernelGGL((k_herm_big<MPT, 1>), dim3(A.bcount[BK]), dim3(BIG_T), 0, s2, A, BK);          \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_herm_big<MPT, 0>), dim3(A.bcount[BK]), dim3(BIG_T), 0, s2, A, BK);          \
+  }
+  P3T_LAUNCH_BIG(1, 7)
+  P3T_LAUNCH_BIG(2, 8)
+  P3T_LAUNCH_BIG(4, 9)
+#undef P3T_LAUNCH_BIG
   if (blocks > 0) {
     if (resume)
       hipLaunchKernelGGL(k_herm_fused<2>, dim3(blocks), dim3(BIG_T), 0, s, A);

@@ -129,10 +129,10 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// Hermite bucket-count words (hermite.hip): [0, 11) the buckets, [11, 18)
-// the parked clusters of buckets 0..6, the parked member count, then the
+// Hermite bucket-count words (hermite.hip): [0, 11) the buckets, [11, 21)
+// the parked clusters of buckets 0..9, the parked member count, then the
 // cluster count and the malformed-input flag.
-constexpr int HERM_BC_PARK0 = 11, HERM_BC_PARKED = 18, HERM_BC_NC = 28, HERM_BC_BAD = 29, HERM_BC_WORDS = 32;
+constexpr int HERM_BC_PARK0 = 11, HERM_BC_PARKED = 21, HERM_BC_NC = 28, HERM_BC_BAD = 29, HERM_BC_WORDS = 32;
 constexpr int HERM_N_BUCKETS = 11;
 // parked members of one p3t_hard_evaluate call at most, and the chunks of
 // the direct sum over all particles for each of them
@@ -257,7 +257,7 @@ struct p3t_ctx {
   int32_t *pk_lev = nullptr;        // parked members' levels (n_cap)
   int32_t *pk_nst = nullptr;        // parked clusters' step counts (n_cap)
   double *pk_e0 = nullptr;          // parked clusters' initial energies (n_cap)
-  int32_t *pk_lists = nullptr;      // parked clusters per bucket (7 * SLOW_CAP)
+  int32_t *pk_lists = nullptr;      // parked clusters per bucket (10 * n_cap)
   double *m_eff = nullptr;          // masses with the parked members at zero (n_cap)
   int32_t *slow_list = nullptr;     // parked members (SLOW_CAP)
   double *slow_part = nullptr;      // partial sums of the forces on the parked members

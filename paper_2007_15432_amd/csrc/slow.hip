@@ -12,10 +12,13 @@
 //     Section 2.2 (eq. of the P3T split, changeover K at the larger cut-off),
 //     and every (i, s) that passes the neighbour test of Section 2.3 is
 //     reported in both directions;
+//   - in mixed precision the pairs beyond the larger cut-off (K = 1) take
+//     the Newtonian term in FP32 from an FP64 offset, like the far-particle
+//     kernel; everything else is FP64;
 //   - every s in S gets sum_{j != s} over all particles, directly (partial
 //     sums over SLOW_CHUNKS ranges of j, added in order), and the pairs
 //     (s, s') with s' in S are reported from both sides.
-// Sums are in FP64 and in a fixed order, so the result is reproducible; the
+// Sums are accumulated in FP64 in a fixed order, so the result is reproducible; the
 // pairs arrive in any order (the CSR build sorts every row).
 #include "force_common.h"
 
@@ -44,6 +47,35 @@ __device__ __forceinline__ void soft_term(const SoftPair &P, double dx, double d
   az += f * dz;
 }
 
+// The pair term for a pair at d = x_j - x_i: K(r / max(r_out)) = 1 beyond
+// the larger cut-off, where MIXED evaluates the Newtonian term in FP32 (the
+// offset is formed in FP64, as in the far-particle kernel); inside it, and
+// always without MIXED, the FP64 soft term.
+template <bool MIXED>
+__device__ __forceinline__ void pair_term(const SoftPair &P, double dx, double dy, double dz, double gm, double invi,
+                                          double invj, double &ax, double &ay, double &az) {
+  if (MIXED) {
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double inv = fmin(invi, invj);
+    if (r2 * (inv * inv) > 1.0 + 1e-12) {  // y > 1: K = 1
+      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+      const float ri = rsqrtf(fx * fx + fy * fy + fz * fz);
+      const float f = (float)gm * ri * ri * ri;
+      ax += (double)(f * fx);
+      ay += (double)(f * fy);
+      az += (double)(f * fz);
+      return;
+    }
+  }
+  soft_term(P, dx, dy, dz, gm, invi, invj, ax, ay, az);
+}
+
+// reach of the neighbour test: no pair beyond the larger search radius passes
+__device__ __forceinline__ bool may_neighbour(double dx, double dy, double dz, double rsi, double rsj) {
+  const double rs = fmax(rsi, rsj);
+  return dx * dx + dy * dy + dz * dz < rs * rs * (1.0 + 1e-12);
+}
+
 __device__ __forceinline__ void push_pair(DevCounters *cnt, int2 *pairs, int64_t cap, int a, int b) {
   const unsigned long long q = atomicAdd(&cnt->n_pairs, 1ull);
   if ((int64_t)q < cap)
@@ -66,6 +98,7 @@ struct SlowArgs {
   SoftPair P;
   double rsch2, rsch3, dt;
 };
+
 
 constexpr int ST = 256;  // threads per block of the direct kernels
 
@@ -111,6 +144,7 @@ __global__ void k_slow_scatter(int64_t n, int ns, const int32_t *__restrict__ li
 }
 
 // every particle outside S: add the terms of S, report its pairs with S
+template <bool MIXED>
 __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
   __shared__ double tx[ST], ty[ST], tz[ST], tvx[ST], tvy[ST], tvz[ST], tm[ST], tro[ST], trs[ST], tinv[ST];
   __shared__ int32_t tid_[ST];
@@ -145,7 +179,9 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
       __syncthreads();
       if (act) {
         for (int k = 0; k < m; ++k) {
-          soft_term(A.P, tx[k] - xi, ty[k] - yi, tz[k] - zi, A.P.G * tm[k], invi, tinv[k], ax, ay, az);
+          const double dx = tx[k] - xi, dy = ty[k] - yi, dz = tz[k] - zi;
+          pair_term<MIXED>(A.P, dx, dy, dz, A.P.G * tm[k], invi, tinv[k], ax, ay, az);
+          if (!may_neighbour(dx, dy, dz, rsi, trs[k])) continue;
           if (tx[k] == xi && ty[k] == yi && tz[k] == zi) coincident = true;
           if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, tx[k], ty[k], tz[k], tvx[k], tvy[k], tvz[k],
                              tm[k], tro[k], trs[k], A.P.G, A.rsch2, A.rsch3, A.dt)) {
@@ -171,6 +207,7 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
 // Each particle of the chunk is loaded once for SG members.
 constexpr int SG = 8;
 
+template <bool MIXED>
 __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
   __shared__ double red[3 * SG][ST / WAVE];
   const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
@@ -197,7 +234,7 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
     // j = s itself gives r = 0, hence K = 0 and an exact zero term
 #pragma unroll
     for (int g = 0; g < SG; ++g)
-      if (g < gc) soft_term(A.P, xj - xi[g], yj - yi[g], zj - zi[g], gmj, invi[g], invj, ax[g], ay[g], az[g]);
+      if (g < gc) pair_term<MIXED>(A.P, xj - xi[g], yj - yi[g], zj - zi[g], gmj, invi[g], invj, ax[g], ay[g], az[g]);
     if (A.slow[j]) {  // pairs within S (rare)
       for (int g = 0; g < gc; ++g) {
         const int64_t i = ig[g];
@@ -286,8 +323,14 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
   A.rsch3 = c->P.r_search3;
   A.dt = c->P.dt_soft;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + ST - 1) / ST));
-  hipLaunchKernelGGL(k_slow_into, dim3(g), dim3(ST), 0, s, A);
-  hipLaunchKernelGGL(k_slow_from, dim3(SLOW_CHUNKS, (ns + SG - 1) / SG), dim3(ST), 0, s, A);
+  const dim3 gf(SLOW_CHUNKS, (ns + SG - 1) / SG);
+  if (c->P.precision == 1) {
+    hipLaunchKernelGGL(k_slow_into<true>, dim3(g), dim3(ST), 0, s, A);
+    hipLaunchKernelGGL(k_slow_from<true>, gf, dim3(ST), 0, s, A);
+  } else {
+    hipLaunchKernelGGL(k_slow_into<false>, dim3(g), dim3(ST), 0, s, A);
+    hipLaunchKernelGGL(k_slow_from<false>, gf, dim3(ST), 0, s, A);
+  }
   hipLaunchKernelGGL(k_slow_reduce, dim3((ns + 255) / 256), dim3(256), 0, s, A);
   return hipGetLastError();
 }
