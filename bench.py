@@ -47,7 +47,8 @@ PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published, packed)
 METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force error"
 
 
-def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None, overlap=False):
+def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None, overlap=False,
+             slow_log2=9):
     from paper_2007_15432_amd.driver import P3TStepper
 
     dev = "cuda:0"
@@ -61,7 +62,7 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
     m = torch.tensor(disk.mass, dtype=torch.float64, device=dev)
     # force at the initial state, kept for the error measurement
-    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph, overlap=overlap)
+    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph, overlap=overlap, slow_log2=slow_log2)
     acc0 = st.acc.clone()
     r_out0 = st.r_out.clone()
     for _ in range(warmup):
@@ -245,6 +246,8 @@ def main():
                     help="mixed: FP32 bulk / FP64 near, slow clusters overlapped with the tree; fp64: plain FP64, "
                          "hard part then tree; mixed_serial: mixed precision, hard part then tree")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph run of the mixed path")
+    ap.add_argument("--slow-log2", type=int, default=9,
+                    help="mixed path: clusters still running after 2^k block steps finish beside the tree")
     ap.add_argument("--no-autotune", action="store_true", help="use --n-group / --n-leaf and the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the FETCH/WRITE counters)")
@@ -282,7 +285,7 @@ def main():
     for name in args.paths.split(","):
         prec = 1 if name.startswith("mixed") else 0
         results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, n_group, n_leaf, kcfg=kcfg,
-                                 overlap=name == "mixed")
+                                 overlap=name == "mixed", slow_log2=args.slow_log2)
         r = results[name]
         print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
               f"force {r['stages_ms']['force']:.2f} ms, {r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}",
@@ -290,7 +293,7 @@ def main():
     graph = None
     if not args.no_graph:
         g = run_path(p3t, torch, disk, 1, args.steps, args.warmup, n_group, n_leaf, graph=True, kcfg=kcfg,
-                     overlap=True)
+                     overlap=True, slow_log2=args.slow_log2)
         graph = {k: g[k] for k in ("value", "ms_per_step", "interactions_per_step")}
         graph["path"] = "mixed with the slow clusters overlapped, tree + walk + force replayed from one captured " \
                         "hipGraph per step"
@@ -318,7 +321,8 @@ def main():
             "workload": f"disk1m_masslaw: N={disk.n} planetesimals, a in [0.5, 5] au, sigma ~ a^-3/2, "
                         "dN/dm ~ m^-2.5 on [1e-10, 1e-8], rms e = 2 rms i = 2 h(1e-9); theta=0.5 quadrupole; "
                         f"groups <= {n_group}, leaves <= {n_leaf}; launch shapes autotuned; one P3T soft step "
-                        "per step (hard part overlapped with the tree for clusters past 2^9 block steps)",
+                        f"per step (hard part overlapped with the tree for clusters past 2^{args.slow_log2} block "
+                        "steps)",
             "path": head,
         },
         "roofline": {k: v for k, v in h["roofline"].items()},
