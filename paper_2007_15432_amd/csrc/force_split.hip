@@ -88,22 +88,38 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
     ax[s] = ay[s] = az[s] = 0.0;
   }
   const int32_t *Ln = A.pool + h.off + h.n_cell;
+  // the next tile's entry of this lane is loaded into registers while the
+  // current tile is evaluated (its gathers are the kernel's memory latency)
+  double4 na;
+  double2 nb;
+  int nj = -2;
+  auto fetch = [&](int t0) {
+    const int nt = min(WAVE, h.n_near - t0);
+    const int ntp = min(WAVE, (nt + UNR - 1) / UNR * UNR);
+    if (lane < nt) {
+      const int j = Ln[t0 + lane];
+      const double r = A.sreach[j];
+      na = make_double4(A.sx[j], A.sy[j], A.sz[j], A.G * A.sm[j]);
+      nb = make_double2(A.sinv[j], r * r * kCandMargin);
+      nj = j;
+    } else if (lane < ntp) {
+      na = make_double4(h.cx + kDummyOffset, h.cy, h.cz, 0.0);
+      nb = make_double2(1.0, 0.0);
+      nj = -2;
+    }
+  };
+  if (h.n_near > 0) fetch(0);
   for (int t0 = 0; t0 < h.n_near; t0 += WAVE) {
     const int nt = min(WAVE, h.n_near - t0);
     const int ntp = min(WAVE, (nt + UNR - 1) / UNR * UNR);
     __syncthreads();
-    if (lane < nt) {
-      const int j = Ln[t0 + lane];
-      const double r = A.sreach[j];
-      T.a[lane] = make_double4(A.sx[j], A.sy[j], A.sz[j], A.G * A.sm[j]);
-      T.b[lane] = make_double2(A.sinv[j], r * r * kCandMargin);
-      T.j[lane] = j;
-    } else if (lane < ntp) {
-      T.a[lane] = make_double4(h.cx + kDummyOffset, h.cy, h.cz, 0.0);
-      T.b[lane] = make_double2(1.0, 0.0);
-      T.j[lane] = -2;
+    if (lane < ntp) {
+      T.a[lane] = na;
+      T.b[lane] = nb;
+      T.j[lane] = nj;
     }
     __syncthreads();
+    if (t0 + WAVE < h.n_near) fetch(t0 + WAVE);
     unsigned cm[2][IPL];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -123,8 +139,11 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
             const double r2 = dx * dx + dy * dy + dz * dz;
             // r = 0 (the particle itself, or a coincident pair, which the
             // candidate test reports) gives y ~ 0 < gamma, so K = 0 and the
-            // term vanishes exactly: rinv^3 = 1e225 stays finite
-            const double r2s = fmax(r2, kTinyR2);
+            // term vanishes exactly: rinv^3 = 1e225 stays finite.  Adding
+            // the floor changes no r^2 above 1e-134 (it is below half an
+            // ulp there) and costs one add instead of a max with operand
+            // canonicalisation.
+            const double r2s = r2 + kTinyR2;
             const double rinv = rsqrt(r2s);
             const double y = r2s * rinv * fmin(invi[s], b.x);
             const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
@@ -135,7 +154,9 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
             ay[s] += f * dy;
             az[s] += f * dz;
             // reach^2 of both sides carry the candidate margin already
-            if (jidx != ii[s] && (r2 <= rch2[s] || r2 <= b.y)) cm[half][s] |= bit;
+            // evaluated without short-circuit, so no branch per pair
+            const bool cand = (jidx != ii[s]) & ((r2 <= rch2[s]) | (r2 <= b.y));
+            cm[half][s] |= cand ? bit : 0u;
           }
         }
       }
