@@ -209,3 +209,38 @@ def test_hard_evaluate_empty(gpu, orc):
     zi = torch.zeros(0, dtype=torch.int32, device=DEV)
     acc, nc, ns = ctx.hard_evaluate(z3, z3, z, z, z, zi, z, z, slow_log2=3)
     assert acc.numel() == 0 and nc == 0 and ns == 0
+
+
+@pytest.mark.parametrize("n,r_cut0", [(4096, 10.0), (2048, 4.0)])
+def test_hard_evaluate_parks_big_clusters(gpu, orc, n, r_cut0):
+    """Dense rings: clusters of tens to hundreds of members, which take the
+    one-workgroup path.  The budget is chosen from a run without parking so
+    that clusters of more than 16 members park where possible; the state and
+    neighbour lists equal the serial call bit for bit (overlapped when at
+    most 1024 members park, through the fallback otherwise)."""
+    d = diskgen.dense_ring(n, seed=11)
+    op = orc.Params(r_cut0=r_cut0)
+    ro, rs, _ = orc.cutoffs(d.pos, d.vel, d.mass, op)
+    p = params(gpu, orc, theta=0.5, multipole=2, precision=0).replace(r_cut0=r_cut0)
+    s = dict(p=p, pos=T(d.pos), vel=T(d.vel), m=T(d.mass), ro=T(ro), rs=T(rs),
+             dt=torch.zeros(d.n, dtype=torch.float64, device=DEV),
+             steps=torch.zeros(d.n, dtype=torch.int32, device=DEV))
+    probe = overlapped(gpu, s, 29)[0]  # no parking: the step counts of this integration
+    L = pick_slow_log2(probe["steps"], 8, 1000) or 2
+    a = serial(gpu, s)
+    b = overlapped(gpu, s, L)[0]
+    st_b = b["steps"].cpu().numpy()
+    ctx = gpu.Context(p)
+    ctx.evaluate(s["pos"], s["vel"], s["m"], s["ro"], s["rs"])
+    _, _, lab = ctx.neighbour_list(labels=True)
+    cl_ptr, members = ctx.clusters(lab)
+    cp, mem = cl_ptr.cpu().numpy(), members.cpu().numpy()
+    sizes = np.diff(cp)
+    big_parked = sum(1 for k in range(len(sizes)) if sizes[k] > 16 and st_b[mem[cp[k]]] > (1 << L))
+    past = int((st_b > (1 << L)).sum())
+    print(f"n={n} r_cut0={r_cut0}: clusters {len(sizes)}, largest {int(sizes.max())}, slow_log2 {L}, "
+          f"parked {b['ns']}, past the budget {past}, clusters above 16 members parked {big_parked}")
+    assert sizes.max() > 16  # the workgroup path is exercised
+    for k in ("pos", "vel", "dt", "rp", "col", "steps"):
+        assert torch.equal(a[k] if k in a else probe[k], b[k]), k
+    assert b["ns"] == (past if past <= 1024 else 0)
