@@ -210,21 +210,21 @@ constexpr int SG = 8;
 template <bool MIXED>
 __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
   __shared__ double red[3 * SG][ST / WAVE];
+  __shared__ double4 mem_x[SG];  // the block's members: x, y, z, 1 / r_out (read as broadcasts)
+  __shared__ int64_t mem_i[SG];
   const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
   const int s0 = blockIdx.y * SG;
   const int gc = min(SG, A.ns - s0);  // members in this block, uniform
   const int64_t n = A.n;
-  int64_t ig[SG];
-  double xi[SG], yi[SG], zi[SG], invi[SG], ax[SG], ay[SG], az[SG];
-#pragma unroll
-  for (int g = 0; g < SG; ++g) {
-    ig[g] = A.list[s0 + (g < gc ? g : gc - 1)];
-    xi[g] = A.pos[ig[g]];
-    yi[g] = A.pos[n + ig[g]];
-    zi[g] = A.pos[2 * n + ig[g]];
-    invi[g] = 1.0 / A.ro[ig[g]];
-    ax[g] = ay[g] = az[g] = 0.0;
+  if (t < SG) {
+    const int64_t i = A.list[s0 + (t < gc ? t : gc - 1)];
+    mem_i[t] = i;
+    mem_x[t] = make_double4(A.pos[i], A.pos[n + i], A.pos[2 * n + i], 1.0 / A.ro[i]);
   }
+  __syncthreads();
+  double ax[SG], ay[SG], az[SG];
+#pragma unroll
+  for (int g = 0; g < SG; ++g) ax[g] = ay[g] = az[g] = 0.0;
   const int64_t chunk = (n + SLOW_CHUNKS - 1) / SLOW_CHUNKS;
   const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
   bool coincident = false;
@@ -233,15 +233,20 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
     const double mj = A.mass[j], roj = A.ro[j], gmj = A.P.G * mj, invj = 1.0 / roj;
     // j = s itself gives r = 0, hence K = 0 and an exact zero term
 #pragma unroll
-    for (int g = 0; g < SG; ++g)
-      if (g < gc) pair_term<MIXED>(A.P, xj - xi[g], yj - yi[g], zj - zi[g], gmj, invi[g], invj, ax[g], ay[g], az[g]);
+    for (int g = 0; g < SG; ++g) {
+      if (g < gc) {
+        const double4 q = mem_x[g];
+        pair_term<MIXED>(A.P, xj - q.x, yj - q.y, zj - q.z, gmj, q.w, invj, ax[g], ay[g], az[g]);
+      }
+    }
     if (A.slow[j]) {  // pairs within S (rare)
       for (int g = 0; g < gc; ++g) {
-        const int64_t i = ig[g];
+        const int64_t i = mem_i[g];
         if (j == i) continue;
-        if (xj == xi[g] && yj == yi[g] && zj == zi[g]) coincident = true;
-        if (neighbour_test(xi[g], yi[g], zi[g], A.vel[i], A.vel[n + i], A.vel[2 * n + i], A.mass[i], A.ro[i], A.rs[i],
-                           xj, yj, zj, A.vel[j], A.vel[n + j], A.vel[2 * n + j], mj, roj, A.rs[j], A.P.G, A.rsch2,
+        const double4 q = mem_x[g];
+        if (xj == q.x && yj == q.y && zj == q.z) coincident = true;
+        if (neighbour_test(q.x, q.y, q.z, A.vel[i], A.vel[n + i], A.vel[2 * n + i], A.mass[i], A.ro[i], A.rs[i], xj,
+                           yj, zj, A.vel[j], A.vel[n + j], A.vel[2 * n + j], mj, roj, A.rs[j], A.P.G, A.rsch2,
                            A.rsch3, A.dt))
           push_pair(A.cnt, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
       }

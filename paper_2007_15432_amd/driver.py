@@ -83,10 +83,17 @@ class P3TStepper:
                 self.r_search_next, out=self.acc, slow_log2=self.slow_log2, graph=self.graph)
             if self.recompute:
                 # the radii just used become those of the next hard part;
-                # the next evaluation's come from the state at hand
-                self.r_out.copy_(self.r_out_next)
-                self.r_search.copy_(self.r_search_next)
-                self.v_ran.copy_(self.v_ran_next)
+                # the next evaluation's come from the state at hand.  A
+                # captured evaluation keeps its buffers (copy); otherwise the
+                # two sets simply trade places.
+                if self.graph:
+                    self.r_out.copy_(self.r_out_next)
+                    self.r_search.copy_(self.r_search_next)
+                    self.v_ran.copy_(self.v_ran_next)
+                else:
+                    self.r_out, self.r_out_next = self.r_out_next, self.r_out
+                    self.r_search, self.r_search_next = self.r_search_next, self.r_search
+                    self.v_ran, self.v_ran_next = self.v_ran_next, self.v_ran
                 c.compute_cutoffs(self.pos, self.vel, self.mass,
                                   out=(self.r_out_next, self.r_search_next, self.v_ran_next))
             c.kick(self.acc, self.vel, 0.5 * self.dt)
