@@ -827,7 +827,10 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   __shared__ int act[BIG_ACT];
   __shared__ double res[6 * BIG_ACT];
   const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7], act, res};
-  const int blk = blockIdx.x;
+  // workgroups are dispatched roughly in index order: the buckets of the
+  // larger clusters (fewer, longer chains) take the first indices, the
+  // singletons the last, so the long chains start first
+  const int blk = gridDim.x - 1 - blockIdx.x;
   // bucket of this workgroup (boff is non-decreasing).  Only constant
   // indices into the argument struct: a run-time index would make the
   // compiler copy the whole struct to per-lane scratch memory.
