@@ -708,7 +708,8 @@ p3t_status ensure_overlap(p3t_ctx *c) {
   auto bytes = [](int64_t count, size_t sz) { return ((size_t)count * sz + 255) & ~size_t(255); };
   const size_t total = 4 * bytes(3 * nc, sizeof(double)) + bytes(nc, sizeof(int64_t)) + 2 * bytes(nc, sizeof(int32_t)) +
                        2 * bytes(nc, sizeof(double)) + bytes(10 * nc, sizeof(int32_t)) + bytes(nc, sizeof(int32_t)) +
-                       bytes((int64_t)SLOW_CAP * SLOW_CHUNKS * 3, sizeof(double));
+                       bytes((int64_t)SLOW_CAP * SLOW_CHUNKS * 3, sizeof(double)) + bytes(3 * nc, sizeof(double)) +
+                       bytes(64 * SLOW_CAP, sizeof(int2));
   c->ov_n_cap = 0;
   c->pk_x = nullptr;
   HIP_OK(c, dev_alloc(c->ov_buf, (int64_t)total));
@@ -727,7 +728,10 @@ p3t_status ensure_overlap(p3t_ctx *c) {
   c->pk_lists = A.take<int32_t>(10 * nc);
   c->slow_list = A.take<int32_t>(nc);
   c->slow_part = A.take<double>((int64_t)SLOW_CAP * SLOW_CHUNKS * 3);
-  if (!c->slow_part) return fail(c, P3T_ERR_HIP, "overlap buffer layout overflow (internal)");
+  c->acc_d = A.take<double>(3 * nc);
+  c->pairs_d = A.take<int2>(64 * SLOW_CAP);
+  c->pairs_d_cap = 64 * SLOW_CAP;
+  if (!c->pairs_d) return fail(c, P3T_ERR_HIP, "overlap buffer layout overflow (internal)");
   c->ov_n_cap = nc;
   return P3T_OK;
 }
@@ -782,7 +786,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
     // too many for the direct sums: finish them here, then evaluate as usual
     HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr,
                           nullptr, steps, hc, 0, 1, c->stream, c->stream, nullptr, nullptr));
-    HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, nullptr, ns));  // copies the state back only
+    HIP_OK(c, slow_merge(c, pos3, vel3, nullptr, ns));  // copies the state back only
     HIP_OK(c, hipMemsetAsync(c->slow_flag, 0, (size_t)n, c->stream));
     if (c->timing) {
       ev_record(c, 10);
@@ -793,10 +797,13 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
     return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
   }
   if (ns > 0) {
+    // resume, then the direct terms of S, both beside the evaluation below
+    HIP_OK(c, hipMemsetAsync(&c->cnt->n_pairs_d, 0, sizeof(unsigned long long), c->stream));
     HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
     HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
     HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
                           steps, hc, 0, 1, c->slow_stream, c->slow_stream, nullptr, nullptr));
+    HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, ns, c->slow_stream));
     HIP_OK(c, hipEventRecord(c->slow_ev[1], c->slow_stream));
   }
   // everyone else: tree, walk and force at the new state, S massless (with
@@ -805,16 +812,17 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   c->slow_active = 1;
   st = p3t_evaluate(c, n, pos3, vel3, c->m_eff, r_out, r_search, acc3, use_graph);
   c->slow_active = 0;
-  // join; S's new state goes back into pos3 / vel3 inside slow_direct
+  // join: S's new state into pos3 / vel3, its terms into acc3
   if (ns > 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slow_ev[1], 0));
   ev_record(c, 15);
-  if (ns > 0) HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, acc3, ns));
   if (st != P3T_OK && st != P3T_ERR_NUMERIC) {
     // the state is still that of p3t_hard_step; the force is not
+    if (ns > 0) HIP_OK(c, slow_merge(c, pos3, vel3, nullptr, ns));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->force_valid = false;
     return st;
   }
+  if (ns > 0) HIP_OK(c, slow_merge(c, pos3, vel3, acc3, ns));
   const p3t_status st_eval = st;  // P3T_ERR_NUMERIC: flagged, but complete
   ev_record(c, 16);
   DevCounters h;

@@ -62,6 +62,7 @@ struct DevCounters {
   unsigned long long n_chunks;     // subtree roots of the bottom-up moment pass
   unsigned long long queue[3];    // persistent queues of the split force kernels
   unsigned long long n_cand;      // neighbour candidates appended (split force)
+  unsigned long long n_pairs_d;   // pairs of the parked members' direct terms (p3t_hard_evaluate)
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -261,6 +262,9 @@ struct p3t_ctx {
   double *m_eff = nullptr;          // masses with the parked members at zero (n_cap)
   int32_t *slow_list = nullptr;     // parked members (SLOW_CAP)
   double *slow_part = nullptr;      // partial sums of the forces on the parked members
+  double *acc_d = nullptr;          // the parked members' direct terms (3 n_cap)
+  int2 *pairs_d = nullptr;          // their neighbour pairs (pairs_d_cap)
+  int64_t pairs_d_cap = 0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -322,8 +326,13 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
                        int resume, hipStream_t s, hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join);
 hipError_t aux_streams(p3t_ctx *c);
 // slow.hip: the direct terms of the parked members after their integration
+// the direct terms of S on stream s, into acc_d / pairs_d (pos3, vel3: the
+// state of everyone else; S's from the park buffers)
 hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const double *mass, const double *r_out,
-                       const double *r_search, double *acc3, int ns);
+                       const double *r_search, int ns, hipStream_t s);
+// after the join, on the main stream: S's state into pos3 / vel3, and (acc3
+// not null) the direct terms into acc3 and their pairs behind the others
+hipError_t slow_merge(p3t_ctx *c, double *pos3, double *vel3, double *acc3, int ns);
 hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns);
 hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                             double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,

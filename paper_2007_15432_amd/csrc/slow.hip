@@ -76,8 +76,9 @@ __device__ __forceinline__ bool may_neighbour(double dx, double dy, double dz, d
   return dx * dx + dy * dy + dz * dz < rs * rs * (1.0 + 1e-12);
 }
 
-__device__ __forceinline__ void push_pair(DevCounters *cnt, int2 *pairs, int64_t cap, int a, int b) {
-  const unsigned long long q = atomicAdd(&cnt->n_pairs, 1ull);
+__device__ __forceinline__ void push_pair(DevCounters *cnt, unsigned long long *n_pairs, int2 *pairs, int64_t cap, int a,
+                                          int b) {
+  const unsigned long long q = atomicAdd(n_pairs, 1ull);
   if ((int64_t)q < cap)
     pairs[q] = make_int2(a, b);
   else
@@ -86,6 +87,7 @@ __device__ __forceinline__ void push_pair(DevCounters *cnt, int2 *pairs, int64_t
 
 struct SlowArgs {
   const double *pos, *vel, *mass, *ro, *rs;
+  const double *spos, *svel;  // final state of the members of S (indexed like pos / vel)
   const uint8_t *slow;
   const int32_t *list;
   int ns;
@@ -93,6 +95,7 @@ struct SlowArgs {
   double *acc;
   double *part;
   DevCounters *cnt;
+  unsigned long long *n_pairs;  // counter of `pairs`
   int2 *pairs;
   int64_t pair_cap;
   SoftPair P;
@@ -164,12 +167,12 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
       __syncthreads();
       if (t < m) {
         const int64_t j = A.list[s0 + t];
-        tx[t] = A.pos[j];
-        ty[t] = A.pos[n + j];
-        tz[t] = A.pos[2 * n + j];
-        tvx[t] = A.vel[j];
-        tvy[t] = A.vel[n + j];
-        tvz[t] = A.vel[2 * n + j];
+        tx[t] = A.spos[j];
+        ty[t] = A.spos[n + j];
+        tz[t] = A.spos[2 * n + j];
+        tvx[t] = A.svel[j];
+        tvy[t] = A.svel[n + j];
+        tvz[t] = A.svel[2 * n + j];
         tm[t] = A.mass[j];
         tro[t] = A.ro[j];
         tinv[t] = 1.0 / A.ro[j];
@@ -185,18 +188,16 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
           if (tx[k] == xi && ty[k] == yi && tz[k] == zi) coincident = true;
           if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, tx[k], ty[k], tz[k], tvx[k], tvy[k], tvz[k],
                              tm[k], tro[k], trs[k], A.P.G, A.rsch2, A.rsch3, A.dt)) {
-            push_pair(A.cnt, A.pairs, A.pair_cap, (int32_t)i, tid_[k]);
-            push_pair(A.cnt, A.pairs, A.pair_cap, tid_[k], (int32_t)i);
+            push_pair(A.cnt, A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, tid_[k]);
+            push_pair(A.cnt, A.n_pairs, A.pairs, A.pair_cap, tid_[k], (int32_t)i);
           }
         }
       }
     }
-    if (act) {
-      const double nx = A.acc[i] + ax, ny = A.acc[n + i] + ay, nz = A.acc[2 * n + i] + az;
-      A.acc[i] = nx;
-      A.acc[n + i] = ny;
-      A.acc[2 * n + i] = nz;
-      if (!(isfinite(nx) && isfinite(ny) && isfinite(nz))) set_flag(A.cnt, P3T_FLAG_NAN);
+    if (act) {  // the terms of S alone; added to the tree's force after the join
+      A.acc[i] = ax;
+      A.acc[n + i] = ay;
+      A.acc[2 * n + i] = az;
       if (coincident) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
     }
   }
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
   if (t < SG) {
     const int64_t i = A.list[s0 + (t < gc ? t : gc - 1)];
     mem_i[t] = i;
-    mem_x[t] = make_double4(A.pos[i], A.pos[n + i], A.pos[2 * n + i], 1.0 / A.ro[i]);
+    mem_x[t] = make_double4(A.spos[i], A.spos[n + i], A.spos[2 * n + i], 1.0 / A.ro[i]);
   }
   __syncthreads();
   double ax[SG], ay[SG], az[SG];
@@ -229,7 +230,9 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
   const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
   bool coincident = false;
   for (int64_t j = j0 + t; j < j1; j += ST) {
-    const double xj = A.pos[j], yj = A.pos[n + j], zj = A.pos[2 * n + j];
+    const bool sj = A.slow[j];
+    const double *pj = sj ? A.spos : A.pos;  // members of S: their final state
+    const double xj = pj[j], yj = pj[n + j], zj = pj[2 * n + j];
     const double mj = A.mass[j], roj = A.ro[j], gmj = A.P.G * mj, invj = 1.0 / roj;
     // j = s itself gives r = 0, hence K = 0 and an exact zero term
 #pragma unroll
@@ -239,16 +242,16 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
         pair_term<MIXED>(A.P, xj - q.x, yj - q.y, zj - q.z, gmj, q.w, invj, ax[g], ay[g], az[g]);
       }
     }
-    if (A.slow[j]) {  // pairs within S (rare)
+    if (sj) {  // pairs within S (rare)
       for (int g = 0; g < gc; ++g) {
         const int64_t i = mem_i[g];
         if (j == i) continue;
         const double4 q = mem_x[g];
         if (xj == q.x && yj == q.y && zj == q.z) coincident = true;
-        if (neighbour_test(q.x, q.y, q.z, A.vel[i], A.vel[n + i], A.vel[2 * n + i], A.mass[i], A.ro[i], A.rs[i], xj,
-                           yj, zj, A.vel[j], A.vel[n + j], A.vel[2 * n + j], mj, roj, A.rs[j], A.P.G, A.rsch2,
-                           A.rsch3, A.dt))
-          push_pair(A.cnt, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
+        if (neighbour_test(q.x, q.y, q.z, A.svel[i], A.svel[n + i], A.svel[2 * n + i], A.mass[i], A.ro[i], A.rs[i],
+                           xj, yj, zj, A.svel[j], A.svel[n + j], A.svel[2 * n + j], mj, roj, A.rs[j], A.P.G,
+                           A.rsch2, A.rsch3, A.dt))
+          push_pair(A.cnt, A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
       }
     }
   }
@@ -286,29 +289,58 @@ __global__ void k_slow_reduce(SlowArgs A) {
   }
 }
 
+// after the join: the tree's force plus the terms of S (members of S: the
+// direct sum alone), and the state of S into pos / vel
+__global__ void k_slow_merge(int64_t n, const uint8_t *__restrict__ slow, const double *__restrict__ acc_d,
+                             double *__restrict__ acc, DevCounters *cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool s = slow[i];
+    double a[3];
+    for (int d = 0; d < 3; ++d) {
+      a[d] = s ? acc_d[d * n + i] : acc[d * n + i] + acc_d[d * n + i];
+      acc[d * n + i] = a[d];
+    }
+    if (!(isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]))) set_flag(cnt, P3T_FLAG_NAN);
+  }
+}
+
+// the pairs of the direct terms go behind those of the force kernels; a
+// second launch moves the counter (every thread of the first reads it)
+__global__ void k_slow_pairs(const int2 *__restrict__ pd, int64_t cap_d, int2 *__restrict__ pairs, int64_t cap,
+                             DevCounters *cnt) {
+  const unsigned long long nd = cnt->n_pairs_d, base = cnt->n_pairs;
+  const unsigned long long m = nd < (unsigned long long)cap_d ? nd : (unsigned long long)cap_d;
+  for (unsigned long long k = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+       k += (unsigned long long)gridDim.x * blockDim.x) {
+    if (base + k < (unsigned long long)cap)
+      pairs[base + k] = pd[k];
+    else
+      set_flag(cnt, P3T_FLAG_PAIR_OVERFLOW);
+  }
+}
+
+__global__ void k_slow_pairs_count(DevCounters *cnt) { cnt->n_pairs += cnt->n_pairs_d; }
+
 }  // namespace
 
 hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns) {
   hipStream_t s = c->stream;
-  if (ns > 1 && ns <= SLOW_CAP) hipLaunchKernelGGL(k_sort_list, dim3(1), dim3(SLOW_CAP), 0, s, c->slow_list, ns);
   const int64_t n = c->n;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256));
   hipLaunchKernelGGL(k_mask_mass, dim3(g), dim3(256), 0, s, n, mass, (const uint8_t *)c->slow_flag, c->m_eff);
+  (void)ns;
   return hipGetLastError();
 }
 
 hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const double *mass, const double *r_out,
-                       const double *r_search, double *acc3, int ns) {
-  hipStream_t s = c->stream;
+                       const double *r_search, int ns, hipStream_t s) {
   const int64_t n = c->n;
-  const unsigned gs = (unsigned)std::min<int64_t>(65536, (ns + 255) / 256);
-  hipLaunchKernelGGL(k_slow_scatter, dim3(gs), dim3(256), 0, s, n, ns, (const int32_t *)c->slow_list,
-                     (const double *)c->pk_x, (const double *)c->pk_v, const_cast<double *>(pos3),
-                     const_cast<double *>(vel3));
-  if (!acc3) return hipGetLastError();  // state only
+  if (ns > 1 && ns <= SLOW_CAP) hipLaunchKernelGGL(k_sort_list, dim3(1), dim3(SLOW_CAP), 0, s, c->slow_list, ns);
   SlowArgs A;
   A.pos = pos3;
   A.vel = vel3;
+  A.spos = c->pk_x;
+  A.svel = c->pk_v;
   A.mass = mass;
   A.ro = r_out;
   A.rs = r_search;
@@ -316,11 +348,12 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
   A.list = c->slow_list;
   A.ns = ns;
   A.n = n;
-  A.acc = acc3;
+  A.acc = c->acc_d;
   A.part = c->slow_part;
   A.cnt = c->cnt;
-  A.pairs = c->pairs;
-  A.pair_cap = c->pair_cap;
+  A.n_pairs = &c->cnt->n_pairs_d;
+  A.pairs = c->pairs_d;
+  A.pair_cap = c->pairs_d_cap;
   A.P.G = c->P.G;
   A.P.gamma = c->P.gamma;
   A.P.inv1mg = 1.0 / (1.0 - c->P.gamma);
@@ -337,6 +370,23 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
     hipLaunchKernelGGL(k_slow_from<false>, gf, dim3(ST), 0, s, A);
   }
   hipLaunchKernelGGL(k_slow_reduce, dim3((ns + 255) / 256), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+hipError_t slow_merge(p3t_ctx *c, double *pos3, double *vel3, double *acc3, int ns) {
+  hipStream_t s = c->stream;
+  const int64_t n = c->n;
+  const unsigned gs = (unsigned)std::min<int64_t>(65536, (ns + 255) / 256);
+  hipLaunchKernelGGL(k_slow_scatter, dim3(gs), dim3(256), 0, s, n, ns, (const int32_t *)c->slow_list,
+                     (const double *)c->pk_x, (const double *)c->pk_v, pos3, vel3);
+  if (!acc3) return hipGetLastError();  // state only
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256));
+  hipLaunchKernelGGL(k_slow_merge, dim3(g), dim3(256), 0, s, n, (const uint8_t *)c->slow_flag,
+                     (const double *)c->acc_d, acc3, c->cnt);
+  const unsigned gp = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (c->pairs_d_cap + 255) / 256));
+  hipLaunchKernelGGL(k_slow_pairs, dim3(gp), dim3(256), 0, s, (const int2 *)c->pairs_d, c->pairs_d_cap, c->pairs,
+                     c->pair_cap, c->cnt);
+  hipLaunchKernelGGL(k_slow_pairs_count, dim3(1), dim3(1), 0, s, c->cnt);
   return hipGetLastError();
 }
 
