@@ -1,25 +1,28 @@
-// slow.hip -- the soft interactions of the members of slow clusters, summed
-// directly once their Hermite integration has finished.
+// slow.hip -- the soft interactions of the members of parked clusters.
 //
-// p3t_hard_evaluate integrates the clusters that will take many block steps
-// (the set S of their members) on a second stream, on copies of the state,
-// while the tree of the other particles is built, walked and evaluated at
-// the post-drift state.  In that tree the members of S carry zero mass
-// (their pre-drift positions only shape the boxes), and the force kernels
-// report no neighbour pair that involves them.  After the join:
-//   - the copies of S's positions and velocities go back into the state;
-//   - every particle i outside S adds sum_{s in S} of the soft pair term of
-//     Section 2.2 (eq. of the P3T split, changeover K at the larger cut-off),
-//     and every (i, s) that passes the neighbour test of Section 2.3 is
-//     reported in both directions;
+// p3t_hard_evaluate parks the clusters still running after a block-step
+// budget (the set S of their members) and resumes them on a second stream,
+// while the main stream builds, walks and evaluates the tree of everyone
+// else at the post-drift state, with the members of S massless (their
+// pre-drift positions only shape the boxes) and no neighbour pair involving
+// them reported.  On the second stream, after the resume, with S's final
+// state read from the park buffers:
+//   - every particle i outside S gets sum_{s in S} of the soft pair term of
+//     Section 2.2 (changeover K at the larger cut-off, eq. (rout2)), and
+//     every (i, s) that passes the neighbour test of Section 2.3 is reported
+//     in both directions;
+//   - every s in S gets sum_{j != s} over all particles (partial sums over
+//     SLOW_CHUNKS ranges of j, added in order), and the pairs (s, s') with s'
+//     in S are reported from both sides;
 //   - in mixed precision the pairs beyond the larger cut-off (K = 1) take
 //     the Newtonian term in FP32 from an FP64 offset, like the far-particle
-//     kernel; everything else is FP64;
-//   - every s in S gets sum_{j != s} over all particles, directly (partial
-//     sums over SLOW_CHUNKS ranges of j, added in order), and the pairs
-//     (s, s') with s' in S are reported from both sides.
-// Sums are accumulated in FP64 in a fixed order, so the result is reproducible; the
-// pairs arrive in any order (the CSR build sorts every row).
+//     kernel; everything else is FP64.
+// These go into a force buffer and a pair buffer of their own.  After the
+// join the main stream adds them to the tree's force (members of S take the
+// direct sum alone), appends the pairs behind the force kernels' pairs and
+// copies S's final state into pos / vel.  Sums are accumulated in FP64 in a
+// fixed order, so the result is reproducible; the pairs arrive in any order
+// (the CSR build sorts every row).
 #include "force_common.h"
 
 namespace p3t {
