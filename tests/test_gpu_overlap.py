@@ -244,3 +244,41 @@ def test_hard_evaluate_parks_big_clusters(gpu, orc, n, r_cut0):
     for k in ("pos", "vel", "dt", "rp", "col", "steps"):
         assert torch.equal(a[k] if k in a else probe[k], b[k]), k
     assert b["ns"] == (past if past <= 1024 else 0)
+
+
+def test_overlapped_full_size_sampled(gpu, orc):
+    """The benchmark configuration (2^20-particle disk, theta 0.5
+    quadrupole, mixed precision, budget 2^9) after three overlapped steps:
+    the forces of the particles whose cluster ran past the budget (parked,
+    summed directly) against the oracle's direct sum, and the rms error over
+    2,048 sampled particles within the truncation bound of this disk."""
+    from paper_2007_15432_amd.driver import P3TStepper
+
+    d = diskgen.workload("disk1m_masslaw")
+    p = params(gpu, orc, theta=0.5, multipole=2, precision=1)
+    ctx = gpu.Context(p)
+    ctx.reserve(d.n, 4 * d.n)
+    st = P3TStepper(ctx, T(d.pos), T(d.vel), T(d.mass), overlap=True, slow_log2=9)
+    parked = []
+    for _ in range(3):
+        st.step()
+        parked.append(st.n_slow)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    # the state of the last evaluation: positions and forces before the
+    # second half kick are not kept, so compare the force against the
+    # post-step positions the stepper evaluated at
+    pos, m, ro = st.pos.cpu().numpy(), st.mass.cpu().numpy(), st.r_out.cpu().numpy()
+    acc = st.acc.cpu().numpy()
+    op = orc.Params()
+    long_ = np.nonzero(st.steps.cpu().numpy() > (1 << 9))[0]
+    print("parked per step", parked, "members past the budget in the last step", len(long_))
+    assert parked[-1] == len(long_) > 0
+    ref_s = orc.soft_acc(pos, m, ro, op, idx=long_)
+    e_s = errs(acc[:, long_], ref_s)
+    idx = diskgen.sample_indices(d.n, 2048, 77)
+    ref = orc.soft_acc(pos, m, ro, op, idx=idx)
+    e = errs(acc[:, idx], ref)
+    print("parked members vs oracle", e_s, "sample", e)
+    assert e_s[2] < 1e-6
+    assert e[0] < 2e-3 and e[1] < 5e-4
