@@ -40,11 +40,11 @@ struct HermArgs {
   double *dt_hard, *e_rel;
   int32_t *nsteps;
   int32_t *msteps;  // per particle: block steps of its cluster (nullable)
-  // Parking: with budget > 0 a cluster still
-  // running after `budget` block steps saves its state to pk and stops;
-  // resume = 1 continues parked clusters from pk and writes their final
-  // state to pos / vel.
-  int budget, resume;
+  // Parking: in the parking launches (k_herm_fused<1>, k_herm_big<., 1>) a
+  // cluster still running after `budget` block steps saves its state to pk
+  // and stops; the resume launches (mode 2) continue parked clusters from pk
+  // and write their final state to pos / vel (the park buffers).
+  int budget;
   struct {
     double *x, *v, *a, *j;  // per member (3n each), at the member's own time
     int64_t *t;             // per member: its time in ticks
@@ -1042,7 +1042,6 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   A.nsteps = n_steps;
   A.msteps = steps_out;
   A.budget = budget;
-  A.resume = resume;
   A.pk.x = c->pk_x;
   A.pk.v = c->pk_v;
   A.pk.a = c->pk_a;
