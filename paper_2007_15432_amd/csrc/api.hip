@@ -785,7 +785,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   if (ns > SLOW_CAP) {
     // too many for the direct sums: finish them here, then evaluate as usual
     HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr,
-                          nullptr, steps, hc, 0, 1, c->stream, c->stream, nullptr, nullptr));
+                          nullptr, steps, hc, 0, 1, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
     HIP_OK(c, slow_merge(c, pos3, vel3, nullptr, ns));  // copies the state back only
     HIP_OK(c, hipMemsetAsync(c->slow_flag, 0, (size_t)n, c->stream));
     if (c->timing) {
@@ -802,7 +802,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
     HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
     HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
     HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
-                          steps, hc, 0, 1, c->slow_stream, c->slow_stream, nullptr, nullptr));
+                          steps, hc, 0, 1, c->slow_stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
     HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, ns, c->slow_stream));
     HIP_OK(c, hipEventRecord(c->slow_ev[1], c->slow_stream));
   }
