@@ -48,12 +48,12 @@ METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force
 
 
 def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None, overlap=False,
-             slow_log2=9):
+             slow_log2=9, isolated=1):
     from paper_2007_15432_amd.driver import P3TStepper
 
     dev = "cuda:0"
     params = p3t.Params.defaults().replace(theta=0.5, multipole=2, precision=precision, n_group_max=n_group,
-                                           n_leaf_max=n_leaf)
+                                           n_leaf_max=n_leaf, isolated=isolated)
     ctx = p3t.Context(params)
     ctx.reserve(disk.n, 4 * disk.n)
     if kcfg:
@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph run of the mixed path")
     ap.add_argument("--slow-log2", type=int, default=9,
                     help="mixed path: clusters still running after 2^k block steps finish beside the tree")
+    ap.add_argument("--isolated", choices=("kepler", "hermite"), default="kepler",
+                    help="particles without neighbours: Kepler drift (the paper's method) or Hermite with the star")
     ap.add_argument("--no-autotune", action="store_true", help="use --n-group / --n-leaf and the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the FETCH/WRITE counters)")
@@ -281,11 +283,12 @@ def main():
         kcfg = tuned.kernel
         print(f"# autotuned in {tuned.seconds:.1f} s: {tuned.params} {tuned.kernel} ({tuned.ms:.2f} ms per "
               "tree+walk+force)", file=sys.stderr, flush=True)
+    iso = 1 if args.isolated == "kepler" else 0
     results = {}
     for name in args.paths.split(","):
         prec = 1 if name.startswith("mixed") else 0
         results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, n_group, n_leaf, kcfg=kcfg,
-                                 overlap=name == "mixed", slow_log2=args.slow_log2)
+                                 overlap=name == "mixed", slow_log2=args.slow_log2, isolated=iso)
         r = results[name]
         print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
               f"force {r['stages_ms']['force']:.2f} ms, {r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}",
@@ -293,7 +296,7 @@ def main():
     graph = None
     if not args.no_graph:
         g = run_path(p3t, torch, disk, 1, args.steps, args.warmup, n_group, n_leaf, graph=True, kcfg=kcfg,
-                     overlap=True, slow_log2=args.slow_log2)
+                     overlap=True, slow_log2=args.slow_log2, isolated=iso)
         graph = {k: g[k] for k in ("value", "ms_per_step", "interactions_per_step")}
         graph["path"] = "mixed with the slow clusters overlapped, tree + walk + force replayed from one captured " \
                         "hipGraph per step"
@@ -322,7 +325,7 @@ def main():
                         "dN/dm ~ m^-2.5 on [1e-10, 1e-8], rms e = 2 rms i = 2 h(1e-9); theta=0.5 quadrupole; "
                         f"groups <= {n_group}, leaves <= {n_leaf}; launch shapes autotuned; one P3T soft step "
                         f"per step (hard part overlapped with the tree for clusters past 2^{args.slow_log2} block "
-                        "steps)",
+                        f"steps); particles without neighbours: {args.isolated}",
             "path": head,
         },
         "roofline": {k: v for k, v in h["roofline"].items()},

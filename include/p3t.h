@@ -49,6 +49,7 @@ typedef enum {
 #define P3T_FLAG_KMAX 0x20u           /* Hermite step below dt_soft * 2^-k_max */
 #define P3T_FLAG_NSTEPS 0x40u         /* Hermite block-step count limit reached */
 #define P3T_FLAG_BIG_CLUSTER 0x80u    /* a cluster used the large-cluster path */
+#define P3T_FLAG_UNBOUND 0x100u       /* an isolated particle's orbit is not bound (left in place; isolated = 1) */
 
 /* Parameters.  Defaults (p3t_default_params) are the paper's values where it
  * prints them (Section 3.1: eta = 0.01, eta_0 = 0.1 eta, Rsearch0..3 = 1.1,
@@ -72,6 +73,8 @@ typedef struct {
   int32_t vran_min_count;/* bins with fewer members use the rms over all particles */
   int32_t k_max;         /* deepest Hermite block level (step dt_soft * 2^-k_max), <= 40 */
   int32_t cluster_cap;   /* clusters above this size use the one-workgroup large path */
+  int32_t isolated;      /* clusters of one particle in the hard part: 0 Hermite with the star only,
+                            1 Kepler drift as p3t_kepler_drift (Section 2.2) */
 } p3t_params;
 
 /* Counters and phase times of the last evaluation (p3t_get_stats). */
@@ -174,6 +177,25 @@ p3t_status p3t_hermite_cluster_step(p3t_ctx *ctx, int64_t n, int64_t n_clusters,
 
 /* Soft kick, eq. (HamiltonSol): vel3 += h * acc3 (3n each). */
 p3t_status p3t_kick(p3t_ctx *ctx, int64_t n, double h, const double *acc3, double *vel3);
+
+/* Kepler drift of particles without neighbours (Section 2.2: the hard part
+ * of an isolated particle is its orbit about the star, from Kepler's equation
+ * solved by Newton-Raphson).  Each listed particle moves for dt on the
+ * two-body orbit of mu = G * m_star of the context's parameters, its own mass
+ * neglected: Newton-Raphson from dE = n dt on Kepler's equation in the
+ * eccentric-anomaly difference dE, dE - e cos E0 sin dE + e sin E0 (1 - cos dE)
+ * = n dt (to |step| <= 1e-15 max(1, |dE|), at most 50 iterations), then the f
+ * and g functions.  FP64.  pos3, vel3 (3n, x row then y row then z row) are
+ * updated in place for the listed particles only.  list (n_list int32
+ * indices into the n particles, distinct; NULL: all particles, n_list must
+ * then equal n).  iters (n_list int32, nullable) receives the Newton
+ * iterations per list entry, -1 for an orbit that is not bound (1/a <= 0 or
+ * not finite), which is left unchanged, -2 for an index outside [0, n),
+ * which is skipped.  n_unbound_host (nullable): the call synchronises and
+ * writes the number of orbits that were not bound; P3T_ERR_ARG then also
+ * reports indices outside [0, n).  P3T_ERR_STATE when G * m_star <= 0. */
+p3t_status p3t_kepler_drift(p3t_ctx *ctx, int64_t n, double dt, double *pos3, double *vel3, const int32_t *list,
+                            int64_t n_list, int32_t *iters, int64_t *n_unbound_host);
 
 /* The hard part of a soft step (Section 2.2, steps (4)-(5)) in one call,
  * from the neighbour pairs of the last p3t_compute_soft_force (or

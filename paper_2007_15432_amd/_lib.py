@@ -35,6 +35,7 @@ class CParams(C.Structure):
         ("multipole", C.c_int32), ("precision", C.c_int32), ("cutoff_mode", C.c_int32), ("hill_length", C.c_int32),
         ("n_group_max", C.c_int32), ("n_leaf_max", C.c_int32), ("vran_bins", C.c_int32),
         ("vran_min_count", C.c_int32), ("k_max", C.c_int32), ("cluster_cap", C.c_int32),
+        ("isolated", C.c_int32),
     ]
 
 
@@ -73,6 +74,7 @@ SIGNATURES = {
     "p3t_clusters": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.POINTER(_i64)]),
     "p3t_hermite_cluster_step": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "p3t_kick": (C.c_int, [_vp, _i64, _d, _vp, _vp]),
+    "p3t_kepler_drift": (C.c_int, [_vp, _i64, _d, _vp, _vp, _vp, _i64, _vp, C.POINTER(_i64)]),
     "p3t_evaluate": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i32]),
     "p3t_hard_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)]),
     "p3t_hard_evaluate": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,

@@ -50,6 +50,7 @@ class Params:
     vran_min_count: int = 8
     k_max: int = 40
     cluster_cap: int = 1024
+    isolated: int = 0
 
     @classmethod
     def defaults(cls) -> "Params":
@@ -340,3 +341,22 @@ class Context:
         self._vec3(vel, n, "vel")
         self._bind()
         self._check(self.L.p3t_kick(self._h, n, float(h), _ptr(acc), _ptr(vel)), "kick")
+
+    def kepler_drift(self, pos, vel, dt: float | None = None, index=None, iters: bool = False, count: bool = True):
+        """Drift the listed particles (index: int32 tensor, None = all) for dt
+        (default dt_soft) on their two-body orbits about the star, in place.
+        Returns (n_unbound or None, per-entry Newton iterations or None)."""
+        n = int(pos.shape[1])
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        m = n
+        if index is not None:
+            m = int(index.shape[0])
+            self._vec(index, m, "index", torch.int32)
+        it = torch.empty(max(m, 1), dtype=torch.int32, device=self.device) if iters else None
+        nu = C.c_int64(0)
+        self._bind()
+        self._check(self.L.p3t_kepler_drift(self._h, n, float(self.params.dt_soft if dt is None else dt), _ptr(pos),
+                                            _ptr(vel), _ptr(index), m, _ptr(it),
+                                            C.byref(nu) if count else None), "kepler_drift")
+        return (int(nu.value) if count else None), (None if it is None else it[:m])

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -15,7 +16,8 @@ using namespace p3t;
 
 namespace {
 
-constexpr unsigned NUMERIC_BITS = P3T_FLAG_COINCIDENT | P3T_FLAG_NAN | P3T_FLAG_KMAX | P3T_FLAG_NSTEPS;
+constexpr unsigned NUMERIC_BITS =
+    P3T_FLAG_COINCIDENT | P3T_FLAG_NAN | P3T_FLAG_KMAX | P3T_FLAG_NSTEPS | P3T_FLAG_UNBOUND;
 constexpr unsigned RETRY_BITS = P3T_FLAG_LIST_OVERFLOW | P3T_FLAG_STACK_OVERFLOW | P3T_FLAG_PAIR_OVERFLOW;
 
 p3t_status fail(p3t_ctx *c, p3t_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
@@ -56,6 +58,7 @@ const char *check_params(const p3t_params &P) {
   if (P.vran_min_count < 1) return "vran_min_count must be >= 1";
   if (P.k_max < 0 || P.k_max > 40) return "k_max must be in [0, 40]";
   if (P.cluster_cap < 1) return "cluster_cap must be >= 1";
+  if (P.isolated != 0 && P.isolated != 1) return "isolated must be 0 or 1";
   return nullptr;
 }
 
@@ -252,6 +255,7 @@ void p3t_default_params(p3t_params *P) {
   P->vran_min_count = 8;
   P->k_max = 40;
   P->cluster_cap = 1024;
+  P->isolated = 0;
 }
 
 namespace {
@@ -666,6 +670,28 @@ p3t_status p3t_kick(p3t_ctx *c, int64_t n, double h, const double *acc3, double 
   if (!c) return P3T_ERR_ARG;
   if (n < 0 || bad_ptr(acc3, n) || bad_ptr(vel3, n) || !std::isfinite(h)) return fail(c, P3T_ERR_ARG, "kick: bad argument");
   HIP_OK(c, kick(n, h, acc3, vel3, c->stream));
+  return P3T_OK;
+}
+
+p3t_status p3t_kepler_drift(p3t_ctx *c, int64_t n, double dt, double *pos3, double *vel3, const int32_t *list,
+                            int64_t n_list, int32_t *iters, int64_t *n_unbound_host) {
+  if (!c) return P3T_ERR_ARG;
+  if (n < 0 || n_list < 0 || bad_ptr(pos3, n) || bad_ptr(vel3, n) || !std::isfinite(dt))
+    return fail(c, P3T_ERR_ARG, "kepler_drift: bad argument");
+  if (n_list > 0 && !list && n_list != n) return fail(c, P3T_ERR_ARG, "kepler_drift: without a list n_list must equal n");
+  if (n_list > 0 && n == 0) return fail(c, P3T_ERR_ARG, "kepler_drift: list given for n = 0");
+  const double mu = c->P.G * c->P.m_star;
+  if (!(mu > 0.0) || !std::isfinite(mu)) return fail(c, P3T_ERR_STATE, "kepler_drift: G m_star must be > 0");
+  const size_t off = offsetof(DevCounters, n_unbound);
+  HIP_OK(c, hipMemsetAsync((char *)c->cnt + off, 0, 2 * sizeof(unsigned long long), c->stream));
+  HIP_OK(c, kepler_drift(n, n_list, list, mu, dt, pos3, vel3, iters, c->cnt, c->stream));
+  if (n_unbound_host) {
+    DevCounters h;
+    p3t_status st;
+    if ((st = sync_counters(c, &h)) != P3T_OK) return st;
+    *n_unbound_host = (int64_t)h.n_unbound;
+    if (h.n_bad_index) return fail(c, P3T_ERR_ARG, "kepler_drift: %llu list entries outside [0, n)", h.n_bad_index);
+  }
   return P3T_OK;
 }
 

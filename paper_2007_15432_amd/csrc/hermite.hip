@@ -1078,6 +1078,13 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
   for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = resume ? (bk < 10 ? hc[HERM_BC_PARK0 + bk] : 0) : hc[bk];
+  if (P.isolated == 1 && !resume && A.bcount[0] > 0) {
+    // clusters of one member: their two-body orbits, exactly (they never park)
+    if ((e = kepler_singles(n, A.bcount[0], A.blists, cl_ptr, cl_members, A.GM, P.dt_soft, pos3, vel3, dt_hard,
+                            steps_out, e_rel_err, n_steps, c->cnt, s)) != hipSuccess)
+      return e;
+    A.bcount[0] = 0;
+  }
   // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG /
   // lanes per member); the clusters of 65 members and more run at the same
   // time in their own launches (one workgroup each)

@@ -63,6 +63,8 @@ struct DevCounters {
   unsigned long long queue[3];    // persistent queues of the split force kernels
   unsigned long long n_cand;      // neighbour candidates appended (split force)
   unsigned long long n_pairs_d;   // pairs of the parked members' direct terms (p3t_hard_evaluate)
+  unsigned long long n_unbound;   // orbits that are not bound (p3t_kepler_drift)
+  unsigned long long n_bad_index; // list entries outside [0, n) (p3t_kepler_drift)
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -292,6 +294,11 @@ int64_t radix_hist_need(int64_t n);
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t bbox_reduce(const double *pos3, int64_t n, double *part, double *out, hipStream_t s);
 hipError_t kick(int64_t n, double h, const double *acc3, double *vel3, hipStream_t s);
+hipError_t kepler_drift(int64_t n, int64_t n_list, const int32_t *list, double mu, double dt, double *pos3,
+                        double *vel3, int32_t *iters, DevCounters *cnt, hipStream_t s);
+hipError_t kepler_singles(int64_t n, int32_t count, const int32_t *blist, const int32_t *cl_ptr,
+                          const int32_t *members, double mu, double dt, double *pos3, double *vel3, double *dt_hard,
+                          int32_t *msteps, double *e_rel, int32_t *nsteps, DevCounters *cnt, hipStream_t s);
 
 // cutoff.hip
 int64_t cut_part_need(int64_t n_cap);
