@@ -16,7 +16,8 @@ eccentric anomaly dE (the f and g functions):
     fd = -a^2 n sin dE / (r r0),       gd = 1 - (a/r)(1 - cos dE),
     x = f x0 + g v0,  v = fd x0 + gd v0.
 
-Unbound states (1/a <= 0) are returned unchanged and reported in the mask.
+States that are not on a bound orbit (1/a <= 0, or 1/a not finite as at the
+star's own position) are returned unchanged and reported in the mask.
 """
 from __future__ import annotations
 
@@ -29,8 +30,13 @@ def kepler_drift(pos, vel, mu: float, dt: float, tol: float = 1e-15, max_iter: i
     v0 = np.asarray(vel, dtype=np.float64)
     r0 = np.sqrt((x0 * x0).sum(0))
     v2 = (v0 * v0).sum(0)
+    with np.errstate(all="ignore"):  # states off a bound orbit are masked out below
+        return _drift(x0, v0, r0, v2, mu, dt, tol, max_iter)
+
+
+def _drift(x0, v0, r0, v2, mu, dt, tol, max_iter):
     inv_a = 2.0 / r0 - v2 / mu
-    bound = inv_a > 0.0
+    bound = (inv_a > 0.0) & np.isfinite(inv_a)
     a = np.where(bound, 1.0 / np.where(bound, inv_a, 1.0), 1.0)
     n = np.sqrt(mu / a ** 3)
     ec = 1.0 - r0 / a

@@ -8,12 +8,17 @@ an independent integrator.
   * two drifts compose into one;
   * a single particle against the oracle's Hermite integrator (star only),
     to the Hermite's own accuracy;
-  * an unbound state is left alone and reported.
+  * the disk generator's elements advanced in mean anomaly by n dt (its own
+    Kepler solver on the anomaly itself, not on its difference);
+  * an unbound state, and one at the star's position, are left alone and
+    reported.
 """
 import math
 
 import numpy as np
 import pytest
+
+import diskgen
 
 from oracle.kepler import kepler_drift
 
@@ -115,5 +120,30 @@ def test_single_particle_matches_the_hermite_oracle(orc):
 def test_unbound_state_is_left_alone():
     x0 = np.array([[1.0], [0.0], [0.0]])
     v0 = np.array([[0.0], [1.6], [0.0]])  # above escape speed sqrt(2)
+    x, v, ok, _ = kepler_drift(x0, v0, MU, 0.5)
+    assert not ok[0] and np.array_equal(x, x0) and np.array_equal(v, v0)
+
+
+def test_state_at_the_advanced_mean_anomaly():
+    """elements_to_state at M + n dt against a drift from the state at M:
+    two different routes through Kepler's equation."""
+    d = diskgen.workload("disk64k_masslaw", n=4096)
+    rng = np.random.default_rng(9)
+    inc = d.inc
+    Om, om, M = (rng.random(d.n) * 2 * math.pi for _ in range(3))
+    e = np.minimum(d.e * 30.0, 0.8)  # a wider spread of eccentricities than the disk's
+    x0, v0 = diskgen.elements_to_state(d.a, e, inc, Om, om, M)
+    for dt in (1.0 / 64, 0.9, 7.0):
+        nm = np.sqrt(1.0 / d.a ** 3)
+        x1, v1 = diskgen.elements_to_state(d.a, e, inc, Om, om, M + nm * dt)
+        x, v, ok, _ = kepler_drift(x0, v0, 1.0, dt)
+        assert ok.all()
+        assert np.abs(x - x1).max() < 1e-11 * np.abs(x1).max(), dt
+        assert np.abs(v - v1).max() < 1e-11 * np.abs(v1).max(), dt
+
+
+def test_state_at_the_star_is_left_alone():
+    x0 = np.zeros((3, 1))
+    v0 = np.array([[0.1], [0.0], [0.0]])
     x, v, ok, _ = kepler_drift(x0, v0, MU, 0.5)
     assert not ok[0] and np.array_equal(x, x0) and np.array_equal(v, v0)
