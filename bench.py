@@ -112,6 +112,31 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     return out
 
 
+def kepler_leg(p3t, torch, disk, launches=20):
+    """The isolated-particle Kepler drift (p3t_kepler_drift, kernel k_kepler)
+    over the whole disk, event-timed on the context's stream: 48 B of state
+    read and 48 B written per particle."""
+    ctx = p3t.Context(p3t.Params.defaults())
+    pos = torch.tensor(disk.pos, dtype=torch.float64, device="cuda:0")
+    vel = torch.tensor(disk.vel, dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        ctx.kepler_drift(pos, vel, count=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(launches):
+        ctx.kepler_drift(pos, vel, count=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    nu, _ = ctx.kepler_drift(pos, vel)
+    ctx.close()
+    byt = 96 * disk.n
+    ach = byt / (ms * 1e-3) / 1e9
+    return dict(kernel="k_kepler", bound="hbm", achieved=ach, peak=8000.0, unit="GB/s", frac=ach / 8000.0,
+                avg_ms=ms, bytes_per_launch=byt, n_unbound=nu)
+
+
 KERNEL_NAMES = {"near": "k_near", "far": "k_far", "cell": "k_cell"}
 
 
@@ -303,6 +328,9 @@ def main():
         print(f"# mixed (graph): {g['value']:.4g} interactions/s, {g['ms_per_step']:.2f} ms/step", file=sys.stderr,
               flush=True)
     head = "mixed" if "mixed" in results else next(iter(results))
+    kep = kepler_leg(p3t, torch, disk)
+    print(f"# kepler drift: {kep['avg_ms'] * 1e3:.1f} us per launch, {kep['achieved']:.0f} GB/s", file=sys.stderr,
+          flush=True)
     base, errs = (None, {})
     if not args.no_cpu and "fp64" in results:
         base, errs = cpu_baseline(disk, results, args.cpu_sample)
@@ -340,6 +368,7 @@ def main():
             line[name] = {k: r[k] for k in ("value", "ms_per_step", "interactions_per_step", "stages_ms", "roofline",
                                             "kernels")}
             line[name]["force_error"] = errs.get(name)
+    line["kepler_drift"] = kep
     line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters", "n_slow")}
     if graph:
         line["graph"] = graph

@@ -50,6 +50,7 @@ __device__ __forceinline__ int drift_one(int64_t n, int64_t i, double mu, double
   const double M = nm * dt;
   double dE = M, s, c;
   int it = 0;
+  bool conv = false;
   while (it < KEPLER_MAX_ITER) {
     sincos(dE, &s, &c);
     const double F = dE - ec * s + es * (1.0 - c) - M;
@@ -57,9 +58,17 @@ __device__ __forceinline__ int drift_one(int64_t n, int64_t i, double mu, double
     const double step = F / Fp;
     dE -= step;
     ++it;
-    if (!(fabs(step) > KEPLER_TOL * fmax(1.0, fabs(dE)))) break;
+    if (!(fabs(step) > KEPLER_TOL * fmax(1.0, fabs(dE)))) {
+      // the last step is below 1e-15 relative: rotate (s, c) by it instead of
+      // a new sincos (the neglected terms are of order step^2)
+      const double s1 = s - c * step;
+      c += s * step;
+      s = s1;
+      conv = true;
+      break;
+    }
   }
-  sincos(dE, &s, &c);
+  if (!conv) sincos(dE, &s, &c);
   const double r = a * (1.0 - ec * c + es * s);
   const double f = 1.0 - (a / r0) * (1.0 - c);
   const double g = dt + (s - dE) / nm;
