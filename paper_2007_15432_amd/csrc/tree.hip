@@ -194,12 +194,18 @@ __global__ __launch_bounds__(256) void k_moments_local(int n, const double *__re
                                                        p3t::CellMom *cm, const int32_t *__restrict__ parent,
                                                        int32_t *visit, const int32_t *__restrict__ chunk,
                                                        const p3t::DevCounters *cnt) {
+  // arrival counters of the chunk's internal nodes: a subtree over leaves
+  // [first, first + count) of the radix tree has its count - 1 internal
+  // nodes among the indices [first, first + count)
+  __shared__ int lvisit[CHUNK];
   const int leaf0 = n - 1;
   const int nch = (int)cnt->n_chunks;
   for (int ci = blockIdx.x; ci < nch; ci += gridDim.x) {
     const int r = chunk[ci];
     const int first = r >= leaf0 ? r - leaf0 : wn[r].first;
     const int count = r >= leaf0 ? 1 : wn[r].count;
+    for (int t = threadIdx.x; t < CHUNK; t += blockDim.x) lvisit[t] = 0;
+    __syncthreads();
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
       const int k = first + t;
       const int leaf = leaf0 + k;
@@ -226,7 +232,10 @@ __global__ __launch_bounds__(256) void k_moments_local(int n, const double *__re
       while (node >= 0) {
         // first arrival: the sibling will finish; only the second arrival
         // combines (a third would mean a malformed tree: stop, never loop)
-        if (atomicAdd(&visit[node], 1) != 1) break;
+        const unsigned off = (unsigned)(node - first);
+        const int prev = off < (unsigned)count && count <= CHUNK ? atomicAdd(&lvisit[off], 1)
+                                                                  : atomicAdd(&visit[node], 1);
+        if (prev != 1) break;
         __threadfence_block();
         combine_node(node, wn, cm);
         __threadfence_block();
