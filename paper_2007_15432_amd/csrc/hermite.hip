@@ -1078,13 +1078,10 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
   for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = resume ? (bk < 10 ? hc[HERM_BC_PARK0 + bk] : 0) : hc[bk];
-  if (P.isolated == 1 && !resume && A.bcount[0] > 0) {
-    // clusters of one member: their two-body orbits, exactly (they never park)
-    if ((e = kepler_singles(n, A.bcount[0], A.blists, cl_ptr, cl_members, A.GM, P.dt_soft, pos3, vel3, dt_hard,
-                            steps_out, e_rel_err, n_steps, c->cnt, s)) != hipSuccess)
-      return e;
-    A.bcount[0] = 0;
-  }
+  // clusters of one member: their two-body orbits, exactly (they never
+  // park); launched beside the big clusters below when there are any
+  const int32_t n_single = (P.isolated == 1 && !resume) ? A.bcount[0] : 0;
+  if (n_single > 0) A.bcount[0] = 0;
   // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG /
   // lanes per member); the clusters of 65 members and more run at the same
   // time in their own launches (one workgroup each)
@@ -1102,6 +1099,9 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
     if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s2, ev_fork, 0)) != hipSuccess) return e;
   }
+  if (n_single > 0 && (e = kepler_singles(n, n_single, A.blists, cl_ptr, cl_members, A.GM, P.dt_soft, pos3, vel3,
+                                           dt_hard, steps_out, e_rel_err, n_steps, c->cnt, s2)) != hipSuccess)
+    return e;
   const int mode = resume ? 2 : (budget > 0 ? 1 : 0);
 #define P3T_LAUNCH_BIG(MPT, BK)                                                                         \
   if (A.bcount[BK] > 0) {                                                                               \
