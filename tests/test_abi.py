@@ -67,3 +67,24 @@ def test_create_rejects_bad_params_without_gpu(lib):
     h = ctypes.c_void_p()
     assert lib.p3t_create(ctypes.byref(cp), None, ctypes.byref(h)) == _lib.P3T_ERR_ARG
     assert not h.value
+
+
+def test_isolated_solver_parameter(lib):
+    """Clusters of one member: Hermite (0) by default, the Kepler drift (1) on
+    request; anything else is rejected before any device call."""
+    from paper_2007_15432_amd import _lib
+
+    cp = _lib.CParams()
+    lib.p3t_default_params(ctypes.byref(cp))
+    assert cp.isolated == 0 and cp.cluster_cap == 1024  # the field after it still lines up
+    cp.isolated = 2
+    h = ctypes.c_void_p()
+    assert lib.p3t_create(ctypes.byref(cp), None, ctypes.byref(h)) == _lib.P3T_ERR_ARG
+    assert not h.value
+
+
+def test_kepler_drift_without_context_is_an_argument_error(lib):
+    from paper_2007_15432_amd import _lib
+
+    n = ctypes.c_int64(0)
+    assert lib.p3t_kepler_drift(None, 0, 0.1, None, None, None, 0, None, ctypes.byref(n)) == _lib.P3T_ERR_ARG
