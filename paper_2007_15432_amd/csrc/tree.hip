@@ -187,24 +187,64 @@ __global__ void k_chunk_compact(int n_nodes, const int32_t *__restrict__ flag, c
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt->n_chunks = (unsigned long long)pos[n_nodes];
 }
 
-__global__ __launch_bounds__(256) void k_moments_local(int n, const double *__restrict__ sx,
-                                                       const double *__restrict__ sy, const double *__restrict__ sz,
-                                                       const double *__restrict__ sm,
-                                                       const double *__restrict__ sreach, p3t::WalkNode *wn,
-                                                       p3t::CellMom *cm, const int32_t *__restrict__ parent,
-                                                       int32_t *visit, const int32_t *__restrict__ chunk,
-                                                       const p3t::DevCounters *cnt) {
-  // arrival counters of the chunk's internal nodes: a subtree over leaves
-  // [first, first + count) of the radix tree has its count - 1 internal
-  // nodes among the indices [first, first + count)
+// What a parent needs of a child: box, centre of mass, mass, quadrupole,
+// reach (136 B).  The chunk's internal nodes keep theirs in LDS while the
+// climb runs; a leaf's comes from the particle arrays.
+struct NodeRec {
+  double lo[3], hi[3], com[3];
+  double mass, reach;
+  double q[6];
+};
+static_assert(sizeof(NodeRec) == 136, "NodeRec layout");
+
+// Bottom-up within one chunk, the records of its internal nodes in LDS: a
+// subtree of the radix tree over leaves [first, first + count) numbers its
+// count - 1 internal nodes inside [first, first + count), so node - first
+// indexes a slot.  Same arithmetic, in the same order, as combine_node.
+constexpr int MOM_T = 1024;
+
+__global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__restrict__ sx,
+                                                         const double *__restrict__ sy, const double *__restrict__ sz,
+                                                         const double *__restrict__ sm,
+                                                         const double *__restrict__ sreach, p3t::WalkNode *wn,
+                                                         p3t::CellMom *cm, const int32_t *__restrict__ parent,
+                                                         int32_t *visit, const int32_t *__restrict__ chunk,
+                                                         p3t::DevCounters *cnt) {
+  __shared__ NodeRec rec[CHUNK];
   __shared__ int lvisit[CHUNK];
+  __shared__ int tleft[CHUNK], tright[CHUNK], tpar[CHUNK];  // the chunk's topology
   const int leaf0 = n - 1;
   const int nch = (int)cnt->n_chunks;
+  auto child = [&](int c, int first, int count, NodeRec &o) -> bool {
+    if (c >= leaf0) {
+      const int k = c - leaf0;
+      o.lo[0] = o.hi[0] = o.com[0] = sx[k];
+      o.lo[1] = o.hi[1] = o.com[1] = sy[k];
+      o.lo[2] = o.hi[2] = o.com[2] = sz[k];
+      o.mass = sm[k];
+      o.reach = sreach[k];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) o.q[q] = 0.0;
+      return true;
+    }
+    const unsigned off = (unsigned)(c - first);
+    if (off >= (unsigned)count) return false;
+    o = rec[off];
+    return true;
+  };
   for (int ci = blockIdx.x; ci < nch; ci += gridDim.x) {
     const int r = chunk[ci];
     const int first = r >= leaf0 ? r - leaf0 : wn[r].first;
-    const int count = r >= leaf0 ? 1 : wn[r].count;
+    const int count = r >= leaf0 ? 1 : min(wn[r].count, CHUNK);
     for (int t = threadIdx.x; t < CHUNK; t += blockDim.x) lvisit[t] = 0;
+    for (int t = threadIdx.x; t < count; t += blockDim.x) {
+      const int node = first + t;
+      if (node < leaf0) {  // one index of the range may be a node outside the subtree: loaded, never used
+        tleft[t] = wn[node].left;
+        tright[t] = wn[node].right;
+        tpar[t] = parent[node];
+      }
+    }
     __syncthreads();
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
       const int k = first + t;
@@ -227,20 +267,58 @@ __global__ __launch_bounds__(256) void k_moments_local(int n, const double *__re
 #pragma unroll
       for (int q = 0; q < 6; ++q) c.q[q] = 0.0;
       cm[leaf] = c;
-      __threadfence_block();
       int node = (leaf == r) ? -1 : parent[leaf];
       while (node >= 0) {
+        const unsigned off = (unsigned)(node - first);
+        if (off >= (unsigned)count) {  // not a radix subtree: reported, never indexed
+          p3t::set_flag(cnt, P3T_FLAG_NAN);
+          break;
+        }
         // first arrival: the sibling will finish; only the second arrival
         // combines (a third would mean a malformed tree: stop, never loop)
-        const unsigned off = (unsigned)(node - first);
-        const int prev = off < (unsigned)count && count <= CHUNK ? atomicAdd(&lvisit[off], 1)
-                                                                  : atomicAdd(&visit[node], 1);
-        if (prev != 1) break;
-        __threadfence_block();
-        combine_node(node, wn, cm);
-        __threadfence_block();
+        if (atomicAdd(&lvisit[off], 1) != 1) break;
+        // the sibling's record is in LDS: order LDS only (the global
+        // records are read by later kernels)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        const int a = tleft[off], b = tright[off];
+        NodeRec ra, rb;
+        if (!child(a, first, count, ra) || !child(b, first, count, rb)) {
+          p3t::set_flag(cnt, P3T_FLAG_NAN);
+          break;
+        }
+        NodeRec o;
+        const double M = ra.mass + rb.mass;
+        o.mass = M;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          o.lo[d] = fmin(ra.lo[d], rb.lo[d]);
+          o.hi[d] = fmax(ra.hi[d], rb.hi[d]);
+          o.com[d] = M > 0.0 ? (ra.mass * ra.com[d] + rb.mass * rb.com[d]) / M : 0.5 * (o.lo[d] + o.hi[d]);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o.q[q] = ra.q[q] + rb.q[q];
+        quad_shift(o.q, ra.mass, ra.com[0] - o.com[0], ra.com[1] - o.com[1], ra.com[2] - o.com[2]);
+        quad_shift(o.q, rb.mass, rb.com[0] - o.com[0], rb.com[1] - o.com[1], rb.com[2] - o.com[2]);
+        o.reach = fmax(ra.reach, rb.reach);
+        rec[off] = o;
+        // the node's range and children are already in its record
+        p3t::WalkNode &wo = wn[node];
+        p3t::CellMom co;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          wo.lo[d] = o.lo[d];
+          wo.hi[d] = o.hi[d];
+          wo.com[d] = o.com[d];
+          co.com[d] = o.com[d];
+        }
+        wo.reach = o.reach;
+        co.mass = M;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) co.q[q] = o.q[q];
+        cm[node] = co;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
         if (node == r) break;
-        node = parent[node];
+        node = tpar[off];
       }
     }
     __syncthreads();
@@ -319,7 +397,7 @@ hipError_t tree_moments(p3t_ctx *c, int64_t n) {
     return e;
   hipLaunchKernelGGL(k_chunk_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
                      c->group_node, c->cnt);
-  hipLaunchKernelGGL(k_moments_local, dim3(c->n_cu * 8), dim3(256), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm,
+  hipLaunchKernelGGL(k_moments_local, dim3(c->n_cu * 2), dim3(MOM_T), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm,
                      c->sreach, c->wnode, c->cmom, c->parent, c->visit, c->group_node, c->cnt);
   hipLaunchKernelGGL(k_moments_top, dim3(1), dim3(1024), 0, s, c->wnode, c->cmom, c->parent, c->visit, c->group_node,
                      c->cnt);
