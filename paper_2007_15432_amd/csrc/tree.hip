@@ -40,23 +40,44 @@ __global__ void k_morton(int64_t n, const double *__restrict__ pos, const double
   }
 }
 
-__global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ pos,
-                         const double *__restrict__ vel, const double *__restrict__ m, const double *__restrict__ ro,
-                         const double *__restrict__ rs, double *__restrict__ sx, double *__restrict__ sy,
-                         double *__restrict__ sz, double *__restrict__ svx, double *__restrict__ svy,
-                         double *__restrict__ svz, double *__restrict__ sm, double *__restrict__ sro,
-                         double *__restrict__ sinv, double *__restrict__ sreach, double *__restrict__ srs,
-                         int32_t *__restrict__ sid) {
+// The caller's rows packed into one 72-B record per particle (coalesced on
+// both sides), so that the gather below reads one record per particle where
+// it would read nine 8-B elements from nine scattered rows.
+constexpr int PACK = 9;
+
+__global__ void k_pack(int64_t n, const double *__restrict__ pos, const double *__restrict__ vel,
+                       const double *__restrict__ m, const double *__restrict__ ro, const double *__restrict__ rs,
+                       double *__restrict__ rec) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double *r = rec + PACK * i;
+    r[0] = pos[i];
+    r[1] = pos[n + i];
+    r[2] = pos[2 * n + i];
+    r[3] = vel[i];
+    r[4] = vel[n + i];
+    r[5] = vel[2 * n + i];
+    r[6] = m[i];
+    r[7] = ro[i];
+    r[8] = rs[i];
+  }
+}
+
+__global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ rec,
+                         double *__restrict__ sx, double *__restrict__ sy, double *__restrict__ sz,
+                         double *__restrict__ svx, double *__restrict__ svy, double *__restrict__ svz,
+                         double *__restrict__ sm, double *__restrict__ sro, double *__restrict__ sinv,
+                         double *__restrict__ sreach, double *__restrict__ srs, int32_t *__restrict__ sid) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = perm[k];
-    sx[k] = pos[i];
-    sy[k] = pos[n + i];
-    sz[k] = pos[2 * n + i];
-    svx[k] = vel[i];
-    svy[k] = vel[n + i];
-    svz[k] = vel[2 * n + i];
-    sm[k] = m[i];
-    const double o = ro[i], s = rs[i];
+    const double *r = rec + PACK * i;
+    sx[k] = r[0];
+    sy[k] = r[1];
+    sz[k] = r[2];
+    svx[k] = r[3];
+    svy[k] = r[4];
+    svz[k] = r[5];
+    sm[k] = r[6];
+    const double o = r[7], s = r[8];
     sro[k] = o;
     sinv[k] = 1.0 / o;
     sreach[k] = fmax(o, s);
@@ -376,9 +397,14 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
   if ((e = radix_sort_pairs(k, v, ka, va, n, nullptr, 0, 64, c->radix_hist, c->radix_hist_cap, c->scan_tmp,
                             c->scan_tmp_cap, s)) != hipSuccess)
     return e;
-  // after an even number of passes the result is back in keys / perm
-  hipLaunchKernelGGL(k_gather, dim3(g1d(n)), dim3(256), 0, s, n, v, pos3, vel3, mass, r_out, r_search, c->sx, c->sy,
-                     c->sz, c->svx, c->svy, c->svz, c->sm, c->sro, c->sinv, c->sreach, c->srs, c->sid);
+  // after an even number of passes the result is back in keys / perm.  The
+  // node records are rebuilt below, so their storage (96 B per node, 2n - 1
+  // nodes) holds the packed rows until then.
+  static_assert(PACK * sizeof(double) <= 2 * sizeof(WalkNode), "packed rows exceed the node storage");
+  double *rec = reinterpret_cast<double *>(c->wnode);
+  hipLaunchKernelGGL(k_pack, dim3(g1d(n)), dim3(256), 0, s, n, pos3, vel3, mass, r_out, r_search, rec);
+  hipLaunchKernelGGL(k_gather, dim3(g1d(n)), dim3(256), 0, s, n, v, rec, c->sx, c->sy, c->sz, c->svx, c->svy, c->svz,
+                     c->sm, c->sro, c->sinv, c->sreach, c->srs, c->sid);
   if (n > 1) {
     hipLaunchKernelGGL(k_radix_tree, dim3(g1d(n - 1)), dim3(256), 0, s, (int)n, k, c->wnode, c->parent);
   }
