@@ -174,11 +174,15 @@ __device__ __forceinline__ void combine_node(int node, p3t::WalkNode *wn, p3t::C
   quad_shift(co.q, ca.mass, ca.com[0] - co.com[0], ca.com[1] - co.com[1], ca.com[2] - co.com[2]);
   quad_shift(co.q, cb.mass, cb.com[0] - co.com[0], cb.com[1] - co.com[1], cb.com[2] - co.com[2]);
   o.reach = fmax(wa.reach, wb.reach);
-  o.first = wn[node].first;
-  o.count = wn[node].count;
-  o.left = a;
-  o.right = b;
-  wn[node] = o;
+  // range and children are already in the record (and may be read meanwhile)
+  p3t::WalkNode &w = wn[node];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    w.lo[d] = o.lo[d];
+    w.hi[d] = o.hi[d];
+    w.com[d] = o.com[d];
+  }
+  w.reach = o.reach;
   cm[node] = co;
 }
 
@@ -346,9 +350,21 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
   }
 }
 
+// Workgroup 0 climbs from every chunk root to the root; the other
+// workgroups meanwhile flag the interaction groups, which need only the node
+// counts (group g: count(g) <= ng and g is the root or count(parent) > ng).
 __global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::CellMom *cm,
                                                       const int32_t *__restrict__ parent, int32_t *visit,
-                                                      const int32_t *__restrict__ chunk, const p3t::DevCounters *cnt) {
+                                                      const int32_t *__restrict__ chunk, const p3t::DevCounters *cnt,
+                                                      int n_nodes, int ng, int32_t *__restrict__ flag) {
+  if (blockIdx.x > 0) {
+    for (int g = (blockIdx.x - 1) * blockDim.x + threadIdx.x; g < n_nodes; g += (gridDim.x - 1) * blockDim.x) {
+      const int c = wn[g].count;
+      const int p = (g == 0) ? -1 : parent[g];
+      flag[g] = (c <= ng && (p < 0 || wn[p].count > ng)) ? 1 : 0;
+    }
+    return;
+  }
   const int nch = (int)cnt->n_chunks;
   for (int ci = threadIdx.x; ci < nch; ci += blockDim.x) {
     const int r = chunk[ci];
@@ -360,16 +376,6 @@ __global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::Ce
       __threadfence_block();
       node = parent[node];
     }
-  }
-}
-
-// group g: count(g) <= ng and (g is the root or count(parent) > ng)
-__global__ void k_group_flag(int n_nodes, const p3t::WalkNode *__restrict__ wn, const int32_t *__restrict__ parent,
-                             int ng, int32_t *__restrict__ flag) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_nodes; g += gridDim.x * blockDim.x) {
-    const int c = wn[g].count;
-    const int p = (g == 0) ? -1 : parent[g];
-    flag[g] = (c <= ng && (p < 0 || wn[p].count > ng)) ? 1 : 0;
   }
 }
 
@@ -425,10 +431,9 @@ hipError_t tree_moments(p3t_ctx *c, int64_t n) {
                      c->group_node, c->cnt);
   hipLaunchKernelGGL(k_moments_local, dim3(c->n_cu * 2), dim3(MOM_T), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm,
                      c->sreach, c->wnode, c->cmom, c->parent, c->visit, c->group_node, c->cnt);
-  hipLaunchKernelGGL(k_moments_top, dim3(1), dim3(1024), 0, s, c->wnode, c->cmom, c->parent, c->visit, c->group_node,
-                     c->cnt);
-  hipLaunchKernelGGL(k_group_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->wnode, c->parent,
-                     c->P.n_group_max, c->group_flag);
+  const unsigned gflag = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (n_nodes + 1023) / 1024));
+  hipLaunchKernelGGL(k_moments_top, dim3(1 + gflag), dim3(1024), 0, s, c->wnode, c->cmom, c->parent, c->visit,
+                     c->group_node, c->cnt, (int)n_nodes, c->P.n_group_max, c->group_flag);
   if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_group_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
