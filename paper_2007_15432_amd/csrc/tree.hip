@@ -235,7 +235,7 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
                                                          p3t::CellMom *cm, const int32_t *__restrict__ parent,
                                                          int32_t *visit, const int32_t *__restrict__ chunk,
                                                          p3t::DevCounters *cnt) {
-  __shared__ NodeRec rec[CHUNK];
+  __shared__ __align__(16) NodeRec rec[CHUNK];
   __shared__ int lvisit[CHUNK];
   __shared__ int tleft[CHUNK], tright[CHUNK], tpar[CHUNK];  // the chunk's topology
   const int leaf0 = n - 1;
@@ -270,10 +270,16 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
         tpar[t] = parent[node];
       }
     }
-    __syncthreads();
+    // leaf records, staged in the (still unused) record slots and written
+    // out as consecutive 16-B words: 96-B and 80-B records stored lane by
+    // lane would leave every store instruction on scattered partial lines
+    static_assert(CHUNK * sizeof(p3t::WalkNode) <= sizeof(rec) && CHUNK * sizeof(p3t::CellMom) <= sizeof(rec),
+                  "leaf records exceed the staging area");
+    p3t::WalkNode *lw = reinterpret_cast<p3t::WalkNode *>(rec);
+    p3t::CellMom *lc = reinterpret_cast<p3t::CellMom *>(rec);
+    const uint4 *stage = reinterpret_cast<const uint4 *>(rec);
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
       const int k = first + t;
-      const int leaf = leaf0 + k;
       p3t::WalkNode w;
       w.lo[0] = w.hi[0] = w.com[0] = sx[k];
       w.lo[1] = w.hi[1] = w.com[1] = sy[k];
@@ -283,15 +289,35 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
       w.count = 1;
       w.left = -1;
       w.right = -1;
-      wn[leaf] = w;
+      lw[t] = w;
+    }
+    __syncthreads();
+    {
+      uint4 *dst = reinterpret_cast<uint4 *>(wn + leaf0 + first);
+      const int words = count * (int)(sizeof(p3t::WalkNode) / sizeof(uint4));
+      for (int q = threadIdx.x; q < words; q += blockDim.x) dst[q] = stage[q];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < count; t += blockDim.x) {
+      const int k = first + t;
       p3t::CellMom c;
-      c.com[0] = w.com[0];
-      c.com[1] = w.com[1];
-      c.com[2] = w.com[2];
+      c.com[0] = sx[k];
+      c.com[1] = sy[k];
+      c.com[2] = sz[k];
       c.mass = sm[k];
 #pragma unroll
       for (int q = 0; q < 6; ++q) c.q[q] = 0.0;
-      cm[leaf] = c;
+      lc[t] = c;
+    }
+    __syncthreads();
+    {
+      uint4 *dst = reinterpret_cast<uint4 *>(cm + leaf0 + first);
+      const int words = count * (int)(sizeof(p3t::CellMom) / sizeof(uint4));
+      for (int q = threadIdx.x; q < words; q += blockDim.x) dst[q] = stage[q];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < count; t += blockDim.x) {
+      const int leaf = leaf0 + first + t;
       int node = (leaf == r) ? -1 : parent[leaf];
       while (node >= 0) {
         const unsigned off = (unsigned)(node - first);
