@@ -90,60 +90,64 @@ __global__ __launch_bounds__(256) void k_cut_minmax(const double *__restrict__ p
 }
 
 // Per chunk of CUT_CHUNK particles: bin index of each particle and, per bin,
-// the chunk's sum of u^2 and member count (fixed-order reductions).
+// the chunk's sum of u^2 and member count.  The chunk's bins and u^2 are
+// staged in LDS; L = CUT_T / nbins threads share a bin, each summing every
+// L-th entry in index order, and the L partials are added in order: a fixed
+// reduction order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(CUT_T) void k_cut_bins(int64_t n, const double *__restrict__ R,
                                                     const double *__restrict__ u2, const double *__restrict__ mm,
                                                     int nbins, int32_t *__restrict__ bin_out,
                                                     double *__restrict__ psum, double *__restrict__ pcnt) {
-  __shared__ double shs[CUT_T / WAVE];
-  __shared__ double shc[CUT_T / WAVE];
+  __shared__ int sb[CUT_CHUNK];
+  __shared__ double su[CUT_CHUNK];
+  __shared__ double ps[CUT_T], pc[CUT_T];
   const int t = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * CUT_CHUNK;
   const double Rmin = mm[0], Rmax = mm[1];
   const double lspan = (Rmax > Rmin && Rmin > 0.0) ? log(Rmax / Rmin) : 0.0;
-  int b[CUT_PER];
-  double u[CUT_PER];
 #pragma unroll
   for (int q = 0; q < CUT_PER; ++q) {
-    const int64_t i = base + (int64_t)q * CUT_T + t;
-    b[q] = -1;
-    u[q] = 0.0;
+    const int j = q * CUT_T + t;
+    const int64_t i = base + j;
+    int bb = -1;
+    double u = 0.0;
     if (i < n) {
-      int bb = 0;
+      bb = 0;
       if (lspan > 0.0) {
         const double tt = floor((double)nbins * (log(R[i] / Rmin) / lspan));
         bb = tt < 0.0 ? 0 : (tt > (double)(nbins - 1) ? nbins - 1 : (int)tt);
       }
-      b[q] = bb;
-      u[q] = u2[i];
+      u = u2[i];
       bin_out[i] = bb;
     }
+    sb[j] = bb;
+    su[j] = u;
   }
-  for (int k = 0; k < nbins; ++k) {
-    double s = 0.0, c = 0.0;
-#pragma unroll
-    for (int q = 0; q < CUT_PER; ++q)
-      if (b[q] == k) {
-        s += u[q];
+  __syncthreads();
+  const int L = nbins >= CUT_T ? 1 : CUT_T / nbins;  // threads per bin
+  const int k = t / L, part = t - k * L;
+  double s = 0.0, c = 0.0;
+  if (k < nbins) {
+    for (int j = part; j < CUT_CHUNK; j += L) {
+      if (sb[j] == k) {
+        s += su[j];
         c += 1.0;
       }
-    s = wave_sum(s);
-    c = wave_sum(c);
-    if ((t & (WAVE - 1)) == 0) {
-      shs[t / WAVE] = s;
-      shc[t / WAVE] = c;
     }
-    __syncthreads();
-    if (t == 0) {
-      double ts = 0.0, tc = 0.0;
-      for (int w = 0; w < CUT_T / WAVE; ++w) {
-        ts += shs[w];
-        tc += shc[w];
+  }
+  ps[t] = s;
+  pc[t] = c;
+  __syncthreads();
+  for (int kk = t; kk < nbins; kk += CUT_T) {
+    double ts = 0.0, tc = 0.0;
+    if (nbins <= CUT_T) {
+      for (int p = 0; p < L; ++p) {
+        ts += ps[kk * L + p];
+        tc += pc[kk * L + p];
       }
-      psum[(int64_t)k * gridDim.x + blockIdx.x] = ts;  // [bin][chunk]
-      pcnt[(int64_t)k * gridDim.x + blockIdx.x] = tc;
     }
-    __syncthreads();
+    psum[(int64_t)kk * gridDim.x + blockIdx.x] = ts;  // [bin][chunk]
+    pcnt[(int64_t)kk * gridDim.x + blockIdx.x] = tc;
   }
 }
 
