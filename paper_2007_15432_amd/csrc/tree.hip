@@ -376,6 +376,8 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
   }
 }
 
+constexpr int TOP_SLOTS = 4096;  // power of two
+
 // Workgroup 0 climbs from every chunk root to the root; the other
 // workgroups meanwhile flag the interaction groups, which need only the node
 // counts (group g: count(g) <= ng and g is the root or count(parent) > ng).
@@ -391,12 +393,32 @@ __global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::Ce
     }
     return;
   }
+  // arrival counters of the top nodes in an LDS hash table (open
+  // addressing on the node id); a node that finds the table full uses its
+  // global counter, and so does its sibling's arrival (the table only fills)
+  __shared__ int hkey[TOP_SLOTS], hcnt[TOP_SLOTS];
+  for (int q = threadIdx.x; q < TOP_SLOTS; q += blockDim.x) {
+    hkey[q] = -1;
+    hcnt[q] = 0;
+  }
+  __syncthreads();
   const int nch = (int)cnt->n_chunks;
   for (int ci = threadIdx.x; ci < nch; ci += blockDim.x) {
     const int r = chunk[ci];
     int node = r == 0 ? -1 : parent[r];
     while (node >= 0) {
-      if (atomicAdd(&visit[node], 1) != 1) break;
+      unsigned h = ((unsigned)node * 2654435761u) & (TOP_SLOTS - 1);
+      int slot = -1;
+      for (int probe = 0; probe < TOP_SLOTS; ++probe) {
+        const int k = atomicCAS(&hkey[h], -1, node);
+        if (k == -1 || k == node) {
+          slot = (int)h;
+          break;
+        }
+        h = (h + 1) & (TOP_SLOTS - 1);
+      }
+      const int prev = slot >= 0 ? atomicAdd(&hcnt[slot], 1) : atomicAdd(&visit[node], 1);
+      if (prev != 1) break;
       __threadfence_block();
       combine_node(node, wn, cm);
       __threadfence_block();
