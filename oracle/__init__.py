@@ -47,7 +47,7 @@ class _Params(C.Structure):
         ("r_search2", C.c_double), ("r_search3", C.c_double),
         ("dt_soft", C.c_double), ("eta", C.c_double), ("eta0", C.c_double),
         ("hill_length", C.c_int32), ("vran_bins", C.c_int32),
-        ("vran_min_count", C.c_int32), ("k_max", C.c_int32),
+        ("vran_min_count", C.c_int32), ("k_max", C.c_int32), ("cutoff_mode", C.c_int32),
     ]
 
 
@@ -72,12 +72,13 @@ class Params:
     vran_bins: int = 64
     vran_min_count: int = 8
     k_max: int = 40
+    cutoff_mode: int = 0  # 0: individual radii (eq. (rout2)), 1: shared (eq. (rout1))
 
     def c(self) -> _Params:
         return _Params(self.G, self.m_star, self.gamma, self.r_cut0, self.r_cut1,
                        self.r_search0, self.r_search1, self.r_search2, self.r_search3,
                        self.dt_soft, self.eta, self.eta0, self.hill_length,
-                       self.vran_bins, self.vran_min_count, self.k_max)
+                       self.vran_bins, self.vran_min_count, self.k_max, self.cutoff_mode)
 
 
 _lib = None

@@ -33,6 +33,7 @@ typedef struct {
   int32_t vran_bins;      /* number of log-spaced radial bins for v_ran */
   int32_t vran_min_count; /* bins with fewer members use the global rms */
   int32_t k_max;          /* deepest block-step level: dt_soft * 2^-k_max */
+  int32_t cutoff_mode;    /* 0: individual radii (eq. (rout2)), 1: shared radii (eq. (rout1)) */
 } orc_params;
 
 /* status bits reported by the oracle */
@@ -136,9 +137,10 @@ double orc_dKdy(double y, double gamma) {
  *   r_Hill,i  = (m_i / 3 M_*)^(1/3) a_i,   a_i the osculating semi-major axis
  *   r_out,i   = max(Rcut0 r_Hill,i, Rcut1 v_ran,i dt)
  *   r_search,i = Rsearch0 r_out,i + Rsearch1 v_ran,i dt
- * Readings (the paper defines v_ran,i only as "the mean random velocity for
- * particles around the i-th particle", random velocity being the difference
- * between the particle's velocity and the Kepler velocity):
+ * Readings (eq. (routi2) takes v_ran,i as an average random velocity of
+ * the particles near particle i, without saying which particles or which
+ * average; the random velocity is the departure of a particle's velocity
+ * from the Kepler velocity):
  *   - Kepler velocity: circular speed sqrt(G M_* / |x|) along phi-hat =
  *     (-y, x, 0) / sqrt(x^2 + y^2);
  *   - "around the particle": the particle's bin among vran_bins log-spaced
@@ -146,6 +148,10 @@ double orc_dKdy(double y, double gamma) {
  *   - "mean": root mean square of |v - v_K| over the bin; a bin with fewer
  *     than vran_min_count members uses the rms over all particles;
  *   - an unbound particle (2/r - v^2/GM <= 0) uses a_i = |x_i|.
+ * Shared cut-off (cutoff_mode = 1): eq. (rout1) gives every interaction the
+ * largest cut-off radius of all particles, and Section 2.3 gives every pair
+ * the largest search radius of all particles; both maxima are taken over
+ * the individual radii above and stored for every particle.
  * Outputs r_out, r_search and v_ran per particle.  Returns 0. */
 int orc_cutoffs(int64_t n, const double *pos, const double *vel, const double *m, const orc_params *p,
                 double *r_out, double *r_search, double *v_ran) {
@@ -206,6 +212,17 @@ int orc_cutoffs(int64_t n, const double *pos, const double *vel, const double *m
     r_out[i] = ro;
     r_search[i] = p->r_search0 * ro + p->r_search1 * vr * p->dt_soft;
     if (v_ran) v_ran[i] = vr;
+  }
+  if (p->cutoff_mode == 1) {
+    double ro_max = r_out[0], rs_max = r_search[0];
+    for (int64_t i = 1; i < n; ++i) {
+      if (r_out[i] > ro_max) ro_max = r_out[i];
+      if (r_search[i] > rs_max) rs_max = r_search[i];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      r_out[i] = ro_max;
+      r_search[i] = rs_max;
+    }
   }
   free(R); free(u2); free(rh); free(bsum); free(bcnt); free(bin);
   return 0;
