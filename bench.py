@@ -4,19 +4,25 @@ MI355X, N = 2^20 planetesimal disk (0.5-5 au, surface density ~ a^-3/2,
 dN/dm ~ m^-2.5 on [1e-10, 1e-8]), theta = 0.5 quadrupole cells, groups of
 <= 128 i-particles.
 
-A step is one pass of the whole hot path on the GPU (cut-off radii, first
-kick, neighbour clusters, Hermite hard part, tree build, walk, soft force with
-neighbour pairs, neighbour CSR and cluster indices, second kick).  value =
-interactions evaluated per step / wall time per step, inputs resident in HBM.
+A step is one pass of the whole hot path on the GPU (first kick, neighbour
+CSR, cluster indices and cluster CSR, Hermite hard part, cut-off radii of the
+current state, tree build, walk, soft force with neighbour pairs, second
+kick).  The radii that the integration uses stay fixed between collisions
+(Section 2.2 step (9)); warm-up and timed steps run consecutively from the
+initial disk, with no restart.  value = interactions evaluated per step /
+wall time per step, inputs resident in HBM.
+
 The mixed-precision batched form is the headline: its hard part parks the
 clusters still running after 2^9 block steps and finishes them on a second
 stream beside the tree (p3t_hard_evaluate), and the interactions counted are
-the tree's (the direct terms of the parked members are not added).  The plain
-FP64 path and the mixed path without the overlap run beside it.
+the tree's (the direct terms of the parked members are not added).  Beside
+it: the plain FP64 path with the same overlap (precision alone), and both
+precisions with the hard part before the tree (the overlap alone).
 
 Prints one JSON line.  Only the cpu_baseline leg touches the CPU oracle: it
-times the oracle's direct sum on a sample of i-particles and, with the same
-oracle rows, reports each GPU path's rms force error.
+times the oracle's direct sum on a sample of i-particles (and the oracle
+Hermite on config 4) and, with the same oracle rows, reports each GPU path's
+rms force error.
 """
 from __future__ import annotations
 
@@ -45,11 +51,15 @@ FLOPS_QUAD = 54
 PEAK_FP64 = 78.6e12   # MI355X vector FP64 (256 CU x 128 flop/clk x 2.4 GHz)
 PEAK_FP32 = 157.3e12  # MI355X vector FP32 (published, packed)
 METRIC = "soft-force interactions/s at N=2^20, mixed vs FP64 at stated RMS force error"
-SEG_STEPS = 12  # steps from the initial disk before an untimed restart
 
 
 def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=False, kcfg=None, overlap=False,
              slow_log2=9, isolated=1):
+    """warmup + steps consecutive P3T steps from the initial disk, no
+    restart.  The cut-off radii stay fixed between collisions (Section 2.2
+    step (9)); the radii of the current state are still computed every step
+    (the stepper's monitor buffers), so that row a1 is part of the timed
+    step."""
     from paper_2007_15432_amd.driver import P3TStepper
 
     dev = "cuda:0"
@@ -60,63 +70,54 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     if kcfg:
         ctx.set_kernel_config(**kcfg)
     m = torch.tensor(disk.mass, dtype=torch.float64, device=dev)
-
-    def fresh():
-        pos = torch.tensor(disk.pos, dtype=torch.float64, device=dev)
-        vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
-        return P3TStepper(ctx, pos, vel, m, recompute_cutoffs=True, graph=graph, overlap=overlap,
-                          slow_log2=slow_log2)
-
-    # With the radii recomputed every step the disk reaches the cluster cap
-    # after about 20 steps, so longer runs restart from the initial state
-    # (untimed) every SEG_STEPS steps; each segment is timed on its own.
-    w_seg = min(warmup, SEG_STEPS // 2)
-    k_seg = SEG_STEPS - w_seg
-    # force at the initial state, kept for the error measurement
-    st = fresh()
-    acc0 = st.acc.clone()
+    pos = torch.tensor(disk.pos, dtype=torch.float64, device=dev)
+    vel = torch.tensor(disk.vel, dtype=torch.float64, device=dev)
+    st = P3TStepper(ctx, pos, vel, m, graph=graph, overlap=overlap, slow_log2=slow_log2, monitor_cutoffs=True)
+    acc0 = st.acc.clone()  # force at the initial state, for the error measurement
     r_out0 = st.r_out.clone()
-    extra = warmup - w_seg  # warm-up beyond the per-segment share, in fresh chunks
-    while extra > 0:
-        for _ in range(min(extra, SEG_STEPS)):
-            st.step()
-        extra -= SEG_STEPS
-        st = fresh()
-    inter = near = far = cell = 0
-    stage = {k: 0.0 for k in ("ms_cutoffs", "ms_tree", "ms_walk", "ms_force", "ms_neighbour", "ms_hermite",
-                              "ms_near", "ms_far", "ms_cell", "ms_cand", "ms_direct")}
+    for _ in range(warmup):
+        st.step()
+    near = far = cell = heval = hpair = 0
+    stage = {k: 0.0 for k in ("ms_cutoffs", "ms_tree", "ms_sort", "ms_walk", "ms_force", "ms_neighbour",
+                              "ms_clusters", "ms_hermite", "ms_near", "ms_far", "ms_cell", "ms_cand", "ms_direct")}
     n_slow = 0
-    elapsed = 0.0
-    done = 0
-    while done < steps:
-        if done > 0:
-            st = fresh()
-        for _ in range(w_seg):
-            st.step()
-        ctx.set_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(min(k_seg, steps - done)):
-            st.step()
-            s = ctx.stats()
-            near += s["n_near"]
-            far += s["n_far"]
-            cell += s["n_cell"]
-            for k in stage:
-                stage[k] += s[k]
-            n_slow += st.n_slow
-            done += 1
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ctx.set_timing(False)
-        elapsed += t1 - t0
+    max_steps = []  # longest block-step chain of each step (device scalars, read after the timed region)
+    largest = []    # largest cluster of each step
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.step()
+        s = ctx.stats()
+        near += s["n_near"]
+        far += s["n_far"]
+        cell += s["n_cell"]
+        heval += s["n_heval"]
+        hpair += s["n_hpair"]
+        for k in stage:
+            stage[k] += s[k]
+        n_slow += st.n_slow
+        max_steps.append(st.steps.max())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    max_steps = [int(v) for v in max_steps]
     inter = near + far + cell
-    sec = elapsed / steps
+    sec = (t1 - t0) / steps
     s = ctx.stats()
     out = dict(value=inter / steps / sec, ms_per_step=1e3 * sec, interactions_per_step=inter // steps,
                n_near=near // steps, n_far=far // steps, n_cell=cell // steps, n_groups=s["n_groups"],
                n_pairs=s["n_pairs"], n_clusters=st.n_clusters, n_slow=n_slow / steps,
-               stages_ms={k[3:]: v / steps for k, v in stage.items()})
+               stages_ms={k[3:]: v / steps for k, v in stage.items()},
+               hermite=dict(evaluations=heval // steps, pair_terms=hpair // steps, max_block_steps=max(max_steps),
+                            mean_max_block_steps=sum(max_steps) / steps))
+    h = out["hermite"]
+    ms_h = out["stages_ms"]["hermite"]
+    if ms_h > 0 and not overlap:
+        # the serial hard part is latency-bound by its longest chain
+        h["pair_terms_per_s"] = hpair / steps / (ms_h * 1e-3)
+        h["us_per_block_step_of_longest_chain"] = 1e3 * ms_h / h["mean_max_block_steps"]
+    out["memory_stages"] = memory_rates(out, disk.n)
     if graph:  # kernels inside the graph are not timed one by one
         ctx.close()
         return out
@@ -130,10 +131,36 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     out["kernels"] = ks
     out["_acc0"] = acc0.cpu().numpy()
     out["_r_out0"] = r_out0.cpu().numpy()
-    if overlap:  # the last overlapped evaluation, for its own error
-        out["_final"] = (st.pos.cpu().numpy(), st.acc.cpu().numpy(), st.r_out.cpu().numpy())
+    out["_final"] = (st.pos.cpu().numpy(), st.acc.cpu().numpy(), st.r_out.cpu().numpy())
+    out["largest_cluster"] = int(torch.bincount(ctx.neighbour_list(labels=True)[2].long()).max())
     ctx.close()
     return out
+
+
+# Algorithmic bytes of the memory-bound stages (per particle, or per
+# neighbour pair), as the design notes derive them:
+#   sort:      keys (8 B) and permutation (4 B) read and written once;
+#   tree:      the caller's rows read once (x, v, m, r_out, r_search: 72 B),
+#              the Morton-ordered copy written once (11 x 8 B + 4 B id),
+#              the sort (24 B) and one 176-B node record (walk box + moments)
+#              per 8 particles;
+#   clusters:  each neighbour pair read once (8 B) and written once into
+#              the CSR (4 B), row pointers (8 B), labels (4 B) and the
+#              cluster CSR (4 B + 4 B) per particle.
+BYTES_SORT = 24
+BYTES_TREE = 72 + 92 + BYTES_SORT + 176 // 8
+BYTES_CLUSTERS_PARTICLE, BYTES_CLUSTERS_PAIR = 20, 12
+
+
+def memory_rates(out, n):
+    st = out["stages_ms"]
+    res = {}
+    for name, ms, byt in (("tree", st["tree"], BYTES_TREE * n), ("sort", st["sort"], BYTES_SORT * n),
+                          ("clusters", st["clusters"], BYTES_CLUSTERS_PARTICLE * n + BYTES_CLUSTERS_PAIR * out["n_pairs"])):
+        if ms > 0:
+            gbs = byt / (ms * 1e-3) / 1e9
+            res[name] = dict(bound="hbm", bytes=byt, ms=ms, achieved=gbs, unit="GB/s", frac=gbs / 8000.0)
+    return res
 
 
 def kepler_leg(p3t, torch, disk, launches=20):
@@ -242,9 +269,52 @@ def autotune(p3t, torch, disk, n_group, n_leaf):
     return res
 
 
-def cpu_baseline(disk, results, sample, seed=33):
+def hermite_workload():
+    """Config 4: 20,000 neighbour clusters (lognormal sizes, median 4, max
+    256) drawn from the 65,536-particle disk, eta = 0.02."""
+    import diskgen
+    import oracle
+
+    p = oracle.Params(eta=0.02, eta0=0.002)
+    d = diskgen.workload("disk64k_masslaw")
+    ro, _, _ = oracle.cutoffs(d.pos, d.vel, d.mass, p)
+    cl = diskgen.hermite_clusters(d, n_clusters=20000, seed=4, n_max=256, r_out=ro)
+    return p, cl
+
+
+def hermite_leg(p3t, torch, cl, p, reps=3):
+    """The batched Hermite hard part on config 4 (p3t_hermite_cluster_step):
+    median wall time of `reps` calls from the same state, the Hermite work
+    counters, pair terms per second."""
+    import numpy as np
+
+    dev = "cuda:0"
+    gp = p3t.Params.defaults().replace(eta=p.eta, eta0=p.eta0, dt_soft=p.dt_soft)
+    ctx = p3t.Context(gp)
+    T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    m, ro = T(cl["mass"]), T(cl["r_out"])
+    ptr, mem = T(cl["cl_ptr"], torch.int32), T(np.arange(cl["pos"].shape[1], dtype=np.int32), torch.int32)
+    times = []
+    for _ in range(reps + 1):
+        pos, vel = T(cl["pos"]), T(cl["vel"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, nst = ctx.hermite_cluster_step(pos, vel, m, ro, ptr, mem, energy=False, steps=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    s = ctx.stats()
+    ctx.close()
+    ms = 1e3 * float(np.median(times[1:]))
+    return dict(clusters=int(cl["cl_ptr"].shape[0] - 1), members=int(cl["pos"].shape[1]), ms=ms,
+                evaluations=s["n_heval"], pair_terms=s["n_hpair"], pair_terms_per_s=s["n_hpair"] / (ms * 1e-3),
+                max_block_steps=int(nst.max()))
+
+
+def cpu_baseline(disk, results, sample, seed=33, herm=None):
     """Oracle (plain CPU FP64 direct sum) on a bounded sample of i-particles:
-    timing, and the reference rows for the GPU paths' rms force error."""
+    median of three timings on all host threads, one timing on one thread
+    (a smaller sample), the oracle Hermite on config 4, and the reference
+    rows for the GPU paths' rms force error."""
     import numpy as np
 
     import diskgen
@@ -253,9 +323,19 @@ def cpu_baseline(disk, results, sample, seed=33):
     idx = diskgen.sample_indices(disk.n, sample, seed)
     p = oracle.Params()
     ro = results["fp64"]["_r_out0"]
+    threads = oracle.num_threads()
+    dts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ref = oracle.soft_acc(disk.pos, disk.mass, ro, p, idx=idx)
+        dts.append(time.perf_counter() - t0)
+    dt = float(np.median(dts))
+    idx1 = idx[: max(1, sample // 32)]
+    oracle.set_threads(1)
     t0 = time.perf_counter()
-    ref = oracle.soft_acc(disk.pos, disk.mass, ro, p, idx=idx)
-    dt = time.perf_counter() - t0
+    oracle.soft_acc(disk.pos, disk.mass, ro, p, idx=idx1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     errs = {}
     for name, r in results.items():
         a = r["_acc0"][:, idx]
@@ -266,8 +346,8 @@ def cpu_baseline(disk, results, sample, seed=33):
     for name, r in results.items():
         if "_final" not in r:
             continue
-        # the overlapped evaluation after the timed steps (slow members' terms
-        # exact), on a smaller sample at that state
+        # each path's evaluation after its timed steps (its own state), on a
+        # smaller sample
         pos_f, acc_f, ro_f = r["_final"]
         idx_f = diskgen.sample_indices(disk.n, 2048, seed + 1)
         ref_f = oracle.soft_acc(pos_f, disk.mass, ro_f, p, idx=idx_f)
@@ -276,24 +356,37 @@ def cpu_baseline(disk, results, sample, seed=33):
         den = (ref_f ** 2).sum(0)
         errs[name]["after_steps"] = dict(eps_rms=float(np.sqrt(np.mean(num / den))),
                                          eps_global=float(np.sqrt(num.sum() / den.sum())), sample=len(idx_f))
-    base = dict(value=len(idx) * (disk.n - 1) / dt, unit="interactions/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{len(idx)} i-particles (seed {seed}) x all {disk.n} j, direct FP64 sum, {dt:.1f} s")
+    base = dict(value=len(idx) * (disk.n - 1) / dt, unit="interactions/s", cores=threads, kind="oracle",
+                sample=f"{len(idx)} i-particles (seed {seed}) x all {disk.n} j, direct FP64 sum, median of 3: "
+                       f"{dt:.2f} s ({', '.join(f'{x:.2f}' for x in dts)})",
+                one_thread=dict(value=len(idx1) * (disk.n - 1) / dt1, cores=1,
+                                sample=f"first {len(idx1)} of those i-particles, {dt1:.2f} s"))
+    if herm is not None:
+        hp, cl = herm
+        n = cl["pos"].shape[1]
+        t0 = time.perf_counter()
+        _, _, _, _, ns, stat = oracle.hermite_clusters(cl["pos"], cl["vel"], cl["mass"], cl["r_out"], cl["cl_ptr"],
+                                                       np.arange(n, dtype=np.int32), hp)
+        th = time.perf_counter() - t0
+        base["hermite"] = dict(seconds=th, cores=threads, clusters=int(cl["cl_ptr"].shape[0] - 1), members=int(n),
+                               max_block_steps=int(ns.max()), status=int(stat),
+                               sample="config 4: 20,000 clusters from the 65,536-particle disk, eta 0.02")
     return base, errs
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--n-group", type=int, default=128)
     ap.add_argument("--n-leaf", type=int, default=16)
-    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--paths", default="mixed,fp64,mixed_serial",
-                    help="mixed: FP32 bulk / FP64 near, slow clusters overlapped with the tree; fp64: plain FP64, "
-                         "hard part then tree; mixed_serial: mixed precision, hard part then tree")
+    ap.add_argument("--paths", default="mixed,fp64,mixed_serial,fp64_serial",
+                    help="mixed: FP32 bulk / FP64 near; fp64: plain FP64; both with the slow clusters overlapped "
+                         "with the tree; *_serial: the same precision with the hard part before the tree")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph run of the mixed path")
     ap.add_argument("--slow-log2", type=int, default=9,
                     help="mixed path: clusters still running after 2^k block steps finish beside the tree")
@@ -337,10 +430,11 @@ def main():
     for name in args.paths.split(","):
         prec = 1 if name.startswith("mixed") else 0
         results[name] = run_path(p3t, torch, disk, prec, args.steps, args.warmup, n_group, n_leaf, kcfg=kcfg,
-                                 overlap=name == "mixed", slow_log2=args.slow_log2, isolated=iso)
+                                 overlap=not name.endswith("_serial"), slow_log2=args.slow_log2, isolated=iso)
         r = results[name]
         print(f"# {name}: {r['value']:.4g} interactions/s, {r['ms_per_step']:.2f} ms/step, "
-              f"force {r['stages_ms']['force']:.2f} ms, {r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}",
+              f"force {r['stages_ms']['force']:.2f} ms, hermite {r['stages_ms']['hermite']:.2f} ms, "
+              f"{r['roofline']['kernel']} frac {r['roofline']['frac']:.3f}, largest cluster {r['largest_cluster']}",
               file=sys.stderr, flush=True)
     graph = None
     if not args.no_graph:
@@ -355,9 +449,13 @@ def main():
     kep = kepler_leg(p3t, torch, disk)
     print(f"# kepler drift: {kep['avg_ms'] * 1e3:.1f} us per launch, {kep['achieved']:.0f} GB/s", file=sys.stderr,
           flush=True)
+    herm = hermite_workload()
+    hl = hermite_leg(p3t, torch, herm[1], herm[0])
+    print(f"# hermite config 4: {hl['ms']:.2f} ms, {hl['pair_terms_per_s']:.3g} pair terms/s", file=sys.stderr,
+          flush=True)
     base, errs = (None, {})
     if not args.no_cpu and "fp64" in results:
-        base, errs = cpu_baseline(disk, results, args.cpu_sample)
+        base, errs = cpu_baseline(disk, results, args.cpu_sample, herm=herm)
     h = results[head]
     line = {
         "metric": METRIC,
@@ -377,7 +475,9 @@ def main():
                         "dN/dm ~ m^-2.5 on [1e-10, 1e-8], rms e = 2 rms i = 2 h(1e-9); theta=0.5 quadrupole; "
                         f"groups <= {n_group}, leaves <= {n_leaf}; launch shapes autotuned; one P3T soft step "
                         f"per step (hard part overlapped with the tree for clusters past 2^{args.slow_log2} block "
-                        f"steps); particles without neighbours: {args.isolated}",
+                        f"steps); particles without neighbours: {args.isolated}; cut-off radii fixed between "
+                        f"collisions, the current ones computed every step; {args.warmup + args.steps} "
+                        "consecutive steps from the initial disk",
             "path": head,
         },
         "roofline": {k: v for k, v in h["roofline"].items()},
@@ -385,15 +485,21 @@ def main():
         "interactions_per_step": h["interactions_per_step"],
         "stages_ms": h["stages_ms"],
         "kernels": h["kernels"],
+        "memory_stages": h["memory_stages"],
         "force_error": errs.get(head),
     }
     for name, r in results.items():
         if name != head:
             line[name] = {k: r[k] for k in ("value", "ms_per_step", "interactions_per_step", "stages_ms", "roofline",
-                                            "kernels")}
+                                            "kernels", "memory_stages", "hermite", "largest_cluster")}
             line[name]["force_error"] = errs.get(name)
+    line["hermite"] = dict(step=h["hermite"], config4=hl)
+    for name in ("mixed_serial", "fp64_serial"):
+        if name in results:
+            line["hermite"]["serial_" + name.split("_")[0]] = results[name]["hermite"]
     line["kepler_drift"] = kep
-    line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters", "n_slow")}
+    line["counts"] = {k: h[k] for k in ("n_near", "n_far", "n_cell", "n_groups", "n_pairs", "n_clusters", "n_slow",
+                                        "largest_cluster")}
     if graph:
         line["graph"] = graph
     if tuned:

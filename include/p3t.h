@@ -37,7 +37,7 @@ typedef enum {
   P3T_ERR_HIP = 3,      /* HIP runtime error */
   P3T_ERR_STATE = 4,    /* call order violated (e.g. force before tree) */
   P3T_ERR_NUMERIC = 5,  /* device reported NaN / coincident particles / step underflow */
-  P3T_ERR_CLUSTER = 6   /* cluster larger than the configured cap */
+  P3T_ERR_CLUSTER = 6   /* kept for compatibility; no longer returned (clusters of any size are integrated) */
 } p3t_status;
 
 /* Device status word bits (p3t_get_status). */
@@ -48,7 +48,7 @@ typedef enum {
 #define P3T_FLAG_PAIR_OVERFLOW 0x10u  /* neighbour-pair buffer exceeded its capacity (retried internally) */
 #define P3T_FLAG_KMAX 0x20u           /* Hermite step below dt_soft * 2^-k_max */
 #define P3T_FLAG_NSTEPS 0x40u         /* Hermite block-step count limit reached */
-#define P3T_FLAG_BIG_CLUSTER 0x80u    /* a cluster used the large-cluster path */
+#define P3T_FLAG_BIG_CLUSTER 0x80u    /* a cluster took the percolated-cluster path (above cluster_cap members) */
 #define P3T_FLAG_UNBOUND 0x100u       /* an isolated particle's orbit is not bound (left in place; isolated = 1) */
 
 /* Parameters.  Defaults (p3t_default_params) are the paper's values where it
@@ -72,7 +72,8 @@ typedef struct {
   int32_t vran_bins;     /* log-spaced cylindrical-radius bins for the random velocity */
   int32_t vran_min_count;/* bins with fewer members use the rms over all particles */
   int32_t k_max;         /* deepest Hermite block level (step dt_soft * 2^-k_max), <= 40 */
-  int32_t cluster_cap;   /* clusters above this size use the one-workgroup large path */
+  int32_t cluster_cap;   /* clusters above min(cluster_cap, 1024) members take the percolated-cluster
+                            path of the hard part (p3t_hermite_cluster_step); default 1024 */
   int32_t isolated;      /* clusters of one particle in the hard part: 0 Hermite with the star only,
                             1 Kepler drift as p3t_kepler_drift (Section 2.2) */
 } p3t_params;
@@ -95,6 +96,13 @@ typedef struct {
   int32_t timing;       /* 1 if the phase times above were measured */
   int32_t n_slow;       /* members of slow clusters in the last p3t_hard_evaluate */
   double ms_direct;     /* p3t_hard_evaluate: the direct terms of the slow members */
+  /* the last hard part (p3t_hard_step, p3t_hard_evaluate, p3t_hermite_cluster_step),
+     read at the next synchronising call: Hermite force evaluations of members
+     due in a block step, and the pair terms among them (each member due
+     evaluates every other member of its cluster) */
+  int64_t n_heval, n_hpair;
+  double ms_sort;       /* the radix sort inside the tree build */
+  double ms_clusters;   /* neighbour CSR, labels and cluster CSR at the start of the hard part */
 } p3t_stats;
 
 /* Fill *p_host with the defaults described above. */
@@ -118,9 +126,11 @@ p3t_status p3t_reserve(p3t_ctx *ctx, int64_t n_max, int64_t nnz_max);
  * eq. (rsearch)):  r_out,i = max(Rcut0 r_Hill,i, Rcut1 v_ran,i dt),
  * r_search,i = Rsearch0 r_out,i + Rsearch1 v_ran,i dt, with v_ran,i the rms
  * random velocity (|v - v_Kepler|) of the particle's radial bin.  In shared
- * mode (eq. (rout1)) every r_out,i is replaced by max_k r_out,k before
- * r_search is formed.  Outputs (n doubles each) r_out, r_search, v_ran
- * (v_ran nullable). */
+ * mode (cutoff_mode = 1, eq. (rout1); Section 2.3 for the search radius)
+ * every r_out,i is then replaced by max_k r_out,k and every r_search,i by
+ * max_k r_search,k, so that every pair uses the same two radii.  Outputs (n
+ * doubles each) r_out, r_search, v_ran (v_ran nullable; v_ran stays the
+ * particle's own bin value in both modes). */
 p3t_status p3t_compute_cutoffs(p3t_ctx *ctx, int64_t n, const double *pos3, const double *vel3,
                                const double *mass, double *r_out, double *r_search, double *v_ran);
 
@@ -169,8 +179,16 @@ p3t_status p3t_clusters(p3t_ctx *ctx, int64_t n, const int32_t *label, int32_t *
  * (<= 0: initial criterion).  e_rel_err (n_clusters, nullable) receives
  * |E_end - E_start| / |E_start| of eq. (hard) restricted to the cluster;
  * n_steps (n_clusters int32, nullable) the number of block steps taken.
- * Clusters of more than 1024 members return P3T_ERR_CLUSTER (nothing is
- * integrated); malformed cl_ptr / cl_members return P3T_ERR_ARG. */
+ * Clusters of up to 64 members share one launch (several per wavefront),
+ * clusters of 65..1024 members take one workgroup each.  A cluster above
+ * min(cluster_cap, 1024) members means the neighbour graph has percolated
+ * (Section 3.2.3: the paper then integrates it directly on one process):
+ * it is integrated with the same scheme by the percolated-cluster path,
+ * member states in device memory, one wavefront per member due in a block
+ * step summing its partners over the whole chip, two launches per block
+ * step issued in batches by the host (the call then blocks until those
+ * clusters are done), and P3T_FLAG_BIG_CLUSTER is set in the status word.
+ * Malformed cl_ptr / cl_members return P3T_ERR_ARG. */
 p3t_status p3t_hermite_cluster_step(p3t_ctx *ctx, int64_t n, int64_t n_clusters, const int32_t *cl_ptr,
                                     const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
                                     const double *r_out, double *dt_hard, double *e_rel_err, int32_t *n_steps);
@@ -204,14 +222,17 @@ p3t_status p3t_kepler_drift(p3t_ctx *ctx, int64_t n, double dt, double *pos3, do
  * cluster over dt_soft (as p3t_hermite_cluster_step), all on the device with
  * one host synchronisation (the cluster-size buckets).  pos3, vel3 (3n) are
  * updated in place; mass, r_out (n) as for p3t_hermite_cluster_step; dt_hard
- * (n, nullable) carries each particle's hard step.  *n_clusters_host
- * (nullable) receives the number of clusters.  Conditions detected on the
+ * (n, nullable) carries each particle's hard step.  steps (n int32,
+ * nullable) receives the block steps taken by each particle's cluster (1 for
+ * a Kepler-drifted particle).  *n_clusters_host (nullable) receives the
+ * number of clusters.  Conditions detected on the
  * device during the integration (P3T_FLAG_KMAX, P3T_FLAG_NSTEPS,
  * P3T_FLAG_NAN) are left in the status word for p3t_get_status or the next
- * synchronising call.  P3T_ERR_STATE without a prior force evaluation,
- * P3T_ERR_CLUSTER for a cluster above 1024 members. */
+ * synchronising call.  P3T_ERR_STATE without a prior force evaluation.
+ * Clusters above min(cluster_cap, 1024) members take the percolated-cluster
+ * path (see p3t_hermite_cluster_step). */
 p3t_status p3t_hard_step(p3t_ctx *ctx, double *pos3, double *vel3, const double *mass, const double *r_out,
-                         double *dt_hard, int64_t *n_clusters_host);
+                         double *dt_hard, int32_t *steps, int64_t *n_clusters_host);
 
 /* p3t_build_tree followed by p3t_compute_soft_force in one call.  With
  * use_graph = 1 the whole device sequence (bounding box, Morton keys, radix
@@ -230,9 +251,11 @@ p3t_status p3t_evaluate(p3t_ctx *ctx, int64_t n, const double *pos3, const doubl
 
 /* p3t_hard_step followed by p3t_evaluate (Section 2.2, steps (4)-(7)), with
  * the long-running clusters taken off the critical path.  Every cluster of
- * 1..64 members that is still running after 2^slow_log2 block steps saves
- * its block-step state and stops ("parks"), as long as the parked members
- * fit in 1024 (the others run to the end); the parked members form S.  The
+ * up to min(cluster_cap, 1024) members that is still running after
+ * 2^slow_log2 block steps saves its block-step state and stops ("parks"),
+ * as long as the parked members fit in 1024 (otherwise all of them finish
+ * before the evaluation, which is then the ordinary one; a percolated
+ * cluster never parks); the parked members form S.  The
  * parked clusters then finish on a second stream, continuing exactly where
  * they stopped, while the tree, walk and soft force of Section 2.2 run at
  * the new state with the members of S given zero mass; after both finish,
@@ -302,11 +325,25 @@ p3t_status p3t_set_timing(p3t_ctx *ctx, int32_t on);
      waves_per_cu     persistent grid of the split kernels in wavefronts per
                       compute unit (1..64; capped by the kernel's occupancy).
      walk_waves_per_cu persistent grid of the walk (1..64).
+     direct_pair_cap  capacity (pairs) of the neighbour-pair buffer of the
+                      parked members' direct terms in p3t_hard_evaluate;
+                      0 keeps the current one (initially 65,536).  When a
+                      call finds more pairs, the buffer grows and the
+                      evaluation is redone, so the result does not depend on
+                      it; a small value lets a test reach that path.
+     top_slots        entries of the LDS hash table that holds the arrival
+                      counters of the tree's top climb (a power of two,
+                      1..4096; 0 keeps the current one, initially 4096).
+                      Nodes that find no free entry within 32 probes use a
+                      counter in device memory; the moments do not depend on
+                      the choice.
    Host memory; p3t_set_kernel_config rejects values outside these ranges
-   with P3T_ERR_ARG and leaves the previous shape in place. */
+   with P3T_ERR_ARG and leaves the previous shape in place.  Zero-filled
+   fields of a struct from p3t_get_kernel_config keep their meaning. */
 typedef struct {
   int32_t force_split, force_unroll, force_persistent, waves_per_cu, walk_waves_per_cu;
-  int32_t reserved[3];
+  int32_t direct_pair_cap, top_slots;
+  int32_t reserved[1];
 } p3t_kernel_config;
 p3t_status p3t_set_kernel_config(p3t_ctx *ctx, const p3t_kernel_config *cfg_host);
 p3t_status p3t_get_kernel_config(p3t_ctx *ctx, p3t_kernel_config *cfg_host);

@@ -112,6 +112,8 @@ def lib():
         L.orc_labels.argtypes = [C.c_int64, ip, i32p, i32p]
         L.orc_soft_adjoint.argtypes = [C.c_int64, dp, dp, dp, C.c_double, C.c_double, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -137,6 +139,11 @@ def _f64(a, shape=None):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of later oracle calls; returns the count now in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 # -- changeover functions -------------------------------------------------

@@ -721,3 +721,15 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads of later calls (timing at a stated core
+ * count); returns the number now in effect. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+  return orc_num_threads();
+}

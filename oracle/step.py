@@ -43,6 +43,7 @@ class StepState:
     row_ptr: np.ndarray
     col: np.ndarray
     dt_hard: np.ndarray
+    steps: np.ndarray | None = None  # block steps of each particle's cluster in the last hard part
     n_clusters: int = 0
     hermite_status: int = 0
 
@@ -64,13 +65,15 @@ def init(pos, vel, mass, r_out, r_search, p: Params) -> StepState:
 
 def hard_part(pos, vel, mass, r_out, row_ptr, col, dt_hard, p: Params, isolated: int = 0):
     """Steps (4)-(5): clusters from the neighbour rows, each integrated over
-    dt_soft.  Returns (pos, vel, n_clusters, status); dt_hard is updated in
-    place."""
+    dt_soft.  Returns (pos, vel, n_clusters, status, steps) with steps the
+    block-step count of each particle's cluster (1 for a Kepler drift);
+    dt_hard is updated in place."""
     lab, _ = labels(row_ptr, col)
     cl_ptr, members = cluster_csr(lab)
     nc = cl_ptr.shape[0] - 1
     sizes = np.diff(cl_ptr)
     pos, vel = pos.copy(), vel.copy()
+    steps = np.zeros(pos.shape[1], dtype=np.int64)
     if isolated:
         single = members[cl_ptr[:-1][sizes == 1]]
         multi = np.flatnonzero(sizes > 1)
@@ -84,13 +87,16 @@ def hard_part(pos, vel, mass, r_out, row_ptr, col, dt_hard, p: Params, isolated:
             raise FloatingPointError("an isolated particle is not on a bound orbit")
         status = 0
         if multi.size:
-            pos, vel, _, _, _, status = hermite_clusters(pos, vel, mass, r_out, m_ptr, m_mem, p, dt_hard=dt_hard)
+            pos, vel, _, _, ns, status = hermite_clusters(pos, vel, mass, r_out, m_ptr, m_mem, p, dt_hard=dt_hard)
+            steps[m_mem] = np.repeat(ns, np.diff(m_ptr))
         pos[:, single] = xs
         vel[:, single] = vs
         dt_hard[single] = 0.0
+        steps[single] = 1
     else:
-        pos, vel, _, _, _, status = hermite_clusters(pos, vel, mass, r_out, cl_ptr, members, p, dt_hard=dt_hard)
-    return pos, vel, nc, status
+        pos, vel, _, _, ns, status = hermite_clusters(pos, vel, mass, r_out, cl_ptr, members, p, dt_hard=dt_hard)
+        steps[members] = np.repeat(ns, sizes)
+    return pos, vel, nc, status, steps
 
 
 def step(s: StepState, mass, r_out, r_search, p: Params, isolated: int = 0) -> StepState:
@@ -99,10 +105,10 @@ def step(s: StepState, mass, r_out, r_search, p: Params, isolated: int = 0) -> S
     h = 0.5 * p.dt_soft
     vel = s.vel + h * s.acc                                             # (3)
     dt_hard = s.dt_hard.copy()
-    pos, vel, nc, status = hard_part(s.pos, vel, mass, r_out, s.row_ptr, s.col, dt_hard, p, isolated)  # (4)-(5)
+    pos, vel, nc, status, steps = hard_part(s.pos, vel, mass, r_out, s.row_ptr, s.col, dt_hard, p, isolated)  # (4)-(5)
     acc, rp, col = evaluate(pos, vel, mass, r_out, r_search, p)        # (7)
     vel = vel + h * acc                                                 # (8)
-    return StepState(pos, vel, acc, rp, col, dt_hard, nc, status)
+    return StepState(pos, vel, acc, rp, col, dt_hard, steps, nc, status)
 
 
 def run(pos, vel, mass, r_out, r_search, p: Params, n_steps: int, isolated: int = 0):

@@ -47,13 +47,15 @@ class CStats(C.Structure):
         ("ms_neighbour", C.c_double), ("ms_hermite", C.c_double),
         ("ms_near", C.c_double), ("ms_far", C.c_double), ("ms_cell", C.c_double), ("ms_cand", C.c_double),
         ("timing", C.c_int32), ("n_slow", C.c_int32), ("ms_direct", C.c_double),
+        ("n_heval", C.c_int64), ("n_hpair", C.c_int64), ("ms_sort", C.c_double), ("ms_clusters", C.c_double),
     ]
 
 
 class CKernelConfig(C.Structure):
     _fields_ = [
         ("force_split", C.c_int32), ("force_unroll", C.c_int32), ("force_persistent", C.c_int32),
-        ("waves_per_cu", C.c_int32), ("walk_waves_per_cu", C.c_int32), ("reserved", C.c_int32 * 3),
+        ("waves_per_cu", C.c_int32), ("walk_waves_per_cu", C.c_int32), ("direct_pair_cap", C.c_int32),
+        ("top_slots", C.c_int32), ("reserved", C.c_int32 * 1),
     ]
 
 
@@ -76,7 +78,7 @@ SIGNATURES = {
     "p3t_kick": (C.c_int, [_vp, _i64, _d, _vp, _vp]),
     "p3t_kepler_drift": (C.c_int, [_vp, _i64, _d, _vp, _vp, _vp, _i64, _vp, C.POINTER(_i64)]),
     "p3t_evaluate": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i32]),
-    "p3t_hard_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)]),
+    "p3t_hard_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)]),
     "p3t_hard_evaluate": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
                                     C.POINTER(_i64), C.POINTER(_i64)]),
     "p3t_soft_force_frozen": (C.c_int, [_vp, _vp, _vp, _vp]),

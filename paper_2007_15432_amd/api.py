@@ -131,7 +131,8 @@ class Context:
     def set_timing(self, on: bool = True):
         self._check(self.L.p3t_set_timing(self._h, 1 if on else 0), "set_timing")
 
-    KERNEL_KEYS = ("force_split", "force_unroll", "force_persistent", "waves_per_cu", "walk_waves_per_cu")
+    KERNEL_KEYS = ("force_split", "force_unroll", "force_persistent", "waves_per_cu", "walk_waves_per_cu",
+                   "direct_pair_cap", "top_slots")
 
     def kernel_config(self) -> dict:
         k = _lib.CKernelConfig()
@@ -215,9 +216,11 @@ class Context:
         self.n = n
         return acc
 
-    def hard_step(self, pos, vel, mass, r_out, dt_hard=None) -> int:
+    def hard_step(self, pos, vel, mass, r_out, dt_hard=None, steps=None) -> int:
         """Clusters from the last evaluation's neighbour pairs and their
-        Hermite integration over dt_soft, in place; returns the cluster count."""
+        Hermite integration over dt_soft, in place; returns the cluster count.
+        `steps` (int32 (n,), nullable) receives each particle's cluster step
+        count."""
         n = self.n
         self._vec3(pos, n, "pos")
         self._vec3(vel, n, "vel")
@@ -225,10 +228,12 @@ class Context:
         self._vec(r_out, n, "r_out")
         if dt_hard is not None:
             self._vec(dt_hard, n, "dt_hard")
+        if steps is not None:
+            self._vec(steps, n, "steps", dtype=torch.int32)
         nc = C.c_int64(0)
         self._bind()
         self._check(self.L.p3t_hard_step(self._h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(r_out), _ptr(dt_hard),
-                                         C.byref(nc)), "hard_step")
+                                         _ptr(steps), C.byref(nc)), "hard_step")
         return int(nc.value)
 
     def hard_evaluate(self, pos, vel, mass, r_out_hard, dt_hard, steps, r_out, r_search, out=None,

@@ -205,6 +205,8 @@ p3t_status harvest_status(p3t_ctx *c, unsigned *new_bits) {
   p3t_status st = sync_counters(c, &h);
   if (st != P3T_OK) return st;
   const unsigned bits = h.status;
+  c->stats.n_heval = (int64_t)h.n_heval;
+  c->stats.n_hpair = (int64_t)h.n_hpair;
   if (bits) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, bits);
   c->host_status |= bits;
   if (new_bits) *new_bits = bits;
@@ -280,7 +282,8 @@ uint64_t graph_key(const p3t_ctx *c, int64_t n, const void *const *ptrs, int np)
   const void *own[] = {c->arena.base, c->pool, c->slot_lists, c->slot_stack, c->pairs, c->cands, c->csr_col};
   for (const void *q : own) h = mix(h, (uint64_t)(uintptr_t)q);
   const int64_t caps[] = {c->n_cap, c->pool_cap, c->slot_cap_list, c->slot_cap_stack, c->pair_cap, c->cand_cap,
-                          c->walk_slots, c->fcfg.split, c->fcfg.unroll, c->fcfg.waves_per_cu, c->force_persistent};
+                          c->walk_slots, c->fcfg.split, c->fcfg.unroll, c->fcfg.waves_per_cu, c->force_persistent,
+                          c->top_slots};
   for (int64_t v : caps) h = mix(h, (uint64_t)v);
   h = mix(h, (uint64_t)c->slow_active);
   const unsigned char *pb = reinterpret_cast<const unsigned char *>(&c->P);
@@ -334,8 +337,9 @@ p3t_status p3t_destroy(p3t_ctx *c) {
   if (c->slow_stream) hipStreamDestroy(c->slow_stream);
   for (auto &ev : c->slow_ev)
     if (ev) hipEventDestroy(ev);
-  void *bufs[] = {c->arena.base, c->pool,     c->slot_lists, c->slot_stack, c->pairs,
-                  c->csr_col,    c->cands,    c->adj_buf,    c->ov_buf};
+  void *bufs[] = {c->arena.base, c->pool,    c->slot_lists, c->slot_stack, c->pairs,
+                  c->csr_col,    c->cands,   c->adj_buf,    c->ov_buf,     c->pairs_d,
+                  c->huge_buf};
   for (void *b : bufs)
     if (b) hipFree(b);
   for (auto &e : c->ev)
@@ -419,7 +423,10 @@ p3t_status p3t_build_tree(p3t_ctx *c, int64_t n, const double *pos3, const doubl
   DevCounters h;
   if ((st = sync_counters(c, &h)) != P3T_OK) return st;
   c->n_groups = (int64_t)h.n_groups;
-  if (c->timing) c->stats.ms_tree = ev_ms(c, 2, 3);
+  if (c->timing) {
+    c->stats.ms_tree = ev_ms(c, 2, 3);
+    c->stats.ms_sort = ev_ms(c, 17, 18);
+  }
   c->stats.n = n;
   c->stats.n_nodes = 2 * n - 1;
   c->stats.n_groups = c->n_groups;
@@ -486,6 +493,8 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
       continue;
     }
     c->n_pairs = (int64_t)h.n_pairs;
+    c->stats.n_heval = (int64_t)h.n_heval;
+    c->stats.n_hpair = (int64_t)h.n_hpair;
     c->stats.n_near = (int64_t)h.n_near;
     c->stats.n_far = (int64_t)h.n_far;
     c->stats.n_cell = (int64_t)h.n_cell;
@@ -577,6 +586,8 @@ p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double 
     return p3t_compute_soft_force(c, acc3);
   }
   c->n_pairs = (int64_t)h.n_pairs;
+  c->stats.n_heval = (int64_t)h.n_heval;
+  c->stats.n_hpair = (int64_t)h.n_hpair;
   c->stats.n_near = (int64_t)h.n_near;
   c->stats.n_far = (int64_t)h.n_far;
   c->stats.n_cell = (int64_t)h.n_cell;
@@ -652,8 +663,6 @@ p3t_status p3t_hermite_cluster_step(p3t_ctx *c, int64_t n, int64_t n_clusters, c
   ev_record(c, 9);
   hipError_t e =
       hermite_clusters(c, n, n_clusters, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps);
-  if (e == hipErrorInvalidValue)
-    return fail(c, P3T_ERR_CLUSTER, "hermite_cluster_step: a cluster exceeds 1024 members (percolation)");
   if (e == hipErrorInvalidDevicePointer)
     return fail(c, P3T_ERR_ARG, "hermite_cluster_step: cl_ptr not non-decreasing or a member outside [0, n)");
   HIP_OK(c, e);
@@ -696,7 +705,7 @@ p3t_status p3t_kepler_drift(p3t_ctx *c, int64_t n, double dt, double *pos3, doub
 }
 
 p3t_status p3t_hard_step(p3t_ctx *c, double *pos3, double *vel3, const double *mass, const double *r_out,
-                         double *dt_hard, int64_t *n_clusters_host) {
+                         double *dt_hard, int32_t *steps, int64_t *n_clusters_host) {
   if (!c) return P3T_ERR_ARG;
   if (!c->force_valid) return fail(c, P3T_ERR_STATE, "hard_step: no neighbour pairs (call p3t_compute_soft_force)");
   const int64_t n = c->n;
@@ -708,34 +717,46 @@ p3t_status p3t_hard_step(p3t_ctx *c, double *pos3, double *vel3, const double *m
   HIP_OK(c, build_csr(c, n, c->n_pairs));
   HIP_OK(c, labels_cc(c, n, c->hs_label));
   HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  ev_record(c, 19);
   int64_t nc = 0;
   hipError_t e = hermite_clusters(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr,
-                                  nullptr, c->node_scan + n, &nc);
-  if (e == hipErrorInvalidValue)
-    return fail(c, P3T_ERR_CLUSTER, "hard_step: a cluster exceeds 1024 members (percolation)");
+                                  nullptr, c->node_scan + n, &nc, steps);
   HIP_OK(c, e);
   ev_record(c, 10);
   if (n_clusters_host) *n_clusters_host = nc;
   if (c->timing) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->stats.ms_hermite = ev_ms(c, 9, 10);
+    c->stats.ms_clusters = ev_ms(c, 9, 19);
   }
   return P3T_OK;
 }
 
 namespace {
 
+// pair buffer of the parked members' direct terms (its own allocation, grown
+// when the count after a join exceeds it)
+p3t_status ensure_pairs_d(p3t_ctx *c, int64_t cap) {
+  if (c->pairs_d && c->pairs_d_alloc >= cap) {
+    c->pairs_d_cap = cap;
+    return P3T_OK;
+  }
+  HIP_OK(c, dev_alloc(c->pairs_d, cap));
+  c->pairs_d_alloc = c->pairs_d_cap = cap;
+  return P3T_OK;
+}
+
 // buffers of p3t_hard_evaluate's slow split, sized for n_cap particles
 p3t_status ensure_overlap(p3t_ctx *c) {
   if (!c->slow_ev[0])
     for (auto &ev : c->slow_ev) HIP_OK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  if (c->ov_buf && c->ov_n_cap >= c->n_cap) return P3T_OK;
+  const int64_t pcap = c->pairs_d_cap > 0 ? c->pairs_d_cap : 64 * SLOW_CAP;
+  if (c->ov_buf && c->ov_n_cap >= c->n_cap) return ensure_pairs_d(c, pcap);
   const int64_t nc = c->n_cap;
   auto bytes = [](int64_t count, size_t sz) { return ((size_t)count * sz + 255) & ~size_t(255); };
   const size_t total = 4 * bytes(3 * nc, sizeof(double)) + bytes(nc, sizeof(int64_t)) + 2 * bytes(nc, sizeof(int32_t)) +
                        2 * bytes(nc, sizeof(double)) + bytes(10 * nc, sizeof(int32_t)) + bytes(nc, sizeof(int32_t)) +
-                       bytes((int64_t)SLOW_CAP * SLOW_CHUNKS * 3, sizeof(double)) + bytes(3 * nc, sizeof(double)) +
-                       bytes(64 * SLOW_CAP, sizeof(int2));
+                       bytes((int64_t)SLOW_CAP * SLOW_CHUNKS * 3, sizeof(double)) + bytes(3 * nc, sizeof(double));
   c->ov_n_cap = 0;
   c->pk_x = nullptr;
   HIP_OK(c, dev_alloc(c->ov_buf, (int64_t)total));
@@ -755,11 +776,9 @@ p3t_status ensure_overlap(p3t_ctx *c) {
   c->slow_list = A.take<int32_t>(nc);
   c->slow_part = A.take<double>((int64_t)SLOW_CAP * SLOW_CHUNKS * 3);
   c->acc_d = A.take<double>(3 * nc);
-  c->pairs_d = A.take<int2>(64 * SLOW_CAP);
-  c->pairs_d_cap = 64 * SLOW_CAP;
-  if (!c->pairs_d) return fail(c, P3T_ERR_HIP, "overlap buffer layout overflow (internal)");
+  if (!c->acc_d) return fail(c, P3T_ERR_HIP, "overlap buffer layout overflow (internal)");
   c->ov_n_cap = nc;
-  return P3T_OK;
+  return ensure_pairs_d(c, pcap);
 }
 
 }  // namespace
@@ -786,11 +805,10 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   HIP_OK(c, build_csr(c, n, c->n_pairs));
   HIP_OK(c, labels_cc(c, n, c->hs_label));
   HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  ev_record(c, 19);
   int32_t hc[HERM_BC_WORDS];
   hipError_t e = herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc);
   if (n_clusters_host) *n_clusters_host = hc[HERM_BC_NC];
-  if (e == hipErrorInvalidValue)
-    return fail(c, P3T_ERR_CLUSTER, "hard_evaluate: a cluster exceeds 1024 members (percolation)");
   HIP_OK(c, e);
   HIP_OK(c, aux_streams(c));
   const int budget = split ? (slow_log2 < 30 ? 1 << slow_log2 : 1 << 30) : 0;
@@ -800,7 +818,10 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   ev_record(c, 10);
   if (!split) {
     st = p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
-    if (c->timing) c->stats.ms_hermite = ev_ms(c, 9, 10);
+    if (c->timing) {
+      c->stats.ms_hermite = ev_ms(c, 9, 10);
+      c->stats.ms_clusters = ev_ms(c, 9, 19);
+    }
     return st;
   }
   // the clusters parked by the step budget finish on their own stream
@@ -818,6 +839,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
       ev_record(c, 10);
       HIP_OK(c, hipStreamSynchronize(c->stream));
       c->stats.ms_hermite = ev_ms(c, 9, 10);
+      c->stats.ms_clusters = ev_ms(c, 9, 19);
     }
     c->stats.n_slow = 0;
     return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
@@ -825,6 +847,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   if (ns > 0) {
     // resume, then the direct terms of S, both beside the evaluation below
     HIP_OK(c, hipMemsetAsync(&c->cnt->n_pairs_d, 0, sizeof(unsigned long long), c->stream));
+    HIP_OK(c, hipMemsetAsync(&c->cnt->status_d, 0, sizeof(unsigned int), c->stream));
     HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
     HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
     HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
@@ -855,19 +878,31 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   if ((st = sync_counters(c, &h)) != P3T_OK) return st;
   if (c->timing) {
     c->stats.ms_hermite = ev_ms(c, 9, 10);
+    c->stats.ms_clusters = ev_ms(c, 9, 19);
     c->stats.ms_direct = ev_ms(c, 15, 16);
   }
   c->stats.n_slow = ns;
   if (n_slow_host) *n_slow_host = ns;
-  if (h.status & RETRY_BITS) {
-    // the direct pairs did not fit: grow, and evaluate again at the final state
-    if ((st = grow_for_retry(c, h)) != P3T_OK) return st;
+  // the second stream's bits (coincident pairs, NaN) join the status here
+  const unsigned bits_d = ns > 0 ? h.status_d & NUMERIC_BITS : 0u;
+  const bool direct_overflow = ns > 0 && (int64_t)h.n_pairs_d > c->pairs_d_cap;
+  if ((h.status & RETRY_BITS) || direct_overflow) {
+    // a pair buffer was too small: grow it, and evaluate again at the final
+    // state (an ordinary evaluation, every term from the tree)
+    c->host_status |= bits_d;
+    if (direct_overflow) {
+      const int64_t need = (int64_t)h.n_pairs_d;
+      if ((st = ensure_pairs_d(c, need + need / 4 + 1024)) != P3T_OK) return st;
+    }
+    if ((h.status & RETRY_BITS) && (st = grow_for_retry(c, h)) != P3T_OK) return st;
     return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, 0);
   }
   c->n_pairs = (int64_t)h.n_pairs;
   c->stats.n_pairs = c->n_pairs;
-  const unsigned num = h.status & NUMERIC_BITS;
-  c->host_status |= h.status;
+  c->stats.n_heval = (int64_t)h.n_heval;
+  c->stats.n_hpair = (int64_t)h.n_hpair;
+  const unsigned num = (h.status | bits_d) & NUMERIC_BITS;
+  c->host_status |= h.status | bits_d;
   if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
   if (num)
     return fail(c, P3T_ERR_NUMERIC, "hard_evaluate: device status 0x%x (coincident particles or NaN)", num);
@@ -917,8 +952,11 @@ p3t_status p3t_set_kernel_config(p3t_ctx *c, const p3t_kernel_config *k) {
   const int u = k->force_unroll;
   if ((k->force_split != 0 && k->force_split != 1) || (u != 1 && u != 2 && u != 4 && u != 8) ||
       (k->force_persistent != 0 && k->force_persistent != 1) || k->waves_per_cu < 1 || k->waves_per_cu > 64 ||
-      k->walk_waves_per_cu < 1 || k->walk_waves_per_cu > 64)
+      k->walk_waves_per_cu < 1 || k->walk_waves_per_cu > 64 || k->direct_pair_cap < 0 || k->top_slots < 0 ||
+      k->top_slots > 4096 || (k->top_slots & (k->top_slots - 1)) != 0)
     return fail(c, P3T_ERR_ARG, "set_kernel_config: value out of range");
+  if (k->direct_pair_cap > 0) c->pairs_d_cap = k->direct_pair_cap;  // allocated (or grown) when next needed
+  if (k->top_slots > 0) c->top_slots = k->top_slots;
   c->fcfg.split = k->force_split;
   c->fcfg.unroll = u;
   c->fcfg.waves_per_cu = k->waves_per_cu;
@@ -943,6 +981,8 @@ p3t_status p3t_get_kernel_config(p3t_ctx *c, p3t_kernel_config *k) {
   k->force_persistent = c->force_persistent;
   k->waves_per_cu = c->fcfg.waves_per_cu;
   k->walk_waves_per_cu = c->walk_waves_per_cu;
+  k->direct_pair_cap = (int32_t)std::min<int64_t>(c->pairs_d_cap > 0 ? c->pairs_d_cap : 64 * SLOW_CAP, INT32_MAX);
+  k->top_slots = c->top_slots;
   return P3T_OK;
 }
 

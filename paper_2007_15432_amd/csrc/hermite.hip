@@ -18,7 +18,9 @@
 //   sizes 65..256: one 256-thread workgroup per cluster (same launch);
 //   sizes 257..1024: separate launches with 2 or 4 members per thread.
 // Predicted states are shared through LDS.
+#include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "p3t_internal.h"
 
@@ -242,6 +244,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Work counters: n_eval evaluations of a member of a cluster of `size`
+// (each sums size - 1 partners), summed over the wavefront, one atomic.
+// Every lane of the wavefront must call it.
+__device__ __forceinline__ void count_work(const HermArgs &A, int n_eval, int size) {
+  unsigned long long e = (unsigned long long)n_eval, p = (unsigned long long)n_eval * (unsigned long long)(size - 1);
+  if (size <= 0) e = p = 0;
+  e = wave_sum(e);
+  p = wave_sum(p);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && e > 0) {
+    atomicAdd(&A.cnt->n_heval, e);
+    atomicAdd(&A.cnt->n_hpair, p);
+  }
+}
+
 struct Lds {
   double *px, *py, *pz, *pvx, *pvy, *pvz, *pgm, *pinv;
   int *act;     // big clusters: active members of the step (BIG_ACT)
@@ -374,6 +390,7 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   }
   bool parked = false;
   const int budget = PARK ? A.budget : INT_MAX;
+  int n_eval = 0;  // block steps in which this lane's member was due (lead copies only)
   for (int it = 0;; ++it) {
     const int64_t te = mem ? t + ((int64_t)1 << (TICK_BITS - lev)) : LLONG_MAX;
     // every step divides T and each member's time is a multiple of its
@@ -446,8 +463,10 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
       const double h = (double)(tn - t) * tick;
       t = tn;
       correct(x, v, a0, j0, xp, vp, a1, j1, h, t, lev, A);
+      n_eval += sub == 0 ? 1 : 0;
     }
   }
+  count_work(A, n_eval, size);
   if (PARK) {
     // park the clusters still running: their first lane takes the slots
     const int64_t te = mem ? t + ((int64_t)1 << (TICK_BITS - lev)) : LLONG_MAX;
@@ -638,6 +657,7 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, int bk, const
     it = A.pk.nst[c];
   }
   const int budget = PARK ? A.budget : INT_MAX;
+  int n_ev = 0;  // evaluations of this thread's members
   for (int its = 0;; ++it, ++its) {
     int64_t tel = LLONG_MAX;
 #pragma unroll
@@ -673,6 +693,7 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, int bk, const
         A.pk.members[slot + tid + BIG_T * u] = gid[u];
         A.pk.flag[gid[u]] = 1;
       }
+      count_work(A, n_ev, size);
       return;  // the whole workgroup: finished by the resume launch
     }
     if (it >= A.max_iter) {
@@ -772,8 +793,10 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, int bk, const
       const double h = (double)(tn - t[u]) * A.tick;
       t[u] = tn;
       correct(x[u], v[u], a0[u], j0[u], xp[u], vp[u], a1, j1, h, t[u], lev[u], A);
+      ++n_ev;
     }
   }
+  count_work(A, n_ev, size);
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < MPT; ++u) {
@@ -873,7 +896,8 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A, int bk) {
 // usually only a few of their members are active, and that path spreads an
 // active member's partner loop over a whole wavefront, where the wavefront
 // segment path would walk it serially in one lane.
-__device__ __forceinline__ int bucket_of(int size) {
+__device__ __forceinline__ int bucket_of(int size, int cap) {
+  if (size > cap) return 10;  // the percolated-cluster path
   if (size <= 1) return 0;
   if (size <= 2) return 1;
   if (size <= 4) return 2;
@@ -893,7 +917,7 @@ __device__ __forceinline__ int bucket_of(int size) {
 // with one global atomic per bucket, then writes the entries in cluster
 // order.  (One atomic per wavefront and bucket contended on the same eleven
 // counters across the whole grid.)
-__device__ __forceinline__ int cluster_bucket(int64_t c, int64_t n, const int32_t *__restrict__ cl_ptr,
+__device__ __forceinline__ int cluster_bucket(int64_t c, int64_t n, int cap, const int32_t *__restrict__ cl_ptr,
                                               const int32_t *__restrict__ members, int32_t *__restrict__ bcount) {
   const int a = cl_ptr[c], b = cl_ptr[c + 1];
   bool ok = a >= 0 && b >= a;
@@ -905,16 +929,18 @@ __device__ __forceinline__ int cluster_bucket(int64_t c, int64_t n, const int32_
     atomicOr(&bcount[BC_BAD], 1);
     return -1;
   }
-  return b > a ? bucket_of(b - a) : -1;
+  return b > a ? bucket_of(b - a, cap) : -1;
 }
 
 struct BucketArgs {
   int64_t nc_host;
   const int64_t *nc_dev;
   int64_t stride, n;
+  int cap;  // clusters above this many members take the percolated-cluster path
   const int32_t *cl_ptr, *members;
   int32_t *bcount, *blists;
   int32_t *cl_bk;  // bucket chosen per cluster (between the sweeps)
+  DevCounters *cnt;
 };
 
 __global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
@@ -922,14 +948,18 @@ __global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
   const int64_t nc = B.nc_dev ? *B.nc_dev : B.nc_host;  // clusters (at most stride)
   int32_t *bcount = B.bcount;
-  if (blockIdx.x == 0 && tid == 0) bcount[BC_NC] = (int32_t)nc;
+  if (blockIdx.x == 0 && tid == 0) {
+    bcount[BC_NC] = (int32_t)nc;
+    B.cnt->n_heval = 0;  // the work counters of this hard part
+    B.cnt->n_hpair = 0;
+  }
   const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
   if (tid < N_BUCKETS) cnt[tid] = 0;
   __syncthreads();
   for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {
     const int64_t c = b0 + tid;
-    const int bk = c < c1 ? cluster_bucket(c, B.n, B.cl_ptr, B.members, bcount) : -1;
+    const int bk = c < c1 ? cluster_bucket(c, B.n, B.cap, B.cl_ptr, B.members, bcount) : -1;
     if (c < c1) B.cl_bk[c] = bk;
     for (int q = 0; q < N_BUCKETS; ++q) {
       const unsigned long long mask = __ballot(bk == q);
@@ -1000,19 +1030,26 @@ hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr,
   B.nc_dev = nc_dev;
   B.stride = nc;
   B.n = n;
+  B.cap = std::min(c->P.cluster_cap, 1024);
   B.cl_ptr = cl_ptr;
   B.members = cl_members;
   B.bcount = c->herm_bcount;
   B.blists = c->herm_blists;
   B.cl_bk = c->herm_clbk;
+  B.cnt = c->cnt;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
   hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, B);
   if ((e = hipMemcpyAsync(hc, c->herm_bcount, sizeof(int32_t) * BC_WORDS, hipMemcpyDeviceToHost, s)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  if (hc[BC_BAD]) return hipErrorInvalidDevicePointer;                 // malformed cluster arrays
-  if (hc[10] > 0) return hipErrorInvalidValue;  // a cluster above 1024 members
+  if (hc[BC_BAD]) return hipErrorInvalidDevicePointer;  // malformed cluster arrays
   return hipSuccess;
+}
+
+__global__ void k_huge_flag(DevCounters *cnt, unsigned bits) { set_flag(cnt, bits); }
+
+namespace {
+hipError_t huge_clusters(p3t_ctx *c, const HermArgs &A, int count, hipStream_t s);
 }
 
 // Integrates the clusters of the buckets (counts in hc[0, 11)) on stream s;
@@ -1092,7 +1129,9 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
     blocks += (A.bcount[bk] + per_block - 1) / per_block;
   }
   for (int bk = 7; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
-  const bool big = A.bcount[7] > 0 || A.bcount[8] > 0 || A.bcount[9] > 0;
+  // clusters above 1024 members (never parked): the percolated-cluster path
+  const int n_huge = resume ? 0 : A.bcount[10];
+  const bool big = A.bcount[7] > 0 || A.bcount[8] > 0 || A.bcount[9] > 0 || n_huge > 0;
   hipStream_t s2 = s;
   if (big && blocks > 0 && s_big != s) {
     s2 = s_big;
@@ -1124,6 +1163,13 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
     else
       hipLaunchKernelGGL(k_herm_fused<0>, dim3(blocks), dim3(BIG_T), 0, s, A);
   }
+  if (n_huge > 0) {
+    // issued after the fused launch, so that it runs beside them; the host
+    // waits here until the percolated clusters are done
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = huge_clusters(c, A, n_huge, s2)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_huge_flag, dim3(1), dim3(1), 0, s2, c->cnt, (unsigned)P3T_FLAG_BIG_CLUSTER);
+  }
   if (s2 != s) {  // join
     if ((e = hipEventRecord(ev_join, s2)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s, ev_join, 0)) != hipSuccess) return e;
@@ -1144,7 +1190,8 @@ hipError_t aux_streams(p3t_ctx *c) {
 
 hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                             double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
-                            double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev, int64_t *nc_out) {
+                            double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev, int64_t *nc_out,
+                            int32_t *steps_out) {
   if (nc_out) *nc_out = 0;
   if (nc <= 0) return hipSuccess;  // with nc_dev, nc is an upper bound (the particle count)
   int32_t hc[BC_WORDS];
@@ -1152,8 +1199,338 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   if (nc_out) *nc_out = hc[BC_NC];
   if (e != hipSuccess) return e;
   if ((e = aux_streams(c)) != hipSuccess) return e;
-  return herm_launch(c, n, nc, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps, nullptr, hc, 0,
-                     0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]);
+  return herm_launch(c, n, nc, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps, steps_out, hc,
+                     0, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]);
 }
+
+// ---------------------------------------------------------------- percolated clusters
+// Clusters above 1024 members: the neighbour graph has percolated (Section
+// 3.2.3 of the paper integrates such a cluster directly, with Hermite, on
+// one process).  Here the cluster is spread over the whole chip with its
+// member states in device memory, and each block step is two launches:
+//   k_huge_predict  every member predicted to the block time tn (the
+//                   minimum next time of the previous step), the active
+//                   members (due at tn) listed and flagged;
+//   k_huge_step     one wavefront per active member sums its partners
+//                   lane-parallel over all members' predicted states, then
+//                   corrects it and takes its new level; every member's
+//                   next time goes into an atomic minimum, the next tn.
+// The host issues the launches in batches and reads a done word after each
+// batch (no grid-wide barrier inside a kernel).  Same arithmetic per member
+// as the other paths (hard_pair, star_term, correct, initial_level), with
+// the partner sums added in wave-reduction order.
+struct HugeArgs {
+  int c, M;                          // cluster index, members
+  const int32_t *mem;                // the cluster's members (cl_members + cl_ptr[c])
+  double *x, *v, *a, *j, *xp, *vp;   // 3M each, component d of member k at d * M + k
+  double *m, *gm, *inv, *e;          // M each: mass, G m, 1 / r_out, energy partials
+  int64_t *t;                        // M: time in ticks
+  int32_t *lev, *act, *aflag;        // M: level, active list, active flag
+  unsigned long long *tn;            // [2] next block time (double-buffered by step parity)
+  int32_t *nact;                     // [2] active members of the step
+  int32_t *nst;                      // block steps so far
+  int32_t *done;                     // 1 once every member reached dt_soft
+  double *E;                         // [0] energy before, [1] after
+};
+constexpr int HUGE_T = 256;
+
+__global__ __launch_bounds__(HUGE_T) void k_huge_load(HermArgs A, HugeArgs H) {
+  const int64_t n = A.n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    H.tn[0] = H.tn[1] = ~0ull;
+    H.nact[0] = H.nact[1] = 0;
+    *H.nst = 0;
+    *H.done = 0;
+  }
+  for (int k = blockIdx.x * HUGE_T + threadIdx.x; k < H.M; k += gridDim.x * HUGE_T) {
+    const int64_t g = H.mem[k];
+    double x[3], v[3];
+    for (int d = 0; d < 3; ++d) {
+      x[d] = A.pos[d * n + g];
+      v[d] = A.vel[d * n + g];
+      H.x[d * H.M + k] = x[d];
+      H.v[d * H.M + k] = v[d];
+    }
+    const double m = A.mass[g];
+    H.m[k] = m;
+    H.gm[k] = A.G * m;
+    H.inv[k] = 1.0 / A.ro[g];
+    H.t[k] = 0;
+    H.e[k] = 0.5 * m * dot3(v, v) - A.GM * m * rsqrt(dot3(x, x));
+  }
+}
+
+// One wavefront per member: INIT forms the forces at t = 0, the initial
+// level and the first next time, and adds the pair energies (eq. (hard),
+// partners above the member); otherwise only the energy of the final state.
+template <bool INIT>
+__global__ __launch_bounds__(HUGE_T) void k_huge_eval(HermArgs A, HugeArgs H) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wave = (blockIdx.x * HUGE_T + threadIdx.x) / WAVE, n_waves = gridDim.x * (HUGE_T / WAVE);
+  const int M = H.M;
+  for (int k = wave; k < M; k += n_waves) {  // uniform per wavefront
+    const double xk[3] = {H.x[k], H.x[M + k], H.x[2 * M + k]};
+    const double vk[3] = {H.v[k], H.v[M + k], H.v[2 * M + k]};
+    const double ik = H.inv[k], mk = H.m[k];
+    double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0}, e = 0.0;
+    for (int q = lane; q < M; q += WAVE) {
+      if (q == k) continue;
+      const double dx = H.x[q] - xk[0], dy = H.x[M + q] - xk[1], dz = H.x[2 * M + q] - xk[2];
+      const double invR = fmin(ik, H.inv[q]);
+      if (INIT)
+        hard_pair(dx, dy, dz, H.v[q] - vk[0], H.v[M + q] - vk[1], H.v[2 * M + q] - vk[2], H.gm[q], invR, A, pa, pj);
+      if (q > k) {
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        e -= mk * H.gm[q] * (1.0 - changeover_W(r * invR, A)) / r;
+      }
+    }
+    e = wave_sum(e);
+    if (INIT) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        pa[d] = wave_sum(pa[d]);
+        pj[d] = wave_sum(pj[d]);
+      }
+    }
+    if (lane == 0) {
+      if (INIT) {
+        double a0[3], j0[3];
+        star_term(xk, vk, A.GM, a0, j0);
+        for (int d = 0; d < 3; ++d) {
+          a0[d] += pa[d];
+          j0[d] += pj[d];
+          H.a[d * M + k] = a0[d];
+          H.j[d * M + k] = j0[d];
+        }
+        const int lev = initial_level(a0, j0, true, H.mem[k], A);
+        H.lev[k] = lev;
+        atomicMin(&H.tn[0], (unsigned long long)1 << (TICK_BITS - lev));
+        H.e[k] += e;
+      } else {
+        H.e[k] = 0.5 * mk * dot3(vk, vk) - A.GM * mk * rsqrt(dot3(xk, xk)) + e;
+      }
+    }
+  }
+}
+
+// E[which] = sum of the energy partials, in a fixed order
+__global__ __launch_bounds__(HUGE_T) void k_huge_esum(HugeArgs H, int which) {
+  __shared__ double sh[HUGE_T];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < H.M; k += HUGE_T) s += H.e[k];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = HUGE_T / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) H.E[which] = sh[0];
+}
+
+__global__ __launch_bounds__(HUGE_T) void k_huge_predict(HermArgs A, HugeArgs H, int s) {
+  if (*H.done) return;
+  const unsigned long long T = 1ull << TICK_BITS;
+  const unsigned long long tnu = H.tn[s & 1];
+  if (tnu > T) {  // every member has reached dt_soft (see seg_body)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *H.done = 1;
+    return;
+  }
+  const int64_t tn = (int64_t)tnu;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    H.tn[(s + 1) & 1] = ~0ull;  // filled by this step's k_huge_step
+    H.nact[(s + 1) & 1] = 0;
+    *H.nst += 1;
+  }
+  const int M = H.M;
+  for (int k = blockIdx.x * HUGE_T + threadIdx.x; k < M; k += gridDim.x * HUGE_T) {
+    const int64_t tk = H.t[k];
+    const double dl = (double)(tn - tk) * A.tick;
+    const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double x = H.x[d * M + k], v = H.v[d * M + k], a = H.a[d * M + k], j = H.j[d * M + k];
+      H.xp[d * M + k] = x + v * dl + a * d2 + j * d3;
+      H.vp[d * M + k] = v + a * dl + j * d2;
+    }
+    const bool due = tk + ((int64_t)1 << (TICK_BITS - H.lev[k])) == tn;
+    H.aflag[k] = due ? 1 : 0;
+    if (due) H.act[atomicAdd(&H.nact[s & 1], 1)] = k;
+  }
+}
+
+__global__ __launch_bounds__(HUGE_T) void k_huge_step(HermArgs A, HugeArgs H, int s) {
+  if (*H.done) return;
+  const unsigned long long tnu = H.tn[s & 1];
+  if (tnu > (1ull << TICK_BITS)) return;
+  const int64_t tn = (int64_t)tnu;
+  const int M = H.M;
+  unsigned long long *next = &H.tn[(s + 1) & 1];
+  // members not due keep their state: their next time as it stands
+  for (int k = blockIdx.x * HUGE_T + threadIdx.x; k < M; k += gridDim.x * HUGE_T)
+    if (!H.aflag[k]) atomicMin(next, (unsigned long long)(H.t[k] + ((int64_t)1 << (TICK_BITS - H.lev[k]))));
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wave = (blockIdx.x * HUGE_T + threadIdx.x) / WAVE, n_waves = gridDim.x * (HUGE_T / WAVE);
+  const int na = H.nact[s & 1];
+  for (int q0 = wave; q0 < na; q0 += n_waves) {  // uniform per wavefront
+    const int k = H.act[q0];
+    const double xp[3] = {H.xp[k], H.xp[M + k], H.xp[2 * M + k]};
+    const double vp[3] = {H.vp[k], H.vp[M + k], H.vp[2 * M + k]};
+    const double ik = H.inv[k];
+    double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0};
+    for (int q = lane; q < M; q += WAVE) {
+      if (q == k) continue;
+      hard_pair(H.xp[q] - xp[0], H.xp[M + q] - xp[1], H.xp[2 * M + q] - xp[2], H.vp[q] - vp[0],
+                H.vp[M + q] - vp[1], H.vp[2 * M + q] - vp[2], H.gm[q], fmin(ik, H.inv[q]), A, pa, pj);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      pa[d] = wave_sum(pa[d]);
+      pj[d] = wave_sum(pj[d]);
+    }
+    if (lane == 0) {
+      double a1[3], j1[3], x[3], v[3], a0[3], j0[3];
+      star_term(xp, vp, A.GM, a1, j1);
+      for (int d = 0; d < 3; ++d) {
+        a1[d] += pa[d];
+        j1[d] += pj[d];
+        x[d] = H.x[d * M + k];
+        v[d] = H.v[d * M + k];
+        a0[d] = H.a[d * M + k];
+        j0[d] = H.j[d * M + k];
+      }
+      const double h = (double)(tn - H.t[k]) * A.tick;
+      int lev = H.lev[k];
+      correct(x, v, a0, j0, xp, vp, a1, j1, h, tn, lev, A);
+      for (int d = 0; d < 3; ++d) {
+        H.x[d * M + k] = x[d];
+        H.v[d * M + k] = v[d];
+        H.a[d * M + k] = a0[d];
+        H.j[d * M + k] = j0[d];
+      }
+      H.t[k] = tn;
+      H.lev[k] = lev;
+      atomicMin(next, (unsigned long long)(tn + ((int64_t)1 << (TICK_BITS - lev))));
+    }
+  }
+  // work counters: the step's due members, each over M - 1 partners
+  if (blockIdx.x == 0 && threadIdx.x == 0 && na > 0) {
+    atomicAdd(&A.cnt->n_heval, (unsigned long long)na);
+    atomicAdd(&A.cnt->n_hpair, (unsigned long long)na * (unsigned long long)(M - 1));
+  }
+}
+
+__global__ __launch_bounds__(HUGE_T) void k_huge_store(HermArgs A, HugeArgs H) {
+  const int64_t n = A.n;
+  const int M = H.M;
+  const int nst = *H.nst;
+  for (int k = blockIdx.x * HUGE_T + threadIdx.x; k < M; k += gridDim.x * HUGE_T) {
+    const int64_t g = H.mem[k];
+    double x[3];
+    for (int d = 0; d < 3; ++d) {
+      x[d] = H.x[d * M + k];
+      A.pos[d * n + g] = x[d];
+      A.vel[d * n + g] = H.v[d * M + k];
+    }
+    if (A.dt_hard) A.dt_hard[g] = ldexp(A.dt_soft, -H.lev[k]);
+    if (A.msteps) A.msteps[g] = nst;
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) set_flag(A.cnt, P3T_FLAG_NAN);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (A.e_rel) A.e_rel[H.c] = fabs(H.E[1] - H.E[0]) / fabs(H.E[0]);
+    if (A.nsteps) A.nsteps[H.c] = nst;
+  }
+}
+
+namespace {
+
+// device memory of the percolated-cluster path, sized for M members
+hipError_t huge_buffers(p3t_ctx *c, int64_t M, HugeArgs &H) {
+  auto bytes = [](int64_t count, size_t sz) { return ((size_t)count * sz + 255) & ~size_t(255); };
+  const size_t need = 6 * bytes(3 * M, sizeof(double)) + 4 * bytes(M, sizeof(double)) + bytes(M, sizeof(int64_t)) +
+                      3 * bytes(M, sizeof(int32_t)) + 4 * 256;
+  hipError_t e;
+  if (!c->huge_buf || c->huge_bytes < need) {
+    if (c->huge_buf && (e = hipFree(c->huge_buf)) != hipSuccess) return e;
+    c->huge_buf = nullptr;
+    c->huge_bytes = 0;
+    if ((e = hipMalloc((void **)&c->huge_buf, need)) != hipSuccess) return e;
+    c->huge_bytes = need;
+  }
+  Arena A;
+  A.base = c->huge_buf;
+  A.size = c->huge_bytes;
+  double **d3[6] = {&H.x, &H.v, &H.a, &H.j, &H.xp, &H.vp};
+  for (auto p : d3) *p = A.take<double>(3 * M);
+  H.m = A.take<double>(M);
+  H.gm = A.take<double>(M);
+  H.inv = A.take<double>(M);
+  H.e = A.take<double>(M);
+  H.t = A.take<int64_t>(M);
+  H.lev = A.take<int32_t>(M);
+  H.act = A.take<int32_t>(M);
+  H.aflag = A.take<int32_t>(M);
+  H.tn = A.take<unsigned long long>(2);
+  H.nact = A.take<int32_t>(2);
+  H.nst = A.take<int32_t>(2);
+  H.done = H.nst + 1;
+  H.E = A.take<double>(2);
+  return H.E ? hipSuccess : hipErrorOutOfMemory;
+}
+
+constexpr int HUGE_BATCH = 32;  // block steps issued between two reads of the done word
+
+// Every cluster of bucket 10 (above 1024 members), one after the other on
+// stream s; blocks the host until they are integrated.
+hipError_t huge_clusters(p3t_ctx *c, const HermArgs &A, int count, hipStream_t s) {
+  hipError_t e;
+  std::vector<int32_t> ids(count);
+  if ((e = hipMemcpyAsync(ids.data(), A.blists + (int64_t)10 * A.nc, sizeof(int32_t) * count, hipMemcpyDeviceToHost,
+                          s)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  std::vector<int32_t> lo(count), hi(count);
+  int64_t m_max = 0;
+  for (int q = 0; q < count; ++q) {
+    int32_t b[2];
+    if ((e = hipMemcpy(b, A.cl_ptr + ids[q], sizeof(b), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+    lo[q] = b[0];
+    hi[q] = b[1];
+    m_max = std::max<int64_t>(m_max, b[1] - b[0]);
+  }
+  HugeArgs H;
+  if ((e = huge_buffers(c, m_max, H)) != hipSuccess) return e;
+  for (int q = 0; q < count; ++q) {
+    H.c = ids[q];
+    H.M = hi[q] - lo[q];
+    H.mem = A.members + lo[q];
+    const unsigned g1 = (unsigned)std::min<int64_t>(4096, (H.M + HUGE_T - 1) / HUGE_T);
+    const unsigned gw = (unsigned)std::min<int64_t>((int64_t)c->n_cu * 8, (H.M + 3) / 4);  // a wavefront per member
+    hipLaunchKernelGGL(k_huge_load, dim3(g1), dim3(HUGE_T), 0, s, A, H);
+    hipLaunchKernelGGL(k_huge_eval<true>, dim3(gw), dim3(HUGE_T), 0, s, A, H);
+    hipLaunchKernelGGL(k_huge_esum, dim3(1), dim3(HUGE_T), 0, s, H, 0);
+    for (int step = 0;;) {
+      for (int b = 0; b < HUGE_BATCH; ++b, ++step) {
+        hipLaunchKernelGGL(k_huge_predict, dim3(g1), dim3(HUGE_T), 0, s, A, H, step);
+        hipLaunchKernelGGL(k_huge_step, dim3(gw), dim3(HUGE_T), 0, s, A, H, step);
+      }
+      int32_t st[2];
+      if ((e = hipMemcpyAsync(st, H.nst, sizeof(st), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+      if (st[1]) break;  // done
+      if (st[0] >= A.max_iter) {  // block-step limit, as in the other paths
+        hipLaunchKernelGGL(k_huge_flag, dim3(1), dim3(1), 0, s, A.cnt, (unsigned)P3T_FLAG_NSTEPS);
+        break;
+      }
+    }
+    hipLaunchKernelGGL(k_huge_eval<false>, dim3(gw), dim3(HUGE_T), 0, s, A, H);
+    hipLaunchKernelGGL(k_huge_esum, dim3(1), dim3(HUGE_T), 0, s, H, 1);
+    hipLaunchKernelGGL(k_huge_store, dim3(g1), dim3(HUGE_T), 0, s, A, H);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // the scratch is reused by the next cluster and call: finish before returning
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace
 
 }  // namespace p3t

@@ -51,7 +51,7 @@ static_assert(sizeof(GroupList) == 24, "GroupList layout");
 // device-side counters (one small struct in the arena)
 struct DevCounters {
   unsigned int status;      // P3T_FLAG_* bits
-  unsigned int pad0;
+  unsigned int status_d;    // bits of the parked members' direct terms (second stream, merged after the join)
   unsigned long long pool_cursor;  // list pool allocation cursor
   unsigned long long n_pairs;      // neighbour pairs appended
   unsigned long long n_groups;     // interaction groups
@@ -65,6 +65,8 @@ struct DevCounters {
   unsigned long long n_pairs_d;   // pairs of the parked members' direct terms (p3t_hard_evaluate)
   unsigned long long n_unbound;   // orbits that are not bound (p3t_kepler_drift)
   unsigned long long n_bad_index; // list entries outside [0, n) (p3t_kepler_drift)
+  unsigned long long n_heval;     // Hermite: evaluations of members due in a block step (last hard part)
+  unsigned long long n_hpair;     // Hermite: pair terms of those evaluations
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -164,7 +166,7 @@ struct p3t_ctx {
   int n_cu = 256;
   std::string last_error;
   int timing = 0;
-  hipEvent_t ev[20] = {};
+  hipEvent_t ev[24] = {};
   p3t_stats stats = {};
 
   // capacities
@@ -193,6 +195,7 @@ struct p3t_ctx {
   int force_slots = 0;        // persistent force grid
   int force_persistent = 1;
   int walk_waves_per_cu = 8;  // persistent walk grid
+  int top_slots = 4096;       // LDS hash entries of the tree's top climb (power of two <= 4096)
   struct {
     int split = 1;         // 1: one kernel per interaction class, 0: the fused kernel
     int unroll = 4;        // j-loop unroll of the split kernels (1, 2, 4, 8)
@@ -265,8 +268,10 @@ struct p3t_ctx {
   int32_t *slow_list = nullptr;     // parked members (SLOW_CAP)
   double *slow_part = nullptr;      // partial sums of the forces on the parked members
   double *acc_d = nullptr;          // the parked members' direct terms (3 n_cap)
-  int2 *pairs_d = nullptr;          // their neighbour pairs (pairs_d_cap)
-  int64_t pairs_d_cap = 0;
+  char *huge_buf = nullptr;         // member states of the percolated-cluster path (hermite.hip)
+  size_t huge_bytes = 0;
+  int2 *pairs_d = nullptr;          // their neighbour pairs (pairs_d_cap used of pairs_d_alloc)
+  int64_t pairs_d_cap = 0, pairs_d_alloc = 0;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -344,6 +349,6 @@ hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns);
 hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                             double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
                             double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev = nullptr,
-                            int64_t *nc_out = nullptr);
+                            int64_t *nc_out = nullptr, int32_t *steps_out = nullptr);
 
 }  // namespace p3t

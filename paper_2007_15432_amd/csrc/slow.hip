@@ -79,13 +79,13 @@ __device__ __forceinline__ bool may_neighbour(double dx, double dy, double dz, d
   return dx * dx + dy * dy + dz * dz < rs * rs * (1.0 + 1e-12);
 }
 
-__device__ __forceinline__ void push_pair(DevCounters *cnt, unsigned long long *n_pairs, int2 *pairs, int64_t cap, int a,
-                                          int b) {
+// Slots beyond the capacity are counted but not written: the host compares
+// the count with the capacity after the join (no status bit is set here,
+// because the main stream's evaluation reads and clears the shared status
+// word while these kernels run).
+__device__ __forceinline__ void push_pair(unsigned long long *n_pairs, int2 *pairs, int64_t cap, int a, int b) {
   const unsigned long long q = atomicAdd(n_pairs, 1ull);
-  if ((int64_t)q < cap)
-    pairs[q] = make_int2(a, b);
-  else
-    set_flag(cnt, P3T_FLAG_PAIR_OVERFLOW);
+  if ((int64_t)q < cap) pairs[q] = make_int2(a, b);
 }
 
 struct SlowArgs {
@@ -98,6 +98,7 @@ struct SlowArgs {
   double *acc;
   double *part;
   DevCounters *cnt;
+  unsigned *status;             // status bits of this stream (DevCounters::status_d)
   unsigned long long *n_pairs;  // counter of `pairs`
   int2 *pairs;
   int64_t pair_cap;
@@ -191,8 +192,8 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
           if (tx[k] == xi && ty[k] == yi && tz[k] == zi) coincident = true;
           if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, tx[k], ty[k], tz[k], tvx[k], tvy[k], tvz[k],
                              tm[k], tro[k], trs[k], A.P.G, A.rsch2, A.rsch3, A.dt)) {
-            push_pair(A.cnt, A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, tid_[k]);
-            push_pair(A.cnt, A.n_pairs, A.pairs, A.pair_cap, tid_[k], (int32_t)i);
+            push_pair(A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, tid_[k]);
+            push_pair(A.n_pairs, A.pairs, A.pair_cap, tid_[k], (int32_t)i);
           }
         }
       }
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
       A.acc[i] = ax;
       A.acc[n + i] = ay;
       A.acc[2 * n + i] = az;
-      if (coincident) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
+      if (coincident) atomicOr(A.status, P3T_FLAG_COINCIDENT);
     }
   }
 }
@@ -254,11 +255,11 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
         if (neighbour_test(q.x, q.y, q.z, A.svel[i], A.svel[n + i], A.svel[2 * n + i], A.mass[i], A.ro[i], A.rs[i],
                            xj, yj, zj, A.svel[j], A.svel[n + j], A.svel[2 * n + j], mj, roj, A.rs[j], A.P.G,
                            A.rsch2, A.rsch3, A.dt))
-          push_pair(A.cnt, A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
+          push_pair(A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
       }
     }
   }
-  if (coincident) set_flag(A.cnt, P3T_FLAG_COINCIDENT);
+  if (coincident) atomicOr(A.status, P3T_FLAG_COINCIDENT);
 #pragma unroll
   for (int g = 0; g < SG; ++g) {
     if (g < gc) {
@@ -288,7 +289,7 @@ __global__ void k_slow_reduce(SlowArgs A) {
       a[d] = v;
       A.acc[d * A.n + i] = v;
     }
-    if (!(isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]))) set_flag(A.cnt, P3T_FLAG_NAN);
+    if (!(isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]))) atomicOr(A.status, P3T_FLAG_NAN);
   }
 }
 
@@ -308,7 +309,9 @@ __global__ void k_slow_merge(int64_t n, const uint8_t *__restrict__ slow, const 
 }
 
 // the pairs of the direct terms go behind those of the force kernels; a
-// second launch moves the counter (every thread of the first reads it)
+// second launch moves the counter (every thread of the first reads it).
+// Only the slots that were written are moved (at most cap_d); a count above
+// cap_d makes the host redo the evaluation.
 __global__ void k_slow_pairs(const int2 *__restrict__ pd, int64_t cap_d, int2 *__restrict__ pairs, int64_t cap,
                              DevCounters *cnt) {
   const unsigned long long nd = cnt->n_pairs_d, base = cnt->n_pairs;
@@ -322,7 +325,10 @@ __global__ void k_slow_pairs(const int2 *__restrict__ pd, int64_t cap_d, int2 *_
   }
 }
 
-__global__ void k_slow_pairs_count(DevCounters *cnt) { cnt->n_pairs += cnt->n_pairs_d; }
+__global__ void k_slow_pairs_count(DevCounters *cnt, int64_t cap_d) {
+  const unsigned long long nd = cnt->n_pairs_d;
+  cnt->n_pairs += nd < (unsigned long long)cap_d ? nd : (unsigned long long)cap_d;
+}
 
 }  // namespace
 
@@ -354,6 +360,7 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
   A.acc = c->acc_d;
   A.part = c->slow_part;
   A.cnt = c->cnt;
+  A.status = &c->cnt->status_d;
   A.n_pairs = &c->cnt->n_pairs_d;
   A.pairs = c->pairs_d;
   A.pair_cap = c->pairs_d_cap;
@@ -389,7 +396,7 @@ hipError_t slow_merge(p3t_ctx *c, double *pos3, double *vel3, double *acc3, int 
   const unsigned gp = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (c->pairs_d_cap + 255) / 256));
   hipLaunchKernelGGL(k_slow_pairs, dim3(gp), dim3(256), 0, s, (const int2 *)c->pairs_d, c->pairs_d_cap, c->pairs,
                      c->pair_cap, c->cnt);
-  hipLaunchKernelGGL(k_slow_pairs_count, dim3(1), dim3(1), 0, s, c->cnt);
+  hipLaunchKernelGGL(k_slow_pairs_count, dim3(1), dim3(1), 0, s, c->cnt, c->pairs_d_cap);
   return hipGetLastError();
 }
 

@@ -377,6 +377,7 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
 }
 
 constexpr int TOP_SLOTS = 4096;  // power of two
+constexpr int TOP_PROBES = 32;   // probes per node before it falls back to its counter in device memory
 
 // Workgroup 0 climbs from every chunk root to the root; the other
 // workgroups meanwhile flag the interaction groups, which need only the node
@@ -384,7 +385,8 @@ constexpr int TOP_SLOTS = 4096;  // power of two
 __global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::CellMom *cm,
                                                       const int32_t *__restrict__ parent, int32_t *visit,
                                                       const int32_t *__restrict__ chunk, const p3t::DevCounters *cnt,
-                                                      int n_nodes, int ng, int32_t *__restrict__ flag) {
+                                                      int n_nodes, int ng, int32_t *__restrict__ flag,
+                                                      int slots) {
   if (blockIdx.x > 0) {
     for (int g = (blockIdx.x - 1) * blockDim.x + threadIdx.x; g < n_nodes; g += (gridDim.x - 1) * blockDim.x) {
       const int c = wn[g].count;
@@ -393,11 +395,17 @@ __global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::Ce
     }
     return;
   }
-  // arrival counters of the top nodes in an LDS hash table (open
-  // addressing on the node id); a node that finds the table full uses its
-  // global counter, and so does its sibling's arrival (the table only fills)
+  // Arrival counters of the top nodes in an LDS hash table of `slots`
+  // entries (a power of two <= TOP_SLOTS; open addressing on the node id).
+  // A node that finds neither its key nor a free entry within TOP_PROBES
+  // probes uses its counter in device memory.  Keys are never removed, so the
+  // entries a node probes only ever fill: both arrivals at a node see the
+  // same probe sequence and make the same choice (the second finds the key
+  // the first stored, or the same entries taken by other nodes).
   __shared__ int hkey[TOP_SLOTS], hcnt[TOP_SLOTS];
-  for (int q = threadIdx.x; q < TOP_SLOTS; q += blockDim.x) {
+  const unsigned mask = (unsigned)slots - 1u;
+  const int probes = slots < TOP_PROBES ? slots : TOP_PROBES;
+  for (int q = threadIdx.x; q < slots; q += blockDim.x) {
     hkey[q] = -1;
     hcnt[q] = 0;
   }
@@ -407,15 +415,15 @@ __global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::Ce
     const int r = chunk[ci];
     int node = r == 0 ? -1 : parent[r];
     while (node >= 0) {
-      unsigned h = ((unsigned)node * 2654435761u) & (TOP_SLOTS - 1);
+      unsigned h = ((unsigned)node * 2654435761u) & mask;
       int slot = -1;
-      for (int probe = 0; probe < TOP_SLOTS; ++probe) {
+      for (int probe = 0; probe < probes; ++probe) {
         const int k = atomicCAS(&hkey[h], -1, node);
         if (k == -1 || k == node) {
           slot = (int)h;
           break;
         }
-        h = (h + 1) & (TOP_SLOTS - 1);
+        h = (h + 1) & mask;
       }
       const int prev = slot >= 0 ? atomicAdd(&hcnt[slot], 1) : atomicAdd(&visit[node], 1);
       if (prev != 1) break;
@@ -448,9 +456,11 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
   hipLaunchKernelGGL(k_morton, dim3(g1d(n)), dim3(256), 0, s, n, pos3, c->bbox, c->keys, c->perm);
   uint64_t *k = c->keys, *ka = c->keys_alt;
   int32_t *v = c->perm, *va = c->perm_alt;
+  ev_record(c, 17);
   if ((e = radix_sort_pairs(k, v, ka, va, n, nullptr, 0, 64, c->radix_hist, c->radix_hist_cap, c->scan_tmp,
                             c->scan_tmp_cap, s)) != hipSuccess)
     return e;
+  ev_record(c, 18);
   // after an even number of passes the result is back in keys / perm.  The
   // node records are rebuilt below, so their storage (96 B per node, 2n - 1
   // nodes) holds the packed rows until then.
@@ -481,7 +491,7 @@ hipError_t tree_moments(p3t_ctx *c, int64_t n) {
                      c->sreach, c->wnode, c->cmom, c->parent, c->visit, c->group_node, c->cnt);
   const unsigned gflag = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (n_nodes + 1023) / 1024));
   hipLaunchKernelGGL(k_moments_top, dim3(1 + gflag), dim3(1024), 0, s, c->wnode, c->cmom, c->parent, c->visit,
-                     c->group_node, c->cnt, (int)n_nodes, c->P.n_group_max, c->group_flag);
+                     c->group_node, c->cnt, (int)n_nodes, c->P.n_group_max, c->group_flag, c->top_slots);
   if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_group_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,

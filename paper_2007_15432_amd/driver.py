@@ -10,9 +10,12 @@ libp3t's kernels.
            tree; soft force and neighbour lists at the new state      (7)
            v += a_soft dt/2                                           (8)
 
-The cut-off radii are fixed between collisions (Section 2.4: they are
-recomputed after a merger); `recompute_cutoffs` recomputes them every step
-instead (used to time the cut-off stage as part of the step).
+The cut-off radii are fixed between collisions (Section 2.2 step (9): they
+are recomputed after a merger).  `monitor_cutoffs` computes the radii of the
+current state every step into buffers of their own (r_out_now, r_search_now,
+v_ran_now: what a re-cut after a collision would use) while the integration
+keeps the fixed ones; `recompute_cutoffs` applies new radii every step
+instead.
 
 overlap=True runs (4)-(7) as one p3t_hard_evaluate call: clusters still
 running after 2^slow_log2 block steps park and finish on a second stream
@@ -36,7 +39,7 @@ class P3TStepper:
     acceleration live in fixed buffers)."""
 
     def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False, graph: bool = False,
-                 fused_hard: bool = True, overlap: bool = False, slow_log2: int = 9):
+                 fused_hard: bool = True, overlap: bool = False, slow_log2: int = 9, monitor_cutoffs: bool = False):
         self.ctx = ctx
         self.graph = graph
         self.fused_hard = fused_hard
@@ -48,6 +51,10 @@ class P3TStepper:
         self.dt = ctx.params.dt_soft
         self.recompute = recompute_cutoffs
         self.r_out, self.r_search, self.v_ran = ctx.compute_cutoffs(pos, vel, mass)
+        self.monitor = monitor_cutoffs and not recompute_cutoffs
+        if self.monitor:
+            self.r_out_now, self.r_search_now, self.v_ran_now = (t.clone() for t in (self.r_out, self.r_search,
+                                                                                      self.v_ran))
         self.dt_hard = torch.zeros(self.n, dtype=torch.float64, device=pos.device)
         self.steps = torch.zeros(self.n, dtype=torch.int32, device=pos.device)  # block steps of each cluster
         self.acc = torch.empty((3, self.n), dtype=torch.float64, device=pos.device)
@@ -96,10 +103,13 @@ class P3TStepper:
                     self.v_ran, self.v_ran_next = self.v_ran_next, self.v_ran
                 c.compute_cutoffs(self.pos, self.vel, self.mass,
                                   out=(self.r_out_next, self.r_search_next, self.v_ran_next))
+            elif self.monitor:
+                c.compute_cutoffs(self.pos, self.vel, self.mass, out=(self.r_out_now, self.r_search_now, self.v_ran_now))
             c.kick(self.acc, self.vel, 0.5 * self.dt)
             return
         if self.fused_hard:
-            self.n_clusters = c.hard_step(self.pos, self.vel, self.mass, self.r_out, dt_hard=self.dt_hard)
+            self.n_clusters = c.hard_step(self.pos, self.vel, self.mass, self.r_out, dt_hard=self.dt_hard,
+                                          steps=self.steps)
         else:
             cl_ptr, members = c.clusters(self.label)
             self.n_clusters = int(cl_ptr.shape[0]) - 1
@@ -107,6 +117,8 @@ class P3TStepper:
                                    energy=False)
         if self.recompute:
             c.compute_cutoffs(self.pos, self.vel, self.mass, out=(self.r_out, self.r_search, self.v_ran))
+        elif self.monitor:
+            c.compute_cutoffs(self.pos, self.vel, self.mass, out=(self.r_out_now, self.r_search_now, self.v_ran_now))
         self._evaluate()
         c.kick(self.acc, self.vel, 0.5 * self.dt)
 

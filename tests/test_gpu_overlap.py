@@ -282,3 +282,53 @@ def test_overlapped_full_size_sampled(gpu, orc):
     print("parked members vs oracle", e_s, "sample", e)
     assert e_s[2] < 1e-6
     assert e[0] < 2e-3 and e[1] < 5e-4
+
+
+def test_direct_pair_overflow_redoes_the_evaluation(gpu, orc, stepped):
+    """The parked members' pair buffer made too small (direct_pair_cap = 1):
+    the second stream only counts what does not fit, the host sees the count
+    above the capacity after the join, grows the buffer and evaluates again
+    at the final state.  The result equals hard_step + evaluate bit for bit;
+    the next call, with the grown buffer, is overlapped and gives the same
+    neighbour lists as the serial call."""
+    s = stepped
+    L = pick_slow_log2(s["steps"], 8, 300)
+    if L is None:
+        pytest.skip("no slow clusters in this state")
+    a = serial(gpu, s)
+    ctx = gpu.Context(s["p"])
+    ctx.set_kernel_config(direct_pair_cap=1)
+    for rep in range(2):
+        pos, vel, dt, steps = s["pos"].clone(), s["vel"].clone(), s["dt"].clone(), s["steps"].clone()
+        ctx.evaluate(pos, vel, s["m"], s["ro"], s["rs"])
+        acc, nc, ns = ctx.hard_evaluate(pos, vel, s["m"], s["ro"], dt, steps, s["ro"], s["rs"], slow_log2=L,
+                                        graph=False)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        rp, col, _ = ctx.neighbour_list()
+        cap = ctx.kernel_config()["direct_pair_cap"]
+        print("rep", rep, "parked", ns, "direct pair capacity now", cap)
+        assert ns > 0
+        for k, v in (("pos", pos), ("vel", vel), ("dt", dt), ("rp", rp), ("col", col)):
+            assert torch.equal(a[k], v), k
+        if rep == 0:
+            assert cap > 1
+            assert torch.equal(a["acc"], acc)  # the redone evaluation is the ordinary one
+
+
+@pytest.mark.parametrize("slots", [1, 16])
+def test_top_climb_counter_fallback_is_exact(gpu, orc, stepped, slots):
+    """The top climb's arrival counters in a hash table of `slots` entries:
+    nodes that find no entry use their counter in device memory.  The
+    moments, hence forces and neighbour lists, do not change by a bit."""
+    s = stepped
+    out = []
+    for ts in (0, slots):
+        ctx = gpu.Context(s["p"])
+        if ts:
+            ctx.set_kernel_config(top_slots=ts)
+        acc = ctx.evaluate(s["pos"], s["vel"], s["m"], s["ro"], s["rs"], graph=False)
+        rp, col, _ = ctx.neighbour_list()
+        out.append((acc, rp, col))
+    for x, y in zip(out[0], out[1]):
+        assert torch.equal(x, y)

@@ -92,7 +92,7 @@ def test_serial_step_recomputes_before_the_evaluation():
     n = 4
     pos = torch.zeros((3, n), dtype=torch.float64)
 
-    def hard_step(pos, vel, mass, r_out, dt_hard=None):
+    def hard_step(pos, vel, mass, r_out, dt_hard=None, steps=None):
         ctx.calls.append(("hard_step", float(r_out[0])))
         return 1
 
