@@ -351,8 +351,37 @@ p3t_status p3t_get_kernel_config(p3t_ctx *ctx, p3t_kernel_config *cfg_host);
 p3t_status p3t_get_stats(p3t_ctx *ctx, p3t_stats *out_host);
 /* Read and clear the device status word.  Synchronises. */
 p3t_status p3t_get_status(p3t_ctx *ctx, uint32_t *flags_host);
-/* Text of the last error on this context (static storage of the context). */
+/* Text of the last error on this context (static storage of the context);
+ * with ctx = NULL, of the last failed p3t_compute_cutoffs_noalloc on the
+ * calling thread. */
 const char *p3t_last_error(p3t_ctx *ctx);
+
+/* p3t_compute_cutoffs without a context and without allocating: for callers
+ * that cannot call hipMalloc (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same radii as
+ * p3t_compute_cutoffs with the same parameters, bit for bit: the passes
+ * recompute each particle's cylindrical radius, random velocity and Hill
+ * radius where they need them instead of keeping them in scratch, so the
+ * only scratch (range partials, per-chunk bin sums, bin values) lives in a
+ * file-scope device array of 8 MiB that every GPU the library runs on holds
+ * until the process ends.
+ *   p_host: parameters (validated as by p3t_create; host memory).
+ *   pos3, vel3 (3n), mass (n): inputs; r_out, r_search (n), v_ran (n,
+ *     nullable): outputs.  Device memory, caller-owned.
+ *   hip_stream: a hipStream_t (NULL = the null stream); the call only
+ *     enqueues kernels on it (no synchronisation, no memset).
+ * Limit: the per-chunk bin sums take 2 ceil(n / 1024) vran_bins doubles;
+ * inputs that need more than the 8 MiB (n above about 8.3 million at 64
+ * bins) return P3T_ERR_CAPACITY and launch nothing.  The first call on a
+ * device (n = 0 included) looks the array's address up with
+ * hipGetSymbolAddress; make that call before capturing a graph.  All calls
+ * on one GPU share its array: calls that overlap on one GPU (other streams,
+ * other threads) race and give wrong radii.  Errors: P3T_ERR_ARG (null
+ * parameters or pointers, invalid parameters, n < 0), P3T_ERR_CAPACITY,
+ * P3T_ERR_HIP; text through p3t_last_error(NULL). */
+p3t_status p3t_compute_cutoffs_noalloc(const p3t_params *p_host, int64_t n, const double *pos3, const double *vel3,
+                                       const double *mass, double *r_out, double *r_search, double *v_ran,
+                                       void *hip_stream);
 
 #ifdef __cplusplus
 }

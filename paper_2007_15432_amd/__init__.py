@@ -6,6 +6,6 @@ the computing; this package is its Python binding.  Import is cheap: the
 library is loaded on first use and a missing library is an error.
 """
 from ._lib import LIB_PATH, load  # noqa: F401
-from .api import Context, P3TError, Params  # noqa: F401
+from .api import Context, P3TError, Params, compute_cutoffs_noalloc  # noqa: F401
 
-__all__ = ["load", "LIB_PATH", "Context", "Params", "P3TError"]
+__all__ = ["load", "LIB_PATH", "Context", "Params", "P3TError", "compute_cutoffs_noalloc"]

@@ -89,6 +89,7 @@ SIGNATURES = {
     "p3t_get_stats": (C.c_int, [_vp, C.POINTER(CStats)]),
     "p3t_get_status": (C.c_int, [_vp, C.POINTER(C.c_uint32)]),
     "p3t_last_error": (C.c_char_p, [_vp]),
+    "p3t_compute_cutoffs_noalloc": (C.c_int, [C.POINTER(CParams), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
 
 _lib = None

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["Params", "Context", "P3TError"]
+__all__ = ["Params", "Context", "P3TError", "compute_cutoffs_noalloc"]
 
 
 class P3TError(RuntimeError):
@@ -365,3 +365,31 @@ class Context:
                                             _ptr(vel), _ptr(index), m, _ptr(it),
                                             C.byref(nu) if count else None), "kepler_drift")
         return (int(nu.value) if count else None), (None if it is None else it[:m])
+
+
+def compute_cutoffs_noalloc(params: Params, pos, vel, mass, out):
+    """p3t_compute_cutoffs_noalloc: the cut-off and search radii without a
+    context and without allocating, into out = (r_out, r_search, v_ran or
+    None), on the current stream of the tensors' device."""
+    L = _lib.load()
+    n = int(mass.shape[0])
+    dev = mass.device
+    for t, shape, name in ((pos, (3, n), "pos"), (vel, (3, n), "vel"), (mass, (n,), "mass")):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.device == dev
+                and tuple(t.shape) == shape and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 {shape} tensor on {dev}")
+    ro, rs, vr = out
+    for t, name in ((ro, "r_out"), (rs, "r_search"), (vr, "v_ran")):
+        if t is None and name == "v_ran":
+            continue
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.device == dev
+                and tuple(t.shape) == (n,) and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 ({n},) tensor on {dev}")
+    with torch.cuda.device(dev):
+        st = L.p3t_compute_cutoffs_noalloc(C.byref(params.to_c()), n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(ro),
+                                           _ptr(rs), _ptr(vr), C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    if st != 0:
+        msg = L.p3t_last_error(None)
+        raise P3TError(st, f"compute_cutoffs_noalloc: {msg.decode() if msg else ''}")
+    return ro, rs, vr
+

@@ -227,6 +227,8 @@ double ev_ms(p3t_ctx *c, int a, int b) {
 
 bool bad_ptr(const void *p, int64_t n) { return n > 0 && p == nullptr; }
 
+const char *params_error(const p3t_params &P) { return check_params(P); }
+
 }  // namespace p3t
 
 extern "C" {
@@ -1004,6 +1006,6 @@ p3t_status p3t_get_status(p3t_ctx *c, uint32_t *flags) {
   return P3T_OK;
 }
 
-const char *p3t_last_error(p3t_ctx *c) { return c ? c->last_error.c_str() : "null context"; }
+const char *p3t_last_error(p3t_ctx *c) { return c ? c->last_error.c_str() : noalloc_last_error(); }
 
 }  // extern "C"

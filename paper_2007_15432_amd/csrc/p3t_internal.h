@@ -307,8 +307,16 @@ hipError_t kepler_singles(int64_t n, int32_t count, const int32_t *blist, const 
 
 // cutoff.hip
 int64_t cut_part_need(int64_t n_cap);
+const char *noalloc_last_error();  // last failure of p3t_compute_cutoffs_noalloc on this thread
 hipError_t compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                            double *r_out, double *r_search, double *v_ran);
+hipError_t cutoffs_run(const p3t_params &P, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                       double *r_out, double *r_search, double *v_ran, double *tmp, int32_t *bin, double *part,
+                       hipStream_t s);
+
+// api.hip
+const char *params_error(const p3t_params &P);  // why P is invalid, or nullptr
+bool bad_ptr(const void *p, int64_t n);         // p is null while n > 0
 
 // tree.hip
 hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
