@@ -285,6 +285,18 @@ p3t_status p3t_hard_evaluate(p3t_ctx *ctx, double *pos3, double *vel3, const dou
                              double *acc3, int32_t slow_log2, int32_t use_graph, int64_t *n_clusters_host,
                              int64_t *n_slow_host);
 
+/* Total energy of the particles about the star, eq. (soft) + eq. (hard)
+ * over all particles (Section 3.2.1 measures an integration's error by its
+ * relative change).  The changeover weights of a pair add up to one, so this
+ * is the Newtonian energy
+ *   E = sum_i [m_i |v_i|^2 / 2 - G M_* m_i / |x_i|] - sum_{i<j} G m_i m_j / r_ij,
+ * summed directly, O(N^2), in FP64 with compensated sums in a fixed order
+ * (a diagnostic for runs of modest N; about 1e8 pairs per millisecond).
+ * pos3, vel3 (3n), mass (n): device memory.  Synchronises and writes
+ * *energy_host. */
+p3t_status p3t_total_energy(p3t_ctx *ctx, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                            double *energy_host);
+
 /* Soft force over the CURRENT tree topology and interaction lists at new
  * positions pos3 (3n) and masses mass (n), in the caller's order, with the
  * pair cut-offs of the last p3t_build_tree: the sorted positions and masses

@@ -82,6 +82,7 @@ SIGNATURES = {
     "p3t_hard_evaluate": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
                                     C.POINTER(_i64), C.POINTER(_i64)]),
     "p3t_soft_force_frozen": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "p3t_total_energy": (C.c_int, [_vp, _i64, _vp, _vp, _vp, C.POINTER(_d)]),
     "p3t_soft_kick_adjoint": (C.c_int, [_vp, _d, _vp, _vp, _vp]),
     "p3t_set_timing": (C.c_int, [_vp, _i32]),
     "p3t_set_kernel_config": (C.c_int, [_vp, C.POINTER(CKernelConfig)]),

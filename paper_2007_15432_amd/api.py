@@ -262,6 +262,18 @@ class Context:
                     "hard_evaluate")
         return acc, int(nc.value), int(ns.value)
 
+    def total_energy(self, pos, vel, mass) -> float:
+        """Newtonian total energy of the particles about the star (eq. (soft)
+        + eq. (hard)), direct O(N^2) with compensated sums."""
+        n = int(mass.shape[0])
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        self._vec(mass, n, "mass")
+        e = C.c_double(0.0)
+        self._bind()
+        self._check(self.L.p3t_total_energy(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), C.byref(e)), "total_energy")
+        return float(e.value)
+
     def soft_force_frozen(self, pos, mass, out=None):
         """Soft force at new positions / masses over the current tree topology
         and interaction lists (the function the adjoint differentiates)."""

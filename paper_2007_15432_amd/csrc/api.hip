@@ -911,6 +911,22 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   return st_eval;
 }
 
+p3t_status p3t_total_energy(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                            double *energy_host) {
+  if (!c) return P3T_ERR_ARG;
+  if (n < 0 || n > (int64_t(1) << 30) || !energy_host) return fail(c, P3T_ERR_ARG, "total_energy: bad argument");
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n)) return fail(c, P3T_ERR_ARG, "total_energy: null pointer");
+  *energy_host = 0.0;
+  if (n == 0) return P3T_OK;
+  p3t_status st = ensure_n(c, n);
+  if (st != P3T_OK) return st;
+  double *share = c->tmp_d, *out = c->tmp_d + n;  // 3 n_cap doubles of scratch
+  HIP_OK(c, total_energy(n, pos3, vel3, mass, c->P.G, c->P.G * c->P.m_star, share, out, c->stream));
+  HIP_OK(c, hipMemcpyAsync(energy_host, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return P3T_OK;
+}
+
 p3t_status p3t_soft_force_frozen(p3t_ctx *c, const double *pos3, const double *mass, double *acc3) {
   if (!c) return P3T_ERR_ARG;
   if (!c->force_valid) return fail(c, P3T_ERR_STATE, "soft_force_frozen: no interaction lists (call p3t_compute_soft_force)");

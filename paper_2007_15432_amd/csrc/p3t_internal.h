@@ -305,6 +305,10 @@ hipError_t kepler_singles(int64_t n, int32_t count, const int32_t *blist, const 
                           const int32_t *members, double mu, double dt, double *pos3, double *vel3, double *dt_hard,
                           int32_t *msteps, double *e_rel, int32_t *nsteps, DevCounters *cnt, hipStream_t s);
 
+// energy.hip: total energy into out[0] (share: n doubles of scratch)
+hipError_t total_energy(int64_t n, const double *pos3, const double *vel3, const double *mass, double G, double GM,
+                        double *share, double *out, hipStream_t s);
+
 // cutoff.hip
 int64_t cut_part_need(int64_t n_cap);
 const char *noalloc_last_error();  // last failure of p3t_compute_cutoffs_noalloc on this thread
