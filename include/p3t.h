@@ -50,6 +50,7 @@ typedef enum {
 #define P3T_FLAG_NSTEPS 0x40u         /* Hermite block-step count limit reached */
 #define P3T_FLAG_BIG_CLUSTER 0x80u    /* a cluster took the percolated-cluster path (above cluster_cap members) */
 #define P3T_FLAG_UNBOUND 0x100u       /* an isolated particle's orbit is not bound (left in place; isolated = 1) */
+#define P3T_FLAG_GROUP_BOUND 0x200u   /* more interaction groups than the host's bound (retried internally) */
 
 /* Parameters.  Defaults (p3t_default_params) are the paper's values where it
  * prints them (Section 3.1: eta = 0.01, eta_0 = 0.1 eta, Rsearch0..3 = 1.1,

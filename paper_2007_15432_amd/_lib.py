@@ -24,6 +24,8 @@ FLAG_PAIR_OVERFLOW = 0x10
 FLAG_KMAX = 0x20
 FLAG_NSTEPS = 0x40
 FLAG_BIG_CLUSTER = 0x80
+FLAG_UNBOUND = 0x100
+FLAG_GROUP_BOUND = 0x200
 
 
 class CParams(C.Structure):

@@ -282,9 +282,9 @@ __global__ __launch_bounds__(WAVE) void k_adj_groups(AdjArgs A) {
 __global__ void k_adj_cell_coeffs(AdjArgs A) {
   const int64_t nn = A.n_nodes;
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nn; c += (int64_t)gridDim.x * blockDim.x) {
-    const double M = A.cm[c].mass;
     const double ax = A.cx[c], ay = A.cx[nn + c], az = A.cx[2 * nn + c];
     if (ax == 0.0 && ay == 0.0 && az == 0.0 && A.cmass[c] == 0.0) continue;  // cell never used
+    const double M = A.cm[c].mass;  // (the records of nodes no walk reaches are not written)
     const double iM = 1.0 / M;
     const double px = ax * iM, py = ay * iM, pz = az * iM;
     A.cx[c] = px;

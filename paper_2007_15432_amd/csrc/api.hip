@@ -18,7 +18,8 @@ namespace {
 
 constexpr unsigned NUMERIC_BITS =
     P3T_FLAG_COINCIDENT | P3T_FLAG_NAN | P3T_FLAG_KMAX | P3T_FLAG_NSTEPS | P3T_FLAG_UNBOUND;
-constexpr unsigned RETRY_BITS = P3T_FLAG_LIST_OVERFLOW | P3T_FLAG_STACK_OVERFLOW | P3T_FLAG_PAIR_OVERFLOW;
+constexpr unsigned RETRY_BITS =
+    P3T_FLAG_LIST_OVERFLOW | P3T_FLAG_STACK_OVERFLOW | P3T_FLAG_PAIR_OVERFLOW | P3T_FLAG_GROUP_BOUND;
 
 p3t_status fail(p3t_ctx *c, p3t_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 p3t_status fail(p3t_ctx *c, p3t_status st, const char *fmt, ...) {
@@ -422,16 +423,13 @@ p3t_status p3t_build_tree(p3t_ctx *c, int64_t n, const double *pos3, const doubl
   ev_record(c, 2);
   HIP_OK(c, build_tree(c, n, pos3, vel3, mass, r_out, r_search));
   ev_record(c, 3);
-  DevCounters h;
-  if ((st = sync_counters(c, &h)) != P3T_OK) return st;
-  c->n_groups = (int64_t)h.n_groups;
-  if (c->timing) {
-    c->stats.ms_tree = ev_ms(c, 2, 3);
-    c->stats.ms_sort = ev_ms(c, 17, 18);
-  }
+  // No synchronisation: the group count stays on the device.  The host
+  // keeps a bound for the grid sizes (twice the last count, or n); a larger
+  // count sets P3T_FLAG_GROUP_BOUND and the walk and force are redone.
+  c->n_groups = c->groups_hint > 0 ? std::min<int64_t>(n, 2 * c->groups_hint + 1024) : n;
+  c->tree_timing_pending = c->timing;
   c->stats.n = n;
   c->stats.n_nodes = 2 * n - 1;
-  c->stats.n_groups = c->n_groups;
   c->tree_valid = true;
   return P3T_OK;
 }
@@ -454,6 +452,10 @@ p3t_status grow_for_retry(p3t_ctx *c, const DevCounters &h) {
     c->slot_cap_stack *= 2;
     HIP_OK(c, dev_alloc(c->slot_stack, (int64_t)c->walk_slots * c->slot_cap_stack));
   }
+  if (retry & P3T_FLAG_GROUP_BOUND) {  // more groups than the bound: every group this time
+    c->n_groups = c->n;
+    c->groups_hint = 0;
+  }
   if (retry & P3T_FLAG_PAIR_OVERFLOW) {
     if ((int64_t)h.n_pairs > c->pair_cap) {
       const int64_t cap = (int64_t)h.n_pairs + (int64_t)h.n_pairs / 4 + 1024;
@@ -468,6 +470,10 @@ p3t_status grow_for_retry(p3t_ctx *c, const DevCounters &h) {
     }
   }
   return P3T_OK;
+}
+
+namespace {
+bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st);
 }
 
 p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
@@ -487,37 +493,14 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
     ev_record(c, 5);
     HIP_OK(c, soft_force(c, c->n_groups, acc3));
     ev_record(c, 6);
+    c->graphed = 0;
     DevCounters h;
     if ((st = sync_counters(c, &h)) != P3T_OK) return st;
-    const unsigned retry = h.status & RETRY_BITS;
-    if (retry) {
-      if ((st = grow_for_retry(c, h)) != P3T_OK) return st;
-      continue;
+    unsigned num = 0;
+    if (eval_finish(c, h, &num, &st)) {
+      if (st != P3T_OK) return st;
+      continue;  // grown: walk and force again over the same tree
     }
-    c->n_pairs = (int64_t)h.n_pairs;
-    c->stats.n_heval = (int64_t)h.n_heval;
-    c->stats.n_hpair = (int64_t)h.n_hpair;
-    c->stats.n_near = (int64_t)h.n_near;
-    c->stats.n_far = (int64_t)h.n_far;
-    c->stats.n_cell = (int64_t)h.n_cell;
-    c->stats.n_pairs = c->n_pairs;
-    c->stats.list_entries = (int64_t)h.pool_cursor;
-    if (c->timing) {
-      c->stats.ms_walk = ev_ms(c, 4, 5);
-      c->stats.ms_force = ev_ms(c, 5, 6);
-      if (c->fcfg.split) {
-        c->stats.ms_near = ev_ms(c, 5, 11);
-        c->stats.ms_far = ev_ms(c, 11, 12);
-        c->stats.ms_cell = ev_ms(c, 12, 13);
-        c->stats.ms_cand = ev_ms(c, 13, 14);
-      } else {
-        c->stats.ms_near = c->stats.ms_far = c->stats.ms_cell = c->stats.ms_cand = 0.0;
-      }
-    }
-    const unsigned num = h.status & NUMERIC_BITS;
-    c->host_status |= h.status & ~RETRY_BITS;
-    if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
-    c->force_valid = true;
     if (num)
       return fail(c, P3T_ERR_NUMERIC, "compute_soft_force: device status 0x%x (coincident particles or NaN)", num);
     return P3T_OK;
@@ -525,22 +508,27 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
   return fail(c, P3T_ERR_CAPACITY, "compute_soft_force: scratch still too small after repeated growth");
 }
 
-p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+namespace {
+
+// Tree, walk and soft force enqueued on the context's stream, eagerly or by
+// replaying the captured graph, with no host synchronisation; the caller
+// reads the counters once the work is done and hands them to eval_finish.
+p3t_status eval_enqueue(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                         const double *r_out, const double *r_search, double *acc3, int32_t use_graph) {
-  if (!c) return P3T_ERR_ARG;
-  if (!use_graph || n == 0) {
-    p3t_status st = p3t_build_tree(c, n, pos3, vel3, mass, r_out, r_search);
-    if (st != P3T_OK) return st;
-    return p3t_compute_soft_force(c, acc3);
+  p3t_status st;
+  if (!use_graph) {
+    if ((st = p3t_build_tree(c, n, pos3, vel3, mass, r_out, r_search)) != P3T_OK) return st;
+    ev_record(c, 4);
+    HIP_OK(c, walk_groups(c, c->n_groups));
+    ev_record(c, 5);
+    HIP_OK(c, soft_force(c, c->n_groups, acc3));
+    ev_record(c, 6);
+    c->graphed = 0;
+    return P3T_OK;
   }
-  if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "evaluate: n out of range");
-  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(r_search, n) ||
-      bad_ptr(acc3, n))
-    return fail(c, P3T_ERR_ARG, "evaluate: null pointer");
   c->tree_valid = c->force_valid = false;
   c->n = n;
-  p3t_status st = ensure_n(c, n);
-  if (st != P3T_OK) return st;
+  if ((st = ensure_n(c, n)) != P3T_OK) return st;
   if ((st = ensure_lists(c, n)) != P3T_OK) return st;
   const void *ptrs[] = {pos3, vel3, mass, r_out, r_search, acc3};
   const uint64_t key = graph_key(c, n, ptrs, 6);
@@ -575,19 +563,28 @@ p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double 
   ev_record(c, 2);
   HIP_OK(c, hipGraphLaunch(c->g_exec, c->stream));
   ev_record(c, 6);
-  DevCounters h;
-  if ((st = sync_counters(c, &h)) != P3T_OK) return st;
-  c->n_groups = (int64_t)h.n_groups;
+  c->n_groups = n;
   c->tree_valid = true;
   c->stats.n = n;
   c->stats.n_nodes = 2 * n - 1;
-  c->stats.n_groups = c->n_groups;
+  c->graphed = 1;
+  return P3T_OK;
+}
+
+// The counters h of a finished enqueued evaluation.  A buffer that
+// overflowed is grown (returns true: the evaluation must be redone);
+// otherwise the pair count, groups and statistics are taken over and the
+// numeric bits (coincident pairs, NaN) are left in *num.
+bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st) {
+  *st = P3T_OK;
+  *num = 0;
   if (h.status & RETRY_BITS) {
-    // a buffer overflowed: grow it (the key changes with it) and finish eagerly
-    if ((st = grow_for_retry(c, h)) != P3T_OK) return st;
-    return p3t_compute_soft_force(c, acc3);
+    *st = grow_for_retry(c, h);
+    return true;
   }
   c->n_pairs = (int64_t)h.n_pairs;
+  c->n_groups = c->groups_hint = (int64_t)h.n_groups;
+  c->stats.n_groups = c->n_groups;
   c->stats.n_heval = (int64_t)h.n_heval;
   c->stats.n_hpair = (int64_t)h.n_hpair;
   c->stats.n_near = (int64_t)h.n_near;
@@ -596,14 +593,59 @@ p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double 
   c->stats.n_pairs = c->n_pairs;
   c->stats.list_entries = (int64_t)h.pool_cursor;
   if (c->timing) {
-    c->stats.ms_tree = c->stats.ms_walk = 0.0;
-    c->stats.ms_force = ev_ms(c, 2, 6);  // the whole captured evaluation
-    c->stats.ms_near = c->stats.ms_far = c->stats.ms_cell = c->stats.ms_cand = 0.0;
+    if (c->graphed) {
+      c->stats.ms_tree = c->stats.ms_walk = c->stats.ms_sort = 0.0;
+      c->stats.ms_force = ev_ms(c, 2, 6);  // the whole captured evaluation
+      c->stats.ms_near = c->stats.ms_far = c->stats.ms_cell = c->stats.ms_cand = 0.0;
+    } else {
+      if (c->tree_timing_pending) {  // the tree of this evaluation was timed
+        c->stats.ms_tree = ev_ms(c, 2, 3);
+        c->stats.ms_sort = ev_ms(c, 17, 18);
+      }
+      c->stats.ms_walk = ev_ms(c, 4, 5);
+      c->stats.ms_force = ev_ms(c, 5, 6);
+      if (c->fcfg.split) {
+        c->stats.ms_near = ev_ms(c, 5, 11);
+        c->stats.ms_far = ev_ms(c, 11, 12);
+        c->stats.ms_cell = ev_ms(c, 12, 13);
+        c->stats.ms_cand = ev_ms(c, 13, 14);
+      } else {
+        c->stats.ms_near = c->stats.ms_far = c->stats.ms_cell = c->stats.ms_cand = 0.0;
+      }
+    }
+    c->tree_timing_pending = 0;
   }
-  const unsigned num = h.status & NUMERIC_BITS;
+  *num = h.status & NUMERIC_BITS;
   c->host_status |= h.status;
   if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
   c->force_valid = true;
+  return false;
+}
+
+}  // namespace
+
+p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
+                        const double *r_out, const double *r_search, double *acc3, int32_t use_graph) {
+  if (!c) return P3T_ERR_ARG;
+  if (!use_graph || n == 0) {
+    p3t_status st = p3t_build_tree(c, n, pos3, vel3, mass, r_out, r_search);
+    if (st != P3T_OK) return st;
+    return p3t_compute_soft_force(c, acc3);
+  }
+  if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "evaluate: n out of range");
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(r_search, n) ||
+      bad_ptr(acc3, n))
+    return fail(c, P3T_ERR_ARG, "evaluate: null pointer");
+  p3t_status st = eval_enqueue(c, n, pos3, vel3, mass, r_out, r_search, acc3, 1);
+  if (st != P3T_OK) return st;
+  DevCounters h;
+  if ((st = sync_counters(c, &h)) != P3T_OK) return st;
+  unsigned num = 0;
+  if (eval_finish(c, h, &num, &st)) {
+    // a buffer overflowed: grown (the key changes with it); finish eagerly
+    if (st != P3T_OK) return st;
+    return p3t_compute_soft_force(c, acc3);
+  }
   if (num) return fail(c, P3T_ERR_NUMERIC, "evaluate: device status 0x%x (coincident particles or NaN)", num);
   return P3T_OK;
 }
@@ -861,21 +903,22 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   // S empty too, so that a captured evaluation keeps its arguments)
   HIP_OK(c, slow_prepare(c, mass, ns));
   c->slow_active = 1;
-  st = p3t_evaluate(c, n, pos3, vel3, c->m_eff, r_out, r_search, acc3, use_graph);
+  st = eval_enqueue(c, n, pos3, vel3, c->m_eff, r_out, r_search, acc3, use_graph);
   c->slow_active = 0;
   // join: S's new state into pos3 / vel3, its terms into acc3
   if (ns > 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slow_ev[1], 0));
   ev_record(c, 15);
-  if (st != P3T_OK && st != P3T_ERR_NUMERIC) {
-    // the state is still that of p3t_hard_step; the force is not
+  if (st != P3T_OK) {
+    // nothing of the evaluation ran: the state is that of p3t_hard_step
     if (ns > 0) HIP_OK(c, slow_merge(c, pos3, vel3, nullptr, ns));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->force_valid = false;
     return st;
   }
   if (ns > 0) HIP_OK(c, slow_merge(c, pos3, vel3, acc3, ns));
-  const p3t_status st_eval = st;  // P3T_ERR_NUMERIC: flagged, but complete
   ev_record(c, 16);
+  // the one synchronisation of the evaluation: its counters, the direct
+  // terms' pair count and the second stream's status bits
   DevCounters h;
   if ((st = sync_counters(c, &h)) != P3T_OK) return st;
   if (c->timing) {
@@ -889,7 +932,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   const unsigned bits_d = ns > 0 ? h.status_d & NUMERIC_BITS : 0u;
   const bool direct_overflow = ns > 0 && (int64_t)h.n_pairs_d > c->pairs_d_cap;
   if ((h.status & RETRY_BITS) || direct_overflow) {
-    // a pair buffer was too small: grow it, and evaluate again at the final
+    // a buffer was too small: grow it, and evaluate again at the final
     // state (an ordinary evaluation, every term from the tree)
     c->host_status |= bits_d;
     if (direct_overflow) {
@@ -899,16 +942,13 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
     if ((h.status & RETRY_BITS) && (st = grow_for_retry(c, h)) != P3T_OK) return st;
     return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, 0);
   }
-  c->n_pairs = (int64_t)h.n_pairs;
-  c->stats.n_pairs = c->n_pairs;
-  c->stats.n_heval = (int64_t)h.n_heval;
-  c->stats.n_hpair = (int64_t)h.n_hpair;
-  const unsigned num = (h.status | bits_d) & NUMERIC_BITS;
-  c->host_status |= h.status | bits_d;
-  if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
+  unsigned num = 0;
+  eval_finish(c, h, &num, &st);  // no retry bits here
+  num |= bits_d;
+  c->host_status |= bits_d;
   if (num)
     return fail(c, P3T_ERR_NUMERIC, "hard_evaluate: device status 0x%x (coincident particles or NaN)", num);
-  return st_eval;
+  return P3T_OK;
 }
 
 p3t_status p3t_total_energy(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,

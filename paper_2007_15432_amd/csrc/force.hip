@@ -40,7 +40,7 @@ __global__ __launch_bounds__(WAVE) void k_force(ForceArgs A) {
   __shared__ float4 fB[WAVE];   // mixed cells: G q0..q3
   __shared__ float2 fC[WAVE];   // mixed cells: G q4, q5
   const int lane = threadIdx.x;
-  const int ngroups = uniform_first((int)A.cnt->n_groups);
+  const int ngroups = uniform_first(min((int)A.cnt->n_groups, A.ngroups_bound));
   int iter = 0;
   for (;;) {
     int gi;
@@ -407,6 +407,7 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3, bool froze
   A.rsch3 = P.r_search3;
   A.dt = P.dt_soft;
   A.persistent = c->force_persistent;
+  A.ngroups_bound = (int)std::min<int64_t>(n_groups_max, INT32_MAX);
   A.queue = &c->cnt->force_queue;
   unsigned grid = A.persistent ? (unsigned)c->force_slots : (unsigned)std::max<int64_t>(1, n_groups_max);
   if (c->fcfg.split) return soft_force_split(c, A, (unsigned)std::max<int64_t>(1, n_groups_max), acc3);

@@ -24,6 +24,7 @@ struct ForceArgs {
   double G, gamma, inv1mg;
   double rsch2, rsch3, dt;  // neighbour-test parameters
   int persistent;
+  int ngroups_bound;          // groups processed at most (the host's bound; the count itself is on the device)
   unsigned long long *queue;  // persistent-queue head of this launch
 };
 

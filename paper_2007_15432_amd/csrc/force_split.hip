@@ -205,7 +205,7 @@ template <int UNR>
 __global__ __launch_bounds__(WAVE) void k_near(ForceArgs A) {
   __shared__ NearTile T;
   const int lane = threadIdx.x;
-  const int ngroups = uniform_first((int)A.cnt->n_groups);
+  const int ngroups = uniform_first(min((int)A.cnt->n_groups, A.ngroups_bound));
   for (int iter = 0;; ++iter) {
     const int gi = next_gi(A, lane, iter, ngroups);
     if (gi >= ngroups) break;
@@ -341,7 +341,7 @@ template <bool MIXED, int UNR>
 __global__ __launch_bounds__(WAVE) void k_far(ForceArgs A) {
   __shared__ FarTile T;
   const int lane = threadIdx.x;
-  const int ngroups = uniform_first((int)A.cnt->n_groups);
+  const int ngroups = uniform_first(min((int)A.cnt->n_groups, A.ngroups_bound));
   for (int iter = 0;; ++iter) {
     const int gi = next_gi(A, lane, iter, ngroups);
     if (gi >= ngroups) break;
@@ -536,7 +536,7 @@ template <bool MIXED, bool QUAD, int UNR>
 __global__ __launch_bounds__(WAVE) void k_cell(ForceArgs A) {
   __shared__ CellTile T;
   const int lane = threadIdx.x;
-  const int ngroups = uniform_first((int)A.cnt->n_groups);
+  const int ngroups = uniform_first(min((int)A.cnt->n_groups, A.ngroups_bound));
   for (int iter = 0;; ++iter) {
     const int gi = next_gi(A, lane, iter, ngroups);
     if (gi >= ngroups) break;

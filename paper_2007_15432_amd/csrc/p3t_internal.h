@@ -196,6 +196,9 @@ struct p3t_ctx {
   int force_persistent = 1;
   int walk_waves_per_cu = 8;  // persistent walk grid
   int top_slots = 4096;       // LDS hash entries of the tree's top climb (power of two <= 4096)
+  int64_t groups_hint = 0;    // group count of the last evaluation (bounds the next one's grids)
+  int tree_timing_pending = 0;  // the last tree build recorded its events
+  int graphed = 0;            // the last evaluation replayed the captured graph
   struct {
     int split = 1;         // 1: one kernel per interaction class, 0: the fused kernel
     int unroll = 4;        // j-loop unroll of the split kernels (1, 2, 4, 8)

@@ -226,6 +226,15 @@ static_assert(sizeof(NodeRec) == 136, "NodeRec layout");
 // subtree of the radix tree over leaves [first, first + count) numbers its
 // count - 1 internal nodes inside [first, first + count), so node - first
 // indexes a slot.  Same arithmetic, in the same order, as combine_node.
+//
+// Only the records that something reads are written to device memory: the
+// walk stops at the first node of at most n_leaf particles, so it reads a
+// node (box, centre, reach, range) only if the node's parent holds more than
+// n_leaf particles, and the force kernels read the moments of such nodes
+// when they are accepted as cells; the chunk roots are read by the top
+// climb.  Below that level the climb keeps its records in LDS only (most of
+// the 2n - 1 nodes: about 90% at n_leaf = 16).  A particle's moment record
+// is needed only when it is a chunk root itself.
 constexpr int MOM_T = 1024;
 
 __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__restrict__ sx,
@@ -234,10 +243,11 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
                                                          const double *__restrict__ sreach, p3t::WalkNode *wn,
                                                          p3t::CellMom *cm, const int32_t *__restrict__ parent,
                                                          int32_t *visit, const int32_t *__restrict__ chunk,
-                                                         p3t::DevCounters *cnt) {
+                                                         p3t::DevCounters *cnt, int n_leaf) {
   __shared__ __align__(16) NodeRec rec[CHUNK];
   __shared__ int lvisit[CHUNK];
   __shared__ int tleft[CHUNK], tright[CHUNK], tpar[CHUNK];  // the chunk's topology
+  __shared__ unsigned char wide[CHUNK];  // internal node first + t holds more than n_leaf particles
   const int leaf0 = n - 1;
   const int nch = (int)cnt->n_chunks;
   auto child = [&](int c, int first, int count, NodeRec &o) -> bool {
@@ -268,8 +278,17 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
         tleft[t] = wn[node].left;
         tright[t] = wn[node].right;
         tpar[t] = parent[node];
+        wide[t] = wn[node].count > n_leaf ? 1 : 0;
       }
     }
+    __syncthreads();
+    // is the record of node c (in this chunk) read later: the chunk root,
+    // or a node whose parent (then inside the chunk) is wider than a leaf
+    auto needed = [&](int c, int par) -> bool {
+      if (c == r) return true;
+      const unsigned po = (unsigned)(par - first);
+      return po < (unsigned)count && wide[po];
+    };
     // leaf records, staged in the (still unused) record slots and written
     // out as consecutive 16-B words: 96-B and 80-B records stored lane by
     // lane would leave every store instruction on scattered partial lines
@@ -278,8 +297,11 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
     p3t::WalkNode *lw = reinterpret_cast<p3t::WalkNode *>(rec);
     p3t::CellMom *lc = reinterpret_cast<p3t::CellMom *>(rec);
     const uint4 *stage = reinterpret_cast<const uint4 *>(rec);
+    // the leaves whose walk record is read (staged, then written as 16-B words)
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
       const int k = first + t;
+      const int leaf = leaf0 + k;
+      lvisit[t] = needed(leaf, leaf == r ? -1 : parent[leaf]) ? 1 : 0;  // reset below, before the climb
       p3t::WalkNode w;
       w.lo[0] = w.hi[0] = w.com[0] = sx[k];
       w.lo[1] = w.hi[1] = w.com[1] = sy[k];
@@ -294,12 +316,15 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
     __syncthreads();
     {
       uint4 *dst = reinterpret_cast<uint4 *>(wn + leaf0 + first);
-      const int words = count * (int)(sizeof(p3t::WalkNode) / sizeof(uint4));
-      for (int q = threadIdx.x; q < words; q += blockDim.x) dst[q] = stage[q];
+      constexpr int WPR = (int)(sizeof(p3t::WalkNode) / sizeof(uint4));
+      const int words = count * WPR;
+      for (int q = threadIdx.x; q < words; q += blockDim.x)
+        if (lvisit[q / WPR]) dst[q] = stage[q];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < count; t += blockDim.x) {
-      const int k = first + t;
+    for (int t = threadIdx.x; t < count; t += blockDim.x) lvisit[t] = 0;
+    if (r >= leaf0 && threadIdx.x == 0) {  // a chunk of one particle: the top climb reads its moments
+      const int k = r - leaf0;
       p3t::CellMom c;
       c.com[0] = sx[k];
       c.com[1] = sy[k];
@@ -307,13 +332,7 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
       c.mass = sm[k];
 #pragma unroll
       for (int q = 0; q < 6; ++q) c.q[q] = 0.0;
-      lc[t] = c;
-    }
-    __syncthreads();
-    {
-      uint4 *dst = reinterpret_cast<uint4 *>(cm + leaf0 + first);
-      const int words = count * (int)(sizeof(p3t::CellMom) / sizeof(uint4));
-      for (int q = threadIdx.x; q < words; q += blockDim.x) dst[q] = stage[q];
+      cm[r] = c;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
@@ -352,21 +371,23 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
         quad_shift(o.q, rb.mass, rb.com[0] - o.com[0], rb.com[1] - o.com[1], rb.com[2] - o.com[2]);
         o.reach = fmax(ra.reach, rb.reach);
         rec[off] = o;
-        // the node's range and children are already in its record
-        p3t::WalkNode &wo = wn[node];
-        p3t::CellMom co;
+        if (needed(node, tpar[off])) {
+          // the node's range and children are already in its record
+          p3t::WalkNode &wo = wn[node];
+          p3t::CellMom co;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          wo.lo[d] = o.lo[d];
-          wo.hi[d] = o.hi[d];
-          wo.com[d] = o.com[d];
-          co.com[d] = o.com[d];
+          for (int d = 0; d < 3; ++d) {
+            wo.lo[d] = o.lo[d];
+            wo.hi[d] = o.hi[d];
+            wo.com[d] = o.com[d];
+            co.com[d] = o.com[d];
+          }
+          wo.reach = o.reach;
+          co.mass = M;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) co.q[q] = o.q[q];
+          cm[node] = co;
         }
-        wo.reach = o.reach;
-        co.mass = M;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) co.q[q] = o.q[q];
-        cm[node] = co;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
         if (node == r) break;
         node = tpar[off];
@@ -388,8 +409,10 @@ __global__ __launch_bounds__(1024) void k_moments_top(p3t::WalkNode *wn, p3t::Ce
                                                       int n_nodes, int ng, int32_t *__restrict__ flag,
                                                       int slots) {
   if (blockIdx.x > 0) {
+    // (a particle's record may not be written: its count is 1)
+    const int leaf0 = (n_nodes - 1) / 2;
     for (int g = (blockIdx.x - 1) * blockDim.x + threadIdx.x; g < n_nodes; g += (gridDim.x - 1) * blockDim.x) {
-      const int c = wn[g].count;
+      const int c = g >= leaf0 ? 1 : wn[g].count;
       const int p = (g == 0) ? -1 : parent[g];
       flag[g] = (c <= ng && (p < 0 || wn[p].count > ng)) ? 1 : 0;
     }
@@ -488,7 +511,7 @@ hipError_t tree_moments(p3t_ctx *c, int64_t n) {
   hipLaunchKernelGGL(k_chunk_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
                      c->group_node, c->cnt);
   hipLaunchKernelGGL(k_moments_local, dim3(c->n_cu * 2), dim3(MOM_T), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm,
-                     c->sreach, c->wnode, c->cmom, c->parent, c->visit, c->group_node, c->cnt);
+                     c->sreach, c->wnode, c->cmom, c->parent, c->visit, c->group_node, c->cnt, c->P.n_leaf_max);
   const unsigned gflag = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (n_nodes + 1023) / 1024));
   hipLaunchKernelGGL(k_moments_top, dim3(1 + gflag), dim3(1024), 0, s, c->wnode, c->cmom, c->parent, c->visit,
                      c->group_node, c->cnt, (int)n_nodes, c->P.n_group_max, c->group_flag, c->top_slots);

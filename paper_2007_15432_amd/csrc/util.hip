@@ -113,7 +113,67 @@ hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *
   return scan_impl<int32_t, int64_t>(in, out, n, 1, tmp, tmp_cap, s);
 }
 
+// Exclusive scan of up to SB_MAX counters in one workgroup and one launch
+// (the radix sort's digit-by-tile counters: 65,536 at 2^20 keys).  Chunks
+// of SB_T * SB_I counters pass through LDS: coalesced load, each thread
+// scans its SB_I consecutive counters after a workgroup scan of the
+// per-thread sums (plus the running total of the earlier chunks), coalesced
+// store.  One padding word per SB_I keeps the per-thread runs on distinct
+// LDS banks.
+constexpr int SB_T = 1024, SB_I = 16, SB_CHUNK = SB_T * SB_I;
+constexpr int64_t SB_MAX = 65536;
+
+__device__ __forceinline__ int sb_idx(int i) { return i + i / SB_I; }
+
+__global__ __launch_bounds__(SB_T) void k_scan_block_u32(uint32_t *__restrict__ data, int64_t n) {
+  __shared__ uint32_t buf[SB_CHUNK + SB_CHUNK / SB_I];
+  __shared__ uint32_t ws[SB_T / WAVE];
+  __shared__ uint32_t carry;
+  const int t = threadIdx.x, w = t / WAVE, l = t & (WAVE - 1);
+  if (t == 0) carry = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += SB_CHUNK) {  // uniform
+#pragma unroll
+    for (int q = 0; q < SB_I; ++q) {
+      const int i = q * SB_T + t;
+      buf[sb_idx(i)] = c0 + i < n ? data[c0 + i] : 0u;
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < SB_I; ++q) s += buf[sb_idx(t * SB_I + q)];
+    uint32_t incl = s;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, WAVE);
+      if (l >= o) incl += v;
+    }
+    if (l == WAVE - 1) ws[w] = incl;
+    __syncthreads();
+    uint32_t run = carry + incl - s;
+    for (int q = 0; q < w; ++q) run += ws[q];
+#pragma unroll
+    for (int q = 0; q < SB_I; ++q) {
+      const int i = sb_idx(t * SB_I + q);
+      const uint32_t v = buf[i];
+      buf[i] = run;
+      run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SB_I; ++q) {
+      const int i = q * SB_T + t;
+      if (c0 + i < n) data[c0 + i] = buf[sb_idx(i)];
+    }
+    if (t == SB_T - 1) carry = run;  // the running total after this chunk
+    __syncthreads();
+  }
+}
+
 hipError_t scan_u32_inplace(uint32_t *data, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s) {
+  if (n > SCAN_TILE && n <= SB_MAX) {
+    hipLaunchKernelGGL(k_scan_block_u32, dim3(1), dim3(SB_T), 0, s, data, n);
+    return hipGetLastError();
+  }
   return scan_impl<uint32_t, uint32_t>(data, data, n, 0, tmp, tmp_cap, s);
 }
 

@@ -170,9 +170,13 @@ __global__ void k_reset_queues(DevCounters *cnt) {
 }
 
 // Sort key of a group: (work descending, group index ascending).
+// A device count above n_static (the host's bound, from the last evaluation)
+// sets P3T_FLAG_GROUP_BOUND: the sort and the force then cover only the
+// first n_static groups and the host evaluates again with the bound n.
 __global__ void k_group_keys(const GroupList *__restrict__ gl, const WalkNode *__restrict__ wn, int n_static,
-                             const DevCounters *__restrict__ cnt, uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
+                             DevCounters *cnt, uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
   const int ng = (int)cnt->n_groups;
+  if (ng > n_static && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&cnt->status, P3T_FLAG_GROUP_BOUND);
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_static; g += gridDim.x * blockDim.x) {
     if (g < ng) {
       const GroupList L = gl[g];
