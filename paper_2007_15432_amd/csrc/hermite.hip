@@ -10,13 +10,18 @@
 // of the doubled step.  Energy of eq. (hard) restricted to the cluster before
 // and after.
 //
-// Clusters are bucketed by size and all buckets run in ONE launch, so the
-// long-running clusters of different sizes overlap instead of queueing:
-//   sizes <= 64: SEG = next power of two lanes per cluster, 64/SEG clusters
-//     per wavefront, one member per lane; each wavefront runs its own block
-//     steps and synchronises only with itself (LDS is private per wave);
-//   sizes 65..256: one 256-thread workgroup per cluster (same launch);
-//   sizes 257..1024: separate launches with 2 or 4 members per thread.
+// Clusters are bucketed by size; the buckets up to 64 members run in ONE
+// launch, so the long-running clusters of different sizes overlap instead
+// of queueing:
+//   sizes <= 4: SEG = next power of two lanes per cluster, 64/SEG clusters
+//     per wavefront, one member per lane (seg_body);
+//   sizes 5..64: one wavefront per cluster, one member per lane, the due
+//     members' partner sums spread over the wavefront (wave_body);
+//   each wavefront runs its own block steps and synchronises only with
+//   itself (LDS is private per wave);
+//   sizes 65..1024: one 256-thread workgroup per cluster with 1, 2 or 4
+//     members per thread, in launches of their own beside the fused one;
+//   larger: the percolated-cluster path (device-wide, below).
 // Predicted states are shared through LDS.
 #include <algorithm>
 #include <climits>
@@ -31,6 +36,7 @@ constexpr int BIG_T = 256;
 constexpr int N_BUCKETS = HERM_N_BUCKETS;  // SEG 1..64 (7), 256-thread MPT 1, 2, 4 (3), too big (1)
 constexpr int BC_NC = HERM_BC_NC, BC_BAD = HERM_BC_BAD, BC_WORDS = HERM_BC_WORDS;
 constexpr int PK_MEM = HERM_BC_PARKED - HERM_BC_PARK0;  // parked-member word, relative to the park counts
+constexpr int WAVE_BK0 = 3;  // buckets 3..6 (5..64 members): one wavefront per cluster (wave_body)
 
 struct HermArgs {
   const int32_t *cl_ptr, *members, *blists;
@@ -535,6 +541,291 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   if (lead && A.msteps) A.msteps[gid] = nst;
 }
 
+// ---------------------------------------------------------------- mid-size clusters
+// one butterfly stage (a DPP lane permutation inside rows of 16 lanes)
+// added to six sums; every lane of the wavefront takes part
+template <int CTRL>
+__device__ __forceinline__ void red6(double *pa, double *pj) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    pa[d] += dpp_f64<CTRL>(pa[d]);
+    pj[d] += dpp_f64<CTRL>(pj[d]);
+  }
+}
+
+// minimum over the wavefront, as a wave-uniform value: DPP inside each row
+// of 16 lanes, then the four row minima read into scalar registers (no LDS
+// round trip)
+__device__ __forceinline__ int64_t wave_min_uniform(int64_t v) {
+  v = seg_min(v, 4);
+  const int64_t r0 = uniform_lane64(v, 0), r1 = uniform_lane64(v, 16);
+  const int64_t r2 = uniform_lane64(v, 32), r3 = uniform_lane64(v, 48);
+  const int64_t m01 = r0 < r1 ? r0 : r1, m23 = r2 < r3 ? r2 : r3;
+  return m01 < m23 ? m01 : m23;
+}
+
+// ceil(log2(v)) for 1 <= v <= 64
+__device__ __forceinline__ int ceil_log2(int v) { return v <= 1 ? 0 : 32 - __clz(v - 1); }
+
+// Partner sums (star excluded) of the members listed in L.act[wbase, +n_act)
+// from the states in the LDS slots [wbase, wbase + size): each listed member
+// gets 2^lg lanes, 2^lg = the largest power of two with n_act 2^lg <= 64 and
+// 2^lg <= the cluster's power of two; a lane sums every 2^lg-th partner and
+// DPP adds the partial sums inside each row of 16 lanes.  The sums land in
+// L.res, six doubles per slot: the member at list position a owns the slots
+// [a P, a P + P), P = 2^lg / 16 row partials (1 if 2^lg <= 16), which its
+// own lane adds in order (res_slots gives P).  Every lane of the wavefront
+// must call it.
+__device__ __forceinline__ int res_parts_log2(int lg) { return lg > 4 ? lg - 4 : 0; }
+
+__device__ __forceinline__ int spread_lg(int size, int n_act) { return min(6 - ceil_log2(n_act), ceil_log2(size)); }
+
+__device__ __forceinline__ void spread_sums(const HermArgs &A, const Lds &L, int wbase, int size, int n_act, int lane,
+                                            unsigned long long amask) {
+  const int lg = spread_lg(size, n_act);
+  const int grp = lane >> lg, sub = lane & ((1 << lg) - 1);
+  int k;
+  if (n_act <= 2) {  // the usual case: the members from the due mask, in scalar registers
+    const int k0 = __ffsll((long long)amask) - 1;
+    const int k1 = __ffsll((long long)(amask & (amask - 1))) - 1;
+    k = grp == 0 ? k0 : (grp == 1 ? k1 : -1);
+  } else {
+    k = grp < n_act ? L.act[wbase + grp] : -1;
+  }
+  double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0};
+  if (k >= 0) {
+    const int sk = wbase + k;
+    const double xk = L.px[sk], yk = L.py[sk], zk = L.pz[sk], vxk = L.pvx[sk], vyk = L.pvy[sk], vzk = L.pvz[sk];
+    const double ik = L.pinv[sk];
+    for (int q = sub; q < size; q += 1 << lg) {
+      if (q == k) continue;
+      const int sq = wbase + q;
+      hard_pair(L.px[sq] - xk, L.py[sq] - yk, L.pz[sq] - zk, L.pvx[sq] - vxk, L.pvy[sq] - vyk, L.pvz[sq] - vzk,
+                L.pgm[sq], fmin(ik, L.pinv[sq]), A, pa, pj);
+    }
+  }
+  // one uniform branch per stage for all six sums
+  const int rl = lg < 4 ? lg : 4;
+  if (rl >= 1) red6<DPP_XOR1>(pa, pj);
+  if (rl >= 2) red6<DPP_XOR2>(pa, pj);
+  if (rl >= 3) red6<DPP_HALF_MIRROR>(pa, pj);
+  if (rl >= 4) red6<DPP_MIRROR>(pa, pj);
+  if (k >= 0 && (sub & ((1 << rl) - 1)) == 0) {
+    const int slot = (grp << res_parts_log2(lg)) + (sub >> 4);
+    double *r = L.res + 6 * (wbase + slot);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      r[d] = pa[d];
+      r[3 + d] = pj[d];
+    }
+  }
+}
+
+// adds the partner sums of the member at list position a (after spread_sums)
+__device__ __forceinline__ void add_spread(const Lds &L, int wbase, int a, int lg, double *a1, double *j1) {
+  const int pl = res_parts_log2(lg);
+  for (int p = 0; p < (1 << pl); ++p) {
+    const double *r = L.res + 6 * (wbase + (a << pl) + p);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      a1[d] += r[d];
+      j1[d] += r[3 + d];
+    }
+  }
+}
+
+// One wavefront per cluster of 5..64 members (buckets 3..6), one member per
+// lane.  In a block step usually only a few members are due; their partner
+// sums are spread over the whole wavefront (spread_sums), so a step costs a
+// few pair evaluations per lane instead of size - 1 in the due members'
+// lanes.  The wavefront synchronises only with itself.  Same arithmetic per
+// member as the other paths (hard_pair, star_term, correct, initial_level).
+// MODE 0: plain; 1: park after A.budget block steps; 2: resume parked.
+template <int MODE>
+__device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blist, int count, int ci, const Lds &L,
+                                          int wbase, int bk) {
+  constexpr bool RESUME = MODE == 2, PARK = MODE == 1;
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (ci >= count) return;  // uniform per wavefront; no workgroup barrier follows
+  const int c = blist[ci];
+  const int b = A.cl_ptr[c];
+  const int size = uniform_first(A.cl_ptr[c + 1] - b);
+  const bool mem = lane < size;
+  const int gid = mem ? A.members[b + lane] : 0;
+  const int64_t n = A.n;
+  const int me = wbase + lane;
+  double x[3] = {1.0, 0.0, 0.0}, v[3] = {0.0, 1.0, 0.0}, a0[3], j0[3];
+  double m = 0.0, ro = 1.0;
+  const double *src_x = RESUME ? A.pk.x : A.pos, *src_v = RESUME ? A.pk.v : A.vel;
+  if (mem) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x[d] = src_x[d * n + gid];
+      v[d] = src_v[d * n + gid];
+    }
+    m = A.mass[gid];
+    ro = A.ro[gid];
+  }
+  const double invi = 1.0 / ro;
+  const double GM = A.GM, tick = A.tick;
+  wave_sync();
+  L.pgm[me] = A.G * m;
+  L.pinv[me] = invi;
+  L.px[me] = x[0];
+  L.py[me] = x[1];
+  L.pz[me] = x[2];
+  L.pvx[me] = v[0];
+  L.pvy[me] = v[1];
+  L.pvz[me] = v[2];
+  if (mem) L.act[wbase + lane] = lane;  // every member: the forces at t = 0
+  wave_sync();
+  double E0 = 0.0;
+  int lev = 0;
+  int64_t t = 0;
+  int nst = 0;
+  star_term(x, v, GM, a0, j0);
+  if (!RESUME) {
+    spread_sums(A, L, wbase, size, size, lane, __ballot(mem));
+    double e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
+                         GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
+                   : 0.0;
+    if (mem)
+      for (int q = lane + 1; q < size; ++q) {
+        const int sq = wbase + q;
+        const double dx = L.px[sq] - x[0], dy = L.py[sq] - x[1], dz = L.pz[sq] - x[2];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        e -= m * L.pgm[sq] * (1.0 - changeover_W(r * fmin(invi, L.pinv[sq]), A)) / r;
+      }
+    E0 = seg_sum(e, 6);
+    wave_sync();
+    if (mem) add_spread(L, wbase, lane, spread_lg(size, size), a0, j0);  // list position = lane
+    lev = initial_level(a0, j0, mem, gid, A);
+  } else {
+    if (mem) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        a0[d] = A.pk.a[d * n + gid];
+        j0[d] = A.pk.j[d * n + gid];
+      }
+      t = A.pk.t[gid];
+      lev = A.pk.lev[gid];
+    }
+    nst = A.pk.nst[c];
+    E0 = A.pk.e0[c];
+  }
+  const int64_t T = (int64_t)1 << TICK_BITS;
+  const int budget = PARK ? A.budget : INT_MAX;
+  const int max_iter = A.max_iter;
+  int n_eval = 0;  // block steps in which this lane's member was due
+  bool parked = false;
+  for (int it = 0;; ++it) {
+    const int64_t te = mem ? t + ((int64_t)1 << (TICK_BITS - lev)) : LLONG_MAX;
+    const int64_t tn = wave_min_uniform(te);
+    if (tn > T) break;  // every member has reached T (see seg_body)
+    if (it == budget) {
+      parked = true;
+      break;
+    }
+    if (nst >= max_iter) {
+      if (lane == 0) set_flag(A.cnt, P3T_FLAG_NSTEPS);
+      break;
+    }
+    const bool active = mem && te == tn;
+    const unsigned long long amask = __ballot(active);
+    const int n_act = __popcll(amask);
+    ++nst;
+    double xp[3], vp[3];
+    {
+      const double dl = mem ? (double)(tn - t) * tick : 0.0;
+      const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        xp[d] = x[d] + v[d] * dl + a0[d] * d2 + j0[d] * d3;
+        vp[d] = v[d] + a0[d] * dl + j0[d] * d2;
+      }
+    }
+    wave_sync();
+    L.px[me] = xp[0];
+    L.py[me] = xp[1];
+    L.pz[me] = xp[2];
+    L.pvx[me] = vp[0];
+    L.pvy[me] = vp[1];
+    L.pvz[me] = vp[2];
+    const int apos = popc_below(amask);  // position among the due members
+    if (active && n_act > 2) L.act[wbase + apos] = lane;
+    double a1[3], j1[3];
+    star_term(xp, vp, GM, a1, j1);  // while the LDS writes are in flight
+    wave_sync();
+    spread_sums(A, L, wbase, size, n_act, lane, amask);
+    wave_sync();
+    if (active) {
+      add_spread(L, wbase, apos, spread_lg(size, n_act), a1, j1);
+      const double h = (double)(tn - t) * tick;
+      t = tn;
+      correct(x, v, a0, j0, xp, vp, a1, j1, h, t, lev, A);
+      ++n_eval;
+    }
+  }
+  count_work(A, n_eval, size);
+  if (PARK && parked) {
+    int slot = 0;
+    if (lane == 0) {
+      const int k = atomicAdd(&A.pk.count[bk], 1);
+      A.pk.lists[(int64_t)bk * A.n + k] = c;
+      A.pk.nst[c] = nst;
+      A.pk.e0[c] = E0;
+      slot = atomicAdd(&A.pk.count[PK_MEM], size);
+    }
+    slot = __shfl(slot, 0, WAVE);
+    if (mem) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        A.pk.x[d * n + gid] = x[d];
+        A.pk.v[d * n + gid] = v[d];
+        A.pk.a[d * n + gid] = a0[d];
+        A.pk.j[d * n + gid] = j0[d];
+      }
+      A.pk.t[gid] = t;
+      A.pk.lev[gid] = lev;
+      A.pk.members[slot + lane] = gid;
+      A.pk.flag[gid] = 1;
+    }
+    return;  // finished by the resume launch
+  }
+  // final energy
+  wave_sync();
+  L.px[me] = x[0];
+  L.py[me] = x[1];
+  L.pz[me] = x[2];
+  L.pvx[me] = v[0];
+  L.pvy[me] = v[1];
+  L.pvz[me] = v[2];
+  wave_sync();
+  double e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
+                       GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
+                 : 0.0;
+  if (mem)
+    for (int q = lane + 1; q < size; ++q) {
+      const int sq = wbase + q;
+      const double dx = L.px[sq] - x[0], dy = L.py[sq] - x[1], dz = L.pz[sq] - x[2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      e -= m * L.pgm[sq] * (1.0 - changeover_W(r * fmin(invi, L.pinv[sq]), A)) / r;
+    }
+  const double E1 = seg_sum(e, 6);
+  if (mem) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      A.pos[d * n + gid] = x[d];
+      A.vel[d * n + gid] = v[d];
+    }
+    if (A.dt_hard) A.dt_hard[gid] = ldexp(A.dt_soft, -lev);
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) set_flag(A.cnt, P3T_FLAG_NAN);
+    if (A.msteps) A.msteps[gid] = nst;
+  }
+  if (lane == 0 && A.e_rel) A.e_rel[c] = fabs(E1 - E0) / fabs(E0);
+  if (lane == 0 && A.nsteps) A.nsteps[c] = nst;
+}
+
 // ---------------------------------------------------------------- big clusters
 __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *sh) {
   v = wave_min(v);
@@ -847,8 +1138,8 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   __shared__ double lds[8][BIG_T];
   __shared__ int64_t shi[BIG_T / WAVE];
   __shared__ double shd[BIG_T / WAVE];
-  __shared__ int act[BIG_ACT];
-  __shared__ double res[6 * BIG_ACT];
+  __shared__ int act[BIG_T];
+  __shared__ double res[6 * BIG_T];
   const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7], act, res};
   // workgroups are dispatched roughly in index order: the buckets of the
   // larger clusters (fewer, longer chains) take the first indices, the
@@ -874,7 +1165,10 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
 #pragma unroll
   for (int q = 0; q < 7; ++q)
     if (q == bk) count = A.bcount[q];  // constant indices only (see above)
-  seg_body<MODE>(A, blist, count, ci0, L, wbase, bk);
+  if (bk >= WAVE_BK0)
+    wave_body<MODE>(A, blist, count, ci0, L, wbase, bk);
+  else
+    seg_body<MODE>(A, blist, count, ci0, L, wbase, bk);
 }
 
 template <int MPT, int MODE>
@@ -892,10 +1186,9 @@ __global__ __launch_bounds__(BIG_T) void k_herm_big(HermArgs A, int bk) {
 }
 
 // ---------------------------------------------------------------- bucketing
-// Clusters above 16 members take the one-workgroup path: in a block step
-// usually only a few of their members are active, and that path spreads an
-// active member's partner loop over a whole wavefront, where the wavefront
-// segment path would walk it serially in one lane.
+// Buckets: 0..2 the packed wavefront segments (1, 2, 3-4 members), 3..6 one
+// wavefront per cluster (5-8, 9-16, 17-32, 33-64), 7..9 one workgroup per
+// cluster (65-256, 257-512, 513-1024), 10 the percolated-cluster path.
 __device__ __forceinline__ int bucket_of(int size, int cap) {
   if (size > cap) return 10;  // the percolated-cluster path
   if (size <= 1) return 0;
@@ -903,6 +1196,8 @@ __device__ __forceinline__ int bucket_of(int size, int cap) {
   if (size <= 4) return 2;
   if (size <= 8) return 3;
   if (size <= 16) return 4;
+  if (size <= 32) return 5;
+  if (size <= 64) return 6;
   if (size <= 256) return 7;
   if (size <= 512) return 8;
   if (size <= 1024) return 9;

@@ -283,7 +283,6 @@ namespace p3t {
 // util.hip
 hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, int64_t tmp_cap,
                            hipStream_t s);  // out has n + 1 entries (exclusive, out[n] = total)
-hipError_t scan_u32_inplace(uint32_t *data, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s);
 int64_t scan_tmp_need(int64_t n);
 void reset_queues(p3t_ctx *c);  // queue heads and per-evaluation counters
 hipError_t tree_moments(p3t_ctx *c, int64_t n);

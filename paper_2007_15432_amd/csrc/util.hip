@@ -113,75 +113,14 @@ hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *
   return scan_impl<int32_t, int64_t>(in, out, n, 1, tmp, tmp_cap, s);
 }
 
-// Exclusive scan of up to SB_MAX counters in one workgroup and one launch
-// (the radix sort's digit-by-tile counters: 65,536 at 2^20 keys).  Chunks
-// of SB_T * SB_I counters pass through LDS: coalesced load, each thread
-// scans its SB_I consecutive counters after a workgroup scan of the
-// per-thread sums (plus the running total of the earlier chunks), coalesced
-// store.  One padding word per SB_I keeps the per-thread runs on distinct
-// LDS banks.
-constexpr int SB_T = 1024, SB_I = 16, SB_CHUNK = SB_T * SB_I;
-constexpr int64_t SB_MAX = 65536;
-
-__device__ __forceinline__ int sb_idx(int i) { return i + i / SB_I; }
-
-__global__ __launch_bounds__(SB_T) void k_scan_block_u32(uint32_t *__restrict__ data, int64_t n) {
-  __shared__ uint32_t buf[SB_CHUNK + SB_CHUNK / SB_I];
-  __shared__ uint32_t ws[SB_T / WAVE];
-  __shared__ uint32_t carry;
-  const int t = threadIdx.x, w = t / WAVE, l = t & (WAVE - 1);
-  if (t == 0) carry = 0;
-  for (int64_t c0 = 0; c0 < n; c0 += SB_CHUNK) {  // uniform
-#pragma unroll
-    for (int q = 0; q < SB_I; ++q) {
-      const int i = q * SB_T + t;
-      buf[sb_idx(i)] = c0 + i < n ? data[c0 + i] : 0u;
-    }
-    __syncthreads();
-    uint32_t s = 0;
-#pragma unroll
-    for (int q = 0; q < SB_I; ++q) s += buf[sb_idx(t * SB_I + q)];
-    uint32_t incl = s;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      const uint32_t v = __shfl_up(incl, o, WAVE);
-      if (l >= o) incl += v;
-    }
-    if (l == WAVE - 1) ws[w] = incl;
-    __syncthreads();
-    uint32_t run = carry + incl - s;
-    for (int q = 0; q < w; ++q) run += ws[q];
-#pragma unroll
-    for (int q = 0; q < SB_I; ++q) {
-      const int i = sb_idx(t * SB_I + q);
-      const uint32_t v = buf[i];
-      buf[i] = run;
-      run += v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < SB_I; ++q) {
-      const int i = q * SB_T + t;
-      if (c0 + i < n) data[c0 + i] = buf[sb_idx(i)];
-    }
-    if (t == SB_T - 1) carry = run;  // the running total after this chunk
-    __syncthreads();
-  }
-}
-
-hipError_t scan_u32_inplace(uint32_t *data, int64_t n, int64_t *tmp, int64_t tmp_cap, hipStream_t s) {
-  if (n > SCAN_TILE && n <= SB_MAX) {
-    hipLaunchKernelGGL(k_scan_block_u32, dim3(1), dim3(SB_T), 0, s, data, n);
-    return hipGetLastError();
-  }
-  return scan_impl<uint32_t, uint32_t>(data, data, n, 0, tmp, tmp_cap, s);
-}
-
 // ------------------------------------------------------------------ radix sort
 // Stable LSD radix sort, 8-bit digits.  One block sorts a tile of RS_TILE
-// keys per pass: a digit histogram per tile, a device scan over
-// (digit, tile), then a stable scatter that ranks equal digits inside a
-// wavefront with ballots and across wavefronts with per-round counters.
+// keys per pass: a digit histogram per tile (hist[digit][tile]); one
+// workgroup per digit scans its row over the tiles (exclusive, in place) and
+// stores the row total; the stable scatter adds the exclusive scan of the
+// 256 row totals (done again by every scatter block, in LDS) and ranks equal
+// digits inside a wavefront with ballots and across wavefronts with
+// per-round counters.  Three launches per pass, no device-wide scan.
 constexpr int RS_T = 256;
 constexpr int RS_I = 16;
 constexpr int RS_TILE = RS_T * RS_I;
@@ -211,15 +150,65 @@ __global__ __launch_bounds__(RS_T) void k_radix_hist(const uint64_t *__restrict_
   hist[(int64_t)t * nblocks + blockIdx.x] = h[t];
 }
 
+// Row d of hist (nblocks tile counts of digit d) becomes its exclusive scan;
+// tot[d] receives the row total.  One workgroup per digit.
+constexpr int RR_I = 8;
+__global__ __launch_bounds__(RS_T) void k_radix_rowscan(uint32_t *__restrict__ hist, int nblocks,
+                                                        uint32_t *__restrict__ tot) {
+  __shared__ uint32_t ws[RS_W];
+  uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+  const int t = threadIdx.x, w = t / WAVE, l = t & (WAVE - 1);
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nblocks; c0 += RS_T * RR_I) {  // uniform
+    uint32_t v[RR_I], s = 0;
+#pragma unroll
+    for (int q = 0; q < RR_I; ++q) {
+      const int i = c0 + t * RR_I + q;
+      v[q] = i < nblocks ? row[i] : 0u;
+      s += v[q];
+    }
+    const uint32_t incl = (uint32_t)wave_incl_scan((int)s);
+    if (l == WAVE - 1) ws[w] = incl;
+    __syncthreads();
+    uint32_t run = carry + incl - s, chunk = 0;
+#pragma unroll
+    for (int q = 0; q < RS_W; ++q) {
+      run += q < w ? ws[q] : 0u;
+      chunk += ws[q];
+    }
+#pragma unroll
+    for (int q = 0; q < RR_I; ++q) {
+      const int i = c0 + t * RR_I + q;
+      if (i < nblocks) row[i] = run;
+      run += v[q];
+    }
+    carry += chunk;
+    __syncthreads();  // ws is rewritten by the next chunk
+  }
+  if (t == 0) tot[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(RS_T) void k_radix_scatter(const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin,
                                                         uint64_t *__restrict__ kout, int32_t *__restrict__ vout,
                                                         int64_t n_static, const unsigned long long *n_dev, int shift,
-                                                        const uint32_t *__restrict__ offs, int nblocks) {
+                                                        const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tot,
+                                                        int nblocks) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wc[RS_W][256];
   const int t = threadIdx.x, w = t / WAVE;
   const int64_t n = dev_count(n_static, n_dev);
-  run[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  {
+    // first position of digit t: exclusive scan of the row totals
+    const uint32_t tv = tot[t];
+    const uint32_t incl = (uint32_t)wave_incl_scan((int)tv);
+    if ((t & (WAVE - 1)) == WAVE - 1) wc[0][w] = incl;
+    __syncthreads();
+    uint32_t base = incl - tv;
+#pragma unroll
+    for (int q = 0; q < RS_W; ++q) base += q < w ? wc[0][q] : 0u;
+    run[t] = base + offs[(int64_t)t * nblocks + blockIdx.x];
+    __syncthreads();  // wc is cleared below
+  }
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_I; ++r) {
 #pragma unroll
@@ -262,14 +251,16 @@ hipError_t radix_sort_pairs(uint64_t *&keys, int32_t *&vals, uint64_t *&keys_alt
                             int64_t *tmp, int64_t tmp_cap, hipStream_t s) {
   if (n_static <= 0) return hipSuccess;
   const int64_t nb64 = (n_static + RS_TILE - 1) / RS_TILE;
-  if (256 * nb64 > hist_cap || nb64 > (1 << 30)) return hipErrorInvalidValue;
+  if (256 * nb64 + 256 > hist_cap || nb64 > (1 << 30)) return hipErrorInvalidValue;
   const int nb = (int)nb64;
+  uint32_t *tot = hist + 256 * nb64;  // the 256 row totals follow the counters
+  (void)tmp;
+  (void)tmp_cap;
   for (int shift = bit_lo; shift < bit_hi; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(RS_T), 0, s, keys, n_static, n_dev, shift, hist, nb);
-    hipError_t e = scan_u32_inplace(hist, 256 * nb64, tmp, tmp_cap, s);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(RS_T), 0, s, hist, nb, tot);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(RS_T), 0, s, keys, vals, keys_alt, vals_alt, n_static, n_dev,
-                       shift, hist, nb);
+                       shift, hist, tot, nb);
     uint64_t *tk = keys;
     keys = keys_alt;
     keys_alt = tk;
