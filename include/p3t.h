@@ -51,6 +51,8 @@ typedef enum {
 #define P3T_FLAG_BIG_CLUSTER 0x80u    /* a cluster took the percolated-cluster path (above cluster_cap members) */
 #define P3T_FLAG_UNBOUND 0x100u       /* an isolated particle's orbit is not bound (left in place; isolated = 1) */
 #define P3T_FLAG_GROUP_BOUND 0x200u   /* more interaction groups than the host's bound (retried internally) */
+#define P3T_FLAG_COLL_UNCHECKED 0x400u /* p3t_hard_step_collide: a cluster above 64 members was integrated
+                                           without looking for collisions */
 
 /* Parameters.  Defaults (p3t_default_params) are the paper's values where it
  * prints them (Section 3.1: eta = 0.01, eta_0 = 0.1 eta, Rsearch0..3 = 1.1,
@@ -234,6 +236,66 @@ p3t_status p3t_kepler_drift(p3t_ctx *ctx, int64_t n, double dt, double *pos3, do
  * path (see p3t_hermite_cluster_step). */
 p3t_status p3t_hard_step(p3t_ctx *ctx, double *pos3, double *vel3, const double *mass, const double *r_out,
                          double *dt_hard, int32_t *steps, int64_t *n_clusters_host);
+
+/* p3t_hermite_cluster_step with perfect-accretion collisions (the model
+ * and readings of p3t_hard_step_collide, below) on caller-given clusters.
+ * merged_into (n int32, required) receives for every particle the particle
+ * at its composite's first slot in the cluster's member list (with members
+ * listed in ascending index: the lowest index), its own index otherwise.
+ * eps6 (6 n_clusters doubles, nullable): per cluster eps_0 .. eps_3 (with W),
+ * their total with W replaced by one and with 1 - W.  e_rel_err (nullable):
+ * |E_hard(end) + eps_5 - E_hard(start)| / |E_hard(start)| (the pairs inside
+ * a composite left out of E_hard(end)).  n_steps as p3t_hermite_cluster_step;
+ * *n_collisions_host (nullable): mergers.  Synchronises. */
+p3t_status p3t_hermite_collide(p3t_ctx *ctx, int64_t n, int64_t n_clusters, const int32_t *cl_ptr,
+                               const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
+                               const double *r_out, double *dt_hard, double f_radius, double density,
+                               int32_t *merged_into, double *eps6, double *e_rel_err, int32_t *n_steps,
+                               int64_t *n_collisions_host);
+
+/* The hard part with perfect-accretion collisions (Section 2.5.1): as
+ * p3t_hard_step, and two bodies of a cluster collide when their distance is
+ * below f_radius (R_i + R_j), R = (3 m / (4 pi density))^(1/3) in code units
+ * (density > 0, f_radius >= 0, both finite; f_radius = 0 never collides).  The
+ * colliding bodies become a composite that keeps the centre of mass and the
+ * momentum; inside the hard part its parts stay separate particles (each
+ * with its own r_out) that exchange no force and move with the mass-weighted
+ * mean of their hard accelerations and jerks, and the dissipations of
+ * eq. (e0) ... eq. (e3) are booked.  Readings: collisions are looked for at
+ * every block step among the pairs evaluated there (at least one body due,
+ * predicted states); the first pair in (lower, higher) slot order merges
+ * after the corrector, one merger per block step; the composite's next step
+ * comes from eta_0 and divides the block time; the neighbours of eq. (e3)
+ * are the cluster's other members.  Clusters of 2..64 members look for
+ * collisions (one wavefront each); larger clusters are integrated without
+ * and set P3T_FLAG_COLL_UNCHECKED.
+ * merged_into (n int32, device, required) receives for every particle the
+ * lowest index of its composite (its own index if it did not merge).
+ * eps_host (6 doubles, host, nullable): sums over all mergers of eps_0,
+ * eps_1, eps_2, eps_3 (eq. (e0) ... eq. (e3), with W), of their total with
+ * W replaced by one (the Newtonian energy lost, neighbours only) and with
+ * 1 - W (the hard energy lost).  *n_collisions_host (nullable): number of
+ * mergers.  Synchronises.  Pass the result to p3t_merge_bodies before the
+ * next evaluation: the parts of a composite share one position. */
+p3t_status p3t_hard_step_collide(p3t_ctx *ctx, double *pos3, double *vel3, const double *mass, const double *r_out,
+                                 double *dt_hard, int32_t *steps, double f_radius, double density,
+                                 int32_t *merged_into, double *eps_host, int64_t *n_collisions_host,
+                                 int64_t *n_clusters_host);
+
+/* Perfect accretion after p3t_hard_step_collide (Section 2.5.1): every
+ * composite becomes one particle.  The part at the lowest index keeps the
+ * shared state and takes the composite's mass (summed in index order); the
+ * other parts are removed and the arrays are compacted in index order, in
+ * place: afterwards pos3 / vel3 hold (3, n_new) with row stride n_new in
+ * their first 3 n_new entries, mass, dt_hard (nullable) and steps (nullable)
+ * their first n_new.  *n_new_host (required) receives the new count.
+ * merged_into (n) must map every particle to the lowest index of its
+ * composite, which maps to itself; anything else is P3T_ERR_ARG (checked
+ * before anything is moved).  Invalidates the tree: the next call is an
+ * evaluation with cut-off radii of the new set (Section 2.2, step (9)).
+ * Synchronises. */
+p3t_status p3t_merge_bodies(p3t_ctx *ctx, int64_t n, const int32_t *merged_into, double *pos3, double *vel3,
+                            double *mass, double *dt_hard, int32_t *steps, int64_t *n_new_host);
 
 /* p3t_build_tree followed by p3t_compute_soft_force in one call.  With
  * use_graph = 1 the whole device sequence (bounding box, Morton keys, radix

@@ -105,6 +105,9 @@ def lib():
         L.orc_hermite_one.argtypes = [C.c_int64, dp, dp, dp, dp, pp, C.c_double, dp, ip]
         L.orc_hermite_clusters.argtypes = [C.c_int64, C.c_int64, i32p, i32p, dp, dp, dp, dp, pp,
                                            C.c_double, dp, dp, dp, ip]
+        L.orc_hermite_collide_clusters.argtypes = [C.c_int64, C.c_int64, i32p, i32p, dp, dp, dp, dp, pp,
+                                                   C.c_double, dp, C.c_double, C.c_double, i32p, dp, dp, dp, ip,
+                                                   ip, ip]
         L.orc_neighbour_rows.argtypes = [C.c_int64, dp, dp, dp, dp, dp, pp, C.c_int64, ip, ip, i32p,
                                          C.c_int64]
         L.orc_neighbour_rows.restype = C.c_int64
@@ -256,6 +259,49 @@ def hermite_clusters(pos, vel, mass, r_out, cl_ptr, members, p: Params, dt_soft=
     st = lib().orc_hermite_clusters(n, nc, _i32(cl_ptr), _i32(members), _d(pos), _d(vel), _d(mass),
                                     _d(r_out), C.byref(pc), dt, dh, _d(e0), _d(e1), _i64(ns))
     return pos, vel, e0, e1, ns, int(st)
+
+
+# code units (G = M_sun = 1 au = 1): grams and centimetres per unit
+GRAM = 1.0 / 1.989e33
+CM = 1.0 / 1.495978707e13
+
+
+def density_code(rho_cgs: float) -> float:
+    """A density in g / cm^3 in solar masses per au^3."""
+    return rho_cgs * GRAM / CM ** 3
+
+
+def hermite_collide(pos, vel, mass, r_out, cl_ptr, members, p: Params, f: float, rho: float, dt_soft=None,
+                    dt_hard=None):
+    """Hard part with perfect-accretion collisions (Section 2.5.1), radius
+    enhancement f, bulk density rho (code units).  Returns a dict: pos, vel,
+    merged_into (n,) int32, eps (nc, 6), e0, e1, nsteps, ncoll, tcoll (ticks
+    of dt_soft 2^-40), status.  dt_hard (n,), if given, is updated in place."""
+    mass = _f64(mass)
+    n = mass.shape[0]
+    pos = _f64(pos, (3, n)).copy()
+    vel = _f64(vel, (3, n)).copy()
+    r_out = _f64(r_out, (n,))
+    cl_ptr = np.ascontiguousarray(cl_ptr, dtype=np.int32)
+    members = np.ascontiguousarray(members, dtype=np.int32)
+    nc = cl_ptr.shape[0] - 1
+    merged = np.arange(n, dtype=np.int32)
+    eps = np.zeros((nc, 6))
+    e0, e1 = np.empty(nc), np.empty(nc)
+    ns, nco, tco = (np.empty(nc, dtype=np.int64) for _ in range(3))
+    pc = p.c()
+    dt = p.dt_soft if dt_soft is None else float(dt_soft)
+    dh = None
+    if dt_hard is not None:
+        if not (isinstance(dt_hard, np.ndarray) and dt_hard.dtype == np.float64 and dt_hard.shape == (n,)
+                and dt_hard.flags.c_contiguous):
+            raise ValueError("dt_hard must be a contiguous float64 (n,) array")
+        dh = _d(dt_hard)
+    st = lib().orc_hermite_collide_clusters(n, nc, _i32(cl_ptr), _i32(members), _d(pos), _d(vel), _d(mass),
+                                            _d(r_out), C.byref(pc), dt, dh, float(f), float(rho), _i32(merged),
+                                            _d(eps), _d(e0), _d(e1), _i64(ns), _i64(nco), _i64(tco))
+    return dict(pos=pos, vel=vel, merged_into=merged, eps=eps, e0=e0, e1=e1, nsteps=ns, ncoll=nco, tcoll=tco,
+                status=int(st))
 
 
 # -- neighbours and clusters ----------------------------------------------------

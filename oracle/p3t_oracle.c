@@ -309,7 +309,7 @@ double orc_soft_energy(int64_t n, const double *pos, const double *m, const doub
  * Only the particles i in [i0, i1) are evaluated; all nm act as sources. */
 static int orc_hard_acc_jerk_range(int64_t nm, const double *x, const double *v, const double *m,
                                    const double *r_out, const orc_params *p, int64_t i0, int64_t i1,
-                                   const unsigned char *mask, double *a, double *jk) {
+                                   const unsigned char *mask, const int32_t *comp, double *a, double *jk) {
   const double *X = x, *Y = x + nm, *Z = x + 2 * nm;
   const double *VX = v, *VY = v + nm, *VZ = v + 2 * nm;
   double GM = p->G * p->m_star;
@@ -327,6 +327,7 @@ static int orc_hard_acc_jerk_range(int64_t nm, const double *x, const double *v,
     double jz = -GM * (VZ[i] - c5 * Z[i]) * ir3;
     for (int64_t j = 0; j < nm; ++j) {
       if (j == i) continue;
+      if (comp && comp[j] == comp[i]) continue; /* the two parts of one merged body */
       double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
       double ux = VX[j] - VX[i], uy = VY[j] - VY[i], uz = VZ[j] - VZ[i];
       double d2 = dx * dx + dy * dy + dz * dz;
@@ -355,7 +356,7 @@ static int orc_hard_acc_jerk_range(int64_t nm, const double *x, const double *v,
 
 int orc_hard_acc_jerk(int64_t nm, const double *x, const double *v, const double *m, const double *r_out,
                       const orc_params *p, double *a, double *jk) {
-  return orc_hard_acc_jerk_range(nm, x, v, m, r_out, p, 0, nm, NULL, a, jk);
+  return orc_hard_acc_jerk_range(nm, x, v, m, r_out, p, 0, nm, NULL, NULL, a, jk);
 }
 
 /* Hard-part energy of a particle set, eq. (hard):
@@ -428,7 +429,7 @@ int orc_hermite_one(int64_t nm, double *x, double *v, const double *m, const dou
   unsigned char *act = (unsigned char *)malloc(nm);
   int64_t nsteps = 0;
 
-  err |= orc_hard_acc_jerk_range(nm, x, v, m, r_out, p, 0, nm, NULL, a0, j0);
+  err |= orc_hard_acc_jerk_range(nm, x, v, m, r_out, p, 0, nm, NULL, NULL, a0, j0);
   for (int64_t i = 0; i < nm; ++i) {
     double an = orc_norm3(a0[i], a0[nm + i], a0[2 * nm + i]);
     double jn = orc_norm3(j0[i], j0[nm + i], j0[2 * nm + i]);
@@ -456,7 +457,7 @@ int orc_hermite_one(int64_t nm, double *x, double *v, const double *m, const dou
       }
     }
     /* evaluation of the active members from the predicted states */
-    err |= orc_hard_acc_jerk_range(nm, xp, vp, m, r_out, p, 0, nm, act, a1, j1);
+    err |= orc_hard_acc_jerk_range(nm, xp, vp, m, r_out, p, 0, nm, act, NULL, a1, j1);
     /* corrector and new steps */
     for (int64_t i = 0; i < nm; ++i) {
       if (!act[i]) continue;
@@ -549,6 +550,348 @@ int orc_hermite_clusters(int64_t n, int64_t n_clusters, const int32_t *cl_ptr, c
       if (dh) dt_hard[i] = dh[k];
     }
     free(x); free(v); free(mm); free(ro); free(dh);
+  }
+  return err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Perfect-accretion collisions in the hard part (Section 2.5.1).
+ *
+ * Two bodies collide when r_ij < f (R_p,i + R_p,j), R_p the radius of a
+ * sphere of the body's mass at density rho.  The merged body keeps the
+ * centre of mass and the momentum of the two.  Inside the hard part the two
+ * stay two particles of one composite (Section 2.5.1: each keeps its own
+ * cut-off radius): the hard force on each part is computed without the
+ * mutual term of the composite's parts, and every part then moves with the
+ * mass-weighted mean of its parts' accelerations (and jerks).
+ *
+ * Readings (the paper gives the model, not the scheme's details):
+ *   - collisions are looked for at every block step, between two bodies of
+ *     which at least one is due, with the predicted states at the block time
+ *     (the states the force evaluation uses); of several colliding pairs the
+ *     first in (lower slot, higher slot) order merges, one merger per block
+ *     step;
+ *   - the merger takes the states at the block time after the corrector
+ *     (corrected for due members, predicted for the others); the composite's
+ *     parts get the merged state, the block time, the hard acceleration and
+ *     jerk evaluated there (mass-weighted mean over its parts) and a new step
+ *     from the initial-step criterion with eta_0 (Section 3.1: "also for the
+ *     first step after a collision"), quantised down and refined until the
+ *     block time is a multiple of it; the other members keep their states;
+ *   - the radius of a composite is that of its total mass;
+ *   - the neighbours N_i of eq. (e3) are the other members of the cluster;
+ *   - per merger the dissipations eq. (e0) ... eq. (e3) are added to eps[0..3]
+ *     with W as printed; eps[4] receives the same sum with W replaced by one
+ *     (the change of the Newtonian energy of the cluster, the reading the
+ *     paper gives for that replacement), eps[5] the same with 1 - W (the
+ *     change of the cluster's hard energy, eq. (hard)), so that
+ *     E_hard(end) + sum eps[5] = E_hard(start) up to the integration error.
+ * comp[k] (out) receives the lowest slot of member k's composite. */
+static double orc_body_radius(double M, double rho) { return cbrt(3.0 * M / (4.0 * 3.14159265358979323846 * rho)); }
+
+/* hard-part energy of eq. (hard) with the pairs inside a composite left out */
+static double orc_cluster_energy_comp(int64_t nm, const double *x, const double *v, const double *m,
+                                      const double *r_out, const orc_params *p, const int32_t *comp) {
+  const double *X = x, *Y = x + nm, *Z = x + 2 * nm;
+  const double *VX = v, *VY = v + nm, *VZ = v + 2 * nm;
+  double e = 0.0;
+  for (int64_t i = 0; i < nm; ++i) {
+    double v2 = VX[i] * VX[i] + VY[i] * VY[i] + VZ[i] * VZ[i];
+    double r = sqrt(X[i] * X[i] + Y[i] * Y[i] + Z[i] * Z[i]);
+    e += 0.5 * m[i] * v2 - p->G * p->m_star * m[i] / r;
+  }
+  for (int64_t i = 0; i < nm; ++i)
+    for (int64_t j = i + 1; j < nm; ++j) {
+      if (comp[i] == comp[j]) continue;
+      double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double R = fmax(r_out[i], r_out[j]);
+      e -= p->G * m[i] * m[j] * (1.0 - orc_W(r / R, p->gamma)) / r;
+    }
+  return e;
+}
+
+/* mass-weighted mean of a (3, nm) field over the parts of every composite
+ * of more than one part: sum over the parts in slot order of m q, divided by
+ * the composite's mass; only members with sel[k] (nullable: all) change */
+static void orc_composite_mean(int64_t nm, const double *m, const int32_t *comp, const unsigned char *sel, double *q) {
+  double *tmp = (double *)malloc(sizeof(double) * 3 * nm);
+  memcpy(tmp, q, sizeof(double) * 3 * nm);
+  for (int64_t k = 0; k < nm; ++k) {
+    if (sel && !sel[k]) continue;
+    int multi = 0;
+    for (int64_t l = 0; l < nm; ++l) multi |= (l != k && comp[l] == comp[k]);
+    if (!multi) continue;
+    double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+    for (int64_t l = 0; l < nm; ++l) {
+      if (comp[l] != comp[k]) continue;
+      M += m[l];
+      for (int c = 0; c < 3; ++c) s[c] += m[l] * tmp[c * nm + l];
+    }
+    for (int c = 0; c < 3; ++c) q[c * nm + k] = s[c] / M;
+  }
+  free(tmp);
+}
+
+int orc_hermite_collide_one(int64_t nm, double *x, double *v, const double *m, const double *r_out,
+                            const orc_params *p, double dt_soft, double *dt_hard, double f, double rho,
+                            int32_t *comp, double *eps, int64_t *nsteps_out, int64_t *ncoll_out, int64_t *tcoll_out) {
+  int err = 0;
+  const int64_t T = (int64_t)1 << ORC_TICK_BITS;
+  const double tick = ldexp(dt_soft, -ORC_TICK_BITS);
+  const double G = p->G, GM = p->G * p->m_star;
+  size_t s3 = sizeof(double) * 3 * nm;
+  double *a0 = (double *)malloc(s3), *j0 = (double *)malloc(s3);
+  double *a1 = (double *)malloc(s3), *j1 = (double *)malloc(s3);
+  double *xp = (double *)malloc(s3), *vp = (double *)malloc(s3);
+  double *sx = (double *)malloc(s3), *sv = (double *)malloc(s3);
+  double *an_ = (double *)malloc(s3), *jn_ = (double *)malloc(s3);
+  double *rad = (double *)malloc(sizeof(double) * nm);
+  int64_t *t = (int64_t *)calloc(nm, sizeof(int64_t));
+  int *lev = (int *)malloc(sizeof(int) * nm);
+  unsigned char *act = (unsigned char *)malloc(nm), *sel = (unsigned char *)malloc(nm);
+  int64_t nsteps = 0, ncoll = 0;
+  *tcoll_out = -1;
+  for (int64_t k = 0; k < nm; ++k) {
+    comp[k] = (int32_t)k;
+    rad[k] = orc_body_radius(m[k], rho);
+  }
+
+  err |= orc_hard_acc_jerk_range(nm, x, v, m, r_out, p, 0, nm, NULL, comp, a0, j0);
+  for (int64_t i = 0; i < nm; ++i) {
+    double an = orc_norm3(a0[i], a0[nm + i], a0[2 * nm + i]);
+    double jn = orc_norm3(j0[i], j0[nm + i], j0[2 * nm + i]);
+    double dtc = jn > 0.0 ? p->eta0 * an / jn : dt_soft;
+    if (dt_hard && dt_hard[i] > 0.0) dtc = dt_hard[i];
+    int k = orc_level_for(dt_soft, dtc, p->k_max);
+    if (k > p->k_max) { err |= ORC_ERR_KMAX; k = p->k_max; }
+    lev[i] = k;
+  }
+  for (;;) {
+    int64_t tn = T;
+    for (int64_t i = 0; i < nm; ++i) {
+      int64_t te = t[i] + ((int64_t)1 << (ORC_TICK_BITS - lev[i]));
+      if (te < tn) tn = te;
+    }
+    for (int64_t i = 0; i < nm; ++i) act[i] = (t[i] + ((int64_t)1 << (ORC_TICK_BITS - lev[i]))) == tn;
+    for (int64_t i = 0; i < nm; ++i) {
+      double dl = (double)(tn - t[i]) * tick;
+      double d2 = dl * dl / 2.0, d3 = dl * dl * dl / 6.0;
+      for (int c = 0; c < 3; ++c) {
+        int64_t q = c * nm + i;
+        xp[q] = x[q] + v[q] * dl + a0[q] * d2 + j0[q] * d3;
+        vp[q] = v[q] + a0[q] * dl + j0[q] * d2;
+      }
+    }
+    /* collision test on the predicted states: the first colliding pair of
+     * distinct bodies, at least one of them due */
+    int64_t ci = -1, cj = -1;
+    if (f > 0.0)
+      for (int64_t i = 0; i < nm && ci < 0; ++i)
+        for (int64_t j = i + 1; j < nm; ++j) {
+          if (comp[i] == comp[j] || !(act[i] || act[j])) continue;
+          double dx = xp[j] - xp[i], dy = xp[nm + j] - xp[nm + i], dz = xp[2 * nm + j] - xp[2 * nm + i];
+          double r2 = dx * dx + dy * dy + dz * dz;
+          double rs = f * (rad[i] + rad[j]);
+          if (r2 < rs * rs) { ci = i; cj = j; break; }
+        }
+    err |= orc_hard_acc_jerk_range(nm, xp, vp, m, r_out, p, 0, nm, act, comp, a1, j1);
+    orc_composite_mean(nm, m, comp, act, a1);
+    orc_composite_mean(nm, m, comp, act, j1);
+    for (int64_t i = 0; i < nm; ++i) {
+      if (!act[i]) continue;
+      double h = (double)(tn - t[i]) * tick;
+      double a2[3], a3[3];
+      for (int c = 0; c < 3; ++c) {
+        int64_t q = c * nm + i;
+        double da = a0[q] - a1[q];
+        a2[c] = (-6.0 * da - h * (4.0 * j0[q] + 2.0 * j1[q])) / (h * h);
+        a3[c] = (12.0 * da + 6.0 * h * (j0[q] + j1[q])) / (h * h * h);
+        x[q] = xp[q] + a2[c] * (h * h * h * h) / 24.0 + a3[c] * (h * h * h * h * h) / 120.0;
+        v[q] = vp[q] + a2[c] * (h * h * h) / 6.0 + a3[c] * (h * h * h * h) / 24.0;
+        a0[q] = a1[q];
+        j0[q] = j1[q];
+      }
+      t[i] = tn;
+      double a2e[3] = {a2[0] + a3[0] * h, a2[1] + a3[1] * h, a2[2] + a3[2] * h};
+      double an = orc_norm3(a1[i], a1[nm + i], a1[2 * nm + i]);
+      double jn = orc_norm3(j1[i], j1[nm + i], j1[2 * nm + i]);
+      double a2n = orc_norm3(a2e[0], a2e[1], a2e[2]);
+      double a3n = orc_norm3(a3[0], a3[1], a3[2]);
+      double den = jn * a3n + a2n * a2n;
+      double dtc = den > 0.0 ? sqrt(p->eta * (an * a2n + jn * jn) / den) : dt_soft;
+      int knew = orc_level_for(dt_soft, dtc, p->k_max);
+      int k = lev[i];
+      if (knew < k) {
+        int64_t dbl = (int64_t)1 << (ORC_TICK_BITS - k + 1);
+        if (k > 0 && (t[i] % dbl) == 0) k = k - 1;
+      } else {
+        k = knew;
+      }
+      if (k > p->k_max) { err |= ORC_ERR_KMAX; k = p->k_max; }
+      lev[i] = k;
+    }
+    if (ci >= 0) {
+      /* states at tn: corrected (due members) or predicted (the others) */
+      for (int64_t i = 0; i < nm; ++i)
+        for (int c = 0; c < 3; ++c) {
+          sx[c * nm + i] = act[i] ? x[c * nm + i] : xp[c * nm + i];
+          sv[c * nm + i] = act[i] ? v[c * nm + i] : vp[c * nm + i];
+        }
+      const int32_t A = comp[ci], B = comp[cj];
+      double MA = 0.0, MB = 0.0;
+      for (int64_t k = 0; k < nm; ++k) {
+        if (comp[k] == A) MA += m[k];
+        if (comp[k] == B) MB += m[k];
+      }
+      const double M = MA + MB;
+      double xa[3], xb[3], va[3], vb[3], xn[3], vn[3];
+      for (int c = 0; c < 3; ++c) {
+        xa[c] = sx[c * nm + ci]; xb[c] = sx[c * nm + cj];
+        va[c] = sv[c * nm + ci]; vb[c] = sv[c * nm + cj];
+        xn[c] = (MA * xa[c] + MB * xb[c]) / M;
+        vn[c] = (MA * va[c] + MB * vb[c]) / M;
+      }
+      const double dvx = va[0] - vb[0], dvy = va[1] - vb[1], dvz = va[2] - vb[2];
+      const double e0 = 0.5 * (MA * MB / M) * (dvx * dvx + dvy * dvy + dvz * dvz);          /* eq. (e0) */
+      const double rab = orc_norm3(xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]);
+      double e1 = 0.0, e1u = 0.0, e1h = 0.0;                                                 /* eq. (e1) */
+      for (int64_t a = 0; a < nm; ++a) {
+        if (comp[a] != A) continue;
+        for (int64_t b = 0; b < nm; ++b) {
+          if (comp[b] != B) continue;
+          double W = orc_W(rab / fmax(r_out[a], r_out[b]), p->gamma);
+          e1 -= G * m[a] * m[b] * W / rab;
+          e1u -= G * m[a] * m[b] / rab;
+          e1h -= G * m[a] * m[b] * (1.0 - W) / rab;
+        }
+      }
+      const double e2 = -GM * (MA / orc_norm3(xa[0], xa[1], xa[2]) + MB / orc_norm3(xb[0], xb[1], xb[2]) -
+                               M / orc_norm3(xn[0], xn[1], xn[2]));                      /* eq. (e2) */
+      double e3 = 0.0, e3u = 0.0, e3h = 0.0;                                                 /* eq. (e3) */
+      for (int64_t a = 0; a < nm; ++a) {
+        if (comp[a] != A && comp[a] != B) continue;
+        const double *xo = comp[a] == A ? xa : xb;
+        for (int64_t k = 0; k < nm; ++k) {
+          if (comp[k] == A || comp[k] == B) continue;
+          const double R = fmax(r_out[a], r_out[k]);
+          const double ro = orc_norm3(sx[k] - xo[0], sx[nm + k] - xo[1], sx[2 * nm + k] - xo[2]);
+          const double rn = orc_norm3(sx[k] - xn[0], sx[nm + k] - xn[1], sx[2 * nm + k] - xn[2]);
+          const double Wo = orc_W(ro / R, p->gamma), Wn = orc_W(rn / R, p->gamma);
+          e3 -= G * m[a] * m[k] * (Wo / ro - Wn / rn);
+          e3u -= G * m[a] * m[k] * (1.0 / ro - 1.0 / rn);
+          e3h -= G * m[a] * m[k] * ((1.0 - Wo) / ro - (1.0 - Wn) / rn);
+        }
+      }
+      eps[0] += e0; eps[1] += e1; eps[2] += e2; eps[3] += e3;
+      eps[4] += e0 + e1u + e2 + e3u;
+      eps[5] += e0 + e1h + e2 + e3h;
+      /* the composite takes the merged state at tn */
+      const int32_t cn = A < B ? A : B;
+      const double Rn = orc_body_radius(M, rho);
+      for (int64_t k = 0; k < nm; ++k) {
+        sel[k] = 0;
+        if (comp[k] != A && comp[k] != B) continue;
+        sel[k] = 1;
+        comp[k] = cn;
+        rad[k] = Rn;
+        t[k] = tn;
+        for (int c = 0; c < 3; ++c) {
+          x[c * nm + k] = sx[c * nm + k] = xn[c];
+          v[c * nm + k] = sv[c * nm + k] = vn[c];
+        }
+      }
+      /* its acceleration and jerk at tn from everyone's state at tn */
+      err |= orc_hard_acc_jerk_range(nm, sx, sv, m, r_out, p, 0, nm, sel, comp, an_, jn_);
+      orc_composite_mean(nm, m, comp, sel, an_);
+      orc_composite_mean(nm, m, comp, sel, jn_);
+      for (int64_t k = 0; k < nm; ++k) {
+        if (!sel[k]) continue;
+        for (int c = 0; c < 3; ++c) {
+          a0[c * nm + k] = an_[c * nm + k];
+          j0[c * nm + k] = jn_[c * nm + k];
+        }
+        double an = orc_norm3(an_[k], an_[nm + k], an_[2 * nm + k]);
+        double jn = orc_norm3(jn_[k], jn_[nm + k], jn_[2 * nm + k]);
+        double dtc = jn > 0.0 ? p->eta0 * an / jn : dt_soft;
+        int kl = orc_level_for(dt_soft, dtc, p->k_max);
+        if (kl > p->k_max) { err |= ORC_ERR_KMAX; kl = p->k_max; }
+        while (kl < p->k_max && (tn % ((int64_t)1 << (ORC_TICK_BITS - kl))) != 0) ++kl;
+        lev[k] = kl;
+      }
+      if (ncoll == 0) *tcoll_out = tn;
+      ++ncoll;
+    }
+    ++nsteps;
+    if (tn == T) {
+      int done = 1;
+      for (int64_t i = 0; i < nm; ++i) done &= (t[i] == T);
+      if (done) break;
+    }
+    if (nsteps > 100000000) { err |= ORC_ERR_NSTEPS; break; }
+  }
+  *nsteps_out = nsteps;
+  *ncoll_out = ncoll;
+  if (dt_hard)
+    for (int64_t i = 0; i < nm; ++i) dt_hard[i] = ldexp(dt_soft, -lev[i]);
+  free(a0); free(j0); free(a1); free(j1); free(xp); free(vp); free(sx); free(sv); free(an_); free(jn_);
+  free(rad); free(t); free(lev); free(act); free(sel);
+  return err;
+}
+
+/* Batch driver of orc_hermite_collide_one (clusters as orc_hermite_clusters).
+ * merged_into (n) receives, for every member, the particle index of its
+ * composite's lowest slot (members are listed in ascending index, so the
+ * lowest index); eps (n_clusters x 6), e0 / e1 (hard energies with the pairs
+ * inside composites left out), nsteps, ncoll and tcoll (block time of the
+ * first merger in ticks of dt_soft 2^-40, -1 if none) per cluster; every
+ * output but merged_into is nullable. */
+int orc_hermite_collide_clusters(int64_t n, int64_t n_clusters, const int32_t *cl_ptr, const int32_t *members,
+                                 double *pos, double *vel, const double *m, const double *r_out, const orc_params *p,
+                                 double dt_soft, double *dt_hard, double f, double rho, int32_t *merged_into,
+                                 double *eps, double *e0, double *e1, int64_t *nsteps, int64_t *ncoll, int64_t *tcoll) {
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int64_t c = 0; c < n_clusters; ++c) {
+    int64_t b = cl_ptr[c], nm = cl_ptr[c + 1] - b;
+    if (nm <= 0) continue;
+    double *x = (double *)malloc(sizeof(double) * 3 * nm);
+    double *v = (double *)malloc(sizeof(double) * 3 * nm);
+    double *mm = (double *)malloc(sizeof(double) * nm);
+    double *ro = (double *)malloc(sizeof(double) * nm);
+    double *dh = dt_hard ? (double *)malloc(sizeof(double) * nm) : NULL;
+    int32_t *cp = (int32_t *)malloc(sizeof(int32_t) * nm);
+    for (int64_t k = 0; k < nm; ++k) {
+      int64_t i = members[b + k];
+      for (int q = 0; q < 3; ++q) {
+        x[q * nm + k] = pos[q * n + i];
+        v[q * nm + k] = vel[q * n + i];
+      }
+      mm[k] = m[i];
+      ro[k] = r_out[i];
+      cp[k] = (int32_t)k;
+      if (dh) dh[k] = dt_hard[i];
+    }
+    if (e0) e0[c] = orc_cluster_energy_comp(nm, x, v, mm, ro, p, cp);
+    double ec[6] = {0, 0, 0, 0, 0, 0};
+    int64_t ns = 0, nco = 0, tc = -1;
+    err |= orc_hermite_collide_one(nm, x, v, mm, ro, p, dt_soft, dh, f, rho, cp, ec, &ns, &nco, &tc);
+    if (eps)
+      for (int q = 0; q < 6; ++q) eps[6 * c + q] = ec[q];
+    if (nsteps) nsteps[c] = ns;
+    if (ncoll) ncoll[c] = nco;
+    if (tcoll) tcoll[c] = tc;
+    if (e1) e1[c] = orc_cluster_energy_comp(nm, x, v, mm, ro, p, cp);
+    for (int64_t k = 0; k < nm; ++k) {
+      int64_t i = members[b + k];
+      for (int q = 0; q < 3; ++q) {
+        pos[q * n + i] = x[q * nm + k];
+        vel[q * n + i] = v[q * nm + k];
+      }
+      merged_into[i] = members[b + cp[k]];
+      if (dh) dt_hard[i] = dh[k];
+    }
+    free(x); free(v); free(mm); free(ro); free(dh); free(cp);
   }
   return err;
 }

@@ -28,7 +28,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import Params, cluster_csr, hermite_clusters, labels, neighbour_rows, soft_acc
+from . import Params, cluster_csr, cutoffs, hermite_clusters, hermite_collide, labels, neighbour_rows, soft_acc
 from .kepler import kepler_drift
 
 
@@ -139,3 +139,75 @@ def total_energy(pos, vel, mass, p: Params) -> float:
         r = np.sqrt((d * d).sum(0))
         pair -= p.G * m[i] * float((m[i + 1:] / r).sum())
     return kin + star + pair
+
+
+# -- perfect-accretion collisions (Section 2.5.1) --------------------------------
+def merge_bodies(pos, vel, mass, dt_hard, merged_into):
+    """Each composite left by the hard part becomes one particle: the one at
+    its lowest index keeps the (shared) state and takes the total mass
+    (summed in index order); the others are removed.  Returns (pos, vel,
+    mass, dt_hard, keep) with keep the mask of the surviving indices."""
+    n = mass.shape[0]
+    merged_into = np.asarray(merged_into)
+    keep = merged_into == np.arange(n)
+    total = np.zeros(n)
+    for g in range(n):  # index order
+        total[merged_into[g]] += mass[g]
+    return (np.ascontiguousarray(pos[:, keep]), np.ascontiguousarray(vel[:, keep]), total[keep],
+            np.ascontiguousarray(dt_hard[keep]), keep)
+
+
+def step_collide(s: StepState, mass, r_out, r_search, p: Params, f: float, rho: float, isolated: int = 1):
+    """One soft step with perfect accretion: kick, hard part with collision
+    detection in every cluster (composites move as one body), then, if any
+    merger happened, the composites become single particles and the cut-off
+    and search radii of all particles are recomputed (step (9)); the soft
+    force and neighbour rows of the resulting system, the second kick.
+    Reading: the merger is applied before the evaluation of step (7) rather
+    than after the kick of step (8), so one evaluation serves both the second
+    kick and the next step; the kick of a merged body uses its own soft force
+    (no averaging of the two parts' soft forces, hence no E_disp,Soft).
+    Returns (state, mass, r_out, r_search, eps (6,) summed over the mergers,
+    number of particles removed)."""
+    h = 0.5 * p.dt_soft
+    vel = s.vel + h * s.acc
+    dt_hard = s.dt_hard.copy()
+    lab, _ = labels(s.row_ptr, s.col)
+    cl_ptr, members = cluster_csr(lab)
+    sizes = np.diff(cl_ptr)
+    pos = s.pos.copy()
+    n = pos.shape[1]
+    merged = np.arange(n, dtype=np.int32)
+    eps = np.zeros(6)
+    status = 0
+    steps = np.zeros(n, dtype=np.int64)
+    single = members[cl_ptr[:-1][sizes == 1]] if isolated else np.zeros(0, dtype=np.int32)
+    multi = np.flatnonzero(sizes > 1) if isolated else np.arange(sizes.shape[0])
+    if multi.size:
+        m_ptr = np.zeros(multi.shape[0] + 1, dtype=np.int32)
+        m_ptr[1:] = np.cumsum(sizes[multi])
+        m_mem = np.concatenate([members[cl_ptr[c]:cl_ptr[c + 1]] for c in multi]).astype(np.int32)
+        r = hermite_collide(pos, vel, mass, r_out, m_ptr, m_mem, p, f, rho, dt_hard=dt_hard)
+        pos, vel, status = r["pos"], r["vel"], r["status"]
+        merged[m_mem] = r["merged_into"][m_mem]
+        eps = r["eps"].sum(axis=0)
+        steps[m_mem] = np.repeat(r["nsteps"], np.diff(m_ptr))
+    if single.size:
+        xs, vs, bound, _ = kepler_drift(pos[:, single], vel[:, single], p.G * p.m_star, p.dt_soft)
+        if not bound.all():
+            raise FloatingPointError("an isolated particle is not on a bound orbit")
+        pos[:, single] = xs
+        vel[:, single] = vs
+        dt_hard[single] = 0.0
+        steps[single] = 1
+    removed = 0
+    mass = np.asarray(mass, dtype=np.float64)
+    if np.any(merged != np.arange(n)):
+        pos, vel, mass, dt_hard, keep = merge_bodies(pos, vel, mass, dt_hard, merged)
+        steps = steps[keep]
+        removed = int(n - keep.sum())
+        r_out, r_search, _ = cutoffs(pos, vel, mass, p)
+    acc, rp, col = evaluate(pos, vel, mass, r_out, r_search, p)
+    vel = vel + h * acc
+    return StepState(pos, vel, acc, rp, col, dt_hard, steps, int(sizes.shape[0]), status), mass, r_out, r_search, \
+        eps, removed

@@ -26,6 +26,7 @@ FLAG_NSTEPS = 0x40
 FLAG_BIG_CLUSTER = 0x80
 FLAG_UNBOUND = 0x100
 FLAG_GROUP_BOUND = 0x200
+FLAG_COLL_UNCHECKED = 0x400
 
 
 class CParams(C.Structure):
@@ -81,6 +82,11 @@ SIGNATURES = {
     "p3t_kepler_drift": (C.c_int, [_vp, _i64, _d, _vp, _vp, _vp, _i64, _vp, C.POINTER(_i64)]),
     "p3t_evaluate": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i32]),
     "p3t_hard_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)]),
+    "p3t_hard_step_collide": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp, C.POINTER(_d),
+                                        C.POINTER(_i64), C.POINTER(_i64)]),
+    "p3t_merge_bodies": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)]),
+    "p3t_hermite_collide": (C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp,
+                                      _vp, C.POINTER(_i64)]),
     "p3t_hard_evaluate": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32,
                                     C.POINTER(_i64), C.POINTER(_i64)]),
     "p3t_soft_force_frozen": (C.c_int, [_vp, _vp, _vp, _vp]),

@@ -236,6 +236,81 @@ class Context:
                                          _ptr(steps), C.byref(nc)), "hard_step")
         return int(nc.value)
 
+    def hard_step_collide(self, pos, vel, mass, r_out, merged_into, f_radius: float, density: float, dt_hard=None,
+                          steps=None):
+        """hard_step with perfect-accretion collisions (Section 2.5.1):
+        merged_into (int32 (n,)) receives each particle's composite (lowest
+        index).  Returns (clusters, mergers, eps (6 floats: eps_0..eps_3 with
+        W, their total with W = 1, with 1 - W))."""
+        n = self.n
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        self._vec(mass, n, "mass")
+        self._vec(r_out, n, "r_out")
+        self._vec(merged_into, n, "merged_into", dtype=torch.int32)
+        if dt_hard is not None:
+            self._vec(dt_hard, n, "dt_hard")
+        if steps is not None:
+            self._vec(steps, n, "steps", dtype=torch.int32)
+        nc, ncoll = C.c_int64(0), C.c_int64(0)
+        eps = (C.c_double * 6)()
+        self._bind()
+        self._check(self.L.p3t_hard_step_collide(self._h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(r_out),
+                                                 _ptr(dt_hard), _ptr(steps), float(f_radius), float(density),
+                                                 _ptr(merged_into), eps, C.byref(ncoll), C.byref(nc)),
+                    "hard_step_collide")
+        return int(nc.value), int(ncoll.value), [float(x) for x in eps]
+
+    def hermite_collide(self, pos, vel, mass, r_out, cl_ptr, members, f_radius: float, density: float, dt_hard=None,
+                        energy: bool = True, steps: bool = False):
+        """p3t_hermite_collide on caller-given clusters.  Returns a dict:
+        merged_into (int32 (n,)), eps (float64 (nc, 6)), ncoll, and e_rel /
+        nsteps when asked for."""
+        n = int(mass.shape[0])
+        nc = int(cl_ptr.shape[0]) - 1
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        self._vec(mass, n, "mass")
+        self._vec(r_out, n, "r_out")
+        if dt_hard is not None:
+            self._vec(dt_hard, n, "dt_hard")
+        dev = self.device
+        merged = torch.empty(n, dtype=torch.int32, device=dev)
+        eps = torch.empty((max(nc, 0), 6), dtype=torch.float64, device=dev)
+        e_rel = torch.empty(max(nc, 0), dtype=torch.float64, device=dev) if energy else None
+        ns = torch.empty(max(nc, 0), dtype=torch.int32, device=dev) if steps else None
+        nco = C.c_int64(0)
+        self._bind()
+        self._check(self.L.p3t_hermite_collide(self._h, n, nc, _ptr(cl_ptr), _ptr(members), _ptr(pos), _ptr(vel),
+                                               _ptr(mass), _ptr(r_out), _ptr(dt_hard), float(f_radius),
+                                               float(density), _ptr(merged), _ptr(eps), _ptr(e_rel), _ptr(ns),
+                                               C.byref(nco)), "hermite_collide")
+        out = dict(merged_into=merged, eps=eps, ncoll=int(nco.value))
+        if energy:
+            out["e_rel"] = e_rel
+        if steps:
+            out["nsteps"] = ns
+        return out
+
+    def merge_bodies(self, merged_into, pos, vel, mass, dt_hard=None, steps=None) -> int:
+        """Each composite becomes one particle (Section 2.5.1); the arrays are
+        compacted in place (the first 3 n_new / n_new entries, row stride
+        n_new).  Returns n_new; see merged_views for the compacted tensors."""
+        n = int(mass.shape[0])
+        self._vec3(pos, n, "pos")
+        self._vec3(vel, n, "vel")
+        self._vec(mass, n, "mass")
+        self._vec(merged_into, n, "merged_into", dtype=torch.int32)
+        if dt_hard is not None:
+            self._vec(dt_hard, n, "dt_hard")
+        if steps is not None:
+            self._vec(steps, n, "steps", dtype=torch.int32)
+        nn = C.c_int64(0)
+        self._bind()
+        self._check(self.L.p3t_merge_bodies(self._h, n, _ptr(merged_into), _ptr(pos), _ptr(vel), _ptr(mass),
+                                            _ptr(dt_hard), _ptr(steps), C.byref(nn)), "merge_bodies")
+        return int(nn.value)
+
     def hard_evaluate(self, pos, vel, mass, r_out_hard, dt_hard, steps, r_out, r_search, out=None,
                       slow_log2: int = 9, graph: bool = True):
         """hard_step then evaluate in one call.  Clusters still running after

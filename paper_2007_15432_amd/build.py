@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libp3t.so")
 ARCH = os.environ.get("P3T_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["util.hip", "cutoff.hip", "tree.hip", "walk.hip", "force.hip", "force_split.hip", "nbr.hip", "hermite.hip",
-           "adjoint.hip", "slow.hip", "kepler.hip", "energy.hip", "api.hip"]
+           "adjoint.hip", "slow.hip", "kepler.hip", "energy.hip", "merge.hip", "api.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -342,7 +342,7 @@ p3t_status p3t_destroy(p3t_ctx *c) {
     if (ev) hipEventDestroy(ev);
   void *bufs[] = {c->arena.base, c->pool,    c->slot_lists, c->slot_stack, c->pairs,
                   c->csr_col,    c->cands,   c->adj_buf,    c->ov_buf,     c->pairs_d,
-                  c->huge_buf};
+                  c->huge_buf,   c->coll_buf, c->merge_st,  c->merge_i32};
   for (void *b : bufs)
     if (b) hipFree(b);
   for (auto &e : c->ev)
@@ -719,6 +719,53 @@ p3t_status p3t_hermite_cluster_step(p3t_ctx *c, int64_t n, int64_t n_clusters, c
   return P3T_OK;
 }
 
+p3t_status p3t_hermite_collide(p3t_ctx *c, int64_t n, int64_t n_clusters, const int32_t *cl_ptr,
+                               const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
+                               const double *r_out, double *dt_hard, double f_radius, double density,
+                               int32_t *merged_into, double *eps6, double *e_rel_err, int32_t *n_steps,
+                               int64_t *n_collisions_host) {
+  if (!c) return P3T_ERR_ARG;
+  if (n_collisions_host) *n_collisions_host = 0;
+  if (n < 0 || n_clusters < 0 || n > (int64_t(1) << 30) || n_clusters > (int64_t(1) << 30))
+    return fail(c, P3T_ERR_ARG, "hermite_collide: size out of range");
+  if (!(f_radius >= 0.0) || !std::isfinite(f_radius)) return fail(c, P3T_ERR_ARG, "hermite_collide: f_radius < 0");
+  if (!(density > 0.0) || !std::isfinite(density)) return fail(c, P3T_ERR_ARG, "hermite_collide: density <= 0");
+  if (n_clusters == 0) return P3T_OK;
+  if (!cl_ptr || !cl_members || bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) ||
+      bad_ptr(merged_into, n))
+    return fail(c, P3T_ERR_ARG, "hermite_collide: null pointer");
+  p3t_status st = ensure_n(c, std::max(n, n_clusters));
+  if (st != P3T_OK) return st;
+  if (!eps6 && c->coll_cap < 6 * n_clusters + 6) {
+    HIP_OK(c, dev_alloc(c->coll_buf, 6 * c->n_cap + 6));
+    c->coll_cap = 6 * c->n_cap + 6;
+  }
+  double *ceps = eps6 ? eps6 : c->coll_buf;
+  HIP_OK(c, iota_i32(merged_into, n, c->stream));
+  HIP_OK(c, fill_f64(ceps, 0.0, 6 * n_clusters, c->stream));
+  HermColl hc;
+  hc.f = f_radius;
+  hc.r3 = 3.0 / (4.0 * M_PI * density);
+  hc.merged = merged_into;
+  hc.ceps = ceps;
+  ev_record(c, 9);
+  hipError_t e = hermite_clusters(c, n, n_clusters, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err,
+                                  n_steps, nullptr, nullptr, nullptr, &hc);
+  if (e == hipErrorInvalidDevicePointer)
+    return fail(c, P3T_ERR_ARG, "hermite_collide: cl_ptr not non-decreasing or a member outside [0, n)");
+  HIP_OK(c, e);
+  ev_record(c, 10);
+  DevCounters h;
+  if ((st = sync_counters(c, &h)) != P3T_OK) return st;
+  if (n_collisions_host) *n_collisions_host = (int64_t)h.n_coll;
+  unsigned bits = 0;
+  if ((st = harvest_status(c, &bits)) != P3T_OK) return st;
+  if (c->timing) c->stats.ms_hermite = ev_ms(c, 9, 10);
+  if (bits & NUMERIC_BITS)
+    return fail(c, P3T_ERR_NUMERIC, "hermite_collide: device status 0x%x", bits & NUMERIC_BITS);
+  return P3T_OK;
+}
+
 p3t_status p3t_kick(p3t_ctx *c, int64_t n, double h, const double *acc3, double *vel3) {
   if (!c) return P3T_ERR_ARG;
   if (n < 0 || bad_ptr(acc3, n) || bad_ptr(vel3, n) || !std::isfinite(h)) return fail(c, P3T_ERR_ARG, "kick: bad argument");
@@ -773,6 +820,85 @@ p3t_status p3t_hard_step(p3t_ctx *c, double *pos3, double *vel3, const double *m
     c->stats.ms_hermite = ev_ms(c, 9, 10);
     c->stats.ms_clusters = ev_ms(c, 9, 19);
   }
+  return P3T_OK;
+}
+
+p3t_status p3t_hard_step_collide(p3t_ctx *c, double *pos3, double *vel3, const double *mass, const double *r_out,
+                                 double *dt_hard, int32_t *steps, double f_radius, double density,
+                                 int32_t *merged_into, double *eps_host, int64_t *n_collisions_host,
+                                 int64_t *n_clusters_host) {
+  if (!c) return P3T_ERR_ARG;
+  if (!c->force_valid)
+    return fail(c, P3T_ERR_STATE, "hard_step_collide: no neighbour pairs (call p3t_compute_soft_force)");
+  const int64_t n = c->n;
+  if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(merged_into, n))
+    return fail(c, P3T_ERR_ARG, "hard_step_collide: null pointer");
+  if (!(f_radius >= 0.0) || !std::isfinite(f_radius)) return fail(c, P3T_ERR_ARG, "hard_step_collide: f_radius < 0");
+  if (!(density > 0.0) || !std::isfinite(density)) return fail(c, P3T_ERR_ARG, "hard_step_collide: density <= 0");
+  if (n_clusters_host) *n_clusters_host = 0;
+  if (n_collisions_host) *n_collisions_host = 0;
+  if (eps_host)
+    for (int q = 0; q < 6; ++q) eps_host[q] = 0.0;
+  if (n == 0) return P3T_OK;
+  if (c->coll_cap < 6 * n + 6) {
+    HIP_OK(c, dev_alloc(c->coll_buf, 6 * c->n_cap + 6));
+    c->coll_cap = 6 * c->n_cap + 6;
+  }
+  ev_record(c, 9);
+  HIP_OK(c, build_csr(c, n, c->n_pairs));
+  HIP_OK(c, labels_cc(c, n, c->hs_label));
+  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  ev_record(c, 19);
+  HIP_OK(c, iota_i32(merged_into, n, c->stream));
+  HIP_OK(c, fill_f64(c->coll_buf, 0.0, 6 * n, c->stream));
+  HermColl hc;
+  hc.f = f_radius;
+  hc.r3 = 3.0 / (4.0 * M_PI * density);
+  hc.merged = merged_into;
+  hc.ceps = c->coll_buf;
+  int64_t nc = 0;
+  hipError_t e = hermite_clusters(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr,
+                                  nullptr, c->node_scan + n, &nc, steps, &hc);
+  HIP_OK(c, e);
+  ev_record(c, 10);
+  if (n_clusters_host) *n_clusters_host = nc;
+  HIP_OK(c, sum_rows6(nc, c->coll_buf, c->coll_buf + 6 * n, c->stream));
+  double sums[6];
+  HIP_OK(c, hipMemcpyAsync(sums, c->coll_buf + 6 * n, sizeof(sums), hipMemcpyDeviceToHost, c->stream));
+  DevCounters h;
+  p3t_status st = sync_counters(c, &h);  // synchronises the stream
+  if (st != P3T_OK) return st;
+  if (eps_host)
+    for (int q = 0; q < 6; ++q) eps_host[q] = sums[q];
+  if (n_collisions_host) *n_collisions_host = (int64_t)h.n_coll;
+  if (c->timing) {
+    c->stats.ms_hermite = ev_ms(c, 9, 10);
+    c->stats.ms_clusters = ev_ms(c, 9, 19);
+  }
+  return P3T_OK;
+}
+
+p3t_status p3t_merge_bodies(p3t_ctx *c, int64_t n, const int32_t *merged_into, double *pos3, double *vel3,
+                            double *mass, double *dt_hard, int32_t *steps, int64_t *n_new_host) {
+  if (!c || !n_new_host) return P3T_ERR_ARG;
+  *n_new_host = n;
+  if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "merge_bodies: n out of range");
+  if (n == 0) return P3T_OK;
+  if (bad_ptr(merged_into, n) || bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n))
+    return fail(c, P3T_ERR_ARG, "merge_bodies: null pointer");
+  p3t_status st = ensure_n(c, n);  // node_scan (n + 1) and the scan scratch
+  if (st != P3T_OK) return st;
+  if (c->merge_cap < n) {
+    HIP_OK(c, dev_alloc(c->merge_st, 9 * c->n_cap));
+    HIP_OK(c, dev_alloc(c->merge_i32, 2 * c->n_cap + 1));
+    c->merge_cap = c->n_cap;
+  }
+  c->tree_valid = c->force_valid = false;  // the particle set changes
+  hipError_t e = merge_bodies(c, n, merged_into, pos3, vel3, mass, dt_hard, steps, n_new_host);
+  if (e == hipErrorInvalidValue)
+    return fail(c, P3T_ERR_ARG, "merge_bodies: merged_into is not a composite map (each entry the lowest index "
+                                "of its composite, which maps to itself)");
+  HIP_OK(c, e);
   return P3T_OK;
 }
 

@@ -64,6 +64,11 @@ struct HermArgs {
     int32_t *members;       // parked members (n)
     uint8_t *flag;          // per particle: 1 if parked (cleared by the caller)
   } pk;
+  // perfect-accretion collisions (wave path, k_herm_fused<0, true>): two
+  // bodies merge when r < coll_f (R_i + R_j), R = cbrt(coll_r3 m)
+  double coll_f, coll_r3;
+  int32_t *merged;  // per particle: index of its composite's lowest member (nullable)
+  double *ceps;     // per cluster: six dissipation sums (nullable)
   int64_t n;
   double G, GM, gamma, inv1mg, eta, eta0, dt_soft, tick;
   // powers of dt_soft for the corrector (scaled per level by exact powers of two)
@@ -268,6 +273,10 @@ struct Lds {
   double *px, *py, *pz, *pvx, *pvy, *pvz, *pgm, *pinv;
   int *act;     // big clusters: active members of the step (BIG_ACT)
   double *res;  // big clusters: their reduced partner sums (6 BIG_ACT)
+  // collisions (wave path): composite of each slot (its lowest slot), the
+  // composite's radius, the slot's mass
+  int *cid;
+  double *rad, *pm;
 };
 constexpr int BIG_ACT = 128;  // most active members handled lane-parallel
 
@@ -580,8 +589,13 @@ __device__ __forceinline__ int res_parts_log2(int lg) { return lg > 4 ? lg - 4 :
 
 __device__ __forceinline__ int spread_lg(int size, int n_act) { return min(6 - ceil_log2(n_act), ceil_log2(size)); }
 
-__device__ __forceinline__ void spread_sums(const HermArgs &A, const Lds &L, int wbase, int size, int n_act, int lane,
-                                            unsigned long long amask) {
+// COLL: the two parts of a composite exchange no term, and every evaluated
+// pair of distinct bodies closer than coll_f (R_k + R_q) is a collision;
+// returns the first of them as (lower slot) * 64 + higher slot, or -1
+// (wave-uniform).  Without COLL returns -1.
+template <bool COLL>
+__device__ __forceinline__ int spread_sums(const HermArgs &A, const Lds &L, int wbase, int size, int n_act, int lane,
+                                           unsigned long long amask) {
   const int lg = spread_lg(size, n_act);
   const int grp = lane >> lg, sub = lane & ((1 << lg) - 1);
   int k;
@@ -593,13 +607,23 @@ __device__ __forceinline__ void spread_sums(const HermArgs &A, const Lds &L, int
     k = grp < n_act ? L.act[wbase + grp] : -1;
   }
   double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0};
+  int key = INT_MAX;  // COLL: first colliding pair seen by this lane
   if (k >= 0) {
     const int sk = wbase + k;
     const double xk = L.px[sk], yk = L.py[sk], zk = L.pz[sk], vxk = L.pvx[sk], vyk = L.pvy[sk], vzk = L.pvz[sk];
     const double ik = L.pinv[sk];
+    const int ck = COLL ? L.cid[sk] : 0;
+    const double rk = COLL ? L.rad[sk] : 0.0;
     for (int q = sub; q < size; q += 1 << lg) {
       if (q == k) continue;
       const int sq = wbase + q;
+      if (COLL) {
+        if (L.cid[sq] == ck) continue;  // parts of one composite
+        const double dx = L.px[sq] - xk, dy = L.py[sq] - yk, dz = L.pz[sq] - zk;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double rs = A.coll_f * (rk + L.rad[sq]);
+        if (r2 < rs * rs) key = min(key, min(k, q) * WAVE + max(k, q));
+      }
       hard_pair(L.px[sq] - xk, L.py[sq] - yk, L.pz[sq] - zk, L.pvx[sq] - vxk, L.pvy[sq] - vyk, L.pvz[sq] - vzk,
                 L.pgm[sq], fmin(ik, L.pinv[sq]), A, pa, pj);
     }
@@ -619,6 +643,8 @@ __device__ __forceinline__ void spread_sums(const HermArgs &A, const Lds &L, int
       r[3 + d] = pj[d];
     }
   }
+  if (!COLL || __ballot(key != INT_MAX) == 0ull) return -1;
+  return uniform_first(wave_min(key));
 }
 
 // adds the partner sums of the member at list position a (after spread_sums)
@@ -641,10 +667,40 @@ __device__ __forceinline__ void add_spread(const Lds &L, int wbase, int a, int l
 // lanes.  The wavefront synchronises only with itself.  Same arithmetic per
 // member as the other paths (hard_pair, star_term, correct, initial_level).
 // MODE 0: plain; 1: park after A.budget block steps; 2: resume parked.
-template <int MODE>
+//
+// COLL (MODE 0 only; clusters of 2..64 members): perfect-accretion
+// collisions (Section 2.5.1).  Each slot belongs to a composite (its lowest
+// slot, initially itself); the parts of a composite exchange no term and
+// move with the mass-weighted mean of their accelerations and jerks.  The
+// first colliding pair of a block step (lowest (slot, slot) order, found on
+// the predicted states among the evaluated pairs) merges after the
+// corrector, from the states at the block time (corrected for due members,
+// predicted for the others): centre of mass and momentum, the dissipations
+// eq. (e0) ... eq. (e3) (with W, with one and with 1 - W), acceleration and
+// jerk of the composite at the block time, a new step from eta_0 refined
+// until the block time is a multiple of it.  One merger per block step.
+__device__ __forceinline__ double body_radius(double m, const HermArgs &A) { return cbrt(A.coll_r3 * m); }
+
+// composite mean of q (three components) over the slots of composite cq:
+// sum over its slots in slot order of m q, divided by the summed mass; the
+// values m q of every slot are in L.res (three doubles per slot, at 6 slot)
+__device__ __forceinline__ void composite_mean3(const Lds &L, int wbase, int size, int cq, int off, double *q) {
+  double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+  for (int l = 0; l < size; ++l) {
+    if (L.cid[wbase + l] != cq) continue;
+    M += L.pm[wbase + l];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s[d] += L.res[6 * (wbase + l) + off + d];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) q[d] = s[d] / M;
+}
+
+template <int MODE, bool COLL>
 __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blist, int count, int ci, const Lds &L,
                                           int wbase, int bk) {
   constexpr bool RESUME = MODE == 2, PARK = MODE == 1;
+  static_assert(!COLL || MODE == 0, "collisions run without parking");
   const int lane = threadIdx.x & (WAVE - 1);
   if (ci >= count) return;  // uniform per wavefront; no workgroup barrier follows
   const int c = blist[ci];
@@ -668,6 +724,9 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
   }
   const double invi = 1.0 / ro;
   const double GM = A.GM, tick = A.tick;
+  int mycid = lane;                                        // COLL: composite of this slot
+  double eps[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};          // COLL: dissipations (summed on every lane)
+  int ncoll = 0;
   wave_sync();
   L.pgm[me] = A.G * m;
   L.pinv[me] = invi;
@@ -677,6 +736,11 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
   L.pvx[me] = v[0];
   L.pvy[me] = v[1];
   L.pvz[me] = v[2];
+  if (COLL) {
+    L.cid[me] = lane;
+    L.rad[me] = mem ? body_radius(m, A) : 0.0;
+    L.pm[me] = m;
+  }
   if (mem) L.act[wbase + lane] = lane;  // every member: the forces at t = 0
   wave_sync();
   double E0 = 0.0;
@@ -685,7 +749,7 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
   int nst = 0;
   star_term(x, v, GM, a0, j0);
   if (!RESUME) {
-    spread_sums(A, L, wbase, size, size, lane, __ballot(mem));
+    spread_sums<COLL>(A, L, wbase, size, size, lane, __ballot(mem));
     double e = mem ? 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) -
                          GM * m * rsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2])
                    : 0.0;
@@ -756,14 +820,177 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
     double a1[3], j1[3];
     star_term(xp, vp, GM, a1, j1);  // while the LDS writes are in flight
     wave_sync();
-    spread_sums(A, L, wbase, size, n_act, lane, amask);
+    const int ckey = spread_sums<COLL>(A, L, wbase, size, n_act, lane, amask);
     wave_sync();
+    if (active) add_spread(L, wbase, apos, spread_lg(size, n_act), a1, j1);
+    if (COLL && __ballot(mem && mycid != lane) != 0ull) {
+      // composites: every part moves with the mass-weighted mean
+      wave_sync();
+      if (active) {
+        double *r = L.res + 6 * me;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          r[d] = m * a1[d];
+          r[3 + d] = m * j1[d];
+        }
+      }
+      wave_sync();
+      if (active) {
+        composite_mean3(L, wbase, size, mycid, 0, a1);
+        composite_mean3(L, wbase, size, mycid, 3, j1);
+      }
+    }
     if (active) {
-      add_spread(L, wbase, apos, spread_lg(size, n_act), a1, j1);
       const double h = (double)(tn - t) * tick;
       t = tn;
       correct(x, v, a0, j0, xp, vp, a1, j1, h, t, lev, A);
       ++n_eval;
+    }
+    if (COLL && ckey >= 0) {
+      // ---- merger of the composites of slots ci_ < cj_ at tn
+      const int ci_ = ckey / WAVE, cj_ = ckey % WAVE;
+      double sx[3], sv[3];  // state at tn
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        sx[d] = active ? x[d] : xp[d];
+        sv[d] = active ? v[d] : vp[d];
+      }
+      wave_sync();
+      L.px[me] = sx[0];
+      L.py[me] = sx[1];
+      L.pz[me] = sx[2];
+      L.pvx[me] = sv[0];
+      L.pvy[me] = sv[1];
+      L.pvz[me] = sv[2];
+      wave_sync();
+      const int CA = L.cid[wbase + ci_], CB = L.cid[wbase + cj_];
+      const bool inA = mem && mycid == CA, inB = mem && mycid == CB;
+      const double MA = wave_sum(inA ? m : 0.0), MB = wave_sum(inB ? m : 0.0), M = MA + MB;
+      double xa[3], xb[3], va[3], vb[3], xn[3], vn[3];
+      xa[0] = L.px[wbase + ci_], xa[1] = L.py[wbase + ci_], xa[2] = L.pz[wbase + ci_];
+      xb[0] = L.px[wbase + cj_], xb[1] = L.py[wbase + cj_], xb[2] = L.pz[wbase + cj_];
+      va[0] = L.pvx[wbase + ci_], va[1] = L.pvy[wbase + ci_], va[2] = L.pvz[wbase + ci_];
+      vb[0] = L.pvx[wbase + cj_], vb[1] = L.pvy[wbase + cj_], vb[2] = L.pvz[wbase + cj_];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        xn[d] = (MA * xa[d] + MB * xb[d]) / M;
+        vn[d] = (MA * va[d] + MB * vb[d]) / M;
+      }
+      const double dvx = va[0] - vb[0], dvy = va[1] - vb[1], dvz = va[2] - vb[2];
+      const double e0 = 0.5 * (MA * MB / M) * (dvx * dvx + dvy * dvy + dvz * dvz);  // eq. (e0)
+      const double rab = sqrt((xb[0] - xa[0]) * (xb[0] - xa[0]) + (xb[1] - xa[1]) * (xb[1] - xa[1]) +
+                              (xb[2] - xa[2]) * (xb[2] - xa[2]));
+      double e1 = 0.0, e1u = 0.0, e1h = 0.0, e3 = 0.0, e3u = 0.0, e3h = 0.0;
+      if (inA)  // eq. (e1): every part of A with every part of B
+        for (int l = 0; l < size; ++l) {
+          if (L.cid[wbase + l] != CB) continue;
+          const double W = changeover_W(rab * fmin(invi, L.pinv[wbase + l]), A);
+          const double mm = m * L.pm[wbase + l];
+          e1 -= mm * W / rab;
+          e1u -= mm / rab;
+          e1h -= mm * (1.0 - W) / rab;
+        }
+      if (inA || inB) {  // eq. (e3): the parts of A and B with the other members
+        const double *xo = inA ? xa : xb;
+        for (int l = 0; l < size; ++l) {
+          const int cl = L.cid[wbase + l];
+          if (cl == CA || cl == CB) continue;
+          const int sl = wbase + l;
+          const double iR = fmin(invi, L.pinv[sl]);
+          const double ox = L.px[sl] - xo[0], oy = L.py[sl] - xo[1], oz = L.pz[sl] - xo[2];
+          const double nx = L.px[sl] - xn[0], ny = L.py[sl] - xn[1], nz = L.pz[sl] - xn[2];
+          const double r_o = sqrt(ox * ox + oy * oy + oz * oz), r_n = sqrt(nx * nx + ny * ny + nz * nz);
+          const double Wo = changeover_W(r_o * iR, A), Wn = changeover_W(r_n * iR, A);
+          const double mm = m * L.pm[sl];
+          e3 -= mm * (Wo / r_o - Wn / r_n);
+          e3u -= mm * (1.0 / r_o - 1.0 / r_n);
+          e3h -= mm * ((1.0 - Wo) / r_o - (1.0 - Wn) / r_n);
+        }
+      }
+      const double G = A.G;
+      e1 = G * wave_sum(e1);
+      e1u = G * wave_sum(e1u);
+      e1h = G * wave_sum(e1h);
+      e3 = G * wave_sum(e3);
+      e3u = G * wave_sum(e3u);
+      e3h = G * wave_sum(e3h);
+      const double e2 = -GM * (MA / sqrt(xa[0] * xa[0] + xa[1] * xa[1] + xa[2] * xa[2]) +
+                               MB / sqrt(xb[0] * xb[0] + xb[1] * xb[1] + xb[2] * xb[2]) -
+                               M / sqrt(xn[0] * xn[0] + xn[1] * xn[1] + xn[2] * xn[2]));  // eq. (e2)
+      eps[0] += e0;
+      eps[1] += e1;
+      eps[2] += e2;
+      eps[3] += e3;
+      eps[4] += e0 + e1u + e2 + e3u;
+      eps[5] += e0 + e1h + e2 + e3h;
+      ++ncoll;
+      // the composite takes the merged state at tn
+      const bool inC = inA || inB;
+      const int cn = min(CA, CB);
+      if (inC) {
+        mycid = cn;
+        t = tn;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          x[d] = sx[d] = xn[d];
+          v[d] = sv[d] = vn[d];
+        }
+      }
+      wave_sync();
+      if (inC) {
+        L.cid[me] = cn;
+        L.rad[me] = body_radius(M, A);
+        L.px[me] = xn[0];
+        L.py[me] = xn[1];
+        L.pz[me] = xn[2];
+        L.pvx[me] = vn[0];
+        L.pvy[me] = vn[1];
+        L.pvz[me] = vn[2];
+      }
+      wave_sync();
+      // its acceleration and jerk at tn from everyone's state at tn
+      double an[3], jn[3];
+      star_term(sx, sv, GM, an, jn);
+      if (inC) {
+        double pa[3] = {0.0, 0.0, 0.0}, pj[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < size; ++l) {
+          const int sl = wbase + l;
+          if (L.cid[sl] == cn) continue;
+          hard_pair(L.px[sl] - sx[0], L.py[sl] - sx[1], L.pz[sl] - sx[2], L.pvx[sl] - sv[0], L.pvy[sl] - sv[1],
+                    L.pvz[sl] - sv[2], L.pgm[sl], fmin(invi, L.pinv[sl]), A, pa, pj);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          an[d] += pa[d];
+          jn[d] += pj[d];
+        }
+        double *r = L.res + 6 * me;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          r[d] = m * an[d];
+          r[3 + d] = m * jn[d];
+        }
+      }
+      wave_sync();
+      if (inC) {
+        composite_mean3(L, wbase, size, cn, 0, an);
+        composite_mean3(L, wbase, size, cn, 3, jn);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a0[d] = an[d];
+          j0[d] = jn[d];
+        }
+        // first step after the merger: eta_0 criterion, on a multiple of the step
+        const double anr = norm3(an), jnr = norm3(jn);
+        const double dtc = jnr > 0.0 ? A.eta0 * anr / jnr : A.dt_soft;
+        int kl = level_for(A.dt_soft, dtc, A.k_max);
+        if (kl > A.k_max) {
+          set_flag(A.cnt, P3T_FLAG_KMAX);
+          kl = A.k_max;
+        }
+        while (kl < A.k_max && (tn & (((int64_t)1 << (TICK_BITS - kl)) - 1)) != 0) ++kl;
+        lev = kl;
+      }
     }
   }
   count_work(A, n_eval, size);
@@ -792,7 +1019,7 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
     }
     return;  // finished by the resume launch
   }
-  // final energy
+  // final energy (the pairs inside a composite left out)
   wave_sync();
   L.px[me] = x[0];
   L.py[me] = x[1];
@@ -807,6 +1034,7 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
   if (mem)
     for (int q = lane + 1; q < size; ++q) {
       const int sq = wbase + q;
+      if (COLL && L.cid[sq] == mycid) continue;
       const double dx = L.px[sq] - x[0], dy = L.py[sq] - x[1], dz = L.pz[sq] - x[2];
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       e -= m * L.pgm[sq] * (1.0 - changeover_W(r * fmin(invi, L.pinv[sq]), A)) / r;
@@ -821,9 +1049,16 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
     if (A.dt_hard) A.dt_hard[gid] = ldexp(A.dt_soft, -lev);
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) set_flag(A.cnt, P3T_FLAG_NAN);
     if (A.msteps) A.msteps[gid] = nst;
+    if (COLL && A.merged) A.merged[gid] = A.members[b + mycid];
   }
-  if (lane == 0 && A.e_rel) A.e_rel[c] = fabs(E1 - E0) / fabs(E0);
+  // with mergers the cluster's energy check adds the hard-energy dissipation
+  if (lane == 0 && A.e_rel) A.e_rel[c] = fabs(E1 + eps[5] - E0) / fabs(E0);
   if (lane == 0 && A.nsteps) A.nsteps[c] = nst;
+  if (COLL && lane == 0) {
+    if (A.ceps)
+      for (int q = 0; q < 6; ++q) A.ceps[6 * (int64_t)c + q] = eps[q];
+    if (ncoll > 0) atomicAdd(&A.cnt->n_coll, (unsigned long long)ncoll);
+  }
 }
 
 // ---------------------------------------------------------------- big clusters
@@ -1132,15 +1367,23 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, int bk, const
 }
 
 // Buckets 0..6 (sizes 1..64) in one launch of 256-thread workgroups; the
-// block index selects the bucket (uniform per workgroup).
-template <int MODE>
+// block index selects the bucket (uniform per workgroup).  COLL: every
+// cluster of 2..64 members takes the wavefront path with collisions.
+__host__ __device__ constexpr int clusters_per_wave(int bk, bool coll) {
+  return (coll && bk >= 1) || bk >= WAVE_BK0 ? 1 : WAVE >> (bk + lanes_per_member_log2(bk));
+}
+
+template <int MODE, bool COLL = false>
 __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   __shared__ double lds[8][BIG_T];
   __shared__ int64_t shi[BIG_T / WAVE];
   __shared__ double shd[BIG_T / WAVE];
   __shared__ int act[BIG_T];
   __shared__ double res[6 * BIG_T];
-  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7], act, res};
+  constexpr int NC = COLL ? BIG_T : 1;
+  __shared__ int cid[NC];
+  __shared__ double rad[NC], pm[NC];
+  const Lds L = {lds[0], lds[1], lds[2], lds[3], lds[4], lds[5], lds[6], lds[7], act, res, cid, rad, pm};
   // workgroups are dispatched roughly in index order: the buckets of the
   // larger clusters (fewer, longer chains) take the first indices, the
   // singletons the last, so the long chains start first
@@ -1159,14 +1402,13 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   const int32_t *blist = A.blists + (int64_t)bk * A.nc;
   const int w = threadIdx.x / WAVE;
   const int wbase = w * WAVE;
-  const int per_wave = WAVE >> (bk + lanes_per_member_log2(bk));  // clusters per wavefront
-  const int ci0 = (local * (BIG_T / WAVE) + w) * per_wave;
+  const int ci0 = (local * (BIG_T / WAVE) + w) * clusters_per_wave(bk, COLL);
   int count = 0;
 #pragma unroll
   for (int q = 0; q < 7; ++q)
     if (q == bk) count = A.bcount[q];  // constant indices only (see above)
-  if (bk >= WAVE_BK0)
-    wave_body<MODE>(A, blist, count, ci0, L, wbase, bk);
+  if (bk >= (COLL ? 1 : WAVE_BK0))
+    wave_body<MODE, COLL>(A, blist, count, ci0, L, wbase, bk);
   else
     seg_body<MODE>(A, blist, count, ci0, L, wbase, bk);
 }
@@ -1247,6 +1489,7 @@ __global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
     bcount[BC_NC] = (int32_t)nc;
     B.cnt->n_heval = 0;  // the work counters of this hard part
     B.cnt->n_hpair = 0;
+    B.cnt->n_coll = 0;
   }
   const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
@@ -1357,8 +1600,11 @@ hipError_t huge_clusters(p3t_ctx *c, const HermArgs &A, int count, hipStream_t s
 hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
                        double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
                        double *e_rel_err, int32_t *n_steps, int32_t *steps_out, const int32_t *hc, int budget,
-                       int resume, hipStream_t s, hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join) {
+                       int resume, hipStream_t s, hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join,
+                       const HermColl *coll) {
   hipError_t e;
+  const bool collide = coll != nullptr;
+  if (collide && (resume || budget > 0)) return hipErrorInvalidValue;  // collisions run without parking
   const p3t_params &P = c->P;
   HermArgs A;
   A.cl_ptr = cl_ptr;
@@ -1407,6 +1653,10 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   }
   A.k_max = P.k_max;
   A.max_iter = 1 << 22;
+  A.coll_f = collide ? coll->f : 0.0;
+  A.coll_r3 = collide ? coll->r3 : 0.0;
+  A.merged = collide ? coll->merged : nullptr;
+  A.ceps = collide ? coll->ceps : nullptr;
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
   for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = resume ? (bk < 10 ? hc[HERM_BC_PARK0 + bk] : 0) : hc[bk];
@@ -1420,7 +1670,7 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   int blocks = 0;
   for (int bk = 0; bk < 7; ++bk) {
     A.boff[bk] = blocks;
-    const int per_block = (BIG_T / WAVE) * (WAVE >> (bk + lanes_per_member_log2(bk)));
+    const int per_block = (BIG_T / WAVE) * clusters_per_wave(bk, collide);
     blocks += (A.bcount[bk] + per_block - 1) / per_block;
   }
   for (int bk = 7; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
@@ -1455,9 +1705,14 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
       hipLaunchKernelGGL(k_herm_fused<2>, dim3(blocks), dim3(BIG_T), 0, s, A);
     else if (budget > 0)
       hipLaunchKernelGGL(k_herm_fused<1>, dim3(blocks), dim3(BIG_T), 0, s, A);
+    else if (collide)
+      hipLaunchKernelGGL((k_herm_fused<0, true>), dim3(blocks), dim3(BIG_T), 0, s, A);
     else
       hipLaunchKernelGGL(k_herm_fused<0>, dim3(blocks), dim3(BIG_T), 0, s, A);
   }
+  // collisions are looked for in clusters of up to 64 members only
+  if (collide && big)
+    hipLaunchKernelGGL(k_huge_flag, dim3(1), dim3(1), 0, s, c->cnt, (unsigned)P3T_FLAG_COLL_UNCHECKED);
   if (n_huge > 0) {
     // issued after the fused launch, so that it runs beside them; the host
     // waits here until the percolated clusters are done
@@ -1486,7 +1741,7 @@ hipError_t aux_streams(p3t_ctx *c) {
 hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                             double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
                             double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev, int64_t *nc_out,
-                            int32_t *steps_out) {
+                            int32_t *steps_out, const HermColl *coll) {
   if (nc_out) *nc_out = 0;
   if (nc <= 0) return hipSuccess;  // with nc_dev, nc is an upper bound (the particle count)
   int32_t hc[BC_WORDS];
@@ -1495,7 +1750,7 @@ hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl
   if (e != hipSuccess) return e;
   if ((e = aux_streams(c)) != hipSuccess) return e;
   return herm_launch(c, n, nc, cl_ptr, cl_members, pos3, vel3, mass, r_out, dt_hard, e_rel_err, n_steps, steps_out, hc,
-                     0, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]);
+                     0, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1], coll);
 }
 
 // ---------------------------------------------------------------- percolated clusters

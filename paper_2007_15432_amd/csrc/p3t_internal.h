@@ -67,6 +67,7 @@ struct DevCounters {
   unsigned long long n_bad_index; // list entries outside [0, n) (p3t_kepler_drift)
   unsigned long long n_heval;     // Hermite: evaluations of members due in a block step (last hard part)
   unsigned long long n_hpair;     // Hermite: pair terms of those evaluations
+  unsigned long long n_coll;      // Hermite: mergers of the last hard part with collisions
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -185,6 +186,13 @@ struct p3t_ctx {
   int2 *pairs = nullptr;            // neighbour pairs (i_orig, j_orig)
   int2 *cands = nullptr;            // neighbour candidates (sorted indices)
   int64_t cand_cap = 0;
+  // collisions: per-cluster dissipations (6 per cluster) and their sums (6);
+  // merging: staging rows (9 n) and int scratch (2 n + 1)
+  double *coll_buf = nullptr;
+  int64_t coll_cap = 0;
+  double *merge_st = nullptr;
+  int32_t *merge_i32 = nullptr;
+  int64_t merge_cap = 0;
 
   // state
   int64_t n = 0;
@@ -299,6 +307,8 @@ hipError_t radix_sort_pairs(uint64_t *&keys, int32_t *&vals, uint64_t *&keys_alt
                             int64_t *tmp, int64_t tmp_cap, hipStream_t s);
 int64_t radix_hist_need(int64_t n);
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t iota_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t bbox_reduce(const double *pos3, int64_t n, double *part, double *out, hipStream_t s);
 hipError_t kick(int64_t n, double h, const double *acc3, double *vel3, hipStream_t s);
 hipError_t kepler_drift(int64_t n, int64_t n_list, const int32_t *list, double mu, double dt, double *pos3,
@@ -346,10 +356,23 @@ hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t
 // nc_dev (nullable): the cluster count on the device, nc then only bounds it
 hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                        const int64_t *nc_dev, int32_t *hc);
+// perfect-accretion collisions in the hard part (hermite.hip, wave path)
+struct HermColl {
+  double f;          // radius enhancement factor
+  double r3;         // 3 / (4 pi rho): body radius = cbrt(r3 m)
+  int32_t *merged;   // per particle: lowest index of its composite (identity on entry)
+  double *ceps;      // per cluster: six dissipation sums (zeroed on entry)
+};
 hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
                        double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
                        double *e_rel_err, int32_t *n_steps, int32_t *steps_out, const int32_t *hc, int budget,
-                       int resume, hipStream_t s, hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join);
+                       int resume, hipStream_t s, hipStream_t s_big, hipEvent_t ev_fork, hipEvent_t ev_join,
+                       const HermColl *coll = nullptr);
+// merge.hip: the composites of a hard part with collisions become single
+// particles (see p3t_merge_bodies)
+hipError_t merge_bodies(p3t_ctx *c, int64_t n, const int32_t *merged, double *pos3, double *vel3, double *mass,
+                        double *dt_hard, int32_t *steps, int64_t *n_new);
+hipError_t sum_rows6(int64_t nc, const double *rows, double *out6, hipStream_t s);
 hipError_t aux_streams(p3t_ctx *c);
 // slow.hip: the direct terms of the parked members after their integration
 // the direct terms of S on stream s, into acc_d / pairs_d (pos3, vel3: the
@@ -363,6 +386,6 @@ hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns);
 hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                             double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
                             double *e_rel_err, int32_t *n_steps, const int64_t *nc_dev = nullptr,
-                            int64_t *nc_out = nullptr, int32_t *steps_out = nullptr);
+                            int64_t *nc_out = nullptr, int32_t *steps_out = nullptr, const HermColl *coll = nullptr);
 
 }  // namespace p3t

@@ -25,6 +25,15 @@ recompute_cutoffs the evaluation of step k then uses the radii computed from
 the state of evaluation k-1 (the hard part of step k still uses the radii of
 evaluation k-1, as the P3T split requires): the radii lag one step, because
 the slow members' new state is not known when the tree is built.
+
+collisions=(f, density) (serial path only) looks for perfect-accretion
+collisions in the hard part (p3t_hard_step_collide, Section 2.5.1); after a
+hard part with mergers the composites become single particles
+(p3t_merge_bodies), the particle count drops, and the cut-off and search
+radii of all particles are recomputed (step (9)) before the evaluation of
+step (7), which then serves both the second kick and the next step.
+`n_collisions` and `eps` (six sums, see p3t_hard_step_collide) accumulate
+over the run.
 """
 from __future__ import annotations
 
@@ -39,8 +48,15 @@ class P3TStepper:
     acceleration live in fixed buffers)."""
 
     def __init__(self, ctx: Context, pos, vel, mass, recompute_cutoffs: bool = False, graph: bool = False,
-                 fused_hard: bool = True, overlap: bool = False, slow_log2: int = 9, monitor_cutoffs: bool = False):
+                 fused_hard: bool = True, overlap: bool = False, slow_log2: int = 9, monitor_cutoffs: bool = False,
+                 collisions: tuple[float, float] | None = None):
+        if collisions is not None and (graph or overlap or not fused_hard):
+            raise ValueError("collisions run on the serial path (graph=False, overlap=False, fused_hard=True)")
         self.ctx = ctx
+        self.collisions = collisions
+        self.n_collisions = 0
+        self.eps = [0.0] * 6
+        self.merged = torch.empty(int(mass.shape[0]), dtype=torch.int32, device=pos.device)
         self.graph = graph
         self.fused_hard = fused_hard
         self.overlap = overlap
@@ -107,7 +123,16 @@ class P3TStepper:
                 c.compute_cutoffs(self.pos, self.vel, self.mass, out=(self.r_out_now, self.r_search_now, self.v_ran_now))
             c.kick(self.acc, self.vel, 0.5 * self.dt)
             return
-        if self.fused_hard:
+        if self.collisions is not None:
+            f, rho = self.collisions
+            self.n_clusters, nco, eps = c.hard_step_collide(self.pos, self.vel, self.mass, self.r_out, self.merged, f,
+                                                            rho, dt_hard=self.dt_hard, steps=self.steps)
+            self.n_collisions += nco
+            self.eps = [a + b for a, b in zip(self.eps, eps)]
+            if nco > 0:
+                self._merge()
+                self.r_out, self.r_search, self.v_ran = c.compute_cutoffs(self.pos, self.vel, self.mass)
+        elif self.fused_hard:
             self.n_clusters = c.hard_step(self.pos, self.vel, self.mass, self.r_out, dt_hard=self.dt_hard,
                                           steps=self.steps)
         else:
@@ -121,6 +146,19 @@ class P3TStepper:
             c.compute_cutoffs(self.pos, self.vel, self.mass, out=(self.r_out_now, self.r_search_now, self.v_ran_now))
         self._evaluate()
         c.kick(self.acc, self.vel, 0.5 * self.dt)
+
+    def _merge(self):
+        """Composites to single particles, arrays compacted in place; the
+        tensors become views of their first entries."""
+        nn = self.ctx.merge_bodies(self.merged, self.pos, self.vel, self.mass, dt_hard=self.dt_hard, steps=self.steps)
+        self.pos = self.pos.view(-1)[:3 * nn].view(3, nn)
+        self.vel = self.vel.view(-1)[:3 * nn].view(3, nn)
+        self.mass = self.mass[:nn]
+        self.dt_hard = self.dt_hard[:nn]
+        self.steps = self.steps[:nn]
+        self.merged = self.merged[:nn]
+        self.acc = torch.empty((3, nn), dtype=torch.float64, device=self.pos.device)
+        self.n = nn
 
     def interactions(self) -> int:
         s = self.last
