@@ -23,6 +23,10 @@
 // Then per node A_c = dL/dX_c / M_c, B_c = dL/dM_c - X_c . A_c, and per
 // particle the sums of A and B over its ancestors:
 //   dL/dx_k += m_k sum A,  dL/dm_k += sum B + x_k . sum A.
+// Mixed precision (precision = 1, as the forward force): the K = 1 terms
+// (far particles and cells) are evaluated in FP32 from offsets d formed in
+// FP64 and the cotangent rounded to FP32; every sum stays FP64.  The
+// changeover terms (near particles) are FP64 in both modes.
 #include "p3t_internal.h"
 
 namespace p3t {
@@ -76,6 +80,36 @@ __device__ __forceinline__ void adj_term(double dx, double dy, double dz, double
   s = phi * ld;
 }
 
+// the K = 1 term in FP32: g = m (phi lambda + (phi'/r)(lambda . d) d),
+// phi = G / r^3, phi'/r = -3 G / r^5
+__device__ __forceinline__ void adj_term_f32(double dx, double dy, double dz, double lx, double ly, double lz,
+                                             double mj, float G, double &gx, double &gy, double &gz, double &s) {
+  const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+  const float flx = (float)lx, fly = (float)ly, flz = (float)lz;
+  const float r2 = fx * fx + fy * fy + fz * fz;
+  const float rinv = rsqrtf(r2);
+  const float rinv2 = rinv * rinv;
+  const float phi = G * rinv * rinv2;
+  const float dphi_r = -3.0f * phi * rinv2;
+  const float ld = flx * fx + fly * fy + flz * fz;
+  const float c = dphi_r * ld;
+  const float m = (float)mj;
+  gx = (double)(m * (phi * flx + c * fx));
+  gy = (double)(m * (phi * fly + c * fy));
+  gz = (double)(m * (phi * flz + c * fz));
+  s = (double)(phi * ld);
+}
+
+// one K = 1 term in the path's precision
+template <bool MIXED>
+__device__ __forceinline__ void adj_far(double dx, double dy, double dz, double lx, double ly, double lz, double mj,
+                                        const AdjArgs &A, double &gx, double &gy, double &gz, double &s) {
+  if (MIXED)
+    adj_term_f32(dx, dy, dz, lx, ly, lz, mj, (float)A.G, gx, gy, gz, s);
+  else
+    adj_term(dx, dy, dz, lx, ly, lz, mj, -1.0, A, gx, gy, gz, s);
+}
+
 __global__ void k_adj_prep(AdjArgs A, const double *__restrict__ lam_v3) {
   const int64_t n = A.n;
   double *lam = const_cast<double *>(A.lam);
@@ -104,7 +138,7 @@ struct AdjLds {
 };
 
 // one tile of particles (near: K from the pair cut-off; far: K = 1)
-template <int IPL>
+template <int IPL, bool MIXED>
 __device__ __forceinline__ void adj_tile(const AdjArgs &A, AdjLds &S, const int32_t *L, int t0, int nt, bool near,
                                          int gcount, int lane, const int *ii, const double *xi, const double *yi,
                                          const double *zi, const double *lxi, const double *lyi, const double *lzi,
@@ -129,7 +163,10 @@ __device__ __forceinline__ void adj_tile(const AdjArgs &A, AdjLds &S, const int3
       const bool ok = ii[s] >= 0 && ii[s] != jid;
       const double dx = ok ? x - xi[s] : 1.0, dy = ok ? y - yi[s] : 0.0, dz = ok ? z - zi[s] : 0.0;
       double gx, gy, gz, sc;
-      adj_term(dx, dy, dz, lxi[s], lyi[s], lzi[s], m, near ? fmin(invi[s], inv) : -1.0, A, gx, gy, gz, sc);
+      if (near)
+        adj_term(dx, dy, dz, lxi[s], lyi[s], lzi[s], m, fmin(invi[s], inv), A, gx, gy, gz, sc);
+      else
+        adj_far<MIXED>(dx, dy, dz, lxi[s], lyi[s], lzi[s], m, A, gx, gy, gz, sc);
       if (ok) {
         ox[s] -= gx;
         oy[s] -= gy;
@@ -145,8 +182,11 @@ __device__ __forceinline__ void adj_tile(const AdjArgs &A, AdjLds &S, const int3
     for (int q = 0; q < gcount; ++q) {
       if (S.iid[q] == jid) continue;
       double gx, gy, gz, sc;
-      adj_term(x - S.ix[q], y - S.iy[q], z - S.iz[q], S.ilx[q], S.ily[q], S.ilz[q], m,
-               near ? fmin(S.iinv[q], inv) : -1.0, A, gx, gy, gz, sc);
+      if (near)
+        adj_term(x - S.ix[q], y - S.iy[q], z - S.iz[q], S.ilx[q], S.ily[q], S.ilz[q], m, fmin(S.iinv[q], inv), A, gx,
+                 gy, gz, sc);
+      else
+        adj_far<MIXED>(x - S.ix[q], y - S.iy[q], z - S.iz[q], S.ilx[q], S.ily[q], S.ilz[q], m, A, gx, gy, gz, sc);
       ax += gx;
       ay += gy;
       az += gz;
@@ -159,7 +199,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs &A, AdjLds &S, const int3
   }
 }
 
-template <int IPL>
+template <int IPL, bool MIXED>
 __device__ __forceinline__ void adj_group(const AdjArgs &A, AdjLds &S, int gi, int lane) {
   const int q = uniform_first(A.order ? A.order[gi] : gi);
   const GroupList Lh = A.gl[q];
@@ -197,11 +237,11 @@ __device__ __forceinline__ void adj_group(const AdjArgs &A, AdjLds &S, int gi, i
   }
   const int32_t *Ln = A.pool + off + n_cell;
   for (int t0 = 0; t0 < n_near; t0 += WAVE)
-    adj_tile<IPL>(A, S, Ln, t0, min(WAVE, n_near - t0), true, gcount, lane, ii, xi, yi, zi, lxi, lyi, lzi, invi, ox,
+    adj_tile<IPL, MIXED>(A, S, Ln, t0, min(WAVE, n_near - t0), true, gcount, lane, ii, xi, yi, zi, lxi, lyi, lzi, invi, ox,
                   oy, oz);
   const int32_t *Lf = Ln + n_near;
   for (int t0 = 0; t0 < n_far; t0 += WAVE)
-    adj_tile<IPL>(A, S, Lf, t0, min(WAVE, n_far - t0), false, gcount, lane, ii, xi, yi, zi, lxi, lyi, lzi, invi, ox,
+    adj_tile<IPL, MIXED>(A, S, Lf, t0, min(WAVE, n_far - t0), false, gcount, lane, ii, xi, yi, zi, lxi, lyi, lzi, invi, ox,
                   oy, oz);
   // monopole cells
   const int32_t *Lc = A.pool + off;
@@ -223,7 +263,7 @@ __device__ __forceinline__ void adj_group(const AdjArgs &A, AdjLds &S, int gi, i
 #pragma unroll
       for (int s = 0; s < IPL; ++s) {
         double gx, gy, gz, sc;
-        adj_term(x - xi[s], y - yi[s], z - zi[s], lxi[s], lyi[s], lzi[s], m, -1.0, A, gx, gy, gz, sc);
+        adj_far<MIXED>(x - xi[s], y - yi[s], z - zi[s], lxi[s], lyi[s], lzi[s], m, A, gx, gy, gz, sc);
         if (ii[s] >= 0) {
           ox[s] -= gx;
           oy[s] -= gy;
@@ -237,8 +277,8 @@ __device__ __forceinline__ void adj_group(const AdjArgs &A, AdjLds &S, int gi, i
       double ax = 0.0, ay = 0.0, az = 0.0, am = 0.0;
       for (int q2 = 0; q2 < gcount; ++q2) {
         double gx, gy, gz, sc;
-        adj_term(x - S.ix[q2], y - S.iy[q2], z - S.iz[q2], S.ilx[q2], S.ily[q2], S.ilz[q2], m, -1.0, A, gx, gy, gz,
-                 sc);
+        adj_far<MIXED>(x - S.ix[q2], y - S.iy[q2], z - S.iz[q2], S.ilx[q2], S.ily[q2], S.ilz[q2], m, A, gx, gy, gz,
+                       sc);
         ax += gx;
         ay += gy;
         az += gz;
@@ -261,6 +301,7 @@ __device__ __forceinline__ void adj_group(const AdjArgs &A, AdjLds &S, int gi, i
   }
 }
 
+template <bool MIXED>
 __global__ __launch_bounds__(WAVE) void k_adj_groups(AdjArgs A) {
   __shared__ AdjLds S;
   const int lane = threadIdx.x;
@@ -272,9 +313,9 @@ __global__ __launch_bounds__(WAVE) void k_adj_groups(AdjArgs A) {
     if (uniform_first64(A.gl[q].off) < 0) continue;
     const int cnt = uniform_first(A.wn[uniform_first(A.gl[q].node)].count);
     if (cnt > WAVE)
-      adj_group<2>(A, S, gi, lane);
+      adj_group<2, MIXED>(A, S, gi, lane);
     else
-      adj_group<1>(A, S, gi, lane);
+      adj_group<1, MIXED>(A, S, gi, lane);
   }
 }
 
@@ -358,7 +399,10 @@ hipError_t soft_kick_adjoint(p3t_ctx *c, double h, const double *lam_v3, double 
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 8, (2 * n + 255) / 256));
   hipLaunchKernelGGL(k_adj_prep, dim3(g), dim3(256), 0, s, A, lam_v3);
   hipLaunchKernelGGL(k_adj_reset, dim3(1), dim3(1), 0, s, A.queue);
-  hipLaunchKernelGGL(k_adj_groups, dim3(c->n_cu * 8), dim3(WAVE), 0, s, A);
+  if (c->P.precision == 1)
+    hipLaunchKernelGGL(k_adj_groups<true>, dim3(c->n_cu * 8), dim3(WAVE), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_adj_groups<false>, dim3(c->n_cu * 8), dim3(WAVE), 0, s, A);
   hipLaunchKernelGGL(k_adj_cell_coeffs, dim3(g), dim3(256), 0, s, A);
   hipLaunchKernelGGL(k_adj_final, dim3(g), dim3(256), 0, s, A, h, g_pos3, g_mass);
   return hipGetLastError();

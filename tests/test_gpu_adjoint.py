@@ -162,3 +162,36 @@ def test_leapfrog_full_size_checkpointed(gpu, orc):
     for a, b in zip(out[0], out[1]):
         assert torch.isfinite(a).all()
         assert (a - b).abs().max().item() <= 1e-10 * b.abs().max().item()
+
+
+def test_adjoint_mixed_precision(gpu, orc):
+    """precision = 1: the K = 1 terms of the adjoint in FP32 (as in the
+    forward force).  Against the FP64 adjoint of the same tree and lists:
+    within 1e-5 of the largest entry (FP32 rounding of each term, summed in
+    FP64); against central differences of the FP64 frozen force at 64
+    sampled particles of the 2^18-particle disk: within 1e-3."""
+    import time
+
+    d = diskgen.workload("disk256k_masslaw")
+    ctx64, g, _, _, _ = setup(gpu, orc, d, theta=0.5, multipole=1)
+    ctx32, _, _, _, _ = setup(gpu, orc, d, theta=0.5, multipole=1, precision=1)
+    lam = T(np.random.default_rng(6).normal(size=(3, d.n)))
+    out = {}
+    for name, ctx in (("fp64", ctx64), ("mixed", ctx32)):
+        ctx.soft_kick_adjoint(lam, 1.0)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            gx, gm = ctx.soft_kick_adjoint(lam, 1.0)
+        torch.cuda.synchronize()
+        out[name] = (gx, gm, 1e3 * (time.perf_counter() - t0) / 5)
+    gx64, gm64, t64 = out["fp64"]
+    gx32, gm32, t32 = out["mixed"]
+    ex = ((gx32 - gx64).abs().max() / gx64.abs().max()).item()
+    em = ((gm32 - gm64).abs().max() / gm64.abs().max()).item()
+    print(f"adjoint ms: fp64 {t64:.3f}, mixed {t32:.3f}; mixed vs fp64: x {ex:.2e}, m {em:.2e}")
+    assert ex < 1e-5 and em < 1e-5
+    idx = diskgen.sample_indices(d.n, 64, 55)
+    wx, wm = fd_check(ctx64, g, d.n, lam, idx, gx32, gm32, 1e-9)
+    print("mixed adjoint vs central differences of the FP64 force: x", wx, "m", wm)
+    assert wx < 1e-3 and wm < 1e-3
