@@ -103,6 +103,10 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   total += bytes(n_cap, sizeof(int32_t)) + bytes(n_cap, sizeof(uint8_t));  // cluster buckets, slow flags
   total += 3 * bytes(n_cap + 1, sizeof(int32_t));                             // hard-step labels, clusters
   total += 4096;
+  if (c->prep_state) {  // a cluster preparation may still use the old arena
+    HIP_OK(c, hipEventSynchronize(c->prep_ev[1]));
+    c->prep_state = 0;
+  }
   if (c->arena.base) {
     HIP_OK(c, hipFree(c->arena.base));
     c->arena.base = nullptr;
@@ -197,6 +201,67 @@ p3t_status sync_counters(p3t_ctx *c, DevCounters *h) {
   return P3T_OK;
 }
 
+// Makes the main stream wait for a pending cluster preparation (its scratch
+// is shared with every other call) and drops it.
+void prep_join(p3t_ctx *c) {
+  if (c->prep_state) {
+    hipStreamWaitEvent(c->stream, c->prep_ev[1], 0);
+    c->prep_state = 0;
+  }
+}
+
+// Enqueues on aux_stream the clusters of the next hard part from the pairs
+// of the evaluation just finished: neighbour CSR, labels, cluster CSR and
+// the bucket words (copied to pinned host memory).  It runs beside whatever
+// the caller enqueues next (kicks, radii); p3t_hard_step / p3t_hard_evaluate
+// take the result instead of computing it.
+p3t_status cluster_prep(p3t_ctx *c) {
+  const int64_t n = c->n;
+  if (n <= 0 || !c->force_valid) return P3T_OK;
+  HIP_OK(c, aux_streams(c));
+  if (!c->prep_ev[0])
+    for (auto &ev : c->prep_ev) HIP_OK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  if (!c->hc_pinned) HIP_OK(c, hipHostMalloc((void **)&c->hc_pinned, sizeof(int32_t) * HERM_BC_WORDS));
+  HIP_OK(c, hipEventRecord(c->prep_ev[0], c->stream));
+  HIP_OK(c, hipStreamWaitEvent(c->aux_stream, c->prep_ev[0], 0));
+  struct Swap {  // the cluster functions enqueue on c->stream
+    p3t_ctx *c;
+    hipStream_t main;
+    ~Swap() { c->stream = main; }
+  } swap{c, c->stream};
+  c->stream = c->aux_stream;
+  ev_record(c, 20);
+  HIP_OK(c, build_csr(c, n, c->n_pairs));
+  HIP_OK(c, labels_cc(c, n, c->hs_label));
+  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  HIP_OK(c, herm_bucket_enqueue(c, c->aux_stream, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, c->hc_pinned));
+  ev_record(c, 21);
+  HIP_OK(c, hipEventRecord(c->prep_ev[1], c->aux_stream));
+  c->prep_state = 1;
+  c->prep_n = n;
+  c->prep_timed = c->timing;
+  return P3T_OK;
+}
+
+// The prepared clusters for n particles, if any: the main stream waits for
+// them and hc receives the bucket words (returns false otherwise, after
+// dropping a preparation for another n).
+bool prep_take(p3t_ctx *c, int64_t n, int32_t *hc) {
+  if (c->prep_state != 1 || c->prep_n != n) {
+    prep_join(c);
+    return false;
+  }
+  hipStreamWaitEvent(c->stream, c->prep_ev[1], 0);
+  if (hipEventSynchronize(c->prep_ev[1]) != hipSuccess) {
+    c->prep_state = 0;
+    return false;
+  }
+  for (int k = 0; k < HERM_BC_WORDS; ++k) hc[k] = c->hc_pinned[k];
+  c->prep_state = 0;
+  c->stats.ms_clusters = (c->timing && c->prep_timed) ? ev_ms(c, 20, 21) : 0.0;
+  return true;
+}
+
 // atomic: a kernel on another stream may be setting bits at the same time
 __global__ void k_clear_bits(DevCounters *cnt, unsigned bits) { atomicAnd(&cnt->status, ~bits); }
 
@@ -222,7 +287,10 @@ void ev_record(p3t_ctx *c, int k) {
 }
 double ev_ms(p3t_ctx *c, int a, int b) {
   float ms = 0.0f;
-  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
+  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) {
+    (void)hipGetLastError();  // an event not recorded: no time, and no error left behind for the next check
+    return 0.0;
+  }
   return ms;
 }
 
@@ -347,18 +415,24 @@ p3t_status p3t_destroy(p3t_ctx *c) {
     if (b) hipFree(b);
   for (auto &e : c->ev)
     if (e) hipEventDestroy(e);
+  for (auto &e : c->prep_ev)
+    if (e) hipEventDestroy(e);
+  if (c->hc_pinned) hipHostFree(c->hc_pinned);
   delete c;
   return P3T_OK;
 }
 
 p3t_status p3t_set_stream(p3t_ctx *c, void *stream) {
   if (!c) return P3T_ERR_ARG;
+  // a pending cluster preparation stays valid: every later call makes the
+  // (new) stream wait for it before using its scratch
   c->stream = (hipStream_t)stream;
   return P3T_OK;
 }
 
 p3t_status p3t_set_params(p3t_ctx *c, const p3t_params *p) {
   if (!c || !p) return fail(c, P3T_ERR_ARG, "null argument");
+  prep_join(c);
   const char *why = check_params(*p);
   if (why) return fail(c, P3T_ERR_ARG, "%s", why);
   c->P = *p;
@@ -374,6 +448,7 @@ p3t_status p3t_get_params(p3t_ctx *c, p3t_params *p) {
 
 p3t_status p3t_reserve(p3t_ctx *c, int64_t n_max, int64_t nnz_max) {
   if (!c || n_max < 0 || nnz_max < 0) return fail(c, P3T_ERR_ARG, "reserve: bad argument");
+  prep_join(c);
   p3t_status st = ensure_n(c, n_max);
   if (st != P3T_OK) return st;
   if ((st = ensure_lists(c, n_max)) != P3T_OK) return st;
@@ -408,6 +483,7 @@ p3t_status p3t_compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const 
 p3t_status p3t_build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                           const double *r_out, const double *r_search) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "build_tree: n out of range");
   if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(r_search, n))
     return fail(c, P3T_ERR_ARG, "build_tree: null pointer");
@@ -478,6 +554,7 @@ bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st
 
 p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (!c->tree_valid) return fail(c, P3T_ERR_STATE, "compute_soft_force: no tree (call p3t_build_tree)");
   if (bad_ptr(acc3, c->n)) return fail(c, P3T_ERR_ARG, "compute_soft_force: null pointer");
   c->force_valid = false;
@@ -503,7 +580,7 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
     }
     if (num)
       return fail(c, P3T_ERR_NUMERIC, "compute_soft_force: device status 0x%x (coincident particles or NaN)", num);
-    return P3T_OK;
+    return st;  // the cluster preparation's status
   }
   return fail(c, P3T_ERR_CAPACITY, "compute_soft_force: scratch still too small after repeated growth");
 }
@@ -619,6 +696,7 @@ bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st
   c->host_status |= h.status;
   if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
   c->force_valid = true;
+  if (!*num) *st = cluster_prep(c);
   return false;
 }
 
@@ -636,6 +714,7 @@ p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double 
   if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n) || bad_ptr(r_search, n) ||
       bad_ptr(acc3, n))
     return fail(c, P3T_ERR_ARG, "evaluate: null pointer");
+  prep_join(c);
   p3t_status st = eval_enqueue(c, n, pos3, vel3, mass, r_out, r_search, acc3, 1);
   if (st != P3T_OK) return st;
   DevCounters h;
@@ -647,12 +726,13 @@ p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double 
     return p3t_compute_soft_force(c, acc3);
   }
   if (num) return fail(c, P3T_ERR_NUMERIC, "evaluate: device status 0x%x (coincident particles or NaN)", num);
-  return P3T_OK;
+  return st;
 }
 
 p3t_status p3t_neighbour_list(p3t_ctx *c, int64_t *row_ptr, int32_t *col, int64_t cap, int64_t *nnz_host,
                               int32_t *label) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (!c->force_valid) return fail(c, P3T_ERR_STATE, "neighbour_list: call p3t_compute_soft_force first");
   if (!nnz_host || !row_ptr || cap < 0) return fail(c, P3T_ERR_ARG, "neighbour_list: bad argument");
   const int64_t n = c->n, np = c->n_pairs;
@@ -681,6 +761,7 @@ p3t_status p3t_neighbour_list(p3t_ctx *c, int64_t *row_ptr, int32_t *col, int64_
 p3t_status p3t_clusters(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
                         int64_t *n_clusters_host) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (n < 0 || n > (int64_t(1) << 30) || !n_clusters_host) return fail(c, P3T_ERR_ARG, "clusters: bad argument");
   if (bad_ptr(label, n) || bad_ptr(cl_ptr, n) || bad_ptr(cl_members, n)) return fail(c, P3T_ERR_ARG, "clusters: null");
   *n_clusters_host = 0;
@@ -697,6 +778,7 @@ p3t_status p3t_hermite_cluster_step(p3t_ctx *c, int64_t n, int64_t n_clusters, c
                                     const int32_t *cl_members, double *pos3, double *vel3, const double *mass,
                                     const double *r_out, double *dt_hard, double *e_rel_err, int32_t *n_steps) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (n < 0 || n_clusters < 0 || n > (int64_t(1) << 30) || n_clusters > (int64_t(1) << 30))
     return fail(c, P3T_ERR_ARG, "hermite_cluster_step: size out of range");
   if (n_clusters == 0) return P3T_OK;
@@ -725,6 +807,7 @@ p3t_status p3t_hermite_collide(p3t_ctx *c, int64_t n, int64_t n_clusters, const 
                                int32_t *merged_into, double *eps6, double *e_rel_err, int32_t *n_steps,
                                int64_t *n_collisions_host) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (n_collisions_host) *n_collisions_host = 0;
   if (n < 0 || n_clusters < 0 || n > (int64_t(1) << 30) || n_clusters > (int64_t(1) << 30))
     return fail(c, P3T_ERR_ARG, "hermite_collide: size out of range");
@@ -776,6 +859,7 @@ p3t_status p3t_kick(p3t_ctx *c, int64_t n, double h, const double *acc3, double 
 p3t_status p3t_kepler_drift(p3t_ctx *c, int64_t n, double dt, double *pos3, double *vel3, const int32_t *list,
                             int64_t n_list, int32_t *iters, int64_t *n_unbound_host) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (n < 0 || n_list < 0 || bad_ptr(pos3, n) || bad_ptr(vel3, n) || !std::isfinite(dt))
     return fail(c, P3T_ERR_ARG, "kepler_drift: bad argument");
   if (n_list > 0 && !list && n_list != n) return fail(c, P3T_ERR_ARG, "kepler_drift: without a list n_list must equal n");
@@ -803,22 +887,31 @@ p3t_status p3t_hard_step(p3t_ctx *c, double *pos3, double *vel3, const double *m
   if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n) || bad_ptr(r_out, n))
     return fail(c, P3T_ERR_ARG, "hard_step: null pointer");
   if (n_clusters_host) *n_clusters_host = 0;
-  if (n == 0) return P3T_OK;
+  if (n == 0) {
+    prep_join(c);
+    return P3T_OK;
+  }
+  int32_t hc[HERM_BC_WORDS];
+  const bool prepared = prep_take(c, n, hc);
   ev_record(c, 9);
-  HIP_OK(c, build_csr(c, n, c->n_pairs));
-  HIP_OK(c, labels_cc(c, n, c->hs_label));
-  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  if (!prepared) {
+    HIP_OK(c, build_csr(c, n, c->n_pairs));
+    HIP_OK(c, labels_cc(c, n, c->hs_label));
+    HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  }
   ev_record(c, 19);
-  int64_t nc = 0;
-  hipError_t e = hermite_clusters(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr,
-                                  nullptr, c->node_scan + n, &nc, steps);
+  hipError_t e = prepared ? (hc[HERM_BC_BAD] ? hipErrorInvalidDevicePointer : hipSuccess)
+                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc);
   HIP_OK(c, e);
+  HIP_OK(c, aux_streams(c));
+  HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr, nullptr,
+                        steps, hc, 0, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
   ev_record(c, 10);
-  if (n_clusters_host) *n_clusters_host = nc;
+  if (n_clusters_host) *n_clusters_host = hc[HERM_BC_NC];
   if (c->timing) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->stats.ms_hermite = ev_ms(c, 9, 10);
-    c->stats.ms_clusters = ev_ms(c, 9, 19);
+    if (!prepared) c->stats.ms_clusters = ev_ms(c, 9, 19);
   }
   return P3T_OK;
 }
@@ -844,10 +937,14 @@ p3t_status p3t_hard_step_collide(p3t_ctx *c, double *pos3, double *vel3, const d
     HIP_OK(c, dev_alloc(c->coll_buf, 6 * c->n_cap + 6));
     c->coll_cap = 6 * c->n_cap + 6;
   }
+  int32_t hcw[HERM_BC_WORDS];
+  const bool prepared = prep_take(c, n, hcw);
   ev_record(c, 9);
-  HIP_OK(c, build_csr(c, n, c->n_pairs));
-  HIP_OK(c, labels_cc(c, n, c->hs_label));
-  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  if (!prepared) {
+    HIP_OK(c, build_csr(c, n, c->n_pairs));
+    HIP_OK(c, labels_cc(c, n, c->hs_label));
+    HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  }
   ev_record(c, 19);
   HIP_OK(c, iota_i32(merged_into, n, c->stream));
   HIP_OK(c, fill_f64(c->coll_buf, 0.0, 6 * n, c->stream));
@@ -856,11 +953,14 @@ p3t_status p3t_hard_step_collide(p3t_ctx *c, double *pos3, double *vel3, const d
   hc.r3 = 3.0 / (4.0 * M_PI * density);
   hc.merged = merged_into;
   hc.ceps = c->coll_buf;
-  int64_t nc = 0;
-  hipError_t e = hermite_clusters(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr,
-                                  nullptr, c->node_scan + n, &nc, steps, &hc);
+  hipError_t e = prepared ? (hcw[HERM_BC_BAD] ? hipErrorInvalidDevicePointer : hipSuccess)
+                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hcw);
   HIP_OK(c, e);
+  HIP_OK(c, aux_streams(c));
+  HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr, nullptr,
+                        steps, hcw, 0, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1], &hc));
   ev_record(c, 10);
+  const int64_t nc = hcw[HERM_BC_NC];
   if (n_clusters_host) *n_clusters_host = nc;
   HIP_OK(c, sum_rows6(nc, c->coll_buf, c->coll_buf + 6 * n, c->stream));
   double sums[6];
@@ -873,7 +973,7 @@ p3t_status p3t_hard_step_collide(p3t_ctx *c, double *pos3, double *vel3, const d
   if (n_collisions_host) *n_collisions_host = (int64_t)h.n_coll;
   if (c->timing) {
     c->stats.ms_hermite = ev_ms(c, 9, 10);
-    c->stats.ms_clusters = ev_ms(c, 9, 19);
+    if (!prepared) c->stats.ms_clusters = ev_ms(c, 9, 19);
   }
   return P3T_OK;
 }
@@ -881,6 +981,7 @@ p3t_status p3t_hard_step_collide(p3t_ctx *c, double *pos3, double *vel3, const d
 p3t_status p3t_merge_bodies(p3t_ctx *c, int64_t n, const int32_t *merged_into, double *pos3, double *vel3,
                             double *mass, double *dt_hard, int32_t *steps, int64_t *n_new_host) {
   if (!c || !n_new_host) return P3T_ERR_ARG;
+  prep_join(c);
   *n_new_host = n;
   if (n < 0 || n > (int64_t(1) << 30)) return fail(c, P3T_ERR_ARG, "merge_bodies: n out of range");
   if (n == 0) return P3T_OK;
@@ -970,14 +1071,18 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   if (n == 0) return p3t_evaluate(c, 0, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
   const bool split = slow_log2 > 0;
   p3t_status st;
+  int32_t hc[HERM_BC_WORDS];
+  const bool prepared = prep_take(c, n, hc);
   if (split && (st = ensure_overlap(c)) != P3T_OK) return st;
   ev_record(c, 9);
-  HIP_OK(c, build_csr(c, n, c->n_pairs));
-  HIP_OK(c, labels_cc(c, n, c->hs_label));
-  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  if (!prepared) {
+    HIP_OK(c, build_csr(c, n, c->n_pairs));
+    HIP_OK(c, labels_cc(c, n, c->hs_label));
+    HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
+  }
   ev_record(c, 19);
-  int32_t hc[HERM_BC_WORDS];
-  hipError_t e = herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc);
+  hipError_t e = prepared ? (hc[HERM_BC_BAD] ? hipErrorInvalidDevicePointer : hipSuccess)
+                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc);
   if (n_clusters_host) *n_clusters_host = hc[HERM_BC_NC];
   HIP_OK(c, e);
   HIP_OK(c, aux_streams(c));
@@ -990,7 +1095,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
     st = p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
     if (c->timing) {
       c->stats.ms_hermite = ev_ms(c, 9, 10);
-      c->stats.ms_clusters = ev_ms(c, 9, 19);
+      if (!prepared) c->stats.ms_clusters = ev_ms(c, 9, 19);
     }
     return st;
   }
@@ -1009,7 +1114,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
       ev_record(c, 10);
       HIP_OK(c, hipStreamSynchronize(c->stream));
       c->stats.ms_hermite = ev_ms(c, 9, 10);
-      c->stats.ms_clusters = ev_ms(c, 9, 19);
+      if (!prepared) c->stats.ms_clusters = ev_ms(c, 9, 19);
     }
     c->stats.n_slow = 0;
     return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
@@ -1049,7 +1154,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   if ((st = sync_counters(c, &h)) != P3T_OK) return st;
   if (c->timing) {
     c->stats.ms_hermite = ev_ms(c, 9, 10);
-    c->stats.ms_clusters = ev_ms(c, 9, 19);
+    if (!prepared) c->stats.ms_clusters = ev_ms(c, 9, 19);
     c->stats.ms_direct = ev_ms(c, 15, 16);
   }
   c->stats.n_slow = ns;
@@ -1074,12 +1179,13 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   c->host_status |= bits_d;
   if (num)
     return fail(c, P3T_ERR_NUMERIC, "hard_evaluate: device status 0x%x (coincident particles or NaN)", num);
-  return P3T_OK;
+  return st;
 }
 
 p3t_status p3t_total_energy(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                             double *energy_host) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (n < 0 || n > (int64_t(1) << 30) || !energy_host) return fail(c, P3T_ERR_ARG, "total_energy: bad argument");
   if (bad_ptr(pos3, n) || bad_ptr(vel3, n) || bad_ptr(mass, n)) return fail(c, P3T_ERR_ARG, "total_energy: null pointer");
   *energy_host = 0.0;
@@ -1095,6 +1201,7 @@ p3t_status p3t_total_energy(p3t_ctx *c, int64_t n, const double *pos3, const dou
 
 p3t_status p3t_soft_force_frozen(p3t_ctx *c, const double *pos3, const double *mass, double *acc3) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (!c->force_valid) return fail(c, P3T_ERR_STATE, "soft_force_frozen: no interaction lists (call p3t_compute_soft_force)");
   if (bad_ptr(pos3, c->n) || bad_ptr(mass, c->n) || bad_ptr(acc3, c->n))
     return fail(c, P3T_ERR_ARG, "soft_force_frozen: null pointer");
@@ -1109,6 +1216,7 @@ p3t_status p3t_soft_force_frozen(p3t_ctx *c, const double *pos3, const double *m
 
 p3t_status p3t_soft_kick_adjoint(p3t_ctx *c, double h, const double *lam_v3, double *g_pos3, double *g_mass) {
   if (!c) return P3T_ERR_ARG;
+  prep_join(c);
   if (!c->force_valid) return fail(c, P3T_ERR_STATE, "soft_kick_adjoint: no interaction lists (call p3t_compute_soft_force)");
   if (bad_ptr(lam_v3, c->n) || bad_ptr(g_pos3, c->n) || bad_ptr(g_mass, c->n))
     return fail(c, P3T_ERR_ARG, "soft_kick_adjoint: null pointer");
@@ -1133,6 +1241,7 @@ p3t_status p3t_set_timing(p3t_ctx *c, int32_t on) {
 
 p3t_status p3t_set_kernel_config(p3t_ctx *c, const p3t_kernel_config *k) {
   if (!c || !k) return P3T_ERR_ARG;
+  prep_join(c);
   const int u = k->force_unroll;
   if ((k->force_split != 0 && k->force_split != 1) || (u != 1 && u != 2 && u != 4 && u != 8) ||
       (k->force_persistent != 0 && k->force_persistent != 1) || k->waves_per_cu < 1 || k->waves_per_cu > 64 ||
@@ -1179,6 +1288,7 @@ p3t_status p3t_get_stats(p3t_ctx *c, p3t_stats *out) {
 
 p3t_status p3t_get_status(p3t_ctx *c, uint32_t *flags) {
   if (!c || !flags) return P3T_ERR_ARG;
+  prep_join(c);
   unsigned bits = 0;
   p3t_status st = harvest_status(c, &bits);
   if (st != P3T_OK) return st;

@@ -1560,7 +1560,17 @@ static void host_changeover_coeffs(double g, HermArgs &A) {
 // BC_WORDS words (the park counts are zero).
 hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                        const int64_t *nc_dev, int32_t *hc) {
-  hipStream_t s = c->stream;
+  hipError_t e = herm_bucket_enqueue(c, c->stream, n, nc, cl_ptr, cl_members, nc_dev, hc);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  if (hc[BC_BAD]) return hipErrorInvalidDevicePointer;  // malformed cluster arrays
+  return hipSuccess;
+}
+
+// The bucket kernel and the copy of the bucket words to hc (host memory) on
+// stream s, without waiting.
+hipError_t herm_bucket_enqueue(p3t_ctx *c, hipStream_t s, int64_t n, int64_t nc, const int32_t *cl_ptr,
+                               const int32_t *cl_members, const int64_t *nc_dev, int32_t *hc) {
   hipError_t e;
   if ((e = fill_i32(c->herm_bcount, 0, BC_WORDS, s)) != hipSuccess) return e;
   BucketArgs B;
@@ -1577,11 +1587,7 @@ hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr,
   B.cnt = c->cnt;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
   hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, B);
-  if ((e = hipMemcpyAsync(hc, c->herm_bcount, sizeof(int32_t) * BC_WORDS, hipMemcpyDeviceToHost, s)) != hipSuccess)
-    return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  if (hc[BC_BAD]) return hipErrorInvalidDevicePointer;  // malformed cluster arrays
-  return hipSuccess;
+  return hipMemcpyAsync(hc, c->herm_bcount, sizeof(int32_t) * BC_WORDS, hipMemcpyDeviceToHost, s);
 }
 
 __global__ void k_huge_flag(DevCounters *cnt, unsigned bits) { set_flag(cnt, bits); }

@@ -186,6 +186,15 @@ struct p3t_ctx {
   int2 *pairs = nullptr;            // neighbour pairs (i_orig, j_orig)
   int2 *cands = nullptr;            // neighbour candidates (sorted indices)
   int64_t cand_cap = 0;
+  // The clusters of the next hard part (CSR, labels, cluster CSR, buckets)
+  // are prepared on aux_stream right after an evaluation, beside the kicks;
+  // prep_state 1 = enqueued for prep_n particles.  Every other call first
+  // makes the main stream wait for it (the scratch is shared) and drops it.
+  int prep_state = 0;
+  int prep_timed = 0;              // the preparation recorded its timing events
+  int64_t prep_n = 0;
+  hipEvent_t prep_ev[2] = {};      // fork (main stream), done (aux stream)
+  int32_t *hc_pinned = nullptr;    // bucket words, pinned host memory
   // collisions: per-cluster dissipations (6 per cluster) and their sums (6);
   // merging: staging rows (9 n) and int scratch (2 n + 1)
   double *coll_buf = nullptr;
@@ -363,6 +372,8 @@ struct HermColl {
   int32_t *merged;   // per particle: lowest index of its composite (identity on entry)
   double *ceps;      // per cluster: six dissipation sums (zeroed on entry)
 };
+hipError_t herm_bucket_enqueue(p3t_ctx *c, hipStream_t s, int64_t n, int64_t nc, const int32_t *cl_ptr,
+                               const int32_t *cl_members, const int64_t *nc_dev, int32_t *hc);
 hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
                        double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
                        double *e_rel_err, int32_t *n_steps, int32_t *steps_out, const int32_t *hc, int budget,
