@@ -422,7 +422,9 @@ typedef struct {
 } p3t_kernel_config;
 p3t_status p3t_set_kernel_config(p3t_ctx *ctx, const p3t_kernel_config *cfg_host);
 p3t_status p3t_get_kernel_config(p3t_ctx *ctx, p3t_kernel_config *cfg_host);
-/* Counters of the last evaluation.  Synchronises. */
+/* Counters and phase times of the last evaluation, as the host read them
+ * when that call finished; does not wait for the device.  The time of a
+ * p3t_compute_cutoffs still running is reported by a later call. */
 p3t_status p3t_get_stats(p3t_ctx *ctx, p3t_stats *out_host);
 /* Read and clear the device status word.  Synchronises. */
 p3t_status p3t_get_status(p3t_ctx *ctx, uint32_t *flags_host);

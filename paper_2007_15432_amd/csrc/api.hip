@@ -97,7 +97,8 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   total += 2 * bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));  // order, keys
   total += bytes(n_cap, sizeof(int32_t)) + bytes(n_cap + 1, sizeof(int64_t));       // row_cnt, csr_ptr
   total += bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));      // uf, cl keys
-  total += bytes(cut_part_need(n_cap), sizeof(double));
+  total += bytes(cut_part_need(n_cap), sizeof(double)) + bytes(n_cap, sizeof(int32_t));  // cut-off bins
+  total += bytes(n_cap + 4, sizeof(uint8_t));                                                // close flags
   total += 2 * bytes(3 * n_cap, sizeof(double));
   total += bytes(HERM_BC_WORDS, sizeof(int32_t)) + bytes(HERM_N_BUCKETS * n_cap, sizeof(int32_t));  // buckets
   total += bytes(n_cap, sizeof(int32_t)) + bytes(n_cap, sizeof(uint8_t));  // cluster buckets, slow flags
@@ -147,6 +148,8 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   c->cl_keys = A.take<uint64_t>(n_cap);
   c->cl_keys_alt = A.take<uint64_t>(n_cap);
   c->cut_part = A.take<double>(cut_part_need(n_cap));
+  c->cut_bin = A.take<int32_t>(n_cap);
+  c->close_flag = A.take<uint8_t>(n_cap + 4);
   c->tmp_d = A.take<double>(3 * n_cap);
   c->acc_s = A.take<double>(3 * n_cap);
   c->herm_bcount = A.take<int32_t>(HERM_BC_WORDS);
@@ -160,6 +163,7 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   HIP_OK(c, hipMemsetAsync(c->cnt, 0, sizeof(DevCounters), c->stream));
   c->n_cap = n_cap;
   c->tree_valid = c->force_valid = false;
+  c->park_flags_valid = 0;
   return P3T_OK;
 }
 
@@ -210,14 +214,36 @@ void prep_join(p3t_ctx *c) {
   }
 }
 
-// Enqueues on aux_stream the clusters of the next hard part from the pairs
-// of the evaluation just finished: neighbour CSR, labels, cluster CSR and
-// the bucket words (copied to pinned host memory).  It runs beside whatever
-// the caller enqueues next (kicks, radii); p3t_hard_step / p3t_hard_evaluate
-// take the result instead of computing it.
-p3t_status cluster_prep(p3t_ctx *c) {
+// Waits (host) for a pending cluster preparation and drops it: before
+// scratch it reads is grown or freed.
+void prep_drop_sync(p3t_ctx *c) {
+  if (c->prep_state) {
+    (void)hipEventSynchronize(c->prep_ev[1]);
+    c->prep_state = 0;
+  }
+}
+
+// The member flags of the close-first dispatch order (close pairs of the
+// last evaluation, members parked in the last hard part).
+CloseSrc close_src(p3t_ctx *c) {
+  CloseSrc f;
+  f.a = c->close_flag;
+  f.b = c->park_flags_valid ? c->slow_flag : nullptr;
+  return f;
+}
+
+// Enqueues on aux_stream, right behind the evaluation just enqueued on the
+// main stream and before its counters are read, the clusters of the next
+// hard part: labels straight from the pair list (its length read on the
+// device), the cluster CSR and the bucket words (copied to pinned host
+// memory).  It runs while the host reads the counters and enqueues the
+// kicks and radii that follow; eval_finish keeps it (prep_confirm) when the
+// evaluation needs no retry.  p3t_hard_step / p3t_hard_evaluate take the
+// result instead of computing it.
+p3t_status prep_enqueue(p3t_ctx *c) {
   const int64_t n = c->n;
-  if (n <= 0 || !c->force_valid) return P3T_OK;
+  if (c->prep_state) prep_join(c);
+  if (n <= 0 || !c->pairs) return P3T_OK;
   HIP_OK(c, aux_streams(c));
   if (!c->prep_ev[0])
     for (auto &ev : c->prep_ev) HIP_OK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -231,28 +257,34 @@ p3t_status cluster_prep(p3t_ctx *c) {
   } swap{c, c->stream};
   c->stream = c->aux_stream;
   ev_record(c, 20);
-  HIP_OK(c, build_csr(c, n, c->n_pairs));
-  HIP_OK(c, labels_cc(c, n, c->hs_label));
-  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem));
-  HIP_OK(c, herm_bucket_enqueue(c, c->aux_stream, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, c->hc_pinned));
+  HIP_OK(c, labels_pairs(c, n, c->hs_label));
+  HIP_OK(c, clusters_csr_dev(c, n, c->hs_label, c->hs_cl_ptr, c->hs_cl_mem, true));
+  // clusters with a close pair at this evaluation, or with a member parked
+  // in the last hard part, are dispatched first
+  const CloseSrc close = close_src(c);
+  // the work counters of the hard part just finished are read after this
+  // is enqueued: prep_take zeroes them instead
+  HIP_OK(c, herm_bucket_enqueue(c, c->aux_stream, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, c->hc_pinned,
+                                false, close));
   ev_record(c, 21);
   HIP_OK(c, hipEventRecord(c->prep_ev[1], c->aux_stream));
-  c->prep_state = 1;
+  c->prep_state = 2;
   c->prep_n = n;
   c->prep_timed = c->timing;
   return P3T_OK;
 }
 
 // The prepared clusters for n particles, if any: the main stream waits for
-// them and hc receives the bucket words (returns false otherwise, after
-// dropping a preparation for another n).
+// them, the work counters of the new hard part are zeroed and hc receives
+// the bucket words (returns false otherwise, after dropping a preparation
+// that does not apply).
 bool prep_take(p3t_ctx *c, int64_t n, int32_t *hc) {
   if (c->prep_state != 1 || c->prep_n != n) {
     prep_join(c);
     return false;
   }
   hipStreamWaitEvent(c->stream, c->prep_ev[1], 0);
-  if (hipEventSynchronize(c->prep_ev[1]) != hipSuccess) {
+  if (hipEventSynchronize(c->prep_ev[1]) != hipSuccess || herm_reset_work(c, c->stream) != hipSuccess) {
     c->prep_state = 0;
     return false;
   }
@@ -292,6 +324,18 @@ double ev_ms(p3t_ctx *c, int a, int b) {
     return 0.0;
   }
   return ms;
+}
+
+// The cut-off radii's event time, once their end event has completed (a
+// later call picks it up otherwise).
+void cut_timing_read(p3t_ctx *c) {
+  if (!c->cut_timing_pending || !c->ev[1]) return;
+  if (hipEventQuery(c->ev[1]) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  c->stats.ms_cutoffs = ev_ms(c, 0, 1);
+  c->cut_timing_pending = 0;
 }
 
 bool bad_ptr(const void *p, int64_t n) { return n > 0 && p == nullptr; }
@@ -473,10 +517,9 @@ p3t_status p3t_compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const 
   ev_record(c, 0);
   HIP_OK(c, compute_cutoffs(c, n, pos3, vel3, mass, r_out, r_search, v_ran));
   ev_record(c, 1);
-  if (c->timing) {
-    HIP_OK(c, hipStreamSynchronize(c->stream));
-    c->stats.ms_cutoffs = ev_ms(c, 0, 1);
-  }
+  // read once the radii are done (cut_timing_read), not waited for here:
+  // the host goes on to enqueue what follows
+  if (c->timing) c->cut_timing_pending = 1;
   return P3T_OK;
 }
 
@@ -571,6 +614,7 @@ p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
     HIP_OK(c, soft_force(c, c->n_groups, acc3));
     ev_record(c, 6);
     c->graphed = 0;
+    if ((st = prep_enqueue(c)) != P3T_OK) return st;
     DevCounters h;
     if ((st = sync_counters(c, &h)) != P3T_OK) return st;
     unsigned num = 0;
@@ -656,6 +700,7 @@ bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st
   *st = P3T_OK;
   *num = 0;
   if (h.status & RETRY_BITS) {
+    prep_drop_sync(c);  // it read a pair list that is redone
     *st = grow_for_retry(c, h);
     return true;
   }
@@ -669,6 +714,7 @@ bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st
   c->stats.n_cell = (int64_t)h.n_cell;
   c->stats.n_pairs = c->n_pairs;
   c->stats.list_entries = (int64_t)h.pool_cursor;
+  cut_timing_read(c);
   if (c->timing) {
     if (c->graphed) {
       c->stats.ms_tree = c->stats.ms_walk = c->stats.ms_sort = 0.0;
@@ -696,7 +742,12 @@ bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st
   c->host_status |= h.status;
   if (h.status) hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(1), 0, c->stream, c->cnt, h.status);
   c->force_valid = true;
-  if (!*num) *st = cluster_prep(c);
+  if (c->prep_state == 2) {
+    if (*num)
+      prep_join(c);
+    else
+      c->prep_state = 1;  // the preparation enqueued behind this evaluation holds
+  }
   return false;
 }
 
@@ -717,6 +768,7 @@ p3t_status p3t_evaluate(p3t_ctx *c, int64_t n, const double *pos3, const double 
   prep_join(c);
   p3t_status st = eval_enqueue(c, n, pos3, vel3, mass, r_out, r_search, acc3, 1);
   if (st != P3T_OK) return st;
+  if ((st = prep_enqueue(c)) != P3T_OK) return st;
   DevCounters h;
   if ((st = sync_counters(c, &h)) != P3T_OK) return st;
   unsigned num = 0;
@@ -901,7 +953,7 @@ p3t_status p3t_hard_step(p3t_ctx *c, double *pos3, double *vel3, const double *m
   }
   ev_record(c, 19);
   hipError_t e = prepared ? (hc[HERM_BC_BAD] ? hipErrorInvalidDevicePointer : hipSuccess)
-                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc);
+                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc, close_src(c));
   HIP_OK(c, e);
   HIP_OK(c, aux_streams(c));
   HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr, nullptr,
@@ -954,7 +1006,7 @@ p3t_status p3t_hard_step_collide(p3t_ctx *c, double *pos3, double *vel3, const d
   hc.merged = merged_into;
   hc.ceps = c->coll_buf;
   hipError_t e = prepared ? (hcw[HERM_BC_BAD] ? hipErrorInvalidDevicePointer : hipSuccess)
-                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hcw);
+                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hcw, close_src(c));
   HIP_OK(c, e);
   HIP_OK(c, aux_streams(c));
   HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out, dt_hard, nullptr, nullptr,
@@ -1082,12 +1134,15 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   }
   ev_record(c, 19);
   hipError_t e = prepared ? (hc[HERM_BC_BAD] ? hipErrorInvalidDevicePointer : hipSuccess)
-                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc);
+                          : herm_bucket(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, c->node_scan + n, hc, close_src(c));
   if (n_clusters_host) *n_clusters_host = hc[HERM_BC_NC];
   HIP_OK(c, e);
   HIP_OK(c, aux_streams(c));
   const int budget = split ? (slow_log2 < 30 ? 1 << slow_log2 : 1 << 30) : 0;
-  if (split) HIP_OK(c, hipMemsetAsync(c->slow_flag, 0, (size_t)n, c->stream));
+  if (split) {
+    HIP_OK(c, hipMemsetAsync(c->slow_flag, 0, (size_t)n, c->stream));
+    c->park_flags_valid = 1;
+  }
   HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
                         steps, hc, budget, 0, c->stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
   ev_record(c, 10);
@@ -1148,6 +1203,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   }
   if (ns > 0) HIP_OK(c, slow_merge(c, pos3, vel3, acc3, ns));
   ev_record(c, 16);
+  if ((st = prep_enqueue(c)) != P3T_OK) return st;
   // the one synchronisation of the evaluation: its counters, the direct
   // terms' pair count and the second stream's status bits
   DevCounters h;
@@ -1165,6 +1221,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   if ((h.status & RETRY_BITS) || direct_overflow) {
     // a buffer was too small: grow it, and evaluate again at the final
     // state (an ordinary evaluation, every term from the tree)
+    prep_drop_sync(c);  // it read an incomplete pair list
     c->host_status |= bits_d;
     if (direct_overflow) {
       const int64_t need = (int64_t)h.n_pairs_d;
@@ -1281,7 +1338,7 @@ p3t_status p3t_get_kernel_config(p3t_ctx *c, p3t_kernel_config *k) {
 
 p3t_status p3t_get_stats(p3t_ctx *c, p3t_stats *out) {
   if (!c || !out) return P3T_ERR_ARG;
-  HIP_OK(c, hipStreamSynchronize(c->stream));
+  cut_timing_read(c);
   *out = c->stats;
   return P3T_OK;
 }

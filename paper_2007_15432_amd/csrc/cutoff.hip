@@ -376,7 +376,7 @@ hipError_t cutoffs_run(const p3t_params &P, int64_t n, const double *pos3, const
 
 hipError_t compute_cutoffs(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                            double *r_out, double *r_search, double *v_ran) {
-  return cutoffs_run(c->P, n, pos3, vel3, mass, r_out, r_search, v_ran, c->tmp_d, c->row_cnt, c->cut_part, c->stream);
+  return cutoffs_run(c->P, n, pos3, vel3, mass, r_out, r_search, v_ran, c->tmp_d, c->cut_bin, c->cut_part, c->stream);
 }
 
 int64_t cut_part_need(int64_t n_cap) {

@@ -133,6 +133,7 @@ __global__ __launch_bounds__(WAVE) void k_force(ForceArgs A) {
             if (pair_is_neighbour(A.sx[i], A.sy[i], A.sz[i], A.svx[i], A.svy[i], A.svz[i], A.sm[i], A.sro[i],
                                   A.srs[i], A.sx[j], A.sy[j], A.sz[j], A.svx[j], A.svy[j], A.svz[j], A.sm[j],
                                   A.sro[j], A.srs[j], A.G, A.rsch2, A.rsch3, A.dt)) {
+              mark_close_pair(A, i, j);
               const unsigned long long p = atomicAdd(&A.cnt->n_pairs, 1ull);
               if ((int64_t)p < A.pair_cap)
                 A.pairs[p] = make_int2(A.sid[i], A.sid[j]);
@@ -398,6 +399,14 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3, bool froze
   A.cand_cap = c->cand_cap;
   A.slow = c->slow_active ? c->slow_flag : nullptr;
   if (frozen) A.pair_cap = A.cand_cap = 0;
+  // the close pairs of this evaluation (a kernel clears the flags: the
+  // evaluation may be captured into a graph)
+  A.close = frozen ? nullptr : c->close_flag;
+  A.close_k = P.G * P.dt_soft * P.dt_soft / (CLOSE_RATIO * CLOSE_RATIO);
+  if (A.close) {
+    const hipError_t e = fill_i32(reinterpret_cast<int32_t *>(c->close_flag), 0, (c->n + 3) / 4, c->stream);
+    if (e != hipSuccess) return e;
+  }
   A.acc = acc3;
   A.n = c->n;
   A.G = P.G;

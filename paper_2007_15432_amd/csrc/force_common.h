@@ -26,7 +26,22 @@ struct ForceArgs {
   int persistent;
   int ngroups_bound;          // groups processed at most (the host's bound; the count itself is on the device)
   unsigned long long *queue;  // persistent-queue head of this launch
+  uint8_t *close;             // caller's order: set for both members of a close neighbour pair (nullable)
+  double close_k;             // G dt_soft^2 / CLOSE_RATIO^2
 };
+
+// Flags both members of the neighbour pair (i, j) (sorted indices) when
+// its free-fall time scale is short against the soft step: (m_i + m_j)
+// close_k >= r^3.  Steers only the dispatch order of the next hard part.
+__device__ __forceinline__ void mark_close_pair(const ForceArgs &A, int i, int j) {
+  if (!A.close) return;
+  const double dx = A.sx[j] - A.sx[i], dy = A.sy[j] - A.sy[i], dz = A.sz[j] - A.sz[i];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  if ((A.sm[i] + A.sm[j]) * A.close_k >= r2 * sqrt(r2)) {
+    A.close[A.sid[i]] = 1;
+    A.close[A.sid[j]] = 1;
+  }
+}
 
 // the split form (one kernel per interaction class), force_split.hip
 hipError_t soft_force_split(p3t_ctx *c, const ForceArgs &A, unsigned nonpersistent_grid, double *acc3);

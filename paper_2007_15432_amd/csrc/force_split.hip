@@ -581,6 +581,7 @@ __global__ void k_cand_test(ForceArgs A) {
     const unsigned long long o0 = (unsigned long long)uniform_lane64(
         (long long)atomicAdd(&A.cnt->n_pairs, lane == leader ? (unsigned long long)__popcll(bal) : 0ull), leader);
     if (nb) {
+      mark_close_pair(A, i, j);
       const unsigned long long q = o0 + popc_below(bal);
       if ((int64_t)q < A.pair_cap)
         A.pairs[q] = make_int2(A.sid[i], A.sid[j]);

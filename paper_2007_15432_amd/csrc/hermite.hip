@@ -37,12 +37,17 @@ constexpr int N_BUCKETS = HERM_N_BUCKETS;  // SEG 1..64 (7), 256-thread MPT 1, 2
 constexpr int BC_NC = HERM_BC_NC, BC_BAD = HERM_BC_BAD, BC_WORDS = HERM_BC_WORDS;
 constexpr int PK_MEM = HERM_BC_PARKED - HERM_BC_PARK0;  // parked-member word, relative to the park counts
 constexpr int WAVE_BK0 = 3;  // buckets 3..6 (5..64 members): one wavefront per cluster (wave_body)
+// Regions of the fused launch: buckets 0..6, then the clusters of buckets
+// 1..3 that hold a close pair (regions 7..9); dispatched from the last
+// region to the first.
+constexpr int FUSED_REGIONS = 10;
 
 struct HermArgs {
   const int32_t *cl_ptr, *members, *blists;
   int64_t nc;                      // clusters (stride of the bucket lists)
-  int bcount[N_BUCKETS];           // clusters per bucket
-  int boff[N_BUCKETS + 1];         // first block of each bucket in the fused launch
+  int bcount[N_BUCKETS];           // clusters per bucket (the close ones of buckets 1..3 not counted)
+  int ccount[4];                   // [1..3]: clusters of buckets 1..3 with a close pair
+  int boff[N_BUCKETS + 1];         // first block of each region of the fused launch (FUSED_REGIONS + 1 used)
   double *pos, *vel;
   const double *mass, *ro;
   double *dt_hard, *e_rel;
@@ -1391,15 +1396,16 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   // bucket of this workgroup (boff is non-decreasing).  Only constant
   // indices into the argument struct: a run-time index would make the
   // compiler copy the whole struct to per-lane scratch memory.
-  int bk = 0, first = 0;
+  int rg = 0, first = 0;
 #pragma unroll
-  for (int q = 1; q < 8; ++q)
+  for (int q = 1; q < FUSED_REGIONS; ++q)
     if (A.boff[q] <= blk) {
-      bk = q;
+      rg = q;
       first = A.boff[q];
     }
   const int local = blk - first;
-  const int32_t *blist = A.blists + (int64_t)bk * A.nc;
+  const bool close = rg >= 7;  // the clusters of bucket rg - 6 with a close pair
+  const int bk = close ? rg - 6 : rg;
   const int w = threadIdx.x / WAVE;
   const int wbase = w * WAVE;
   const int ci0 = (local * (BIG_T / WAVE) + w) * clusters_per_wave(bk, COLL);
@@ -1407,6 +1413,11 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
 #pragma unroll
   for (int q = 0; q < 7; ++q)
     if (q == bk) count = A.bcount[q];  // constant indices only (see above)
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (close && q == bk) count = A.ccount[q];
+  // the close clusters sit at the end of their bucket's list
+  const int32_t *blist = A.blists + (int64_t)bk * A.nc + (close ? A.nc - count : 0);
   if (bk >= (COLL ? 1 : WAVE_BK0))
     wave_body<MODE, COLL>(A, blist, count, ci0, L, wbase, bk);
   else
@@ -1476,59 +1487,84 @@ struct BucketArgs {
   int cap;  // clusters above this many members take the percolated-cluster path
   const int32_t *cl_ptr, *members;
   int32_t *bcount, *blists;
-  int32_t *cl_bk;  // bucket chosen per cluster (between the sweeps)
+  int32_t *cl_bk;  // category chosen per cluster (between the sweeps)
   DevCounters *cnt;
+  int reset_work;  // zero the Hermite work counters
+  CloseSrc close;  // member flags that make a cluster of buckets 1..3 close
 };
 
+__device__ bool cluster_close(int a, int b, const BucketArgs &B) {
+  for (int p = a; p < b; ++p) {
+    const int g = B.members[p];
+    if ((B.close.a && B.close.a[g]) || (B.close.b && B.close.b[g])) return true;
+  }
+  return false;
+}
+
+// Categories: the buckets 0..10, and N_BUCKETS + k - 1 for the clusters of
+// bucket k = 1..3 with a close pair.  The close ones are written from the
+// end of their bucket's list backwards (count in bcount[HERM_BC_CLOSE0 + k
+// - 1]), the others from its start.
+constexpr int N_CATS = N_BUCKETS + 3;
+
 __global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
-  __shared__ int cnt[N_BUCKETS], base[N_BUCKETS];
+  __shared__ int cnt[N_CATS], base[N_CATS];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1);
   const int64_t nc = B.nc_dev ? *B.nc_dev : B.nc_host;  // clusters (at most stride)
   int32_t *bcount = B.bcount;
   if (blockIdx.x == 0 && tid == 0) {
     bcount[BC_NC] = (int32_t)nc;
-    B.cnt->n_heval = 0;  // the work counters of this hard part
-    B.cnt->n_hpair = 0;
-    B.cnt->n_coll = 0;
+    if (B.reset_work) {  // the work counters of this hard part
+      B.cnt->n_heval = 0;
+      B.cnt->n_hpair = 0;
+      B.cnt->n_coll = 0;
+    }
   }
   const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
-  if (tid < N_BUCKETS) cnt[tid] = 0;
+  if (tid < N_CATS) cnt[tid] = 0;
   __syncthreads();
   for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {
     const int64_t c = b0 + tid;
-    const int bk = c < c1 ? cluster_bucket(c, B.n, B.cap, B.cl_ptr, B.members, bcount) : -1;
-    if (c < c1) B.cl_bk[c] = bk;
-    for (int q = 0; q < N_BUCKETS; ++q) {
-      const unsigned long long mask = __ballot(bk == q);
+    int cat = c < c1 ? cluster_bucket(c, B.n, B.cap, B.cl_ptr, B.members, bcount) : -1;
+    if (cat >= 1 && cat <= 3 && (B.close.a || B.close.b) && cluster_close(B.cl_ptr[c], B.cl_ptr[c + 1], B))
+      cat += N_BUCKETS - 1;
+    if (c < c1) B.cl_bk[c] = cat;
+    for (int q = 0; q < N_CATS; ++q) {
+      const unsigned long long mask = __ballot(cat == q);
       if (mask != 0ull && lane == __ffsll((long long)mask) - 1) atomicAdd(&cnt[q], (int)__popcll(mask));
     }
   }
   __syncthreads();
-  if (tid < N_BUCKETS) {
-    base[tid] = cnt[tid] > 0 ? atomicAdd(&bcount[tid], cnt[tid]) : 0;
+  if (tid < N_CATS) {
+    int32_t *word = tid < N_BUCKETS ? &bcount[tid] : &bcount[HERM_BC_CLOSE0 + tid - N_BUCKETS];
+    base[tid] = cnt[tid] > 0 ? atomicAdd(word, cnt[tid]) : 0;
     cnt[tid] = 0;
   }
   __syncthreads();
-  __shared__ int wofs[BIG_T / WAVE][N_BUCKETS];
+  __shared__ int wofs[BIG_T / WAVE][N_CATS];
   const int w = tid / WAVE;
   for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {  // uniform over the workgroup
     const int64_t c = b0 + tid;
-    const int bk = c < c1 ? B.cl_bk[c] : -1;  // as decided above
+    const int cat = c < c1 ? B.cl_bk[c] : -1;  // as decided above
     unsigned long long mine = 0ull;
-    for (int q = 0; q < N_BUCKETS; ++q) {
-      const unsigned long long mask = __ballot(bk == q);
+    for (int q = 0; q < N_CATS; ++q) {
+      const unsigned long long mask = __ballot(cat == q);
       if (lane == 0) wofs[w][q] = (int)__popcll(mask);
-      if (q == bk) mine = mask;
+      if (q == cat) mine = mask;
     }
     __syncthreads();
-    if (bk >= 0) {
+    if (cat >= 0) {
       int off = 0;
-      for (int u = 0; u < w; ++u) off += wofs[u][bk];  // wavefronts take their slots in order
-      B.blists[(int64_t)bk * B.stride + base[bk] + cnt[bk] + off + popc_below(mine)] = (int32_t)c;
+      for (int u = 0; u < w; ++u) off += wofs[u][cat];  // wavefronts take their slots in order
+      const int64_t k = base[cat] + cnt[cat] + off + popc_below(mine);
+      if (cat < N_BUCKETS)
+        B.blists[(int64_t)cat * B.stride + k] = (int32_t)c;
+      else
+        B.blists[(int64_t)(cat - N_BUCKETS + 1) * B.stride + B.stride - 1 - k] = (int32_t)c;
     }
     __syncthreads();
-    if (tid < N_BUCKETS) {
+    if (tid < N_CATS) {
       int tot = 0;
       for (int u = 0; u < BIG_T / WAVE; ++u) tot += wofs[u][tid];
       cnt[tid] += tot;
@@ -1559,8 +1595,8 @@ static void host_changeover_coeffs(double g, HermArgs &A) {
 // Bucket lists and counts (one host synchronisation); hc receives the
 // BC_WORDS words (the park counts are zero).
 hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
-                       const int64_t *nc_dev, int32_t *hc) {
-  hipError_t e = herm_bucket_enqueue(c, c->stream, n, nc, cl_ptr, cl_members, nc_dev, hc);
+                       const int64_t *nc_dev, int32_t *hc, const CloseSrc &close) {
+  hipError_t e = herm_bucket_enqueue(c, c->stream, n, nc, cl_ptr, cl_members, nc_dev, hc, true, close);
   if (e != hipSuccess) return e;
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
   if (hc[BC_BAD]) return hipErrorInvalidDevicePointer;  // malformed cluster arrays
@@ -1570,7 +1606,8 @@ hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr,
 // The bucket kernel and the copy of the bucket words to hc (host memory) on
 // stream s, without waiting.
 hipError_t herm_bucket_enqueue(p3t_ctx *c, hipStream_t s, int64_t n, int64_t nc, const int32_t *cl_ptr,
-                               const int32_t *cl_members, const int64_t *nc_dev, int32_t *hc) {
+                               const int32_t *cl_members, const int64_t *nc_dev, int32_t *hc, bool reset_work,
+                               const CloseSrc &close) {
   hipError_t e;
   if ((e = fill_i32(c->herm_bcount, 0, BC_WORDS, s)) != hipSuccess) return e;
   BucketArgs B;
@@ -1585,9 +1622,24 @@ hipError_t herm_bucket_enqueue(p3t_ctx *c, hipStream_t s, int64_t n, int64_t nc,
   B.blists = c->herm_blists;
   B.cl_bk = c->herm_clbk;
   B.cnt = c->cnt;
+  B.reset_work = reset_work ? 1 : 0;
+  B.close = close;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
   hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, B);
   return hipMemcpyAsync(hc, c->herm_bcount, sizeof(int32_t) * BC_WORDS, hipMemcpyDeviceToHost, s);
+}
+
+__global__ void k_herm_reset_work(DevCounters *cnt) {
+  cnt->n_heval = 0;
+  cnt->n_hpair = 0;
+  cnt->n_coll = 0;
+}
+
+// The Hermite work counters zeroed on stream s (a kernel, not a memset: the
+// caller may be capturing).
+hipError_t herm_reset_work(p3t_ctx *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_herm_reset_work, dim3(1), dim3(1), 0, s, c->cnt);
+  return hipGetLastError();
 }
 
 __global__ void k_huge_flag(DevCounters *cnt, unsigned bits) { set_flag(cnt, bits); }
@@ -1666,6 +1718,8 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   A.cnt = c->cnt;
   host_changeover_coeffs(P.gamma, A);
   for (int bk = 0; bk < N_BUCKETS; ++bk) A.bcount[bk] = resume ? (bk < 10 ? hc[HERM_BC_PARK0 + bk] : 0) : hc[bk];
+  A.ccount[0] = 0;
+  for (int k = 1; k < 4; ++k) A.ccount[k] = resume ? 0 : hc[HERM_BC_CLOSE0 + k - 1];
   // clusters of one member: their two-body orbits, exactly (they never
   // park); launched beside the big clusters below when there are any
   const int32_t n_single = (P.isolated == 1 && !resume) ? A.bcount[0] : 0;
@@ -1673,13 +1727,17 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   // fused launch: buckets 0..6 (clusters per 256-thread block = 4 * 64 / SEG /
   // lanes per member); the clusters of 65 members and more run at the same
   // time in their own launches (one workgroup each)
+  // regions 0..6 the buckets, 7..9 the close clusters of buckets 1..3
+  // (dispatched first)
   int blocks = 0;
-  for (int bk = 0; bk < 7; ++bk) {
-    A.boff[bk] = blocks;
+  for (int rg = 0; rg < FUSED_REGIONS; ++rg) {
+    A.boff[rg] = blocks;
+    const int bk = rg < 7 ? rg : rg - 6;
     const int per_block = (BIG_T / WAVE) * clusters_per_wave(bk, collide);
-    blocks += (A.bcount[bk] + per_block - 1) / per_block;
+    const int cnt = rg < 7 ? A.bcount[bk] : A.ccount[bk];
+    blocks += (cnt + per_block - 1) / per_block;
   }
-  for (int bk = 7; bk <= N_BUCKETS; ++bk) A.boff[bk] = blocks;
+  for (int rg = FUSED_REGIONS; rg <= N_BUCKETS; ++rg) A.boff[rg] = blocks;
   // clusters above 1024 members (never parked): the percolated-cluster path
   const int n_huge = resume ? 0 : A.bcount[10];
   const bool big = A.bcount[7] > 0 || A.bcount[8] > 0 || A.bcount[9] > 0 || n_huge > 0;

@@ -82,25 +82,45 @@ __global__ void k_uf_init(int64_t n, int32_t *__restrict__ p) {
     p[i] = (int32_t)i;
 }
 
+// Joins the components of a and b: the larger root is hooked under the
+// smaller one, so every root stays its component's minimum index.
+__device__ __forceinline__ void uf_union(int32_t *p, int a, int b) {
+  a = uf_find(p, a);
+  b = uf_find(p, b);
+  while (a != b) {
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    // a > b: hook root a under b
+    const int old = atomicCAS(p + a, a, b);
+    if (old == a) break;
+    a = uf_find(p, old);
+    b = uf_find(p, b);
+  }
+}
+
 __global__ void k_uf_link(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, int32_t *p) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
       const int j = col[q];
       if (j <= i) continue;  // each undirected edge once
-      int a = uf_find(p, (int)i), b = uf_find(p, j);
-      while (a != b) {
-        if (a < b) {
-          const int t = a;
-          a = b;
-          b = t;
-        }
-        // a > b: hook root a under b
-        const int old = atomicCAS(p + a, a, b);
-        if (old == a) break;
-        a = uf_find(p, old);
-        b = uf_find(p, b);
-      }
+      uf_union(p, (int)i, j);
     }
+  }
+}
+
+// The same components straight from the unordered pair list, whose length
+// is read on the device (clamped to the buffer): a component does not
+// depend on the order in which its edges are joined.
+__global__ void k_uf_link_pairs(int64_t n, const int2 *__restrict__ pairs, const unsigned long long *__restrict__ np_dev,
+                                int64_t cap, int32_t *p) {
+  const int64_t np = (int64_t)*np_dev < cap ? (int64_t)*np_dev : cap;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < np; q += (int64_t)gridDim.x * blockDim.x) {
+    const int2 e = pairs[q];
+    if (e.x == e.y || (uint32_t)e.x >= (uint64_t)n || (uint32_t)e.y >= (uint64_t)n) continue;
+    uf_union(p, e.x, e.y);
   }
 }
 
@@ -109,11 +129,33 @@ __global__ void k_uf_final(int64_t n, int32_t *p, int32_t *__restrict__ label) {
     label[i] = uf_find(p, (int)i);
 }
 
+// labels and the (label, index) sort keys of the cluster CSR in one pass
+__global__ void k_uf_final_keys(int64_t n, int32_t *p, int32_t *__restrict__ label, uint64_t *__restrict__ key) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = uf_find(p, (int)i);
+    label[i] = r;
+    key[i] = ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)i;
+  }
+}
+
 hipError_t labels_cc(p3t_ctx *c, int64_t n, int32_t *label) {
   hipStream_t s = c->stream;
   hipLaunchKernelGGL(k_uf_init, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent);
   hipLaunchKernelGGL(k_uf_link, dim3(g1d(n)), dim3(256), 0, s, n, c->csr_ptr, c->csr_col, c->uf_parent);
   hipLaunchKernelGGL(k_uf_final, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent, label);
+  return hipGetLastError();
+}
+
+// Labels from the pair list of the last evaluation without building its
+// CSR (the pair count stays on the device), and the cluster sort keys
+// (c->cl_keys) for clusters_csr_dev(..., keys_ready = true).
+hipError_t labels_pairs(p3t_ctx *c, int64_t n, int32_t *label) {
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(k_uf_init, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent);
+  const unsigned gp = (unsigned)std::min<int64_t>(2048, (c->pair_cap + 255) / 256);
+  hipLaunchKernelGGL(k_uf_link_pairs, dim3(gp < 1 ? 1 : gp), dim3(256), 0, s, n, c->pairs, &c->cnt->n_pairs,
+                     c->pair_cap, c->uf_parent);
+  hipLaunchKernelGGL(k_uf_final_keys, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent, label, c->cl_keys);
   return hipGetLastError();
 }
 
@@ -151,11 +193,13 @@ hipError_t clusters_csr(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl
 }
 
 // The same without the host round trip: the cluster count is left at
-// node_scan[n] on the device.
-hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members) {
+// node_scan[n] on the device.  keys_ready: c->cl_keys already holds the
+// keys of label (labels_pairs wrote them).
+hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
+                            bool keys_ready) {
   hipStream_t s = c->stream;
   hipError_t e;
-  hipLaunchKernelGGL(k_cl_keys, dim3(g1d(n)), dim3(256), 0, s, n, label, c->cl_keys);
+  if (!keys_ready) hipLaunchKernelGGL(k_cl_keys, dim3(g1d(n)), dim3(256), 0, s, n, label, c->cl_keys);
   int bits = 1;
   while ((int64_t(1) << bits) < n) ++bits;
   // keys start ascending in the particle index, so a stable sort on the

@@ -136,10 +136,19 @@ __device__ __forceinline__ T wave_max(T v) {
 }
 
 // Hermite bucket-count words (hermite.hip): [0, 11) the buckets, [11, 21)
-// the parked clusters of buckets 0..9, the parked member count, then the
-// cluster count and the malformed-input flag.
-constexpr int HERM_BC_PARK0 = 11, HERM_BC_PARKED = 21, HERM_BC_NC = 28, HERM_BC_BAD = 29, HERM_BC_WORDS = 32;
+// the parked clusters of buckets 0..9, the parked member count, [22, 25)
+// the clusters of buckets 1..3 with a close pair (listed at the end of
+// their bucket's list, apart from the others), then the cluster count and
+// the malformed-input flag.
+constexpr int HERM_BC_PARK0 = 11, HERM_BC_PARKED = 21, HERM_BC_CLOSE0 = 22, HERM_BC_NC = 28, HERM_BC_BAD = 29,
+              HERM_BC_WORDS = 32;
 constexpr int HERM_N_BUCKETS = 11;
+// A neighbour pair counts as close when its free-fall time scale
+// sqrt(r^3 / G(m_i + m_j)) is below dt_soft / CLOSE_RATIO: nearly every
+// cluster that takes hundreds of Hermite block steps holds one (mostly
+// bound pairs), so the hard part dispatches such clusters first.  Only the
+// order of the work depends on it.
+constexpr double CLOSE_RATIO = 0.5;
 // parked members of one p3t_hard_evaluate call at most, and the chunks of
 // the direct sum over all particles for each of them
 constexpr int SLOW_CAP = 1024, SLOW_CHUNKS = 64;
@@ -186,12 +195,17 @@ struct p3t_ctx {
   int2 *pairs = nullptr;            // neighbour pairs (i_orig, j_orig)
   int2 *cands = nullptr;            // neighbour candidates (sorted indices)
   int64_t cand_cap = 0;
-  // The clusters of the next hard part (CSR, labels, cluster CSR, buckets)
-  // are prepared on aux_stream right after an evaluation, beside the kicks;
-  // prep_state 1 = enqueued for prep_n particles.  Every other call first
-  // makes the main stream wait for it (the scratch is shared) and drops it.
+  // The clusters of the next hard part (labels, cluster CSR, buckets) are
+  // prepared on aux_stream right behind an evaluation's kernels, beside the
+  // host's read of its counters and the kicks that follow; prep_state 2 =
+  // enqueued before the counters were read, 1 = the evaluation needed no
+  // retry and the preparation is valid for prep_n particles.  Every other
+  // call first makes the main stream wait for it (the scratch is shared)
+  // and drops it.
   int prep_state = 0;
   int prep_timed = 0;              // the preparation recorded its timing events
+  int cut_timing_pending = 0;      // events 0 / 1 of p3t_compute_cutoffs not read yet
+  int park_flags_valid = 0;        // slow_flag holds the members parked in the last hard part
   int64_t prep_n = 0;
   hipEvent_t prep_ev[2] = {};      // fork (main stream), done (aux stream)
   int32_t *hc_pinned = nullptr;    // bucket words, pinned host memory
@@ -256,6 +270,9 @@ struct p3t_ctx {
   int32_t *uf_parent = nullptr;     // union-find parents (n)
   uint64_t *cl_keys = nullptr, *cl_keys_alt = nullptr;  // cluster sort keys (n)
   double *cut_part = nullptr;       // cut-off bin partial sums
+  uint8_t *close_flag = nullptr;    // per particle: in a close neighbour pair at the last evaluation
+  int32_t *cut_bin = nullptr;       // cut-off radial bin of each particle (n; the cluster
+                                    // preparation may use row_cnt at the same time)
   double *tmp_d = nullptr;          // per-particle FP64 scratch (3n)
   double *acc_s = nullptr;          // soft acceleration in sorted order (3n)
   // second stream for the big Hermite clusters, fork / join events
@@ -310,6 +327,7 @@ int64_t adjoint_buf_need(int64_t n_cap);
 // timing events of the context (recorded only when timing is on)
 void ev_record(p3t_ctx *c, int k);
 double ev_ms(p3t_ctx *c, int a, int b);
+void cut_timing_read(p3t_ctx *c);
 
 hipError_t radix_sort_pairs(uint64_t *&keys, int32_t *&vals, uint64_t *&keys_alt, int32_t *&vals_alt, int64_t n_static,
                             const unsigned long long *n_dev, int bit_lo, int bit_hi, uint32_t *hist, int64_t hist_cap,
@@ -357,14 +375,21 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups, double *acc3, bool frozen = 
 // nbr.hip
 hipError_t build_csr(p3t_ctx *c, int64_t n, int64_t n_pairs);
 hipError_t labels_cc(p3t_ctx *c, int64_t n, int32_t *label);
+hipError_t labels_pairs(p3t_ctx *c, int64_t n, int32_t *label);
 hipError_t clusters_csr(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
                         int64_t *n_clusters);
-hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members);
+hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
+                            bool keys_ready = false);
 
 // hermite.hip
 // nc_dev (nullable): the cluster count on the device, nc then only bounds it
+// Clusters of 2..8 members holding a member flagged in either array
+// (nullable) are dispatched first (see CLOSE_RATIO).
+struct CloseSrc {
+  const uint8_t *a = nullptr, *b = nullptr;
+};
 hipError_t herm_bucket(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
-                       const int64_t *nc_dev, int32_t *hc);
+                       const int64_t *nc_dev, int32_t *hc, const CloseSrc &close = CloseSrc());
 // perfect-accretion collisions in the hard part (hermite.hip, wave path)
 struct HermColl {
   double f;          // radius enhancement factor
@@ -372,8 +397,13 @@ struct HermColl {
   int32_t *merged;   // per particle: lowest index of its composite (identity on entry)
   double *ceps;      // per cluster: six dissipation sums (zeroed on entry)
 };
+// reset_work: also zero the Hermite work counters (n_heval, n_hpair,
+// n_coll); a preparation enqueued before the last evaluation's counters are
+// read leaves them, and herm_reset_work zeroes them when the hard part starts
 hipError_t herm_bucket_enqueue(p3t_ctx *c, hipStream_t s, int64_t n, int64_t nc, const int32_t *cl_ptr,
-                               const int32_t *cl_members, const int64_t *nc_dev, int32_t *hc);
+                               const int32_t *cl_members, const int64_t *nc_dev, int32_t *hc, bool reset_work = true,
+                               const CloseSrc &close = CloseSrc());
+hipError_t herm_reset_work(p3t_ctx *c, hipStream_t s);
 hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_ptr, const int32_t *cl_members,
                        double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,
                        double *e_rel_err, int32_t *n_steps, int32_t *steps_out, const int32_t *hc, int budget,

@@ -94,7 +94,7 @@ class P3TStepper:
 
     @property
     def last(self) -> dict:
-        """Counters of the last evaluation (synchronises)."""
+        """Counters of the last evaluation (host copies; no wait)."""
         return self.ctx.stats()
 
     def step(self):
