@@ -29,6 +29,13 @@
 
 #include "p3t_internal.h"
 
+// No automatic contraction in this file: the fused multiply-adds of the
+// step are written out (fmad), so that the plain, parking and resuming
+// launches, which compile the same formulas into different kernels, round
+// every operation identically (a parked and resumed cluster ends bit for
+// bit where an uninterrupted one does).
+#pragma clang fp contract(off)
+
 namespace p3t {
 
 constexpr int TICK_BITS = 40;
@@ -84,50 +91,63 @@ struct HermArgs {
   DevCounters *cnt;
 };
 
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// x + v dl + a dl^2/2 + j dl^3/6 and v + a dl + j dl^2/2 (d2 = dl^2/2,
+// d3 = dl^3/6), Horner-ordered fused multiply-adds
+__device__ __forceinline__ void predict(const double *x, const double *v, const double *a, const double *j, double dl,
+                                        double d2, double d3, double *xp, double *vp) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xp[d] = fmad(j[d], d3, fmad(a[d], d2, fmad(v[d], dl, x[d])));
+    vp[d] = fmad(j[d], d2, fmad(a[d], dl, v[d]));
+  }
+}
+
 __device__ __forceinline__ double changeover_W(double y, const HermArgs &A) {
   if (y < A.gamma) return A.wc * y;
   if (y >= 1.0) return 1.0;
   double p = A.wp[7];
 #pragma unroll
-  for (int k = 6; k >= 0; --k) p = p * y + A.wp[k];
-  return p + A.wlog * y * log(y) + (1.0 - A.wf1) * y;
+  for (int k = 6; k >= 0; --k) p = fmad(p, y, A.wp[k]);
+  return fmad(1.0 - A.wf1, y, fmad(A.wlog * y, log(y), p));
 }
 
 // hard pair term on i from j: d = x_j - x_i, u = v_j - v_i
 __device__ __forceinline__ void hard_pair(double dx, double dy, double dz, double ux, double uy, double uz, double gmj,
                                           double invR, const HermArgs &A, double *a, double *jk) {
-  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r2 = fmad(dz, dz, fmad(dy, dy, dx * dx));
   const double rinv = rsqrt(r2);
   const double y = r2 * rinv * invR;
   const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
   const double x2 = x * x, x3 = x2 * x;
-  const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+  const double K = x2 * x2 * fmad(x, fmad(x, fmad(-20.0, x, 70.0), -84.0), 35.0);
   const double omx = 1.0 - x;
   const double Ky = (x > 0.0 && x < 1.0) ? 140.0 * x3 * omx * omx * omx * A.inv1mg : 0.0;
-  const double s = dx * ux + dy * uy + dz * uz;
+  const double s = fmad(dz, uz, fmad(dy, uy, dx * ux));
   const double rinv2 = rinv * rinv;
   const double rinv3 = rinv * rinv2;
   const double w = gmj * (1.0 - K) * rinv3;
   const double c1 = 3.0 * s * rinv2;
   const double c2 = gmj * Ky * s * rinv * invR * rinv3;
-  a[0] += w * dx;
-  a[1] += w * dy;
-  a[2] += w * dz;
-  jk[0] += w * (ux - c1 * dx) - c2 * dx;
-  jk[1] += w * (uy - c1 * dy) - c2 * dy;
-  jk[2] += w * (uz - c1 * dz) - c2 * dz;
+  a[0] = fmad(w, dx, a[0]);
+  a[1] = fmad(w, dy, a[1]);
+  a[2] = fmad(w, dz, a[2]);
+  jk[0] = fmad(-c2, dx, fmad(w, fmad(-c1, dx, ux), jk[0]));
+  jk[1] = fmad(-c2, dy, fmad(w, fmad(-c1, dy, uy), jk[1]));
+  jk[2] = fmad(-c2, dz, fmad(w, fmad(-c1, dz, uz), jk[2]));
 }
 
 __device__ __forceinline__ void star_term(const double *x, const double *v, double GM, double *a, double *jk) {
-  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  const double r2 = fmad(x[2], x[2], fmad(x[1], x[1], x[0] * x[0]));
   const double rinv = rsqrt(r2);
   const double rinv3 = rinv * rinv * rinv;
-  const double xv = x[0] * v[0] + x[1] * v[1] + x[2] * v[2];
+  const double xv = fmad(x[2], v[2], fmad(x[1], v[1], x[0] * v[0]));
   const double c5 = 3.0 * xv * rinv * rinv;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     a[d] = -GM * x[d] * rinv3;
-    jk[d] = -GM * (v[d] - c5 * x[d]) * rinv3;
+    jk[d] = -GM * fmad(-c5, x[d], v[d]) * rinv3;
   }
 }
 
@@ -143,10 +163,10 @@ __device__ __forceinline__ int level_for(double dt_soft, double dtc, int kmax) {
   return k;
 }
 
-__device__ __forceinline__ double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
 __device__ __forceinline__ double dot3(const double *a, const double *b) {
-  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+  return fmad(a[2], b[2], fmad(a[1], b[1], a[0] * b[0]));
 }
+__device__ __forceinline__ double norm3(const double *a) { return sqrt(dot3(a, a)); }
 
 // Smallest k >= 0 with P 4^-k <= L (k_max + 1 if none), P = dt_soft^2 den,
 // L = eta num >= 0: the level whose squared step does not exceed the
@@ -175,10 +195,10 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double da = a0[d] - a1[d];
-    a2[d] = (-6.0 * da - h * (4.0 * j0[d] + 2.0 * j1[d])) * ih2;
-    a3[d] = (12.0 * da + 6.0 * h * (j0[d] + j1[d])) * ih3;
-    x[d] = xp[d] + a2[d] * h4_24 + a3[d] * h5_120;
-    v[d] = vp[d] + a2[d] * h3_6 + a3[d] * h4_24;
+    a2[d] = fmad(-h, fmad(4.0, j0[d], 2.0 * j1[d]), -6.0 * da) * ih2;
+    a3[d] = fmad(6.0 * h, j0[d] + j1[d], 12.0 * da) * ih3;
+    x[d] = fmad(a3[d], h5_120, fmad(a2[d], h4_24, xp[d]));
+    v[d] = fmad(a3[d], h4_24, fmad(a2[d], h3_6, vp[d]));
     a0[d] = a1[d];
     j0[d] = j1[d];
   }
@@ -186,7 +206,7 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
   // step's end.  The level is the smallest k with (dt_soft 2^-k)^2 <= dt^2,
   // found without the division and the outer root: dt_soft^2 den 4^-k <=
   // eta num, with |a||a2| = sqrt(|a|^2 |a2|^2) (two roots instead of four).
-  const double a2e[3] = {a2[0] + a3[0] * h, a2[1] + a3[1] * h, a2[2] + a3[2] * h};
+  const double a2e[3] = {fmad(a3[0], h, a2[0]), fmad(a3[1], h, a2[1]), fmad(a3[2], h, a2[2])};
   const double an2 = dot3(a1, a1), jn2 = dot3(j1, j1), a2n2 = dot3(a2e, a2e), a3n2 = dot3(a3, a3);
   const double num = A.eta * (sqrt(an2 * a2n2) + jn2);
   const double den = sqrt(jn2 * a3n2) + a2n2;
@@ -320,9 +340,10 @@ __device__ __forceinline__ double lpm_sum(double v, int ll2) {
 // every LPM-th partner and the partial sums are added across them.
 // MODE 0: plain; 1: park clusters still running after A.budget steps;
 // 2: resume parked clusters
-template <int MODE>
+template <int MODE, int SL2 = -1>
 __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist, int count, int ci0, const Lds &L,
-                                         int wbase, int sl2) {
+                                         int wbase, int sl2_rt) {
+  const int sl2 = SL2 >= 0 ? SL2 : sl2_rt;
   constexpr bool RESUME = MODE == 2, PARK = MODE == 1;
   const int ll2 = lanes_per_member_log2(sl2), cl2 = sl2 + ll2;
   const int SEG = 1 << sl2, LPM = 1 << ll2;
@@ -390,6 +411,13 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
   }
   double E0 = seg_sum(e, cl2);
   int lev = initial_level(a0, j0, mem, gid, A);  // every copy reads the carried step
+  // two-member clusters: the partner's G m and 1 / r_out (lane ^ 1), and
+  // the pair's 1 / max(r_out) as the LDS path forms it
+  double pgm_q = 0.0, pinv_q = 0.0;
+  if constexpr (SL2 == 1) {
+    pgm_q = dpp_f64<DPP_XOR1>(A.G * m);
+    pinv_q = fmin(invi, dpp_f64<DPP_XOR1>(invi));
+  }
   const int64_t T = (int64_t)1 << TICK_BITS;
   const int max_iter = A.max_iter;
   const double tick = A.tick, GM = A.GM;
@@ -430,11 +458,7 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     if (mem && !done) {
       const double dl = (double)(tn - t) * tick;
       const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xp[d] = x[d] + v[d] * dl + a0[d] * d2 + j0[d] * d3;
-        vp[d] = v[d] + a0[d] * dl + j0[d] * d2;
-      }
+      predict(x, v, a0, j0, dl, d2, d3, xp, vp);
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -442,29 +466,39 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
         vp[d] = v[d];
       }
     }
-    wave_sync();
-    if (lead) {
-      L.px[me] = xp[0];
-      L.py[me] = xp[1];
-      L.pz[me] = xp[2];
-      L.pvx[me] = vp[0];
-      L.pvy[me] = vp[1];
-      L.pvz[me] = vp[2];
-    }
-    // the star's term needs only the own predicted state: computed while the
-    // exchange through LDS is in flight (one wavefront runs this chain alone,
-    // so independent work is what hides the FP64 latency)
     double a1[3], j1[3];
-    star_term(xp, vp, GM, a1, j1);
-    wave_sync();
 #pragma unroll
     for (int d = 0; d < 3; ++d) pa[d] = pj[d] = 0.0;
-    if (active) {
-      for (int jj = sub; jj < size; jj += LPM) {
-        if (jj == sl) continue;
-        const int q = sb + jj;
-        hard_pair(L.px[q] - xp[0], L.py[q] - xp[1], L.pz[q] - xp[2], L.pvx[q] - vp[0], L.pvy[q] - vp[1],
-                  L.pvz[q] - vp[2], L.pgm[q], fmin(invi, L.pinv[q]), A, pa, pj);
+    if constexpr (SL2 == 1) {
+      // two members in adjacent lanes: the partner's predicted state comes
+      // over DPP (every lane is active here), no LDS round trip
+      star_term(xp, vp, GM, a1, j1);
+      const double qx = dpp_f64<DPP_XOR1>(xp[0]), qy = dpp_f64<DPP_XOR1>(xp[1]), qz = dpp_f64<DPP_XOR1>(xp[2]);
+      const double qvx = dpp_f64<DPP_XOR1>(vp[0]), qvy = dpp_f64<DPP_XOR1>(vp[1]), qvz = dpp_f64<DPP_XOR1>(vp[2]);
+      if (active && size == 2)
+        hard_pair(qx - xp[0], qy - xp[1], qz - xp[2], qvx - vp[0], qvy - vp[1], qvz - vp[2], pgm_q, pinv_q, A, pa, pj);
+    } else {
+      wave_sync();
+      if (lead) {
+        L.px[me] = xp[0];
+        L.py[me] = xp[1];
+        L.pz[me] = xp[2];
+        L.pvx[me] = vp[0];
+        L.pvy[me] = vp[1];
+        L.pvz[me] = vp[2];
+      }
+      // the star's term needs only the own predicted state: computed while
+      // the exchange through LDS is in flight (one wavefront runs this chain
+      // alone, so independent work is what hides the FP64 latency)
+      star_term(xp, vp, GM, a1, j1);
+      wave_sync();
+      if (active) {
+        for (int jj = sub; jj < size; jj += LPM) {
+          if (jj == sl) continue;
+          const int q = sb + jj;
+          hard_pair(L.px[q] - xp[0], L.py[q] - xp[1], L.pz[q] - xp[2], L.pvx[q] - vp[0], L.pvy[q] - vp[1],
+                    L.pvz[q] - vp[2], L.pgm[q], fmin(invi, L.pinv[q]), A, pa, pj);
+        }
       }
     }
     if (ll2 > 0) {  // partial sums of the member's copies (all lanes take part)
@@ -807,11 +841,7 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
     {
       const double dl = mem ? (double)(tn - t) * tick : 0.0;
       const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xp[d] = x[d] + v[d] * dl + a0[d] * d2 + j0[d] * d3;
-        vp[d] = v[d] + a0[d] * dl + j0[d] * d2;
-      }
+      predict(x, v, a0, j0, dl, d2, d3, xp, vp);
     }
     wave_sync();
     L.px[me] = xp[0];
@@ -1236,10 +1266,7 @@ __device__ __forceinline__ void big_body(const HermArgs &A, int c, int bk, const
     for (int u = 0; u < MPT; ++u) {
       const double dl = mem[u] ? (double)(tn - t[u]) * A.tick : 0.0;
       const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
-      for (int d = 0; d < 3; ++d) {
-        xp[u][d] = x[u][d] + v[u][d] * dl + a0[u][d] * d2 + j0[u][d] * d3;
-        vp[u][d] = v[u][d] + a0[u][d] * dl + j0[u][d] * d2;
-      }
+      predict(x[u], v[u], a0[u], j0[u], dl, d2, d3, xp[u], vp[u]);
     }
     __syncthreads();
 #pragma unroll
@@ -1420,6 +1447,8 @@ __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   const int32_t *blist = A.blists + (int64_t)bk * A.nc + (close ? A.nc - count : 0);
   if (bk >= (COLL ? 1 : WAVE_BK0))
     wave_body<MODE, COLL>(A, blist, count, ci0, L, wbase, bk);
+  else if (bk == 1)
+    seg_body<MODE, 1>(A, blist, count, ci0, L, wbase, bk);
   else
     seg_body<MODE>(A, blist, count, ci0, L, wbase, bk);
 }
@@ -1963,8 +1992,8 @@ __global__ __launch_bounds__(HUGE_T) void k_huge_predict(HermArgs A, HugeArgs H,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double x = H.x[d * M + k], v = H.v[d * M + k], a = H.a[d * M + k], j = H.j[d * M + k];
-      H.xp[d * M + k] = x + v * dl + a * d2 + j * d3;
-      H.vp[d * M + k] = v + a * dl + j * d2;
+      H.xp[d * M + k] = fmad(j, d3, fmad(a, d2, fmad(v, dl, x)));
+      H.vp[d * M + k] = fmad(j, d2, fmad(a, dl, v));
     }
     const bool due = tk + ((int64_t)1 << (TICK_BITS - H.lev[k])) == tn;
     H.aflag[k] = due ? 1 : 0;
