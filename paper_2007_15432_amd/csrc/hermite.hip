@@ -171,15 +171,22 @@ __device__ __forceinline__ double norm3(const double *a) { return sqrt(dot3(a, a
 // Smallest k >= 0 with P 4^-k <= L (k_max + 1 if none), P = dt_soft^2 den,
 // L = eta num >= 0: the level whose squared step does not exceed the
 // squared Aarseth step.  P = 0 (den = 0) gives level 0, as a step of dt_soft.
-// Started one below the exponent estimate; every comparison is exact.
+// Closed form, without a search loop: for P > L > 0 let e = ilogb(P) -
+// ilogb(L) >= 0; P 4^-k <= L holds for 2k >= e + 1 and fails for 2k <= e - 1,
+// and at 2k = e one exact comparison of the scaled P decides.
 __device__ __forceinline__ int level_for_sq(double P, double L, int kmax) {
-  if (!(P > L)) return 0;
-  if (!(L > 0.0)) return kmax + 1;
-  const int e = ilogb(P) - ilogb(L);
-  int k = (e - 1) >> 1;
-  k = k < 0 ? 0 : k;
-  while (k <= kmax && ldexp(P, -2 * k) > L) ++k;
-  return k;
+  const bool ok = P > L && L > 0.0;
+  // ilogb(inf) is INT_MAX: bounded first; then e >= 2 k_max + 2 already
+  // gives k_max + 1
+  int eP = ilogb(ok ? P : 2.0);
+  eP = eP < 1100 ? eP : 1100;
+  int e = eP - ilogb(ok ? L : 1.0);
+  e = e < 2 * kmax + 2 ? e : 2 * kmax + 2;
+  int k = (e + 1) >> 1;
+  k += ((e & 1) == 0 && ldexp(P, -e) > L) ? 1 : 0;
+  k = k > kmax ? kmax + 1 : k;
+  k = (L > 0.0) ? k : kmax + 1;
+  return (P > L) ? k : 0;
 }
 
 // corrector + new level for one active member; its step is h = dt_soft 2^-lev
@@ -189,9 +196,9 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
                                         const double *a1, const double *j1, double h, int64_t tnew, int &lev,
                                         const HermArgs &A) {
   double a2[3], a3[3];
-  const int l = lev;
-  const double ih2 = ldexp(A.inv_dt2, 2 * l), ih3 = ldexp(A.inv_dt3, 3 * l);
-  const double h3_6 = ldexp(A.dt3_6, -3 * l), h4_24 = ldexp(A.dt4_24, -4 * l), h5_120 = ldexp(A.dt5_120, -5 * l);
+  const int l = lev, l2 = l + l, l3 = l2 + l, l4 = l2 + l2, l5 = l4 + l;  // shifts and adds, no multiply
+  const double ih2 = ldexp(A.inv_dt2, l2), ih3 = ldexp(A.inv_dt3, l3);
+  const double h3_6 = ldexp(A.dt3_6, -l3), h4_24 = ldexp(A.dt4_24, -l4), h5_120 = ldexp(A.dt5_120, -l5);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double da = a0[d] - a1[d];
@@ -211,14 +218,11 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
   const double num = A.eta * (sqrt(an2 * a2n2) + jn2);
   const double den = sqrt(jn2 * a3n2) + a2n2;
   const int knew = level_for_sq(A.dt_soft2 * den, num, A.k_max);
-  int k = lev;
-  if (knew < k) {
-    // grow by at most a factor two, and only on a multiple of the doubled step
-    const int64_t dbl = (int64_t)1 << (TICK_BITS - k + 1);
-    if (k > 0 && (tnew & (dbl - 1)) == 0) k = k - 1;
-  } else {
-    k = knew;
-  }
+  // grow by at most a factor two, and only on a multiple of the doubled
+  // step (lev <= k_max <= 40, so the shift stays below 64)
+  const int64_t dbl_mask = ((int64_t)1 << (TICK_BITS - lev + 1)) - 1;
+  const bool grow = lev > 0 && (tnew & dbl_mask) == 0;
+  int k = knew < lev ? (grow ? lev - 1 : lev) : knew;
   if (k > A.k_max) {
     set_flag(A.cnt, P3T_FLAG_KMAX);
     k = A.k_max;
@@ -455,29 +459,26 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
     const bool active = mem && !done && te == tn;
     nst += done ? 0 : 1;
     double xp[3], vp[3];
-    if (mem && !done) {
+    // every lane predicts (a lane whose cluster is done, or that holds no
+    // member, computes a value nobody reads), so no branch is taken here
+    {
       const double dl = (double)(tn - t) * tick;
       const double d2 = dl * dl * 0.5, d3 = dl * dl * dl * (1.0 / 6.0);
       predict(x, v, a0, j0, dl, d2, d3, xp, vp);
-    } else {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xp[d] = x[d];
-        vp[d] = v[d];
-      }
     }
     double a1[3], j1[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) pa[d] = pj[d] = 0.0;
     if constexpr (SL2 == 1) {
       // two members in adjacent lanes: the partner's predicted state comes
-      // over DPP (every lane is active here), no LDS round trip
+      // over DPP (every lane is active here), no LDS round trip, and its
+      // term adds straight onto the star's; lanes that are not due compute
+      // sums nobody reads
       star_term(xp, vp, GM, a1, j1);
       const double qx = dpp_f64<DPP_XOR1>(xp[0]), qy = dpp_f64<DPP_XOR1>(xp[1]), qz = dpp_f64<DPP_XOR1>(xp[2]);
       const double qvx = dpp_f64<DPP_XOR1>(vp[0]), qvy = dpp_f64<DPP_XOR1>(vp[1]), qvz = dpp_f64<DPP_XOR1>(vp[2]);
-      if (active && size == 2)
-        hard_pair(qx - xp[0], qy - xp[1], qz - xp[2], qvx - vp[0], qvy - vp[1], qvz - vp[2], pgm_q, pinv_q, A, pa, pj);
+      hard_pair(qx - xp[0], qy - xp[1], qz - xp[2], qvx - vp[0], qvy - vp[1], qvz - vp[2], pgm_q, pinv_q, A, a1, j1);
     } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) pa[d] = pj[d] = 0.0;
       wave_sync();
       if (lead) {
         L.px[me] = xp[0];
@@ -509,10 +510,12 @@ __device__ __forceinline__ void seg_body(const HermArgs &A, const int32_t *blist
       }
     }
     if (active) {
+      if constexpr (SL2 != 1) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        a1[d] += pa[d];
-        j1[d] += pj[d];
+        for (int d = 0; d < 3; ++d) {
+          a1[d] += pa[d];
+          j1[d] += pj[d];
+        }
       }
       const double h = (double)(tn - t) * tick;
       t = tn;
