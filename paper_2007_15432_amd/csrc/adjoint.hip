@@ -307,7 +307,7 @@ __global__ __launch_bounds__(WAVE) void k_adj_groups(AdjArgs A) {
   const int lane = threadIdx.x;
   const int ngroups = uniform_first((int)A.cnt->n_groups);
   for (;;) {
-    const int gi = uniform_first((int)atomicAdd(A.queue, lane == 0 ? 1ull : 0ull));
+    const int gi = (int)wave_fetch_add(A.queue, 1ull);
     if (gi >= ngroups) break;
     const int q = uniform_first(A.order ? A.order[gi] : gi);
     if (uniform_first64(A.gl[q].off) < 0) continue;

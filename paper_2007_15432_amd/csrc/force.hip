@@ -7,7 +7,9 @@
 // and cells are staged 64 at a time in LDS by the whole wave (coalesced
 // gathers from the Morton-ordered arrays) and read back as broadcasts.
 //
-//   NEAR particles (inside some search reach): FP64, K(y) with
+//   NEAR particles (inside some search reach): FP64 (mixed form: only the
+//     pairs inside the changeover; those beyond both cut-offs, K = 1, in
+//     FP32 from FP64 offsets), K(y) with
 //     y = r / max(r_out,i, r_out,j) = r * min(1/r_out,i, 1/r_out,j),
 //     K = x^4 (35 - 84x + 70x^2 - 20x^3), x = clamp((y - gamma)/(1 - gamma)),
 //     which is W - y W' for the W of eq. (cutfuncW) in closed form; then a
@@ -95,6 +97,12 @@ __global__ __launch_bounds__(WAVE) void k_force(ForceArgs A) {
         tI[lane] = j;
       }
       __syncthreads();
+      // mixed form: the pairs beyond both cut-offs (K = 1) in FP32 from
+      // their FP64 offsets, summed per tile in FP32 and folded into the FP64
+      // sums; inside the changeover FP64 (as the split near kernel does)
+      float tx[IPL], ty[IPL], tz[IPL];
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) tx[s] = ty[s] = tz[s] = 0.0f;
       for (int jj = 0; jj < nt; ++jj) {
         const double4 a = tA[jj];
         const double4 b = tB[jj];
@@ -105,16 +113,37 @@ __global__ __launch_bounds__(WAVE) void k_force(ForceArgs A) {
           const double r2 = dx * dx + dy * dy + dz * dz;
           const bool ok = (jidx != ii[s]) && (r2 > 0.0);
           coincident |= (jidx != ii[s]) && !(r2 > 0.0) && ii[s] >= 0;
-          const double r2s = ok ? r2 : 1.0;
-          const double rinv = rsqrt(r2s);
-          const double y = r2s * rinv * fmin(invi[s], b.x);
-          const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
-          const double x2 = x * x;
-          const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
-          const double f = ok ? a.w * K * rinv * rinv * rinv : 0.0;
-          ax[s] += f * dx;
-          ay[s] += f * dy;
-          az[s] += f * dz;
+          bool chg = true;
+          if (MIXED) {
+            const double inv = fmin(invi[s], b.x);
+            chg = r2 * (inv * inv) < 1.0;
+            const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+            const float ri = __frsqrt_rn(fdx * fdx + fdy * fdy + fdz * fdz);
+            const float f = (chg || !ok) ? 0.0f : (float)a.w * ri * ri * ri;
+            tx[s] += f * fdx;
+            ty[s] += f * fdy;
+            tz[s] += f * fdz;
+          }
+          if (chg) {
+            const double r2s = ok ? r2 : 1.0;
+            const double rinv = rsqrt(r2s);
+            const double y = r2s * rinv * fmin(invi[s], b.x);
+            const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
+            const double x2 = x * x;
+            const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+            const double f = ok ? a.w * K * rinv * rinv * rinv : 0.0;
+            ax[s] += f * dx;
+            ay[s] += f * dy;
+            az[s] += f * dz;
+          }
+        }
+      }
+      if (MIXED) {
+#pragma unroll
+        for (int s = 0; s < IPL; ++s) {
+          ax[s] += (double)tx[s];
+          ay[s] += (double)ty[s];
+          az[s] += (double)tz[s];
         }
       }
       // neighbour candidates of this tile (rare): exact predicate
@@ -397,6 +426,7 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups_max, double *acc3, bool froze
   A.pair_cap = c->pair_cap;
   A.cands = c->cands;
   A.cand_cap = c->cand_cap;
+  A.cand_slab = c->force_persistent ? 512 : 0;
   A.slow = c->slow_active ? c->slow_flag : nullptr;
   if (frozen) A.pair_cap = A.cand_cap = 0;
   // the close pairs of this evaluation (a kernel clears the flags: the

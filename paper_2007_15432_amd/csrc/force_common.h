@@ -19,6 +19,7 @@ struct ForceArgs {
   int2 *cands;  // neighbour candidates (sorted indices), split form
   const uint8_t *slow;  // caller's order: pairs with a flagged member are not reported (nullable)
   int64_t cand_cap;
+  int cand_slab;  // candidate slots a wavefront reserves at a time (0: exactly each tile's)
   double *acc;
   int64_t n;
   double G, gamma, inv1mg;
@@ -89,7 +90,7 @@ __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float v) {
 // the next group index of a persistent launch (every lane executes the
 // atomic; lane 0's ticket is broadcast through a scalar register)
 __device__ __forceinline__ int next_group(unsigned long long *queue, int lane) {
-  return uniform_first((int)atomicAdd(queue, lane == 0 ? 1ull : 0ull));
+  return (int)wave_fetch_add(queue, 1ull);
 }
 
 }  // namespace p3t

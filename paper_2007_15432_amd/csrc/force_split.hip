@@ -2,8 +2,11 @@
 // (eq. (softforce) with the pair cut-off of eq. (rout2); neighbour pairs of
 // Section 2.3), an alternative to the fused kernel of force.hip.
 //
-//   k_near   FP64 with the changeover K; while it runs, each lane records in
-//            a bit mask which j of the current tile are neighbour candidates
+//   k_near   FP64 with the changeover K (mixed form: the pairs beyond both
+//            cut-offs, where K = 1, in FP32 from FP64 offsets, the few
+//            inside the changeover in FP64); while it runs, each lane
+//            records in a bit mask which j of the current tile are
+//            neighbour candidates
 //            (r^2 <= max reach^2, with a relative margin that covers the
 //            rounding of r^2) and appends them after the tile to a candidate
 //            buffer.  Writes the sorted-order accumulator (=).
@@ -70,8 +73,49 @@ struct NearTile {
   int j[WAVE];      // sorted index (-2: padding)
 };
 
-template <int IPL, int UNR>
-__device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h, NearTile &T, int lane) {
+// The FP64 pair term with the changeover for one near pair (r^2 floored,
+// see near_group), added to (ax, ay, az).
+__device__ __forceinline__ void near_term64(const ForceArgs &A, double dx, double dy, double dz, double r2, double gm,
+                                            double invi, double invj, double &ax, double &ay, double &az) {
+  // r = 0 (the particle itself, or a coincident pair, which the candidate
+  // test reports) gives y ~ 0 < gamma, so K = 0 and the term vanishes
+  // exactly: rinv^3 = 1e225 stays finite.  Adding the floor changes no r^2
+  // above 1e-134 (it is below half an ulp there) and costs one add instead
+  // of a max with operand canonicalisation.
+  const double r2s = r2 + kTinyR2;
+  const double rinv = rsqrt(r2s);
+  const double y = r2s * rinv * fmin(invi, invj);
+  const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
+  const double x2 = x * x;
+  const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
+  const double f = gm * K * rinv * rinv * rinv;
+  ax += f * dx;
+  ay += f * dy;
+  az += f * dz;
+}
+
+// MIXED: a pair beyond both cut-offs (y = r / max(r_out) >= 1, so K = 1)
+// takes the Newtonian term in FP32 from its FP64 offset, summed per tile in
+// FP32 and folded into the FP64 sums; the pairs inside the changeover
+// (y < 1, a fraction of a percent of the near lists) are flagged per lane
+// and evaluated in FP64 after the tile.  Without MIXED every pair is FP64.
+// Candidate slots reserved by one wavefront and not used yet: [base, end).
+// A wavefront reserves A.cand_slab slots at a time with one atomic (a
+// returning atomic per tile on the one counter queued behind those of every
+// other wavefront); slots it leaves unused are marked (-1, -1), which the
+// exact test skips.
+struct CandSlab {
+  long long base = 0, end = 0;
+};
+
+__device__ __forceinline__ void close_slab(const ForceArgs &A, const CandSlab &S, int lane) {
+  for (long long q = S.base + lane; q < S.end; q += WAVE)
+    if (q < A.cand_cap) A.cands[q] = make_int2(-1, -1);
+}
+
+template <bool MIXED, int IPL, int UNR>
+__device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h, NearTile &T, int lane,
+                                           CandSlab &S) {
   int ii[IPL];
   double xi[IPL], yi[IPL], zi[IPL], invi[IPL], rch2[IPL], ax[IPL], ay[IPL], az[IPL];
 #pragma unroll
@@ -120,11 +164,14 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
     }
     __syncthreads();
     if (t0 + WAVE < h.n_near) fetch(t0 + WAVE);
-    unsigned cm[2][IPL];
+    unsigned cm[2][IPL], chg_m[2][IPL];
+    float tx[IPL], ty[IPL], tz[IPL];
+#pragma unroll
+    for (int s = 0; s < IPL; ++s) tx[s] = ty[s] = tz[s] = 0.0f;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
 #pragma unroll
-      for (int s = 0; s < IPL; ++s) cm[half][s] = 0u;
+      for (int s = 0; s < IPL; ++s) cm[half][s] = chg_m[half][s] = 0u;
       const int lo = half * 32, hi = min(ntp, lo + 32);
       for (int jj = lo; jj < hi; jj += UNR) {
 #pragma unroll
@@ -133,32 +180,51 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
           const double2 b = T.b[jj + u];
           const int jidx = T.j[jj + u];
           const unsigned bit = 1u << ((jj + u) & 31);
+          const float fw = (float)a.w;
 #pragma unroll
           for (int s = 0; s < IPL; ++s) {
             const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
             const double r2 = dx * dx + dy * dy + dz * dz;
-            // r = 0 (the particle itself, or a coincident pair, which the
-            // candidate test reports) gives y ~ 0 < gamma, so K = 0 and the
-            // term vanishes exactly: rinv^3 = 1e225 stays finite.  Adding
-            // the floor changes no r^2 above 1e-134 (it is below half an
-            // ulp there) and costs one add instead of a max with operand
-            // canonicalisation.
-            const double r2s = r2 + kTinyR2;
-            const double rinv = rsqrt(r2s);
-            const double y = r2s * rinv * fmin(invi[s], b.x);
-            const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
-            const double x2 = x * x;
-            const double K = x2 * x2 * (35.0 + x * (-84.0 + x * (70.0 - 20.0 * x)));
-            const double f = a.w * K * rinv * rinv * rinv;
-            ax[s] += f * dx;
-            ay[s] += f * dy;
-            az[s] += f * dz;
+            if constexpr (MIXED) {
+              const double inv = fmin(invi[s], b.x);
+              const bool chg = r2 * (inv * inv) < 1.0;  // inside the changeover, or r = 0
+              const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+              const float ri = __frsqrt_rn(fdx * fdx + fdy * fdy + fdz * fdz);
+              const float f = chg ? 0.0f : fw * ri * ri * ri;
+              tx[s] += f * fdx;
+              ty[s] += f * fdy;
+              tz[s] += f * fdz;
+              chg_m[half][s] |= (chg & (jidx != ii[s])) ? bit : 0u;
+            } else {
+              near_term64(A, dx, dy, dz, r2, a.w, invi[s], b.x, ax[s], ay[s], az[s]);
+            }
             // reach^2 of both sides carry the candidate margin already
             // evaluated without short-circuit, so no branch per pair
             const bool cand = (jidx != ii[s]) & ((r2 <= rch2[s]) | (r2 <= b.y));
             cm[half][s] |= cand ? bit : 0u;
           }
         }
+      }
+    }
+    if constexpr (MIXED) {
+      // the changeover pairs of this tile in FP64, then the tile's FP32 sums
+#pragma unroll
+      for (int s = 0; s < IPL; ++s) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          unsigned m = ii[s] >= 0 ? chg_m[half][s] : 0u;
+          while (m != 0u) {
+            const int q = 32 * half + __ffs(m) - 1;
+            m &= m - 1u;
+            const double4 a = T.a[q];
+            const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            near_term64(A, dx, dy, dz, r2, a.w, invi[s], T.b[q].x, ax[s], ay[s], az[s]);
+          }
+        }
+        ax[s] += (double)tx[s];
+        ay[s] += (double)ty[s];
+        az[s] += (double)tz[s];
       }
     }
     // hand this tile's candidates (sorted indices) to the exact test
@@ -171,9 +237,14 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
     const int incl = wave_incl_scan(nc);
     const int total = uniform_lane(incl, WAVE - 1);
     if (total > 0) {
-      const long long base =
-          uniform_first64((long long)atomicAdd(&A.cnt->n_cand, lane == 0 ? (unsigned long long)total : 0ull));
-      long long o = base + incl - nc;
+      if (S.base + total > S.end) {  // uniform
+        close_slab(A, S, lane);
+        const long long want = total > A.cand_slab ? total : A.cand_slab;
+        S.base = (long long)wave_fetch_add(&A.cnt->n_cand, (unsigned long long)want);
+        S.end = S.base + want;
+        if (S.end > A.cand_cap && lane == 0) set_flag(A.cnt, P3T_FLAG_PAIR_OVERFLOW);
+      }
+      long long o = S.base + incl - nc;
 #pragma unroll
       for (int s = 0; s < IPL; ++s) {
 #pragma unroll
@@ -187,7 +258,7 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
           }
         }
       }
-      if (base + total > A.cand_cap && lane == 0) set_flag(A.cnt, P3T_FLAG_PAIR_OVERFLOW);
+      S.base += total;
     }
   }
   double *acc = A.acc;
@@ -201,25 +272,27 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
   }
 }
 
-template <int UNR>
+template <bool MIXED, int UNR>
 __global__ __launch_bounds__(WAVE) void k_near(ForceArgs A) {
   __shared__ NearTile T;
   const int lane = threadIdx.x;
   const int ngroups = uniform_first(min((int)A.cnt->n_groups, A.ngroups_bound));
+  CandSlab S;
+  unsigned long long n_int = 0;  // this wavefront's interactions, added once at its end
   for (int iter = 0;; ++iter) {
     const int gi = next_gi(A, lane, iter, ngroups);
     if (gi >= ngroups) break;
     GroupHdr h;
     if (!group_header(A, gi, h)) continue;
     if (h.count > WAVE)
-      near_group<2, UNR>(A, h, T, lane);
+      near_group<MIXED, 2, UNR>(A, h, T, lane, S);
     else
-      near_group<1, UNR>(A, h, T, lane);
-    if (lane == 0) {
-      const unsigned long long ni = (unsigned long long)h.count;
-      atomicAdd(&A.cnt->n_near, ni * (unsigned long long)h.n_near - ni);
-    }
+      near_group<MIXED, 1, UNR>(A, h, T, lane, S);
+    const unsigned long long ni = (unsigned long long)h.count;
+    n_int += ni * (unsigned long long)h.n_near - ni;
   }
+  close_slab(A, S, lane);
+  if (lane == 0 && n_int) atomicAdd(&A.cnt->n_near, n_int);
 }
 
 // ------------------------------------------------------------------ far
@@ -342,6 +415,7 @@ __global__ __launch_bounds__(WAVE) void k_far(ForceArgs A) {
   __shared__ FarTile T;
   const int lane = threadIdx.x;
   const int ngroups = uniform_first(min((int)A.cnt->n_groups, A.ngroups_bound));
+  unsigned long long n_int = 0;  // this wavefront's interactions, added once at its end
   for (int iter = 0;; ++iter) {
     const int gi = next_gi(A, lane, iter, ngroups);
     if (gi >= ngroups) break;
@@ -352,8 +426,9 @@ __global__ __launch_bounds__(WAVE) void k_far(ForceArgs A) {
       far_group<MIXED, 2, UNR>(A, h, T, lane);
     else
       far_group<MIXED, 1, UNR>(A, h, T, lane);
-    if (lane == 0) atomicAdd(&A.cnt->n_far, (unsigned long long)h.count * (unsigned long long)h.n_far);
+    n_int += (unsigned long long)h.count * (unsigned long long)h.n_far;
   }
+  if (lane == 0 && n_int) atomicAdd(&A.cnt->n_far, n_int);
 }
 
 // ------------------------------------------------------------------ cells
@@ -537,6 +612,7 @@ __global__ __launch_bounds__(WAVE) void k_cell(ForceArgs A) {
   __shared__ CellTile T;
   const int lane = threadIdx.x;
   const int ngroups = uniform_first(min((int)A.cnt->n_groups, A.ngroups_bound));
+  unsigned long long n_int = 0;  // this wavefront's interactions, added once at its end
   for (int iter = 0;; ++iter) {
     const int gi = next_gi(A, lane, iter, ngroups);
     if (gi >= ngroups) break;
@@ -547,8 +623,9 @@ __global__ __launch_bounds__(WAVE) void k_cell(ForceArgs A) {
       cell_group<MIXED, QUAD, 2, UNR>(A, h, T, lane);
     else
       cell_group<MIXED, QUAD, 1, UNR>(A, h, T, lane);
-    if (lane == 0) atomicAdd(&A.cnt->n_cell, (unsigned long long)h.count * (unsigned long long)h.n_cell);
+    n_int += (unsigned long long)h.count * (unsigned long long)h.n_cell;
   }
+  if (lane == 0 && n_int) atomicAdd(&A.cnt->n_cell, n_int);
 }
 
 // exact neighbour test of every candidate (sorted indices) -> pairs in the
@@ -563,8 +640,8 @@ __global__ void k_cand_test(ForceArgs A) {
     const long long p = p0 + lane;
     bool nb = false;
     int i = 0, j = 0;
-    if (p < m) {
-      const int2 c = A.cands[p];
+    const int2 c = p < m ? A.cands[p] : make_int2(-1, -1);
+    if (c.x >= 0) {  // (-1, -1): a slot its wavefront left unused
       i = c.x;
       j = c.y;
       // a slow member sits at its pre-drift position here; its pairs are
@@ -578,8 +655,7 @@ __global__ void k_cand_test(ForceArgs A) {
     const unsigned long long bal = __ballot(nb);
     if (bal == 0ull) continue;
     const int leader = __ffsll((long long)bal) - 1;
-    const unsigned long long o0 = (unsigned long long)uniform_lane64(
-        (long long)atomicAdd(&A.cnt->n_pairs, lane == leader ? (unsigned long long)__popcll(bal) : 0ull), leader);
+    const unsigned long long o0 = wave_fetch_add(&A.cnt->n_pairs, (unsigned long long)__popcll(bal), leader);
     if (nb) {
       mark_close_pair(A, i, j);
       const unsigned long long q = o0 + popc_below(bal);
@@ -623,7 +699,10 @@ hipError_t launch_split(p3t_ctx *c, ForceArgs A, unsigned nonpersistent_grid, do
     return A.persistent ? persistent_grid(kernel, c->n_cu, cap) : nonpersistent_grid;
   };
   A.queue = &c->cnt->queue[0];
-  hipLaunchKernelGGL((k_near<UNR>), dim3(grid(k_near<UNR>)), dim3(WAVE), 0, s, A);
+  if (mixed)
+    hipLaunchKernelGGL((k_near<true, UNR>), dim3(grid(k_near<true, UNR>)), dim3(WAVE), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_near<false, UNR>), dim3(grid(k_near<false, UNR>)), dim3(WAVE), 0, s, A);
   ev_record(c, 11);
   A.queue = &c->cnt->queue[1];
   if (mixed)

@@ -99,6 +99,19 @@ __device__ __forceinline__ long long uniform_lane64(long long v, int l) {
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
+// The old value of *p after adding v (wave-uniform) once for the whole
+// wavefront, returned to every lane.  Lane `from` alone issues the atomic:
+// an atomic that every lane executes (the others adding zero) is expanded
+// by the compiler into a scalar loop over the 64 lanes before the single
+// memory operation.  Every lane of the wavefront must call it, with lane
+// `from` active.
+__device__ __forceinline__ unsigned long long wave_fetch_add(unsigned long long *p, unsigned long long v,
+                                                             int from = 0) {
+  unsigned long long r = 0;
+  if ((int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)) == from) r = atomicAdd(p, v);
+  return (unsigned long long)uniform_lane64((long long)r, from);
+}
+
 // inclusive wave scan of int
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int l = lane_id();

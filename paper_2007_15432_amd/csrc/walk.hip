@@ -35,7 +35,7 @@ __global__ __launch_bounds__(WAVE) void k_walk(const WalkNode *__restrict__ wn, 
   for (;;) {
     // every lane executes the atomic (lane 0 adds one, the others zero), so
     // no divergent branch feeds the loop exit; lane 0's ticket goes to an SGPR
-    const int gi = uniform_first((int)atomicAdd(&cnt->walk_queue, lane == 0 ? 1ull : 0ull));
+    const int gi = (int)wave_fetch_add(&cnt->walk_queue, 1ull);
     if (gi >= ngroups) break;
     const int g = group_node[gi];
     double glo[3], ghi[3];
@@ -129,8 +129,7 @@ __global__ __launch_bounds__(WAVE) void k_walk(const WalkNode *__restrict__ wn, 
     }
     __syncthreads();
     const int total = ncell + nnear + nfar;
-    const long long off = uniform_first64(
-        (long long)atomicAdd(&cnt->pool_cursor, lane == 0 ? (unsigned long long)total : 0ull));
+    const long long off = (long long)wave_fetch_add(&cnt->pool_cursor, (unsigned long long)total);
     if (off + total > pool_cap) {
       if (lane == 0) {
         set_flag(cnt, P3T_FLAG_LIST_OVERFLOW);
