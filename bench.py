@@ -45,6 +45,10 @@ sys.path.insert(0, ROOT)
 #   quadrupole cell: monopole 18 + Q d 15 + d.Q d 5 + r^-5 1
 #     + (5/2) dQd r^-7 3 + per-axis c7 d - Q d r^-5 and sum 12           = 54
 FLOPS_NEAR = 35
+#   mixed near pair (K = 1 beyond both cut-offs; all but a fraction of a
+#   percent of the near lists): FP64 offsets 3, r^2 5, changeover test 4
+#   (min, 2 mul, compare); FP32 r^2 5, rsqrt 1, G m r^-3 3, accumulate 6  = 27
+FLOPS_NEAR_MIXED = 27
 FLOPS_FAR = 18
 FLOPS_MONO = 18
 FLOPS_QUAD = 54
@@ -197,7 +201,9 @@ def kernel_rooflines(out, stage, steps, precision):
     interaction) over its event-timed average launch duration."""
     fp32 = precision == 1
     spec = {
-        "near": (out["n_near"] * FLOPS_NEAR, PEAK_FP64, "fp64"),
+        # mixed: mostly FP32 arithmetic on FP64 offsets, priced at the FP32 peak
+        "near": ((out["n_near"] * FLOPS_NEAR_MIXED, PEAK_FP32, "fp32+fp64") if fp32 else
+                 (out["n_near"] * FLOPS_NEAR, PEAK_FP64, "fp64")),
         "far": (out["n_far"] * FLOPS_FAR, PEAK_FP32 if fp32 else PEAK_FP64, "fp32" if fp32 else "fp64"),
         "cell": (out["n_cell"] * FLOPS_QUAD, PEAK_FP32 if fp32 else PEAK_FP64, "fp32" if fp32 else "fp64"),
     }

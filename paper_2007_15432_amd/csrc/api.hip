@@ -1180,6 +1180,7 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
     HIP_OK(c, hipMemsetAsync(&c->cnt->status_d, 0, sizeof(unsigned int), c->stream));
     HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
     HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
+    HIP_OK(c, slow_sort(c, ns, c->slow_stream));  // while the chip is free, not behind the tree's kernels
     HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
                           steps, hc, 0, 1, c->slow_stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
     HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, ns, c->slow_stream));

@@ -436,6 +436,8 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
 // after the join, on the main stream: S's state into pos3 / vel3, and (acc3
 // not null) the direct terms into acc3 and their pairs behind the others
 hipError_t slow_merge(p3t_ctx *c, double *pos3, double *vel3, double *acc3, int ns);
+// the parked members' list in ascending order, before the direct terms
+hipError_t slow_sort(p3t_ctx *c, int ns, hipStream_t s);
 hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns);
 hipError_t hermite_clusters(p3t_ctx *c, int64_t n, int64_t nc, const int32_t *cl_ptr, const int32_t *cl_members,
                             double *pos3, double *vel3, const double *mass, const double *r_out, double *dt_hard,

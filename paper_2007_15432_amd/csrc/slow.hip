@@ -109,14 +109,15 @@ struct SlowArgs {
 
 constexpr int ST = 256;  // threads per block of the direct kernels
 
-// bitonic sort of the slow list (at most SLOW_CAP entries) in one workgroup,
-// so that the direct sums run in ascending member order
+// bitonic sort of the slow list (n <= w entries, w = blockDim.x a power of
+// two <= SLOW_CAP) in one workgroup, so that the direct sums run in
+// ascending member order
 __global__ __launch_bounds__(SLOW_CAP) void k_sort_list(int32_t *a, int n) {
   __shared__ int32_t v[SLOW_CAP];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, w = blockDim.x;
   v[t] = t < n ? a[t] : 0x7fffffff;
   __syncthreads();
-  for (int k = 2; k <= SLOW_CAP; k <<= 1) {
+  for (int k = 2; k <= w; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       const int p = t ^ j;
       if (p > t) {
@@ -341,10 +342,20 @@ hipError_t slow_prepare(p3t_ctx *c, const double *mass, int ns) {
   return hipGetLastError();
 }
 
+// The parked members in ascending order (the list is complete when the
+// budgeted launch ends; the resume does not read it), in a workgroup of the
+// next power of two threads, at least one wavefront.
+hipError_t slow_sort(p3t_ctx *c, int ns, hipStream_t s) {
+  if (ns <= 1 || ns > SLOW_CAP) return hipSuccess;
+  int w = WAVE;
+  while (w < ns) w <<= 1;
+  hipLaunchKernelGGL(k_sort_list, dim3(1), dim3(w), 0, s, c->slow_list, ns);
+  return hipGetLastError();
+}
+
 hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const double *mass, const double *r_out,
                        const double *r_search, int ns, hipStream_t s) {
   const int64_t n = c->n;
-  if (ns > 1 && ns <= SLOW_CAP) hipLaunchKernelGGL(k_sort_list, dim3(1), dim3(SLOW_CAP), 0, s, c->slow_list, ns);
   SlowArgs A;
   A.pos = pos3;
   A.vel = vel3;
