@@ -94,7 +94,7 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   total += bytes(n2, sizeof(int32_t)) + bytes(n2 + 1, sizeof(int64_t));  // group_flag, node_scan
   total += bytes(n_cap, sizeof(int32_t));                               // group_node
   total += bytes(n_cap, sizeof(GroupList));
-  total += 2 * bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));  // order, keys
+  total += bytes(n_cap, sizeof(int32_t));                                           // group order
   total += bytes(n_cap, sizeof(int32_t)) + bytes(n_cap + 1, sizeof(int64_t));       // row_cnt, csr_ptr
   total += bytes(n_cap, sizeof(int32_t)) + 2 * bytes(n_cap, sizeof(uint64_t));      // uf, cl keys
   total += bytes(cut_part_need(n_cap), sizeof(double)) + bytes(n_cap, sizeof(int32_t));  // cut-off bins
@@ -139,9 +139,6 @@ p3t_status alloc_arena(p3t_ctx *c, int64_t n_cap) {
   c->group_node = A.take<int32_t>(n_cap);
   c->glist = A.take<GroupList>(n_cap);
   c->group_order = A.take<int32_t>(n_cap);
-  c->gorder_alt = A.take<int32_t>(n_cap);
-  c->gkey = A.take<uint64_t>(n_cap);
-  c->gkey_alt = A.take<uint64_t>(n_cap);
   c->row_cnt = A.take<int32_t>(n_cap);
   c->csr_ptr = A.take<int64_t>(n_cap + 1);
   c->uf_parent = A.take<int32_t>(n_cap);

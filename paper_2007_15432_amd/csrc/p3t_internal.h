@@ -270,8 +270,6 @@ struct p3t_ctx {
   p3t::CellMom *cmom = nullptr;
   int32_t *group_flag = nullptr;
   int64_t *node_scan = nullptr;     // exclusive scan over nodes (2n)
-  uint64_t *gkey = nullptr, *gkey_alt = nullptr;  // group work keys (n)
-  int32_t *gorder_alt = nullptr;
   int32_t *group_node = nullptr;
   p3t::GroupList *glist = nullptr;
   int32_t *group_order = nullptr;   // groups sorted by work (longest first)

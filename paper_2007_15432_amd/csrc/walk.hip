@@ -21,6 +21,8 @@
 
 namespace p3t {
 
+constexpr int GROUP_CLASSES = 128;
+
 __global__ __launch_bounds__(WAVE) void k_walk(const WalkNode *__restrict__ wn, const int32_t *__restrict__ group_node,
                                                DevCounters *cnt, GroupList *__restrict__ gl, int32_t *__restrict__ pool,
                                                int64_t pool_cap, int32_t *__restrict__ slot_lists, int cap,
@@ -172,22 +174,47 @@ __global__ void k_reset_queues(DevCounters *cnt) {
 // A device count above n_static (the host's bound, from the last evaluation)
 // sets P3T_FLAG_GROUP_BOUND: the sort and the force then cover only the
 // first n_static groups and the host evaluates again with the bound n.
-__global__ void k_group_keys(const GroupList *__restrict__ gl, const WalkNode *__restrict__ wn, int n_static,
-                             DevCounters *cnt, uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
-  const int ng = (int)cnt->n_groups;
-  if (ng > n_static && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&cnt->status, P3T_FLAG_GROUP_BOUND);
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_static; g += gridDim.x * blockDim.x) {
-    if (g < ng) {
-      const GroupList L = gl[g];
-      const uint64_t ni = (uint64_t)wn[L.node].count;
-      uint64_t work = ni * (uint64_t)(L.n_near + L.n_far + 2 * L.n_cell) / 64;
-      if (work > 0xffffffffull) work = 0xffffffffull;
-      key[g] = ((0xffffffffull - work) << 32) | (uint64_t)(uint32_t)g;
-    } else {
-      key[g] = ~0ull;
-    }
-    idx[g] = g;
+// Work of a group (its i-particles times its list entries, cells counted
+// twice), in classes of half an octave: the force kernels take the groups
+// in descending class, so the longest lists start first and the tail of
+// the launch is short.  Only the order of the work depends on it.
+__device__ __forceinline__ int group_class(const GroupList &L, const WalkNode *__restrict__ wn) {
+  const uint64_t ni = (uint64_t)wn[L.node].count;
+  const uint64_t work = ni * (uint64_t)(L.n_near + L.n_far + 2 * L.n_cell) / 64 + 1;
+  const int msb = 63 - __clzll((long long)work);
+  const int half = msb > 0 ? (int)((work >> (msb - 1)) & 1ull) : 0;
+  return min(GROUP_CLASSES - 1, 2 * msb + half);
+}
+
+// One workgroup: a counting sort of the groups by class, largest first
+// (within a class in any order).  A device count above n_static (the host's
+// bound, from the last evaluation) sets P3T_FLAG_GROUP_BOUND: the order and
+// the force then cover only the first n_static groups and the host
+// evaluates again with the bound n.
+__global__ __launch_bounds__(1024) void k_group_order(const GroupList *__restrict__ gl,
+                                                      const WalkNode *__restrict__ wn, int n_static, DevCounters *cnt,
+                                                      int32_t *__restrict__ order) {
+  __shared__ int hist[GROUP_CLASSES];
+  const int t = threadIdx.x;
+  int ng = (int)cnt->n_groups;
+  if (ng > n_static) {
+    if (t == 0) atomicOr(&cnt->status, P3T_FLAG_GROUP_BOUND);
+    ng = n_static;
   }
+  for (int q = t; q < GROUP_CLASSES; q += blockDim.x) hist[q] = 0;
+  __syncthreads();
+  for (int g = t; g < ng; g += blockDim.x) atomicAdd(&hist[group_class(gl[g], wn)], 1);
+  __syncthreads();
+  if (t == 0) {  // exclusive offsets, largest class first
+    int acc = 0;
+    for (int q = GROUP_CLASSES - 1; q >= 0; --q) {
+      const int h = hist[q];
+      hist[q] = acc;
+      acc += h;
+    }
+  }
+  __syncthreads();
+  for (int g = t; g < ng; g += blockDim.x) order[atomicAdd(&hist[group_class(gl[g], wn)], 1)] = g;
 }
 
 hipError_t walk_groups(p3t_ctx *c, int64_t n_groups_max) {
@@ -197,19 +224,11 @@ hipError_t walk_groups(p3t_ctx *c, int64_t n_groups_max) {
   hipLaunchKernelGGL(k_walk, dim3(c->walk_slots), dim3(WAVE), 0, s, c->wnode, c->group_node, c->cnt, c->glist, c->pool,
                      c->pool_cap, c->slot_lists, (int)c->slot_cap_list, c->slot_stack, (int)c->slot_cap_stack, th * th,
                      c->P.n_leaf_max);
-  // longest-first order for the force kernel
-  const int ns = (int)n_groups_max;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n_groups_max + 255) / 256));
-  hipLaunchKernelGGL(k_group_keys, dim3(g), dim3(256), 0, s, c->glist, c->wnode, ns, c->cnt, c->gkey,
-                     c->group_order);
-  uint64_t *k = c->gkey, *ka = c->gkey_alt;
-  int32_t *v = c->group_order, *va = c->gorder_alt;
-  // the device-side group count bounds the sort, so n_groups_max may be any
-  // upper bound (a captured graph passes the particle count)
-  hipError_t e = radix_sort_pairs(k, v, ka, va, n_groups_max, &c->cnt->n_groups, 32, 64, c->radix_hist,
-                                  c->radix_hist_cap, c->scan_tmp, c->scan_tmp_cap, s);
-  if (e != hipSuccess) return e;
-  // 4 passes: the sorted order is back in group_order
+  // longest-first order for the force kernels; the device-side group count
+  // bounds it, so n_groups_max may be any upper bound (a captured graph
+  // passes the particle count)
+  const int ns = (int)std::min<int64_t>(n_groups_max, INT32_MAX);
+  hipLaunchKernelGGL(k_group_order, dim3(1), dim3(1024), 0, s, c->glist, c->wnode, ns, c->cnt, c->group_order);
   return hipGetLastError();
 }
 
