@@ -446,25 +446,39 @@ union CellTile {
 };
 
 template <typename R>
-__device__ __forceinline__ void cell_term(R dx, R dy, R dz, R gm, R q0, R q1, R q2, R q3, R q4, R q5, bool quad,
-                                          R rinv, R &fx, R &fy, R &fz) {
-  // a = G [ M d / r^3 - Q d / r^5 + (5/2) (d.Q d) d / r^7 ],  d = X_c - x_i
+__device__ __forceinline__ R fma_r(R a, R b, R c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_r<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+// The cell term added to (ax, ay, az):
+//   a = G [ M d / r^3 - Q d / r^5 + (5/2) (d.Q d) d / r^7 ],  d = X_c - x_i,
+// as d (G M / r^3 + (5/2) (d.Q d) / r^7) - Q d / r^5, so that each
+// component is two fused multiply-adds onto the running sum.
+template <typename R>
+__device__ __forceinline__ void cell_acc(R dx, R dy, R dz, R gm, R q0, R q1, R q2, R q3, R q4, R q5, bool quad,
+                                         R rinv, R &ax, R &ay, R &az) {
   const R rinv2 = rinv * rinv;
   const R rinv3 = rinv * rinv2;
-  fx = gm * rinv3 * dx;
-  fy = gm * rinv3 * dy;
-  fz = gm * rinv3 * dz;
-  if (quad) {
-    const R qx = q0 * dx + q3 * dy + q4 * dz;
-    const R qy = q3 * dx + q1 * dy + q5 * dz;
-    const R qz = q4 * dx + q5 * dy + q2 * dz;
-    const R dqd = dx * qx + dy * qy + dz * qz;
-    const R rinv5 = rinv3 * rinv2;
-    const R c7 = R(2.5) * dqd * rinv5 * rinv2;
-    fx += c7 * dx - qx * rinv5;
-    fy += c7 * dy - qy * rinv5;
-    fz += c7 * dz - qz * rinv5;
+  if (!quad) {
+    const R f = gm * rinv3;
+    ax = fma_r(f, dx, ax);
+    ay = fma_r(f, dy, ay);
+    az = fma_r(f, dz, az);
+    return;
   }
+  const R qx = fma_r(q4, dz, fma_r(q3, dy, q0 * dx));
+  const R qy = fma_r(q5, dz, fma_r(q1, dy, q3 * dx));
+  const R qz = fma_r(q2, dz, fma_r(q5, dy, q4 * dx));
+  const R dqd = fma_r(dz, qz, fma_r(dy, qy, dx * qx));
+  const R rinv5 = rinv3 * rinv2;
+  const R f = fma_r(gm, rinv3, R(2.5) * dqd * (rinv5 * rinv2));
+  ax = fma_r(-qx, rinv5, fma_r(f, dx, ax));
+  ay = fma_r(-qy, rinv5, fma_r(f, dy, ay));
+  az = fma_r(-qz, rinv5, fma_r(f, dz, az));
 }
 
 template <bool MIXED, bool QUAD, int IPL, int UNR>
@@ -517,11 +531,8 @@ __device__ __forceinline__ void cell_group(const ForceArgs &A, const GroupHdr &h
           for (int s = 0; s < IPL; ++s) {
             const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
             const double r2 = dx * dx + dy * dy + dz * dz;
-            double fx, fy, fz;
-            cell_term<double>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, rsqrt(r2), fx, fy, fz);
-            ax[s] += fx;
-            ay[s] += fy;
-            az[s] += fz;
+            cell_acc<double>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, rsqrt(r2), ax[s], ay[s],
+                             az[s]);
           }
         }
       }
@@ -573,12 +584,8 @@ __device__ __forceinline__ void cell_group(const ForceArgs &A, const GroupHdr &h
           for (int s = 0; s < IPL; ++s) {
             const float dx = a.x - fxi[s], dy = a.y - fyi[s], dz = a.z - fzi[s];
             const float r2 = dx * dx + dy * dy + dz * dz;
-            float fx, fy, fz;
-            cell_term<float>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, __frsqrt_rn(r2), fx, fy,
-                             fz);
-            tx[s] += fx;
-            ty[s] += fy;
-            tz[s] += fz;
+            cell_acc<float>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, __frsqrt_rn(r2), tx[s], ty[s],
+                            tz[s]);
           }
         }
       }

@@ -122,7 +122,7 @@ hipError_t scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *
 // digits inside a wavefront with ballots and across wavefronts with
 // per-round counters.  Three launches per pass, no device-wide scan.
 constexpr int RS_T = 256;
-constexpr int RS_I = 16;
+constexpr int RS_I = 8;  // tiles of 2048 keys: 512 workgroups per pass for 2^20 keys
 constexpr int RS_TILE = RS_T * RS_I;
 constexpr int RS_W = RS_T / WAVE;
 
