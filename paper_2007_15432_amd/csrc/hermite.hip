@@ -1523,6 +1523,7 @@ struct BucketArgs {
   DevCounters *cnt;
   int reset_work;  // zero the Hermite work counters
   CloseSrc close;  // member flags that make a cluster of buckets 1..3 close
+  int32_t *wgc;    // per-chunk category counts, then their offsets (N_CATS rows)
 };
 
 __device__ bool cluster_close(int a, int b, const BucketArgs &B) {
@@ -1536,72 +1537,109 @@ __device__ bool cluster_close(int a, int b, const BucketArgs &B) {
 // Categories: the buckets 0..10, and N_BUCKETS + k - 1 for the clusters of
 // bucket k = 1..3 with a close pair.  The close ones are written from the
 // end of their bucket's list backwards (count in bcount[HERM_BC_CLOSE0 + k
-// - 1]), the others from its start.
+// - 1]), the others from its start.  Three launches, each over one
+// 256-cluster chunk per workgroup: the category counts of every chunk
+// (k_bucket_count), their exclusive scan over the chunks per category
+// (k_bucket_scan, one workgroup per category), and the entries in cluster
+// order (k_bucket_write).  B.wgc holds N_CATS rows of nchunk counts.
 constexpr int N_CATS = N_BUCKETS + 3;
+constexpr int BK_T = 256;
 
-__global__ __launch_bounds__(256) void k_herm_bucket(BucketArgs B) {
-  __shared__ int cnt[N_CATS], base[N_CATS];
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
-  const int64_t nc = B.nc_dev ? *B.nc_dev : B.nc_host;  // clusters (at most stride)
-  int32_t *bcount = B.bcount;
-  if (blockIdx.x == 0 && tid == 0) {
-    bcount[BC_NC] = (int32_t)nc;
+__device__ __forceinline__ int64_t bucket_nc(const BucketArgs &B) {
+  return B.nc_dev ? *B.nc_dev : B.nc_host;  // clusters (at most stride)
+}
+
+// category of cluster c (-1: empty or beyond the count)
+__device__ __forceinline__ int cluster_category(const BucketArgs &B, int64_t c, int64_t nc) {
+  if (c >= nc) return -1;
+  int cat = cluster_bucket(c, B.n, B.cap, B.cl_ptr, B.members, B.bcount);
+  if (cat >= 1 && cat <= 3 && (B.close.a || B.close.b) && cluster_close(B.cl_ptr[c], B.cl_ptr[c + 1], B))
+    cat += N_BUCKETS - 1;
+  return cat;
+}
+
+// per wavefront: the mask of its lanes in category q, for every q (all lanes
+// take part); returns this lane's mask
+__device__ __forceinline__ unsigned long long cat_masks(int cat, int *wcount, int lane) {
+  unsigned long long mine = 0ull;
+  for (int q = 0; q < N_CATS; ++q) {
+    const unsigned long long mask = __ballot(cat == q);
+    if (lane == 0) wcount[q] = (int)__popcll(mask);
+    if (q == cat) mine = mask;
+  }
+  return mine;
+}
+
+__global__ __launch_bounds__(BK_T) void k_bucket_count(BucketArgs B, int nchunk) {
+  __shared__ int wc[BK_T / WAVE][N_CATS];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+  const int64_t nc = bucket_nc(B);
+  if (blockIdx.x == 0 && t == 0) {
+    B.bcount[BC_NC] = (int32_t)nc;
     if (B.reset_work) {  // the work counters of this hard part
       B.cnt->n_heval = 0;
       B.cnt->n_hpair = 0;
       B.cnt->n_coll = 0;
     }
   }
-  const int64_t per = (nc + gridDim.x - 1) / gridDim.x;
-  const int64_t c0 = (int64_t)blockIdx.x * per, c1 = c0 + per < nc ? c0 + per : nc;
-  if (tid < N_CATS) cnt[tid] = 0;
+  const int64_t c = (int64_t)blockIdx.x * BK_T + t;
+  const int cat = cluster_category(B, c, nc);
+  if (c < nc) B.cl_bk[c] = cat;
+  cat_masks(cat, wc[w], lane);
   __syncthreads();
-  for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {
-    const int64_t c = b0 + tid;
-    int cat = c < c1 ? cluster_bucket(c, B.n, B.cap, B.cl_ptr, B.members, bcount) : -1;
-    if (cat >= 1 && cat <= 3 && (B.close.a || B.close.b) && cluster_close(B.cl_ptr[c], B.cl_ptr[c + 1], B))
-      cat += N_BUCKETS - 1;
-    if (c < c1) B.cl_bk[c] = cat;
-    for (int q = 0; q < N_CATS; ++q) {
-      const unsigned long long mask = __ballot(cat == q);
-      if (mask != 0ull && lane == __ffsll((long long)mask) - 1) atomicAdd(&cnt[q], (int)__popcll(mask));
-    }
+  if (t < N_CATS) {
+    int tot = 0;
+    for (int u = 0; u < BK_T / WAVE; ++u) tot += wc[u][t];
+    B.wgc[(int64_t)t * nchunk + blockIdx.x] = tot;
   }
-  __syncthreads();
-  if (tid < N_CATS) {
-    int32_t *word = tid < N_BUCKETS ? &bcount[tid] : &bcount[HERM_BC_CLOSE0 + tid - N_BUCKETS];
-    base[tid] = cnt[tid] > 0 ? atomicAdd(word, cnt[tid]) : 0;
-    cnt[tid] = 0;
+}
+
+// row q of wgc becomes its exclusive scan over the chunks; the row total is
+// the category's count
+__global__ __launch_bounds__(BK_T) void k_bucket_scan(BucketArgs B, int nchunk) {
+  __shared__ int ws[BK_T / WAVE];
+  const int q = blockIdx.x, t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+  int32_t *row = B.wgc + (int64_t)q * nchunk;
+  int carry = 0;
+  for (int c0 = 0; c0 < nchunk; c0 += BK_T) {  // uniform
+    const int i = c0 + t;
+    const int v = i < nchunk ? row[i] : 0;
+    const int incl = wave_incl_scan(v);
+    if (lane == WAVE - 1) ws[w] = incl;
+    __syncthreads();
+    int before = 0, chunk = 0;
+    for (int u = 0; u < BK_T / WAVE; ++u) {
+      before += u < w ? ws[u] : 0;
+      chunk += ws[u];
+    }
+    if (i < nchunk) row[i] = carry + before + incl - v;
+    carry += chunk;
+    __syncthreads();  // ws is rewritten by the next chunk
   }
+  if (t == 0) {
+    if (q < N_BUCKETS)
+      B.bcount[q] = carry;
+    else
+      B.bcount[HERM_BC_CLOSE0 + q - N_BUCKETS] = carry;
+  }
+}
+
+__global__ __launch_bounds__(BK_T) void k_bucket_write(BucketArgs B, int nchunk) {
+  __shared__ int wc[BK_T / WAVE][N_CATS];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+  const int64_t nc = bucket_nc(B);
+  const int64_t c = (int64_t)blockIdx.x * BK_T + t;
+  const int cat = c < nc ? B.cl_bk[c] : -1;  // as decided by k_bucket_count
+  const unsigned long long mine = cat_masks(cat, wc[w], lane);
   __syncthreads();
-  __shared__ int wofs[BIG_T / WAVE][N_CATS];
-  const int w = tid / WAVE;
-  for (int64_t b0 = c0; b0 < c1; b0 += blockDim.x) {  // uniform over the workgroup
-    const int64_t c = b0 + tid;
-    const int cat = c < c1 ? B.cl_bk[c] : -1;  // as decided above
-    unsigned long long mine = 0ull;
-    for (int q = 0; q < N_CATS; ++q) {
-      const unsigned long long mask = __ballot(cat == q);
-      if (lane == 0) wofs[w][q] = (int)__popcll(mask);
-      if (q == cat) mine = mask;
-    }
-    __syncthreads();
-    if (cat >= 0) {
-      int off = 0;
-      for (int u = 0; u < w; ++u) off += wofs[u][cat];  // wavefronts take their slots in order
-      const int64_t k = base[cat] + cnt[cat] + off + popc_below(mine);
-      if (cat < N_BUCKETS)
-        B.blists[(int64_t)cat * B.stride + k] = (int32_t)c;
-      else
-        B.blists[(int64_t)(cat - N_BUCKETS + 1) * B.stride + B.stride - 1 - k] = (int32_t)c;
-    }
-    __syncthreads();
-    if (tid < N_CATS) {
-      int tot = 0;
-      for (int u = 0; u < BIG_T / WAVE; ++u) tot += wofs[u][tid];
-      cnt[tid] += tot;
-    }
-    __syncthreads();
+  if (cat >= 0) {
+    int off = 0;
+    for (int u = 0; u < w; ++u) off += wc[u][cat];  // wavefronts take their slots in order
+    const int64_t k = (int64_t)B.wgc[(int64_t)cat * nchunk + blockIdx.x] + off + popc_below(mine);
+    if (cat < N_BUCKETS)
+      B.blists[(int64_t)cat * B.stride + k] = (int32_t)c;
+    else
+      B.blists[(int64_t)(cat - N_BUCKETS + 1) * B.stride + B.stride - 1 - k] = (int32_t)c;
   }
 }
 
@@ -1656,8 +1694,14 @@ hipError_t herm_bucket_enqueue(p3t_ctx *c, hipStream_t s, int64_t n, int64_t nc,
   B.cnt = c->cnt;
   B.reset_work = reset_work ? 1 : 0;
   B.close = close;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->n_cu * 2, (nc + 255) / 256));
-  hipLaunchKernelGGL(k_herm_bucket, dim3(g), dim3(256), 0, s, B);
+  // the per-chunk counts use the radix sort's histogram buffer, which is
+  // free here (it holds 256 entries per 2048 keys, these N_CATS per 256)
+  const int64_t nchunk = std::max<int64_t>(1, (nc + BK_T - 1) / BK_T);
+  if (nchunk * N_CATS > c->radix_hist_cap || nchunk > INT32_MAX) return hipErrorInvalidValue;
+  B.wgc = reinterpret_cast<int32_t *>(c->radix_hist);
+  hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)nchunk), dim3(BK_T), 0, s, B, (int)nchunk);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(N_CATS), dim3(BK_T), 0, s, B, (int)nchunk);
+  hipLaunchKernelGGL(k_bucket_write, dim3((unsigned)nchunk), dim3(BK_T), 0, s, B, (int)nchunk);
   return hipMemcpyAsync(hc, c->herm_bcount, sizeof(int32_t) * BC_WORDS, hipMemcpyDeviceToHost, s);
 }
 
