@@ -463,14 +463,22 @@ def main():
     if not args.no_cpu and "fp64" in results:
         base, errs = cpu_baseline(disk, results, args.cpu_sample, herm=herm)
     h = results[head]
+    # The headline is the mixed path as a caller runs it fastest: tree + walk
+    # + force replayed from the captured graph.  The same steps run eagerly
+    # first, where every force kernel is event-timed on its own stream (the
+    # kernels of a replayed graph cannot be); the roofline comes from there.
+    use_graph = graph is not None and head == "mixed"
+    if use_graph:
+        graph["same_work"] = graph["interactions_per_step"] == h["interactions_per_step"]
+    top = graph if use_graph else h
     line = {
         "metric": METRIC,
-        "value": h["value"],
+        "value": top["value"],
         "unit": "interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": h["ms_per_step"],
+        "ms_per_step": top["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -484,9 +492,9 @@ def main():
                         f"steps); particles without neighbours: {args.isolated}; cut-off radii fixed between "
                         f"collisions, the current ones computed every step; {args.warmup + args.steps} "
                         "consecutive steps from the initial disk",
-            "path": head,
+            "path": head + (", tree + walk + force replayed from a captured hipGraph" if use_graph else ""),
         },
-        "roofline": {k: v for k, v in h["roofline"].items()},
+        "roofline": dict(h["roofline"], timed_in="eager run of the same path and steps" if use_graph else "this run"),
         "cpu_baseline": base,
         "interactions_per_step": h["interactions_per_step"],
         "stages_ms": h["stages_ms"],
@@ -508,6 +516,9 @@ def main():
                                         "largest_cluster")}
     if graph:
         line["graph"] = graph
+    if use_graph:
+        line["eager"] = {"value": h["value"], "ms_per_step": h["ms_per_step"],
+                         "path": "mixed, every launch issued by the host, stage and kernel events recorded"}
     if tuned:
         line["autotune"] = {"params": tuned.params, "kernel": tuned.kernel, "ms_eval": tuned.ms,
                             "seconds": tuned.seconds, "trials": len(tuned.trials), "list_sweep": tuned.sweep}
