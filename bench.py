@@ -87,7 +87,7 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
     n_slow = 0
     max_steps = []  # longest block-step chain of each step (device scalars, read after the timed region)
     largest = []    # largest cluster of each step
-    ctx.set_timing(True)
+    ctx.set_timing(not graph)  # stage events only where the stages are reported
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -101,11 +101,12 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
         for k in stage:
             stage[k] += s[k]
         n_slow += st.n_slow
-        max_steps.append(st.steps.max())
+        if not graph:  # a reduction per step; the replayed run leaves it out
+            max_steps.append(st.steps.max())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_timing(False)
-    max_steps = [int(v) for v in max_steps]
+    max_steps = [int(v) for v in max_steps] or [int(st.steps.max())]
     inter = near + far + cell
     sec = (t1 - t0) / steps
     s = ctx.stats()
@@ -114,7 +115,7 @@ def run_path(p3t, torch, disk, precision, steps, warmup, n_group, n_leaf, graph=
                n_pairs=s["n_pairs"], n_clusters=st.n_clusters, n_slow=n_slow / steps,
                stages_ms={k[3:]: v / steps for k, v in stage.items()},
                hermite=dict(evaluations=heval // steps, pair_terms=hpair // steps, max_block_steps=max(max_steps),
-                            mean_max_block_steps=sum(max_steps) / steps))
+                            mean_max_block_steps=sum(max_steps) / len(max_steps)))
     h = out["hermite"]
     ms_h = out["stages_ms"]["hermite"]
     if ms_h > 0 and not overlap:

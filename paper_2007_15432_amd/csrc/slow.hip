@@ -12,8 +12,8 @@
 //     every (i, s) that passes the neighbour test of Section 2.3 is reported
 //     in both directions;
 //   - every s in S gets sum_{j != s} over all particles (partial sums over
-//     SLOW_CHUNKS ranges of j, added in order), and the pairs (s, s') with s'
-//     in S are reported from both sides;
+//     SLOW_CHUNKS ranges of j, added in a fixed order), and the pairs
+//     (s, s') with s' in S are reported from both sides;
 //   - in mixed precision the pairs beyond the larger cut-off (K = 1) take
 //     the Newtonian term in FP32 from an FP64 offset, like the far-particle
 //     kernel; everything else is FP64.
@@ -54,15 +54,21 @@ __device__ __forceinline__ void soft_term(const SoftPair &P, double dx, double d
 // the larger cut-off, where MIXED evaluates the Newtonian term in FP32 (the
 // offset is formed in FP64, as in the far-particle kernel); inside it, and
 // always without MIXED, the FP64 soft term.
+// The test y > 1 is taken on the FP32 offset with a margin far above its
+// rounding (a few units in 2^-24): a pair it sends to the FP32 branch has
+// y > 1 exactly, and the few pairs within the margin take the FP64 term,
+// which gives K = 1 for them as well.
+constexpr float kMixedMargin = 1e-5f;
+
 template <bool MIXED>
 __device__ __forceinline__ void pair_term(const SoftPair &P, double dx, double dy, double dz, double gm, double invi,
                                           double invj, double &ax, double &ay, double &az) {
   if (MIXED) {
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double inv = fmin(invi, invj);
-    if (r2 * (inv * inv) > 1.0 + 1e-12) {  // y > 1: K = 1
-      const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-      const float ri = rsqrtf(fx * fx + fy * fy + fz * fz);
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    const float r2f = fx * fx + fy * fy + fz * fz;
+    const float inv = (float)fmin(invi, invj);
+    if (r2f * (inv * inv) > 1.0f + kMixedMargin) {  // y > 1: K = 1
+      const float ri = rsqrtf(r2f);
       const float f = (float)gm * ri * ri * ri;
       ax += (double)(f * fx);
       ay += (double)(f * fy);
@@ -73,9 +79,16 @@ __device__ __forceinline__ void pair_term(const SoftPair &P, double dx, double d
   soft_term(P, dx, dy, dz, gm, invi, invj, ax, ay, az);
 }
 
-// reach of the neighbour test: no pair beyond the larger search radius passes
+// reach of the neighbour test: no pair beyond the larger search radius
+// passes.  MIXED screens on the FP32 offset with a wide margin; the test
+// itself is exact either way.
+template <bool MIXED>
 __device__ __forceinline__ bool may_neighbour(double dx, double dy, double dz, double rsi, double rsj) {
   const double rs = fmax(rsi, rsj);
+  if (MIXED) {
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz, rf = (float)rs;
+    return fx * fx + fy * fy + fz * fz < rf * rf * (1.0f + 1e-4f);
+  }
   return dx * dx + dy * dy + dz * dz < rs * rs * (1.0 + 1e-12);
 }
 
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
         for (int k = 0; k < m; ++k) {
           const double dx = tx[k] - xi, dy = ty[k] - yi, dz = tz[k] - zi;
           pair_term<MIXED>(A.P, dx, dy, dz, A.P.G * tm[k], invi, tinv[k], ax, ay, az);
-          if (!may_neighbour(dx, dy, dz, rsi, trs[k])) continue;
+          if (!may_neighbour<MIXED>(dx, dy, dz, rsi, trs[k])) continue;
           if (tx[k] == xi && ty[k] == yi && tz[k] == zi) coincident = true;
           if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, tx[k], ty[k], tz[k], tvx[k], tvy[k], tvz[k],
                              tm[k], tro[k], trs[k], A.P.G, A.rsch2, A.rsch3, A.dt)) {
@@ -280,16 +293,21 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
   }
 }
 
-__global__ void k_slow_reduce(SlowArgs A) {
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < A.ns; s += gridDim.x * blockDim.x) {
-    const int64_t i = A.list[s];
-    double a[3];
-    for (int d = 0; d < 3; ++d) {
-      double v = 0.0;
-      for (int p = 0; p < SLOW_CHUNKS; ++p) v += A.part[((int64_t)s * SLOW_CHUNKS + p) * 3 + d];
-      a[d] = v;
-      A.acc[d * A.n + i] = v;
-    }
+// one wavefront per member s (blockIdx.x): lane l adds the chunks l,
+// l + 64, ... in order, and the lane sums are combined by a fixed
+// butterfly; lane 0's total is written, so the order never changes
+__global__ __launch_bounds__(WAVE) void k_slow_reduce(SlowArgs A) {
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int64_t i = A.list[s];
+  double a[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double v = 0.0;
+    for (int p = lane; p < SLOW_CHUNKS; p += WAVE) v += A.part[((int64_t)s * SLOW_CHUNKS + p) * 3 + d];
+    a[d] = wave_sum(v);
+  }
+  if (lane == 0) {
+    for (int d = 0; d < 3; ++d) A.acc[d * A.n + i] = a[d];
     if (!(isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]))) atomicOr(A.status, P3T_FLAG_NAN);
   }
 }
@@ -390,7 +408,7 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
     hipLaunchKernelGGL(k_slow_into<false>, dim3(g), dim3(ST), 0, s, A);
     hipLaunchKernelGGL(k_slow_from<false>, gf, dim3(ST), 0, s, A);
   }
-  hipLaunchKernelGGL(k_slow_reduce, dim3((ns + 255) / 256), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_slow_reduce, dim3(ns), dim3(WAVE), 0, s, A);
   return hipGetLastError();
 }
 
