@@ -21,7 +21,7 @@ precisions with the hard part before the tree (the overlap alone).
 
 Prints one JSON line.  Only the cpu_baseline leg touches the CPU oracle: it
 times the oracle's direct sum on a sample of i-particles (and the oracle
-Hermite on config 4) and, with the same oracle rows, reports each GPU path's
+Hermite on the 20,000-cluster batch) and, with the same oracle rows, reports each GPU path's
 rms force error.
 """
 from __future__ import annotations
@@ -290,7 +290,7 @@ def hermite_workload():
 
 
 def hermite_leg(p3t, torch, cl, p, reps=3):
-    """The batched Hermite hard part on config 4 (p3t_hermite_cluster_step):
+    """The batched Hermite hard part on the 20,000-cluster batch (p3t_hermite_cluster_step):
     median wall time of `reps` calls from the same state, the Hermite work
     counters, pair terms per second."""
     import numpy as np
@@ -320,7 +320,7 @@ def hermite_leg(p3t, torch, cl, p, reps=3):
 def cpu_baseline(disk, results, sample, seed=33, herm=None):
     """Oracle (plain CPU FP64 direct sum) on a bounded sample of i-particles:
     median of three timings on all host threads, one timing on one thread
-    (a smaller sample), the oracle Hermite on config 4, and the reference
+    (a smaller sample), the oracle Hermite on the 20,000-cluster batch, and the reference
     rows for the GPU paths' rms force error."""
     import numpy as np
 
@@ -377,7 +377,7 @@ def cpu_baseline(disk, results, sample, seed=33, herm=None):
         th = time.perf_counter() - t0
         base["hermite"] = dict(seconds=th, cores=threads, clusters=int(cl["cl_ptr"].shape[0] - 1), members=int(n),
                                max_block_steps=int(ns.max()), status=int(stat),
-                               sample="config 4: 20,000 clusters from the 65,536-particle disk, eta 0.02")
+                               sample="20,000 clusters from the 65,536-particle disk, eta 0.02")
     return base, errs
 
 
@@ -458,7 +458,7 @@ def main():
           flush=True)
     herm = hermite_workload()
     hl = hermite_leg(p3t, torch, herm[1], herm[0])
-    print(f"# hermite config 4: {hl['ms']:.2f} ms, {hl['pair_terms_per_s']:.3g} pair terms/s", file=sys.stderr,
+    print(f"# hermite batch of 20,000 clusters: {hl['ms']:.2f} ms, {hl['pair_terms_per_s']:.3g} pair terms/s", file=sys.stderr,
           flush=True)
     base, errs = (None, {})
     if not args.no_cpu and "fp64" in results:
@@ -508,7 +508,7 @@ def main():
             line[name] = {k: r[k] for k in ("value", "ms_per_step", "interactions_per_step", "stages_ms", "roofline",
                                             "kernels", "memory_stages", "hermite", "largest_cluster")}
             line[name]["force_error"] = errs.get(name)
-    line["hermite"] = dict(step=h["hermite"], config4=hl)
+    line["hermite"] = dict(step=h["hermite"], batch_20000=hl)
     for name in ("mixed_serial", "fp64_serial"):
         if name in results:
             line["hermite"]["serial_" + name.split("_")[0]] = results[name]["hermite"]
