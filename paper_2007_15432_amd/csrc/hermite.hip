@@ -1411,8 +1411,6 @@ __host__ __device__ constexpr int clusters_per_wave(int bk, bool coll) {
 template <int MODE, bool COLL = false>
 __global__ __launch_bounds__(BIG_T) void k_herm_fused(HermArgs A) {
   __shared__ double lds[8][BIG_T];
-  __shared__ int64_t shi[BIG_T / WAVE];
-  __shared__ double shd[BIG_T / WAVE];
   __shared__ int act[BIG_T];
   __shared__ double res[6 * BIG_T];
   constexpr int NC = COLL ? BIG_T : 1;
