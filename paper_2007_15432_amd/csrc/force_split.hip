@@ -70,8 +70,18 @@ constexpr double kCandMargin = 1.0 + 1.0e-12;
 struct NearTile {
   double4 a[WAVE];  // x, y, z, G m
   double2 b[WAVE];  // 1/r_out, reach^2
+  float4 f[WAVE];   // MIXED: r_out^2 and reach^2 widened by kMixMargin, G m
   int j[WAVE];      // sorted index (-2: padding)
 };
+
+// MIXED screens each pair on the FP32 square of its offset.  Both tests
+// take a margin far above the rounding of that square (a few units in
+// 2^-24): every pair inside the changeover (y < 1) is flagged, and every
+// pair within a search reach is a candidate.  The flagged pairs are then
+// evaluated in FP64 (K = 1 for the few beyond the cut-off), and the exact
+// test decides the candidates.  The tests compare the bit patterns of
+// non-negative floats as integers, which orders them as the floats.
+constexpr double kMixMargin = 1.0e-5;
 
 // The FP64 pair term with the changeover for one near pair (r^2 floored,
 // see near_group), added to (ax, ay, az).
@@ -118,6 +128,7 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
                                            CandSlab &S) {
   int ii[IPL];
   double xi[IPL], yi[IPL], zi[IPL], invi[IPL], rch2[IPL], ax[IPL], ay[IPL], az[IPL];
+  int ro2q[IPL], rch2q[IPL];  // MIXED: bit patterns of the widened FP32 squares
 #pragma unroll
   for (int s = 0; s < IPL; ++s) {
     const int k = lane + WAVE * s;
@@ -130,12 +141,18 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
     invi[s] = A.sinv[i];
     rch2[s] = A.sreach[i] * A.sreach[i] * kCandMargin;
     ax[s] = ay[s] = az[s] = 0.0;
+    if constexpr (MIXED) {
+      const double ro = A.sro[i], r = A.sreach[i];
+      ro2q[s] = __float_as_int((float)(ro * ro * (1.0 + kMixMargin)));
+      rch2q[s] = __float_as_int((float)(r * r * (1.0 + kMixMargin)));
+    }
   }
   const int32_t *Ln = A.pool + h.off + h.n_cell;
   // the next tile's entry of this lane is loaded into registers while the
   // current tile is evaluated (its gathers are the kernel's memory latency)
   double4 na;
   double2 nb;
+  float4 nf;
   int nj = -2;
   auto fetch = [&](int t0) {
     const int nt = min(WAVE, h.n_near - t0);
@@ -145,10 +162,16 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
       const double r = A.sreach[j];
       na = make_double4(A.sx[j], A.sy[j], A.sz[j], A.G * A.sm[j]);
       nb = make_double2(A.sinv[j], r * r * kCandMargin);
+      if constexpr (MIXED) {
+        const double ro = A.sro[j];
+        nf = make_float4((float)(ro * ro * (1.0 + kMixMargin)), (float)(r * r * (1.0 + kMixMargin)), (float)na.w, 0.0f);
+      }
       nj = j;
     } else if (lane < ntp) {
+      // padding: massless, beyond every reach and every cut-off
       na = make_double4(h.cx + kDummyOffset, h.cy, h.cz, 0.0);
       nb = make_double2(1.0, 0.0);
+      nf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       nj = -2;
     }
   };
@@ -160,6 +183,7 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
     if (lane < ntp) {
       T.a[lane] = na;
       T.b[lane] = nb;
+      if constexpr (MIXED) T.f[lane] = nf;
       T.j[lane] = nj;
     }
     __syncthreads();
@@ -177,31 +201,42 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
           const double4 a = T.a[jj + u];
-          const double2 b = T.b[jj + u];
           const int jidx = T.j[jj + u];
           const unsigned bit = 1u << ((jj + u) & 31);
-          const float fw = (float)a.w;
+          if constexpr (MIXED) {
+            const float4 fj = T.f[jj + u];
+            const int ro2j = __float_as_int(fj.x), rch2j = __float_as_int(fj.y);
 #pragma unroll
-          for (int s = 0; s < IPL; ++s) {
-            const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if constexpr (MIXED) {
-              const double inv = fmin(invi[s], b.x);
-              const bool chg = r2 * (inv * inv) < 1.0;  // inside the changeover, or r = 0
+            for (int s = 0; s < IPL; ++s) {
+              const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
               const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-              const float ri = __frsqrt_rn(fdx * fdx + fdy * fdy + fdz * fdz);
-              const float f = chg ? 0.0f : fw * ri * ri * ri;
+              const float r2f = fdx * fdx + fdy * fdy + fdz * fdz;
+              const int r2q = __float_as_int(r2f);
+              // inside the changeover of either side (or r = 0): FP64 below
+              const bool chg = (r2q < ro2q[s]) | (r2q < ro2j);
+              const float ri = __frsqrt_rn(r2f);
+              const float f = chg ? 0.0f : fj.z * ri * ri * ri;
               tx[s] += f * fdx;
               ty[s] += f * fdy;
               tz[s] += f * fdz;
-              chg_m[half][s] |= (chg & (jidx != ii[s])) ? bit : 0u;
-            } else {
-              near_term64(A, dx, dy, dz, r2, a.w, invi[s], b.x, ax[s], ay[s], az[s]);
+              const bool other = jidx != ii[s];
+              chg_m[half][s] |= (chg & other) ? bit : 0u;
+              // evaluated without short-circuit, so no branch per pair
+              const bool cand = other & ((r2q <= rch2q[s]) | (r2q <= rch2j));
+              cm[half][s] |= cand ? bit : 0u;
             }
-            // reach^2 of both sides carry the candidate margin already
-            // evaluated without short-circuit, so no branch per pair
-            const bool cand = (jidx != ii[s]) & ((r2 <= rch2[s]) | (r2 <= b.y));
-            cm[half][s] |= cand ? bit : 0u;
+          } else {
+            const double2 b = T.b[jj + u];
+#pragma unroll
+            for (int s = 0; s < IPL; ++s) {
+              const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
+              const double r2 = dx * dx + dy * dy + dz * dz;
+              near_term64(A, dx, dy, dz, r2, a.w, invi[s], b.x, ax[s], ay[s], az[s]);
+              // reach^2 of both sides carry the candidate margin already;
+              // evaluated without short-circuit, so no branch per pair
+              const bool cand = (jidx != ii[s]) & ((r2 <= rch2[s]) | (r2 <= b.y));
+              cm[half][s] |= cand ? bit : 0u;
+            }
           }
         }
       }
