@@ -50,45 +50,39 @@ __device__ __forceinline__ void soft_term(const SoftPair &P, double dx, double d
   az += f * dz;
 }
 
-// The pair term for a pair at d = x_j - x_i: K(r / max(r_out)) = 1 beyond
-// the larger cut-off, where MIXED evaluates the Newtonian term in FP32 (the
-// offset is formed in FP64, as in the far-particle kernel); inside it, and
-// always without MIXED, the FP64 soft term.
-// The test y > 1 is taken on the FP32 offset with a margin far above its
-// rounding (a few units in 2^-24): a pair it sends to the FP32 branch has
-// y > 1 exactly, and the few pairs within the margin take the FP64 term,
-// which gives K = 1 for them as well.
-constexpr float kMixedMargin = 1e-5f;
+// MIXED: a pair beyond the larger cut-off (y = r / max(r_out) >= 1, so
+// K = 1) takes the Newtonian term in FP32 from its FP64 offset, as in the
+// far-particle kernel; inside it, and always without MIXED, the FP64 soft
+// term.  The pair is screened on the FP32 square of its offset against
+// the squares of both sides' r_out and r_search, widened by margins far
+// above that square's rounding (a few units in 2^-24): every pair inside
+// the changeover goes to the FP64 term (K = 1 for the few within the
+// margin), and every pair within a search reach to the exact test.  The
+// squares are compared as the bit patterns of non-negative floats, which
+// order as the floats do.
+constexpr double kMixMargin = 1e-5, kReachMargin = 1e-4;
 
-template <bool MIXED>
-__device__ __forceinline__ void pair_term(const SoftPair &P, double dx, double dy, double dz, double gm, double invi,
-                                          double invj, double &ax, double &ay, double &az) {
-  if (MIXED) {
-    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-    const float r2f = fx * fx + fy * fy + fz * fz;
-    const float inv = (float)fmin(invi, invj);
-    if (r2f * (inv * inv) > 1.0f + kMixedMargin) {  // y > 1: K = 1
-      const float ri = rsqrtf(r2f);
-      const float f = (float)gm * ri * ri * ri;
-      ax += (double)(f * fx);
-      ay += (double)(f * fy);
-      az += (double)(f * fz);
-      return;
-    }
-  }
-  soft_term(P, dx, dy, dz, gm, invi, invj, ax, ay, az);
+__device__ __forceinline__ int widened_sq(double r, double margin) {
+  return __float_as_int((float)(r * r * (1.0 + margin)));
 }
 
-// reach of the neighbour test: no pair beyond the larger search radius
-// passes.  MIXED screens on the FP32 offset with a wide margin; the test
-// itself is exact either way.
-template <bool MIXED>
-__device__ __forceinline__ bool may_neighbour(double dx, double dy, double dz, double rsi, double rsj) {
+// the K = 1 test and the FP32 term of a MIXED pair: returns true (and adds
+// nothing) for a pair that needs the FP64 soft term
+__device__ __forceinline__ bool mixed_far_term(float ex, float ey, float ez, int r2q, int ro2a, int ro2b, float gm,
+                                               float &fx, float &fy, float &fz) {
+  const bool chg = (r2q < ro2a) | (r2q < ro2b);
+  const float ri = __frsqrt_rn(__int_as_float(r2q));
+  const float f = chg ? 0.0f : gm * ri * ri * ri;
+  fx += f * ex;
+  fy += f * ey;
+  fz += f * ez;
+  return chg;
+}
+
+// reach of the neighbour test without MIXED: no pair beyond the larger
+// search radius passes
+__device__ __forceinline__ bool may_neighbour64(double dx, double dy, double dz, double rsi, double rsj) {
   const double rs = fmax(rsi, rsj);
-  if (MIXED) {
-    const float fx = (float)dx, fy = (float)dy, fz = (float)dz, rf = (float)rs;
-    return fx * fx + fy * fy + fz * fz < rf * rf * (1.0f + 1e-4f);
-  }
   return dx * dx + dy * dy + dz * dz < rs * rs * (1.0 + 1e-12);
 }
 
@@ -168,6 +162,7 @@ __global__ void k_slow_scatter(int64_t n, int ns, const int32_t *__restrict__ li
 template <bool MIXED>
 __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
   __shared__ double tx[ST], ty[ST], tz[ST], tvx[ST], tvy[ST], tvz[ST], tm[ST], tro[ST], trs[ST], tinv[ST];
+  __shared__ int4 tq[ST];  // MIXED: widened r_out^2 and r_search^2 (bit patterns), G m in FP32
   __shared__ int32_t tid_[ST];
   const int t = threadIdx.x;
   const int64_t n = A.n;
@@ -178,6 +173,7 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
     const double xi = A.pos[ic], yi = A.pos[n + ic], zi = A.pos[2 * n + ic];
     const double vxi = A.vel[ic], vyi = A.vel[n + ic], vzi = A.vel[2 * n + ic];
     const double mi = A.mass[ic], roi = A.ro[ic], rsi = A.rs[ic], invi = 1.0 / roi;
+    const int ro2i = MIXED ? widened_sq(roi, kMixMargin) : 0, rs2i = MIXED ? widened_sq(rsi, kReachMargin) : 0;
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool coincident = false;
     for (int s0 = 0; s0 < A.ns; s0 += ST) {
@@ -196,19 +192,39 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
         tinv[t] = 1.0 / A.ro[j];
         trs[t] = A.rs[j];
         tid_[t] = (int32_t)j;
+        if (MIXED)
+          tq[t] = make_int4(widened_sq(A.ro[j], kMixMargin), widened_sq(A.rs[j], kReachMargin),
+                            __float_as_int((float)(A.P.G * A.mass[j])), 0);
       }
       __syncthreads();
       if (act) {
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;  // MIXED: this tile's K = 1 terms
         for (int k = 0; k < m; ++k) {
           const double dx = tx[k] - xi, dy = ty[k] - yi, dz = tz[k] - zi;
-          pair_term<MIXED>(A.P, dx, dy, dz, A.P.G * tm[k], invi, tinv[k], ax, ay, az);
-          if (!may_neighbour<MIXED>(dx, dy, dz, rsi, trs[k])) continue;
+          bool reach;
+          if (MIXED) {
+            const int4 q = tq[k];
+            const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
+            const int r2q = __float_as_int(ex * ex + ey * ey + ez * ez);
+            if (mixed_far_term(ex, ey, ez, r2q, ro2i, q.x, __int_as_float(q.z), fx, fy, fz))
+              soft_term(A.P, dx, dy, dz, A.P.G * tm[k], invi, tinv[k], ax, ay, az);
+            reach = (r2q <= rs2i) | (r2q <= q.y);
+          } else {
+            soft_term(A.P, dx, dy, dz, A.P.G * tm[k], invi, tinv[k], ax, ay, az);
+            reach = may_neighbour64(dx, dy, dz, rsi, trs[k]);
+          }
+          if (!reach) continue;
           if (tx[k] == xi && ty[k] == yi && tz[k] == zi) coincident = true;
           if (neighbour_test(xi, yi, zi, vxi, vyi, vzi, mi, roi, rsi, tx[k], ty[k], tz[k], tvx[k], tvy[k], tvz[k],
                              tm[k], tro[k], trs[k], A.P.G, A.rsch2, A.rsch3, A.dt)) {
             push_pair(A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, tid_[k]);
             push_pair(A.n_pairs, A.pairs, A.pair_cap, tid_[k], (int32_t)i);
           }
+        }
+        if (MIXED) {
+          ax += (double)fx;
+          ay += (double)fy;
+          az += (double)fz;
         }
       }
     }
@@ -230,6 +246,7 @@ template <bool MIXED>
 __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
   __shared__ double red[3 * SG][ST / WAVE];
   __shared__ double4 mem_x[SG];  // the block's members: x, y, z, 1 / r_out (read as broadcasts)
+  __shared__ int mem_q[SG];      // MIXED: their widened r_out^2 (bit patterns)
   __shared__ int64_t mem_i[SG];
   const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
   const int s0 = blockIdx.y * SG;
@@ -239,6 +256,7 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
     const int64_t i = A.list[s0 + (t < gc ? t : gc - 1)];
     mem_i[t] = i;
     mem_x[t] = make_double4(A.spos[i], A.spos[n + i], A.spos[2 * n + i], 1.0 / A.ro[i]);
+    mem_q[t] = widened_sq(A.ro[i], kMixMargin);
   }
   __syncthreads();
   double ax[SG], ay[SG], az[SG];
@@ -252,12 +270,25 @@ __global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
     const double *pj = sj ? A.spos : A.pos;  // members of S: their final state
     const double xj = pj[j], yj = pj[n + j], zj = pj[2 * n + j];
     const double mj = A.mass[j], roj = A.ro[j], gmj = A.P.G * mj, invj = 1.0 / roj;
-    // j = s itself gives r = 0, hence K = 0 and an exact zero term
+    const int ro2j = MIXED ? widened_sq(roj, kMixMargin) : 0;
+    const float gmjf = (float)gmj;
+    // j = s itself gives r = 0, hence K = 0 (FP64 branch) and an exact zero term
 #pragma unroll
     for (int g = 0; g < SG; ++g) {
       if (g < gc) {
         const double4 q = mem_x[g];
-        pair_term<MIXED>(A.P, xj - q.x, yj - q.y, zj - q.z, gmj, q.w, invj, ax[g], ay[g], az[g]);
+        const double dx = xj - q.x, dy = yj - q.y, dz = zj - q.z;
+        if (MIXED) {
+          const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
+          float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+          if (mixed_far_term(ex, ey, ez, __float_as_int(ex * ex + ey * ey + ez * ez), mem_q[g], ro2j, gmjf, fx, fy, fz))
+            soft_term(A.P, dx, dy, dz, gmj, q.w, invj, ax[g], ay[g], az[g]);
+          ax[g] += (double)fx;
+          ay[g] += (double)fy;
+          az[g] += (double)fz;
+        } else {
+          soft_term(A.P, dx, dy, dz, gmj, q.w, invj, ax[g], ay[g], az[g]);
+        }
       }
     }
     if (sj) {  // pairs within S (rare)
