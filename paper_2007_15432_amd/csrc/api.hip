@@ -595,6 +595,7 @@ bool eval_finish(p3t_ctx *c, const DevCounters &h, unsigned *num, p3t_status *st
 p3t_status p3t_compute_soft_force(p3t_ctx *c, double *acc3) {
   if (!c) return P3T_ERR_ARG;
   prep_join(c);
+  c->uf_early = 0;  // a new pair list
   if (!c->tree_valid) return fail(c, P3T_ERR_STATE, "compute_soft_force: no tree (call p3t_build_tree)");
   if (bad_ptr(acc3, c->n)) return fail(c, P3T_ERR_ARG, "compute_soft_force: null pointer");
   c->force_valid = false;
@@ -634,6 +635,7 @@ namespace {
 p3t_status eval_enqueue(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                         const double *r_out, const double *r_search, double *acc3, int32_t use_graph) {
   p3t_status st;
+  c->uf_early = 0;  // a new pair list
   if (!use_graph) {
     if ((st = p3t_build_tree(c, n, pos3, vel3, mass, r_out, r_search)) != P3T_OK) return st;
     ev_record(c, 4);
@@ -1189,6 +1191,9 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   c->slow_active = 1;
   st = eval_enqueue(c, n, pos3, vel3, c->m_eff, r_out, r_search, acc3, use_graph);
   c->slow_active = 0;
+  // the next hard part's union-find over the pairs written so far, while
+  // the main stream would wait for the second one anyway
+  if (ns > 0 && st == P3T_OK) HIP_OK(c, labels_pairs_early(c, n));
   // join: S's new state into pos3 / vel3, its terms into acc3
   if (ns > 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slow_ev[1], 0));
   ev_record(c, 15);

@@ -124,6 +124,21 @@ __global__ void k_uf_link_pairs(int64_t n, const int2 *__restrict__ pairs, const
   }
 }
 
+// The pairs appended last to a pair list of np_dev entries: the nd_dev
+// (clamped to cap_d) at its end, which the direct terms of parked members
+// append after the join.
+__global__ void k_uf_link_tail(int64_t n, const int2 *__restrict__ pairs, const unsigned long long *__restrict__ np_dev,
+                               const unsigned long long *__restrict__ nd_dev, int64_t cap_d, int64_t cap, int32_t *p) {
+  const int64_t np = (int64_t)*np_dev < cap ? (int64_t)*np_dev : cap;
+  const int64_t nd = (int64_t)*nd_dev < cap_d ? (int64_t)*nd_dev : cap_d;
+  const int64_t q0 = np - nd > 0 ? np - nd : 0;
+  for (int64_t q = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < np; q += (int64_t)gridDim.x * blockDim.x) {
+    const int2 e = pairs[q];
+    if (e.x == e.y || (uint32_t)e.x >= (uint64_t)n || (uint32_t)e.y >= (uint64_t)n) continue;
+    uf_union(p, e.x, e.y);
+  }
+}
+
 __global__ void k_uf_final(int64_t n, int32_t *p, int32_t *__restrict__ label) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     label[i] = uf_find(p, (int)i);
@@ -140,6 +155,7 @@ __global__ void k_uf_final_keys(int64_t n, int32_t *p, int32_t *__restrict__ lab
 
 hipError_t labels_cc(p3t_ctx *c, int64_t n, int32_t *label) {
   hipStream_t s = c->stream;
+  c->uf_early = 0;  // the parents are rebuilt here
   hipLaunchKernelGGL(k_uf_init, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent);
   hipLaunchKernelGGL(k_uf_link, dim3(g1d(n)), dim3(256), 0, s, n, c->csr_ptr, c->csr_col, c->uf_parent);
   hipLaunchKernelGGL(k_uf_final, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent, label);
@@ -151,12 +167,36 @@ hipError_t labels_cc(p3t_ctx *c, int64_t n, int32_t *label) {
 // (c->cl_keys) for clusters_csr_dev(..., keys_ready = true).
 hipError_t labels_pairs(p3t_ctx *c, int64_t n, int32_t *label) {
   hipStream_t s = c->stream;
+  if (c->uf_early == n) {
+    // the evaluation's own pairs are joined already (labels_pairs_early):
+    // only the parked members' pairs, appended after the join, remain
+    const unsigned gt = (unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (c->pairs_d_cap + 255) / 256));
+    hipLaunchKernelGGL(k_uf_link_tail, dim3(gt), dim3(256), 0, s, n, c->pairs, &c->cnt->n_pairs, &c->cnt->n_pairs_d,
+                       c->pairs_d_cap, c->pair_cap, c->uf_parent);
+  } else {
+    hipLaunchKernelGGL(k_uf_init, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent);
+    const unsigned gp = (unsigned)std::min<int64_t>(2048, (c->pair_cap + 255) / 256);
+    hipLaunchKernelGGL(k_uf_link_pairs, dim3(gp < 1 ? 1 : gp), dim3(256), 0, s, n, c->pairs, &c->cnt->n_pairs,
+                       c->pair_cap, c->uf_parent);
+  }
+  c->uf_early = 0;
+  hipLaunchKernelGGL(k_uf_final_keys, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent, label, c->cl_keys);
+  return hipGetLastError();
+}
+
+// The union-find over the pairs an evaluation has written so far, on the
+// main stream while it waits for the parked members' direct terms;
+// labels_pairs then joins only the pairs those append.  Marks the parents
+// as holding the first pass for n particles.
+hipError_t labels_pairs_early(p3t_ctx *c, int64_t n) {
+  hipStream_t s = c->stream;
   hipLaunchKernelGGL(k_uf_init, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent);
   const unsigned gp = (unsigned)std::min<int64_t>(2048, (c->pair_cap + 255) / 256);
   hipLaunchKernelGGL(k_uf_link_pairs, dim3(gp < 1 ? 1 : gp), dim3(256), 0, s, n, c->pairs, &c->cnt->n_pairs,
                      c->pair_cap, c->uf_parent);
-  hipLaunchKernelGGL(k_uf_final_keys, dim3(g1d(n)), dim3(256), 0, s, n, c->uf_parent, label, c->cl_keys);
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  c->uf_early = e == hipSuccess ? n : 0;
+  return e;
 }
 
 // ------------------------------------------------------------------ cluster CSR

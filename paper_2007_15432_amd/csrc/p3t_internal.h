@@ -279,6 +279,7 @@ struct p3t_ctx {
   int64_t *csr_ptr = nullptr;       // internal CSR row pointer (n + 1)
   int32_t *csr_col = nullptr;       // internal CSR columns (pair_cap)
   int32_t *uf_parent = nullptr;     // union-find parents (n)
+  int64_t uf_early = 0;             // n if uf_parent holds the first pass of labels_pairs_early, else 0
   uint64_t *cl_keys = nullptr, *cl_keys_alt = nullptr;  // cluster sort keys (n)
   double *cut_part = nullptr;       // cut-off bin partial sums
   uint8_t *close_flag = nullptr;    // per particle: in a close neighbour pair at the last evaluation
@@ -387,6 +388,7 @@ hipError_t soft_force(p3t_ctx *c, int64_t n_groups, double *acc3, bool frozen = 
 hipError_t build_csr(p3t_ctx *c, int64_t n, int64_t n_pairs);
 hipError_t labels_cc(p3t_ctx *c, int64_t n, int32_t *label);
 hipError_t labels_pairs(p3t_ctx *c, int64_t n, int32_t *label);
+hipError_t labels_pairs_early(p3t_ctx *c, int64_t n);
 hipError_t clusters_csr(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
                         int64_t *n_clusters);
 hipError_t clusters_csr_dev(p3t_ctx *c, int64_t n, const int32_t *label, int32_t *cl_ptr, int32_t *cl_members,
