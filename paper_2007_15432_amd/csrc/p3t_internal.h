@@ -164,7 +164,7 @@ constexpr int HERM_N_BUCKETS = 11;
 constexpr double CLOSE_RATIO = 0.5;
 // parked members of one p3t_hard_evaluate call at most, and the chunks of
 // the direct sum over all particles for each of them
-constexpr int SLOW_CAP = 1024, SLOW_CHUNKS = 256;
+constexpr int SLOW_CAP = 1024, SLOW_CHUNKS = 2048;
 
 // ---------------------------------------------------------------- context
 struct Arena {

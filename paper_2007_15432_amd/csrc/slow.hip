@@ -237,91 +237,78 @@ __global__ __launch_bounds__(ST) void k_slow_into(SlowArgs A) {
   }
 }
 
-// members s0 .. s0 + SG - 1 of S (s0 = SG blockIdx.y) against the particles
-// of chunk blockIdx.x: partial sums, and the pairs (s, s') with s' in S.
-// Each particle of the chunk is loaded once for SG members.
-constexpr int SG = 8;
+// Members of S in lanes (SM per workgroup, s = SM blockIdx.y + lane)
+// against the particles of chunk blockIdx.x, which pass through LDS in
+// tiles of SJ and are read back as broadcasts, so each particle is read
+// once per SM members: the partial sum of each member over the chunk, and
+// the pairs (s, s') with s' in S.
+constexpr int SM = 128, SJ = 256;
 
 template <bool MIXED>
-__global__ __launch_bounds__(ST) void k_slow_from(SlowArgs A) {
-  __shared__ double red[3 * SG][ST / WAVE];
-  __shared__ double4 mem_x[SG];  // the block's members: x, y, z, 1 / r_out (read as broadcasts)
-  __shared__ int mem_q[SG];      // MIXED: their widened r_out^2 (bit patterns)
-  __shared__ int64_t mem_i[SG];
-  const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
-  const int s0 = blockIdx.y * SG;
-  const int gc = min(SG, A.ns - s0);  // members in this block, uniform
+__global__ __launch_bounds__(SM) void k_slow_from(SlowArgs A) {
+  __shared__ double4 ja[SJ];  // x, y, z (final state for members of S), G m
+  __shared__ double jinv[SJ];  // 1 / r_out
+  __shared__ int4 jc[SJ];      // widened r_out^2 (bit pattern), G m in FP32 (bit pattern), member of S
+  const int t = threadIdx.x;
+  const int slot = blockIdx.y * SM + t;
+  const bool act = slot < A.ns;
   const int64_t n = A.n;
-  if (t < SG) {
-    const int64_t i = A.list[s0 + (t < gc ? t : gc - 1)];
-    mem_i[t] = i;
-    mem_x[t] = make_double4(A.spos[i], A.spos[n + i], A.spos[2 * n + i], 1.0 / A.ro[i]);
-    mem_q[t] = widened_sq(A.ro[i], kMixMargin);
-  }
-  __syncthreads();
-  double ax[SG], ay[SG], az[SG];
-#pragma unroll
-  for (int g = 0; g < SG; ++g) ax[g] = ay[g] = az[g] = 0.0;
+  const int64_t i = A.list[act ? slot : 0];
+  const double xi = A.spos[i], yi = A.spos[n + i], zi = A.spos[2 * n + i];
+  const double invi = 1.0 / A.ro[i];
+  const int ro2i = widened_sq(A.ro[i], kMixMargin);
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  bool coincident = false;
   const int64_t chunk = (n + SLOW_CHUNKS - 1) / SLOW_CHUNKS;
   const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
-  bool coincident = false;
-  for (int64_t j = j0 + t; j < j1; j += ST) {
-    const bool sj = A.slow[j];
-    const double *pj = sj ? A.spos : A.pos;  // members of S: their final state
-    const double xj = pj[j], yj = pj[n + j], zj = pj[2 * n + j];
-    const double mj = A.mass[j], roj = A.ro[j], gmj = A.P.G * mj, invj = 1.0 / roj;
-    const int ro2j = MIXED ? widened_sq(roj, kMixMargin) : 0;
-    const float gmjf = (float)gmj;
-    // j = s itself gives r = 0, hence K = 0 (FP64 branch) and an exact zero term
-#pragma unroll
-    for (int g = 0; g < SG; ++g) {
-      if (g < gc) {
-        const double4 q = mem_x[g];
-        const double dx = xj - q.x, dy = yj - q.y, dz = zj - q.z;
-        if (MIXED) {
-          const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
-          float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-          if (mixed_far_term(ex, ey, ez, __float_as_int(ex * ex + ey * ey + ez * ez), mem_q[g], ro2j, gmjf, fx, fy, fz))
-            soft_term(A.P, dx, dy, dz, gmj, q.w, invj, ax[g], ay[g], az[g]);
-          ax[g] += (double)fx;
-          ay[g] += (double)fy;
-          az[g] += (double)fz;
-        } else {
-          soft_term(A.P, dx, dy, dz, gmj, q.w, invj, ax[g], ay[g], az[g]);
-        }
-      }
+  for (int64_t b = j0; b < j1; b += SJ) {
+    const int m = (int)(j1 - b < SJ ? j1 - b : SJ);
+    __syncthreads();
+    for (int k = t; k < m; k += SM) {
+      const int64_t j = b + k;
+      const bool sj = A.slow[j];
+      const double *pj = sj ? A.spos : A.pos;  // members of S: their final state
+      const double roj = A.ro[j], gmj = A.P.G * A.mass[j];
+      ja[k] = make_double4(pj[j], pj[n + j], pj[2 * n + j], gmj);
+      jinv[k] = 1.0 / roj;
+      jc[k] = make_int4(widened_sq(roj, kMixMargin), __float_as_int((float)gmj), sj ? 1 : 0, 0);
     }
-    if (sj) {  // pairs within S (rare)
-      for (int g = 0; g < gc; ++g) {
-        const int64_t i = mem_i[g];
+    __syncthreads();
+    if (!act) continue;
+    // j = s itself gives r = 0, hence K = 0 (FP64 term) and an exact zero
+    for (int k = 0; k < m; ++k) {
+      const double4 q = ja[k];
+      const int4 c = jc[k];
+      const double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+      if (MIXED) {
+        const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
+        float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+        if (mixed_far_term(ex, ey, ez, __float_as_int(ex * ex + ey * ey + ez * ez), ro2i, c.x, __int_as_float(c.y), fx,
+                           fy, fz))
+          soft_term(A.P, dx, dy, dz, q.w, invi, jinv[k], ax, ay, az);
+        ax += (double)fx;
+        ay += (double)fy;
+        az += (double)fz;
+      } else {
+        soft_term(A.P, dx, dy, dz, q.w, invi, jinv[k], ax, ay, az);
+      }
+      if (c.z) {  // a pair within S (rare; uniform over the wavefront)
+        const int64_t j = b + k;
         if (j == i) continue;
-        const double4 q = mem_x[g];
-        if (xj == q.x && yj == q.y && zj == q.z) coincident = true;
-        if (neighbour_test(q.x, q.y, q.z, A.svel[i], A.svel[n + i], A.svel[2 * n + i], A.mass[i], A.ro[i], A.rs[i],
-                           xj, yj, zj, A.svel[j], A.svel[n + j], A.svel[2 * n + j], mj, roj, A.rs[j], A.P.G,
+        if (q.x == xi && q.y == yi && q.z == zi) coincident = true;
+        if (neighbour_test(xi, yi, zi, A.svel[i], A.svel[n + i], A.svel[2 * n + i], A.mass[i], A.ro[i], A.rs[i], q.x,
+                           q.y, q.z, A.svel[j], A.svel[n + j], A.svel[2 * n + j], A.mass[j], A.ro[j], A.rs[j], A.P.G,
                            A.rsch2, A.rsch3, A.dt))
           push_pair(A.n_pairs, A.pairs, A.pair_cap, (int32_t)i, (int32_t)j);
       }
     }
   }
+  if (!act) return;
   if (coincident) atomicOr(A.status, P3T_FLAG_COINCIDENT);
-#pragma unroll
-  for (int g = 0; g < SG; ++g) {
-    if (g < gc) {
-      const double sx = wave_sum(ax[g]), sy = wave_sum(ay[g]), sz = wave_sum(az[g]);
-      if (lane == 0) {
-        red[3 * g][w] = sx;
-        red[3 * g + 1][w] = sy;
-        red[3 * g + 2][w] = sz;
-      }
-    }
-  }
-  __syncthreads();
-  if (t < 3 * gc) {
-    double v = 0.0;
-    for (int q = 0; q < ST / WAVE; ++q) v += red[t][q];
-    A.part[((int64_t)(s0 + t / 3) * SLOW_CHUNKS + blockIdx.x) * 3 + t % 3] = v;
-  }
+  double *pp = A.part + ((int64_t)slot * SLOW_CHUNKS + blockIdx.x) * 3;
+  pp[0] = ax;
+  pp[1] = ay;
+  pp[2] = az;
 }
 
 // one wavefront per member s (blockIdx.x): lane l adds the chunks l,
@@ -431,13 +418,13 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
   A.rsch3 = c->P.r_search3;
   A.dt = c->P.dt_soft;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n + ST - 1) / ST));
-  const dim3 gf(SLOW_CHUNKS, (ns + SG - 1) / SG);
+  const dim3 gf(SLOW_CHUNKS, (ns + SM - 1) / SM);
   if (c->P.precision == 1) {
     hipLaunchKernelGGL(k_slow_into<true>, dim3(g), dim3(ST), 0, s, A);
-    hipLaunchKernelGGL(k_slow_from<true>, gf, dim3(ST), 0, s, A);
+    hipLaunchKernelGGL(k_slow_from<true>, gf, dim3(SM), 0, s, A);
   } else {
     hipLaunchKernelGGL(k_slow_into<false>, dim3(g), dim3(ST), 0, s, A);
-    hipLaunchKernelGGL(k_slow_from<false>, gf, dim3(ST), 0, s, A);
+    hipLaunchKernelGGL(k_slow_from<false>, gf, dim3(SM), 0, s, A);
   }
   hipLaunchKernelGGL(k_slow_reduce, dim3(ns), dim3(WAVE), 0, s, A);
   return hipGetLastError();
