@@ -311,22 +311,28 @@ __global__ __launch_bounds__(SM) void k_slow_from(SlowArgs A) {
   pp[2] = az;
 }
 
-// one wavefront per member s (blockIdx.x): lane l adds the chunks l,
-// l + 64, ... in order, and the lane sums are combined by a fixed
-// butterfly; lane 0's total is written, so the order never changes
-__global__ __launch_bounds__(WAVE) void k_slow_reduce(SlowArgs A) {
-  const int s = blockIdx.x, lane = threadIdx.x;
-  const int64_t i = A.list[s];
-  double a[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    double v = 0.0;
-    for (int p = lane; p < SLOW_CHUNKS; p += WAVE) v += A.part[((int64_t)s * SLOW_CHUNKS + p) * 3 + d];
-    a[d] = wave_sum(v);
+// one workgroup of RT threads per member s (blockIdx.x): thread t adds the
+// chunks t, t + RT, ... in order, then the RT sums are combined pairwise in
+// a fixed tree, so the order never changes
+constexpr int RT = 256;
+
+__global__ __launch_bounds__(RT) void k_slow_reduce(SlowArgs A) {
+  __shared__ double red[3][RT];
+  const int s = blockIdx.x, t = threadIdx.x;
+  const double *part = A.part + (int64_t)s * SLOW_CHUNKS * 3;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int p = t; p < SLOW_CHUNKS; p += RT)
+    for (int d = 0; d < 3; ++d) a[d] += part[p * 3 + d];
+  for (int d = 0; d < 3; ++d) red[d][t] = a[d];
+  for (int w = RT / 2; w > 0; w >>= 1) {
+    __syncthreads();
+    if (t < w)
+      for (int d = 0; d < 3; ++d) red[d][t] += red[d][t + w];
   }
-  if (lane == 0) {
-    for (int d = 0; d < 3; ++d) A.acc[d * A.n + i] = a[d];
-    if (!(isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]))) atomicOr(A.status, P3T_FLAG_NAN);
+  if (t == 0) {
+    const int64_t i = A.list[s];
+    for (int d = 0; d < 3; ++d) A.acc[d * A.n + i] = red[d][0];
+    if (!(isfinite(red[0][0]) && isfinite(red[1][0]) && isfinite(red[2][0]))) atomicOr(A.status, P3T_FLAG_NAN);
   }
 }
 
@@ -426,7 +432,7 @@ hipError_t slow_direct(p3t_ctx *c, const double *pos3, const double *vel3, const
     hipLaunchKernelGGL(k_slow_into<false>, dim3(g), dim3(ST), 0, s, A);
     hipLaunchKernelGGL(k_slow_from<false>, gf, dim3(SM), 0, s, A);
   }
-  hipLaunchKernelGGL(k_slow_reduce, dim3(ns), dim3(WAVE), 0, s, A);
+  hipLaunchKernelGGL(k_slow_reduce, dim3(ns), dim3(RT), 0, s, A);
   return hipGetLastError();
 }
 
