@@ -46,9 +46,9 @@ sys.path.insert(0, ROOT)
 #     + (5/2) dQd r^-7 3 + per-axis c7 d - Q d r^-5 and sum 12           = 54
 FLOPS_NEAR = 35
 #   mixed near pair (K = 1 beyond both cut-offs; all but a fraction of a
-#   percent of the near lists): FP64 offsets 3, r^2 5, changeover test 4
-#   (min, 2 mul, compare); FP32 r^2 5, rsqrt 1, G m r^-3 3, accumulate 6  = 27
-FLOPS_NEAR_MIXED = 27
+#   percent of the near lists): FP64 offsets 3, FP32 r^2 5, changeover
+#   screen 2 (two compares), rsqrt 1, G m r^-3 3, accumulate 6             = 20
+FLOPS_NEAR_MIXED = 20
 FLOPS_FAR = 18
 FLOPS_MONO = 18
 FLOPS_QUAD = 54
