@@ -1,8 +1,9 @@
 // tree.hip -- Barnes-Hut tree over the particles (the paper uses the tree of
 // its particle framework, Section 2.1.1; its construction is not specified
 // there).  Built here for one GPU, fully in parallel:
-//   1. bounding box; 63-bit Morton keys on a cube over the box (21 bits/axis;
-//      the thin disk then splits in x/y first and in z only at small scales);
+//   1. bounding box; 48-bit Morton keys on a cube over the box (16 bits/axis,
+//      cells of 2^-16 of the box, far below the leaf scale; the thin disk
+//      then splits in x/y first and in z only at small scales);
 //   2. stable radix sort of (key, index); gather of a Morton-ordered SoA copy;
 //   3. binary radix tree over the sorted keys (one thread per internal node,
 //      Karras 2012), ties broken by the sorted position;
@@ -14,6 +15,7 @@
 
 namespace p3t {
 
+// bit k of v (k < 21) to bit 3k
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   uint64_t x = v & 0x1fffffu;
   x = (x | (x << 32)) & 0x1f00000000ffffull;
@@ -24,11 +26,15 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   return x;
 }
 
+// bits per axis of the Morton keys: 3 MORTON_BITS = 48 key bits, six 8-bit
+// radix passes
+constexpr int MORTON_BITS = 16;
+
 __global__ void k_morton(int64_t n, const double *__restrict__ pos, const double *__restrict__ box,
                          uint64_t *__restrict__ keys, int32_t *__restrict__ perm) {
   const double lx = box[0], ly = box[1], lz = box[2];
   const double ext = fmax(fmax(box[3] - lx, box[4] - ly), box[5] - lz);
-  const double qmax = 2097151.0;  // 2^21 - 1
+  const double qmax = (double)((1 << MORTON_BITS) - 1);
   const double scale = ext > 0.0 ? qmax / ext : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double q[3] = {(pos[i] - lx) * scale, (pos[n + i] - ly) * scale, (pos[2 * n + i] - lz) * scale};
@@ -480,7 +486,7 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
   uint64_t *k = c->keys, *ka = c->keys_alt;
   int32_t *v = c->perm, *va = c->perm_alt;
   ev_record(c, 17);
-  if ((e = radix_sort_pairs(k, v, ka, va, n, nullptr, 0, 64, c->radix_hist, c->radix_hist_cap, c->scan_tmp,
+  if ((e = radix_sort_pairs(k, v, ka, va, n, nullptr, 0, 3 * MORTON_BITS, c->radix_hist, c->radix_hist_cap, c->scan_tmp,
                             c->scan_tmp_cap, s)) != hipSuccess)
     return e;
   ev_record(c, 18);
