@@ -83,6 +83,17 @@ struct NearTile {
 // non-negative floats as integers, which orders them as the floats.
 constexpr double kMixMargin = 1.0e-5;
 
+// 1/sqrt(x) for a finite x >= 1e-150: the hardware estimate (relative
+// error below 2^-22) and one third-order correction y (1 + e/2 + 3e^2/8),
+// e = 1 - x y^2, which leaves an error far below an ulp.  The library
+// rsqrt also selects the estimate for zero, infinite and denormal x, which
+// cannot occur here (a non-finite position gives a NaN either way).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // The FP64 pair term with the changeover for one near pair (r^2 floored,
 // see near_group), added to (ax, ay, az).
 __device__ __forceinline__ void near_term64(const ForceArgs &A, double dx, double dy, double dz, double r2, double gm,
@@ -93,7 +104,7 @@ __device__ __forceinline__ void near_term64(const ForceArgs &A, double dx, doubl
   // above 1e-134 (it is below half an ulp there) and costs one add instead
   // of a max with operand canonicalisation.
   const double r2s = r2 + kTinyR2;
-  const double rinv = rsqrt(r2s);
+  const double rinv = rsqrt_pos(r2s);
   const double y = r2s * rinv * fmin(invi, invj);
   const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
   const double x2 = x * x;
@@ -227,14 +238,17 @@ __device__ __forceinline__ void near_group(const ForceArgs &A, const GroupHdr &h
             }
           } else {
             const double2 b = T.b[jj + u];
+            const long long rch2j = __double_as_longlong(b.y);
 #pragma unroll
             for (int s = 0; s < IPL; ++s) {
               const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
               const double r2 = dx * dx + dy * dy + dz * dz;
               near_term64(A, dx, dy, dz, r2, a.w, invi[s], b.x, ax[s], ay[s], az[s]);
               // reach^2 of both sides carry the candidate margin already;
-              // evaluated without short-circuit, so no branch per pair
-              const bool cand = (jidx != ii[s]) & ((r2 <= rch2[s]) | (r2 <= b.y));
+              // compared as bit patterns of non-negative doubles (ordered as
+              // the doubles), without short-circuit, so no branch per pair
+              const long long r2q = __double_as_longlong(r2);
+              const bool cand = (jidx != ii[s]) & ((r2q <= __double_as_longlong(rch2[s])) | (r2q <= rch2j));
               cm[half][s] |= cand ? bit : 0u;
             }
           }
