@@ -385,7 +385,7 @@ __device__ __forceinline__ void far_group(const ForceArgs &A, const GroupHdr &h,
           for (int s = 0; s < IPL; ++s) {
             const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double rinv = rsqrt(r2);
+            const double rinv = rsqrt_pos(r2);  // r > 0: beyond the group's reach
             const double f = a.w * rinv * rinv * rinv;
             ax[s] += f * dx;
             ay[s] += f * dy;
@@ -580,7 +580,7 @@ __device__ __forceinline__ void cell_group(const ForceArgs &A, const GroupHdr &h
           for (int s = 0; s < IPL; ++s) {
             const double dx = a.x - xi[s], dy = a.y - yi[s], dz = a.z - zi[s];
             const double r2 = dx * dx + dy * dy + dz * dz;
-            cell_acc<double>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, rsqrt(r2), ax[s], ay[s],
+            cell_acc<double>(dx, dy, dz, a.w, qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, QUAD, rsqrt_pos(r2), ax[s], ay[s],
                              az[s]);
           }
         }
