@@ -83,17 +83,6 @@ struct NearTile {
 // non-negative floats as integers, which orders them as the floats.
 constexpr double kMixMargin = 1.0e-5;
 
-// 1/sqrt(x) for a finite x >= 1e-150: the hardware estimate (relative
-// error below 2^-22) and one third-order correction y (1 + e/2 + 3e^2/8),
-// e = 1 - x y^2, which leaves an error far below an ulp.  The library
-// rsqrt also selects the estimate for zero, infinite and denormal x, which
-// cannot occur here (a non-finite position gives a NaN either way).
-__device__ __forceinline__ double rsqrt_pos(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double e = fma(-x * y, y, 1.0);
-  return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-
 // The FP64 pair term with the changeover for one near pair (r^2 floored,
 // see near_group), added to (ax, ay, az).
 __device__ __forceinline__ void near_term64(const ForceArgs &A, double dx, double dy, double dz, double r2, double gm,

@@ -117,7 +117,7 @@ __device__ __forceinline__ double changeover_W(double y, const HermArgs &A) {
 __device__ __forceinline__ void hard_pair(double dx, double dy, double dz, double ux, double uy, double uz, double gmj,
                                           double invR, const HermArgs &A, double *a, double *jk) {
   const double r2 = fmad(dz, dz, fmad(dy, dy, dx * dx));
-  const double rinv = rsqrt(r2);
+  const double rinv = rsqrt_pos(r2);  // distinct members (coincident ones are flagged before)
   const double y = r2 * rinv * invR;
   const double x = fmin(fmax((y - A.gamma) * A.inv1mg, 0.0), 1.0);
   const double x2 = x * x, x3 = x2 * x;
@@ -140,7 +140,7 @@ __device__ __forceinline__ void hard_pair(double dx, double dy, double dz, doubl
 
 __device__ __forceinline__ void star_term(const double *x, const double *v, double GM, double *a, double *jk) {
   const double r2 = fmad(x[2], x[2], fmad(x[1], x[1], x[0] * x[0]));
-  const double rinv = rsqrt(r2);
+  const double rinv = rsqrt_pos(r2);  // a particle away from the star
   const double rinv3 = rinv * rinv * rinv;
   const double xv = fmad(x[2], v[2], fmad(x[1], v[1], x[0] * v[0]));
   const double c5 = 3.0 * xv * rinv * rinv;

@@ -71,6 +71,17 @@ struct DevCounters {
 };
 
 // ---------------------------------------------------------------- device helpers
+// 1/sqrt(x) for a finite, positive, normal x: the hardware estimate
+// (relative error below 2^-22) and one third-order correction
+// y (1 + e/2 + 3e^2/8), e = 1 - x y^2, which leaves an error below an ulp.
+// The library rsqrt adds selects for zero, infinite and denormal x; callers
+// of this one never pass such an x (a non-finite input gives a NaN).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
 
 __device__ __forceinline__ int popc_below(unsigned long long mask) {
