@@ -168,6 +168,12 @@ __device__ __forceinline__ double dot3(const double *a, const double *b) {
 }
 __device__ __forceinline__ double norm3(const double *a) { return sqrt(dot3(a, a)); }
 
+// The square roots of the Aarseth sums, which only decide the level: x
+// times the corrected hardware reciprocal root (within about an ulp of the
+// rounded root), zero for x = 0.  A non-finite x gives a NaN, which the
+// level search maps to level 0 like any other non-finite criterion.
+__device__ __forceinline__ double root_level(double x) { return x > 0.0 ? x * rsqrt_pos(x) : 0.0; }
+
 // Smallest k >= 0 with P 4^-k <= L (k_max + 1 if none), P = dt_soft^2 den,
 // L = eta num >= 0: the level whose squared step does not exceed the
 // squared Aarseth step.  P = 0 (den = 0) gives level 0, as a step of dt_soft.
@@ -215,8 +221,8 @@ __device__ __forceinline__ void correct(double *x, double *v, double *a0, double
   // eta num, with |a||a2| = sqrt(|a|^2 |a2|^2) (two roots instead of four).
   const double a2e[3] = {fmad(a3[0], h, a2[0]), fmad(a3[1], h, a2[1]), fmad(a3[2], h, a2[2])};
   const double an2 = dot3(a1, a1), jn2 = dot3(j1, j1), a2n2 = dot3(a2e, a2e), a3n2 = dot3(a3, a3);
-  const double num = A.eta * (sqrt(an2 * a2n2) + jn2);
-  const double den = sqrt(jn2 * a3n2) + a2n2;
+  const double num = A.eta * (root_level(an2 * a2n2) + jn2);
+  const double den = root_level(jn2 * a3n2) + a2n2;
   const int knew = level_for_sq(A.dt_soft2 * den, num, A.k_max);
   // grow by at most a factor two, and only on a multiple of the doubled
   // step (lev <= k_max <= 40, so the shift stays below 64)
