@@ -624,6 +624,14 @@ __device__ __forceinline__ int64_t wave_min_uniform(int64_t v) {
 // ceil(log2(v)) for 1 <= v <= 64
 __device__ __forceinline__ int ceil_log2(int v) { return v <= 1 ? 0 : 32 - __clz(v - 1); }
 
+// the same minimum when only lanes [0, size) hold values (the others hold
+// the maximum): a cluster of at most 16 members needs the DPP stages of
+// its own power of two and lane 0 alone (uniform branch on size)
+__device__ __forceinline__ int64_t wave_min_members(int64_t v, int size) {
+  if (size <= 16) return uniform_lane64(seg_min(v, ceil_log2(size)), 0);
+  return wave_min_uniform(v);
+}
+
 // Partner sums (star excluded) of the members listed in L.act[wbase, +n_act)
 // from the states in the LDS slots [wbase, wbase + size): each listed member
 // gets 2^lg lanes, 2^lg = the largest power of two with n_act 2^lg <= 64 and
@@ -832,7 +840,7 @@ __device__ __forceinline__ void wave_body(const HermArgs &A, const int32_t *blis
   bool parked = false;
   for (int it = 0;; ++it) {
     const int64_t te = mem ? t + ((int64_t)1 << (TICK_BITS - lev)) : LLONG_MAX;
-    const int64_t tn = wave_min_uniform(te);
+    const int64_t tn = wave_min_members(te, size);
     if (tn > T) break;  // every member has reached T (see seg_body)
     if (it == budget) {
       parked = true;
