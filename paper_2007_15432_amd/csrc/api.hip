@@ -1174,16 +1174,18 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
     return p3t_evaluate(c, n, pos3, vel3, mass, r_out, r_search, acc3, use_graph);
   }
   if (ns > 0) {
-    // resume, then the direct terms of S, both beside the evaluation below
-    HIP_OK(c, hipMemsetAsync(&c->cnt->n_pairs_d, 0, sizeof(unsigned long long), c->stream));
-    HIP_OK(c, hipMemsetAsync(&c->cnt->status_d, 0, sizeof(unsigned int), c->stream));
+    // resume, then (issued below, after the evaluation's launches) the
+    // direct terms of S, both beside the evaluation
     HIP_OK(c, hipEventRecord(c->slow_ev[0], c->stream));
     HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[0], 0));
     HIP_OK(c, slow_sort(c, ns, c->slow_stream));  // while the chip is free, not behind the tree's kernels
     HIP_OK(c, herm_launch(c, n, n, c->hs_cl_ptr, c->hs_cl_mem, pos3, vel3, mass, r_out_hard, dt_hard, nullptr, nullptr,
                           steps, hc, 0, 1, c->slow_stream, c->aux_stream, c->aux_ev[0], c->aux_ev[1]));
-    HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, ns, c->slow_stream));
-    HIP_OK(c, hipEventRecord(c->slow_ev[1], c->slow_stream));
+    // the direct terms' pair counter and status word, cleared on the main
+    // stream while the resume runs
+    HIP_OK(c, hipMemsetAsync(&c->cnt->n_pairs_d, 0, sizeof(unsigned long long), c->stream));
+    HIP_OK(c, hipMemsetAsync(&c->cnt->status_d, 0, sizeof(unsigned int), c->stream));
+    HIP_OK(c, hipEventRecord(c->slow_ev[2], c->stream));
   }
   // everyone else: tree, walk and force at the new state, S massless (with
   // S empty too, so that a captured evaluation keeps its arguments)
@@ -1191,6 +1193,11 @@ p3t_status p3t_hard_evaluate(p3t_ctx *c, double *pos3, double *vel3, const doubl
   c->slow_active = 1;
   st = eval_enqueue(c, n, pos3, vel3, c->m_eff, r_out, r_search, acc3, use_graph);
   c->slow_active = 0;
+  if (ns > 0) {
+    HIP_OK(c, hipStreamWaitEvent(c->slow_stream, c->slow_ev[2], 0));
+    HIP_OK(c, slow_direct(c, pos3, vel3, mass, r_out, r_search, ns, c->slow_stream));
+    HIP_OK(c, hipEventRecord(c->slow_ev[1], c->slow_stream));
+  }
   // the next hard part's union-find over the pairs written so far, while
   // the main stream would wait for the second one anyway
   if (ns > 0 && st == P3T_OK) HIP_OK(c, labels_pairs_early(c, n));

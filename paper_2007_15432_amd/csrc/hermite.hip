@@ -1829,34 +1829,16 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   // clusters above 1024 members (never parked): the percolated-cluster path
   const int n_huge = resume ? 0 : A.bcount[10];
   const bool big = A.bcount[7] > 0 || A.bcount[8] > 0 || A.bcount[9] > 0 || n_huge > 0;
-  // the single-member drifts and the big clusters go to the second stream
-  // whenever the fused launch runs beside them, and are issued after it, so
-  // that the fused launch (the longest chains) is the first to start
   hipStream_t s2 = s;
-  if ((big || n_single > 0) && blocks > 0 && s_big != s) {
+  if (big && blocks > 0 && s_big != s) {
     s2 = s_big;
     if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s2, ev_fork, 0)) != hipSuccess) return e;
   }
+  if (n_single > 0 && (e = kepler_singles(n, n_single, A.blists, cl_ptr, cl_members, A.GM, P.dt_soft, pos3, vel3,
+                                           dt_hard, steps_out, e_rel_err, n_steps, c->cnt, s2)) != hipSuccess)
+    return e;
   const int mode = resume ? 2 : (budget > 0 ? 1 : 0);
-  if (s2 == s && n_single > 0 &&
-      (e = kepler_singles(n, n_single, A.blists, cl_ptr, cl_members, A.GM, P.dt_soft, pos3, vel3, dt_hard, steps_out,
-                          e_rel_err, n_steps, c->cnt, s)) != hipSuccess)
-    return e;
-  if (blocks > 0) {
-    if (resume)
-      hipLaunchKernelGGL(k_herm_fused<2>, dim3(blocks), dim3(BIG_T), 0, s, A);
-    else if (budget > 0)
-      hipLaunchKernelGGL(k_herm_fused<1>, dim3(blocks), dim3(BIG_T), 0, s, A);
-    else if (collide)
-      hipLaunchKernelGGL((k_herm_fused<0, true>), dim3(blocks), dim3(BIG_T), 0, s, A);
-    else
-      hipLaunchKernelGGL(k_herm_fused<0>, dim3(blocks), dim3(BIG_T), 0, s, A);
-  }
-  if (s2 != s && n_single > 0 &&
-      (e = kepler_singles(n, n_single, A.blists, cl_ptr, cl_members, A.GM, P.dt_soft, pos3, vel3, dt_hard, steps_out,
-                          e_rel_err, n_steps, c->cnt, s2)) != hipSuccess)
-    return e;
 #define P3T_LAUNCH_BIG(MPT, BK)                                                                         \
   if (A.bcount[BK] > 0) {                                                                               \
     if (mode == 2)                                                                                      \
@@ -1870,6 +1852,16 @@ hipError_t herm_launch(p3t_ctx *c, int64_t n, int64_t stride, const int32_t *cl_
   P3T_LAUNCH_BIG(2, 8)
   P3T_LAUNCH_BIG(4, 9)
 #undef P3T_LAUNCH_BIG
+  if (blocks > 0) {
+    if (resume)
+      hipLaunchKernelGGL(k_herm_fused<2>, dim3(blocks), dim3(BIG_T), 0, s, A);
+    else if (budget > 0)
+      hipLaunchKernelGGL(k_herm_fused<1>, dim3(blocks), dim3(BIG_T), 0, s, A);
+    else if (collide)
+      hipLaunchKernelGGL((k_herm_fused<0, true>), dim3(blocks), dim3(BIG_T), 0, s, A);
+    else
+      hipLaunchKernelGGL(k_herm_fused<0>, dim3(blocks), dim3(BIG_T), 0, s, A);
+  }
   // collisions are looked for in clusters of up to 64 members only
   if (collide && big)
     hipLaunchKernelGGL(k_huge_flag, dim3(1), dim3(1), 0, s, c->cnt, (unsigned)P3T_FLAG_COLL_UNCHECKED);

@@ -315,7 +315,7 @@ struct p3t_ctx {
   // slow_stream while the tree of everyone else is evaluated on the main stream
   int slow_active = 0;              // force kernels leave pairs with a parked member alone
   hipStream_t slow_stream = nullptr;
-  hipEvent_t slow_ev[2] = {};
+  hipEvent_t slow_ev[3] = {};
   char *ov_buf = nullptr;           // one allocation for the pointers below
   int64_t ov_n_cap = 0;
   double *pk_x = nullptr, *pk_v = nullptr, *pk_a = nullptr, *pk_j = nullptr;  // parked state (3 n_cap each)
