@@ -206,7 +206,8 @@ p3t_status sync_counters(p3t_ctx *c, DevCounters *h) {
 // is shared with every other call) and drops it.
 void prep_join(p3t_ctx *c) {
   if (c->prep_state) {
-    hipStreamWaitEvent(c->stream, c->prep_ev[1], 0);
+    // if the stream cannot be made to wait, the host waits instead
+    if (hipStreamWaitEvent(c->stream, c->prep_ev[1], 0) != hipSuccess) (void)hipEventSynchronize(c->prep_ev[1]);
     c->prep_state = 0;
   }
 }
@@ -280,7 +281,8 @@ bool prep_take(p3t_ctx *c, int64_t n, int32_t *hc) {
     prep_join(c);
     return false;
   }
-  hipStreamWaitEvent(c->stream, c->prep_ev[1], 0);
+  // the host waits for the preparation (it reads the bucket words), which
+  // also orders everything enqueued after this behind it
   if (hipEventSynchronize(c->prep_ev[1]) != hipSuccess || herm_reset_work(c, c->stream) != hipSuccess) {
     c->prep_state = 0;
     return false;
@@ -312,7 +314,7 @@ p3t_status harvest_status(p3t_ctx *c, unsigned *new_bits) {
 
 namespace p3t {
 void ev_record(p3t_ctx *c, int k) {
-  if (c->timing) hipEventRecord(c->ev[k], c->stream);
+  if (c->timing) (void)hipEventRecord(c->ev[k], c->stream);  // timing only: a failure costs a phase time
 }
 double ev_ms(p3t_ctx *c, int a, int b) {
   float ms = 0.0f;
@@ -375,8 +377,8 @@ void p3t_default_params(p3t_params *P) {
 namespace {
 
 void drop_graph(p3t_ctx *c) {
-  if (c->g_exec) hipGraphExecDestroy(c->g_exec);
-  if (c->g_graph) hipGraphDestroy(c->g_graph);
+  if (c->g_exec) (void)hipGraphExecDestroy(c->g_exec);
+  if (c->g_graph) (void)hipGraphDestroy(c->g_graph);
   c->g_exec = nullptr;
   c->g_graph = nullptr;
   c->g_key = 0;
@@ -438,27 +440,28 @@ p3t_status p3t_create(const p3t_params *p, void *stream, p3t_ctx **out) {
 
 p3t_status p3t_destroy(p3t_ctx *c) {
   if (!c) return P3T_ERR_ARG;
-  hipStreamSynchronize(c->stream);
+  // teardown: errors are ignored, every resource is released regardless
+  (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-  if (c->aux_stream) hipStreamSynchronize(c->aux_stream);
-  if (c->aux_stream) hipStreamDestroy(c->aux_stream);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->aux_stream) (void)hipStreamSynchronize(c->aux_stream);
+  if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
   for (auto &ev : c->aux_ev)
-    if (ev) hipEventDestroy(ev);
-  if (c->slow_stream) hipStreamSynchronize(c->slow_stream);
-  if (c->slow_stream) hipStreamDestroy(c->slow_stream);
+    if (ev) (void)hipEventDestroy(ev);
+  if (c->slow_stream) (void)hipStreamSynchronize(c->slow_stream);
+  if (c->slow_stream) (void)hipStreamDestroy(c->slow_stream);
   for (auto &ev : c->slow_ev)
-    if (ev) hipEventDestroy(ev);
+    if (ev) (void)hipEventDestroy(ev);
   void *bufs[] = {c->arena.base, c->pool,    c->slot_lists, c->slot_stack, c->pairs,
                   c->csr_col,    c->cands,   c->adj_buf,    c->ov_buf,     c->pairs_d,
                   c->huge_buf,   c->coll_buf, c->merge_st,  c->merge_i32};
   for (void *b : bufs)
-    if (b) hipFree(b);
+    if (b) (void)hipFree(b);
   for (auto &e : c->ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (auto &e : c->prep_ev)
-    if (e) hipEventDestroy(e);
-  if (c->hc_pinned) hipHostFree(c->hc_pinned);
+    if (e) (void)hipEventDestroy(e);
+  if (c->hc_pinned) (void)hipHostFree(c->hc_pinned);
   delete c;
   return P3T_OK;
 }

@@ -301,7 +301,6 @@ __global__ __launch_bounds__(MOM_T) void k_moments_local(int n, const double *__
     static_assert(CHUNK * sizeof(p3t::WalkNode) <= sizeof(rec) && CHUNK * sizeof(p3t::CellMom) <= sizeof(rec),
                   "leaf records exceed the staging area");
     p3t::WalkNode *lw = reinterpret_cast<p3t::WalkNode *>(rec);
-    p3t::CellMom *lc = reinterpret_cast<p3t::CellMom *>(rec);
     const uint4 *stage = reinterpret_cast<const uint4 *>(rec);
     // the leaves whose walk record is read (staged, then written as 16-B words)
     for (int t = threadIdx.x; t < count; t += blockDim.x) {
@@ -480,7 +479,6 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
                       const double *r_out, const double *r_search) {
   hipStream_t s = c->stream;
   hipError_t e;
-  const int64_t n_nodes = 2 * n - 1;
   if ((e = bbox_reduce(pos3, n, c->bbox_part, c->bbox, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_morton, dim3(g1d(n)), dim3(256), 0, s, n, pos3, c->bbox, c->keys, c->perm);
   uint64_t *k = c->keys, *ka = c->keys_alt;
