@@ -113,13 +113,16 @@ __global__ void k_uf_link(int64_t n, const int64_t *__restrict__ row_ptr, const 
 
 // The same components straight from the unordered pair list, whose length
 // is read on the device (clamped to the buffer): a component does not
-// depend on the order in which its edges are joined.
+// depend on the order in which its edges are joined.  The list holds every
+// pair in both directions (the neighbour test is symmetric, and the direct
+// terms of parked members report both), so each edge is joined once, from
+// its (smaller, larger) entry.
 __global__ void k_uf_link_pairs(int64_t n, const int2 *__restrict__ pairs, const unsigned long long *__restrict__ np_dev,
                                 int64_t cap, int32_t *p) {
   const int64_t np = (int64_t)*np_dev < cap ? (int64_t)*np_dev : cap;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < np; q += (int64_t)gridDim.x * blockDim.x) {
     const int2 e = pairs[q];
-    if (e.x == e.y || (uint32_t)e.x >= (uint64_t)n || (uint32_t)e.y >= (uint64_t)n) continue;
+    if (e.x >= e.y || (uint32_t)e.x >= (uint64_t)n || (uint32_t)e.y >= (uint64_t)n) continue;
     uf_union(p, e.x, e.y);
   }
 }
@@ -134,7 +137,7 @@ __global__ void k_uf_link_tail(int64_t n, const int2 *__restrict__ pairs, const 
   const int64_t q0 = np - nd > 0 ? np - nd : 0;
   for (int64_t q = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < np; q += (int64_t)gridDim.x * blockDim.x) {
     const int2 e = pairs[q];
-    if (e.x == e.y || (uint32_t)e.x >= (uint64_t)n || (uint32_t)e.y >= (uint64_t)n) continue;
+    if (e.x >= e.y || (uint32_t)e.x >= (uint64_t)n || (uint32_t)e.y >= (uint64_t)n) continue;
     uf_union(p, e.x, e.y);
   }
 }
