@@ -105,6 +105,9 @@ __global__ void k_regather_xm(int64_t n, const int32_t *__restrict__ sid, const 
   }
 }
 
+// leaves per subtree of the bottom-up moments' first phase (see below)
+constexpr int CHUNK = 1024;
+
 // common-prefix length of sorted keys i and j (positions break ties)
 __device__ __forceinline__ int prefix_len(const uint64_t *__restrict__ k, int n, int i, int j) {
   if (j < 0 || j >= n) return -1;
@@ -114,8 +117,11 @@ __device__ __forceinline__ int prefix_len(const uint64_t *__restrict__ k, int n,
 }
 
 // Internal node i of the binary radix tree: its key range and split.
+// Also flags the chunk roots (nodes of at most CHUNK leaves whose parent
+// has more; the root if it has at most CHUNK): every node but the root is
+// flagged by its parent, the root by node 0's thread.
 __global__ void k_radix_tree(int n, const uint64_t *__restrict__ k, p3t::WalkNode *__restrict__ wn,
-                             int32_t *__restrict__ parent) {
+                             int32_t *__restrict__ parent, int32_t *__restrict__ chunk_flag) {
   const int leaf0 = n - 1;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n - 1; i += gridDim.x * blockDim.x) {
     const int d = (prefix_len(k, n, i, i + 1) - prefix_len(k, n, i, i - 1)) > 0 ? 1 : -1;
@@ -143,6 +149,11 @@ __global__ void k_radix_tree(int n, const uint64_t *__restrict__ k, p3t::WalkNod
     parent[left] = i;
     parent[right] = i;
     if (i == 0) parent[0] = -1;  // node 0 is the root and never a child
+    const int count = hi - lo + 1;
+    const int cl = (lo == split) ? 1 : split - lo + 1, cr = (hi == split + 1) ? 1 : hi - split;
+    chunk_flag[left] = (cl <= CHUNK && count > CHUNK) ? 1 : 0;
+    chunk_flag[right] = (cr <= CHUNK && count > CHUNK) ? 1 : 0;
+    if (i == 0) chunk_flag[0] = count <= CHUNK ? 1 : 0;
   }
 }
 
@@ -199,7 +210,7 @@ __device__ __forceinline__ void combine_node(int node, p3t::WalkNode *wn, p3t::C
 //   phase 1: one workgroup per chunk writes the leaf records and climbs to the
 //            chunk root (second arrival at a node combines its children);
 //   phase 2: one workgroup climbs from every chunk root to the tree root.
-constexpr int CHUNK = 1024;
+// (CHUNK is defined with the radix tree, which flags the chunk roots.)
 
 __global__ void k_chunk_flag(int n, const p3t::WalkNode *__restrict__ wn, const int32_t *__restrict__ parent,
                              int32_t *__restrict__ flag) {
@@ -475,6 +486,8 @@ static inline unsigned g1d(int64_t n, int64_t cap = 65536) {
   return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
+static hipError_t moments_pass(p3t_ctx *c, int64_t n, bool chunk_flags_ready);
+
 hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                       const double *r_out, const double *r_search) {
   hipStream_t s = c->stream;
@@ -497,19 +510,22 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
   hipLaunchKernelGGL(k_gather, dim3(g1d(n)), dim3(256), 0, s, n, v, rec, c->sx, c->sy, c->sz, c->svx, c->svy, c->svz,
                      c->sm, c->sro, c->sinv, c->sreach, c->srs, c->sid);
   if (n > 1) {
-    hipLaunchKernelGGL(k_radix_tree, dim3(g1d(n - 1)), dim3(256), 0, s, (int)n, k, c->wnode, c->parent);
+    hipLaunchKernelGGL(k_radix_tree, dim3(g1d(n - 1)), dim3(256), 0, s, (int)n, k, c->wnode, c->parent,
+                       c->group_flag);
   }
-  return tree_moments(c, n);
+  return moments_pass(c, n, n > 1);
 }
 
-// Moments, boxes and groups of the current topology (the bottom-up pass).
-hipError_t tree_moments(p3t_ctx *c, int64_t n) {
+// Moments, boxes and groups of the current topology (the bottom-up pass);
+// chunk_flags_ready: the radix tree has just flagged the chunk roots.
+static hipError_t moments_pass(p3t_ctx *c, int64_t n, bool chunk_flags_ready) {
   hipStream_t s = c->stream;
   hipError_t e;
   const int64_t n_nodes = 2 * n - 1;
   if ((e = fill_i32(c->visit, 0, n > 1 ? n - 1 : 1, s)) != hipSuccess) return e;
   // chunk roots (into group_node / node_scan, both free until the groups are formed)
-  hipLaunchKernelGGL(k_chunk_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n, c->wnode, c->parent, c->group_flag);
+  if (!chunk_flags_ready)
+    hipLaunchKernelGGL(k_chunk_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n, c->wnode, c->parent, c->group_flag);
   if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_chunk_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
@@ -525,6 +541,9 @@ hipError_t tree_moments(p3t_ctx *c, int64_t n) {
                      c->group_node, c->cnt);
   return hipGetLastError();
 }
+
+// the bottom-up pass over the current topology (its chunk roots flagged anew)
+hipError_t tree_moments(p3t_ctx *c, int64_t n) { return moments_pass(c, n, false); }
 
 // Same topology, same lists: positions and masses replaced, moments redone.
 hipError_t refresh_tree(p3t_ctx *c, const double *pos3, const double *mass) {
