@@ -72,7 +72,9 @@ __global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const doub
                          double *__restrict__ sx, double *__restrict__ sy, double *__restrict__ sz,
                          double *__restrict__ svx, double *__restrict__ svy, double *__restrict__ svz,
                          double *__restrict__ sm, double *__restrict__ sro, double *__restrict__ sinv,
-                         double *__restrict__ sreach, double *__restrict__ srs, int32_t *__restrict__ sid) {
+                         double *__restrict__ sreach, double *__restrict__ srs, int32_t *__restrict__ sid,
+                         unsigned long long *__restrict__ n_chunks) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_chunks = 0;  // the radix tree that follows lists the chunk roots
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = perm[k];
     const double *r = rec + PACK * i;
@@ -117,11 +119,14 @@ __device__ __forceinline__ int prefix_len(const uint64_t *__restrict__ k, int n,
 }
 
 // Internal node i of the binary radix tree: its key range and split.
-// Also flags the chunk roots (nodes of at most CHUNK leaves whose parent
-// has more; the root if it has at most CHUNK): every node but the root is
-// flagged by its parent, the root by node 0's thread.
+// Also lists the chunk roots of the moments pass (nodes of at most CHUNK
+// leaves whose parent has more; the root if it has at most CHUNK; each is
+// appended by its parent, the root by node 0's thread, n_chunks zeroed
+// before the launch; their order does not matter) and clears the arrival
+// counter of every internal node.
 __global__ void k_radix_tree(int n, const uint64_t *__restrict__ k, p3t::WalkNode *__restrict__ wn,
-                             int32_t *__restrict__ parent, int32_t *__restrict__ chunk_flag) {
+                             int32_t *__restrict__ parent, int32_t *__restrict__ chunk_list,
+                             unsigned long long *__restrict__ n_chunks, int32_t *__restrict__ visit) {
   const int leaf0 = n - 1;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n - 1; i += gridDim.x * blockDim.x) {
     const int d = (prefix_len(k, n, i, i + 1) - prefix_len(k, n, i, i - 1)) > 0 ? 1 : -1;
@@ -149,11 +154,15 @@ __global__ void k_radix_tree(int n, const uint64_t *__restrict__ k, p3t::WalkNod
     parent[left] = i;
     parent[right] = i;
     if (i == 0) parent[0] = -1;  // node 0 is the root and never a child
+    visit[i] = 0;
     const int count = hi - lo + 1;
     const int cl = (lo == split) ? 1 : split - lo + 1, cr = (hi == split + 1) ? 1 : hi - split;
-    chunk_flag[left] = (cl <= CHUNK && count > CHUNK) ? 1 : 0;
-    chunk_flag[right] = (cr <= CHUNK && count > CHUNK) ? 1 : 0;
-    if (i == 0) chunk_flag[0] = count <= CHUNK ? 1 : 0;
+    if (count > CHUNK) {
+      if (cl <= CHUNK) chunk_list[atomicAdd(n_chunks, 1ull)] = left;
+      if (cr <= CHUNK) chunk_list[atomicAdd(n_chunks, 1ull)] = right;
+    } else if (i == 0) {
+      chunk_list[atomicAdd(n_chunks, 1ull)] = 0;
+    }
   }
 }
 
@@ -486,7 +495,7 @@ static inline unsigned g1d(int64_t n, int64_t cap = 65536) {
   return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
-static hipError_t moments_pass(p3t_ctx *c, int64_t n, bool chunk_flags_ready);
+static hipError_t moments_pass(p3t_ctx *c, int64_t n, bool chunks_ready);
 
 hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *vel3, const double *mass,
                       const double *r_out, const double *r_search) {
@@ -508,28 +517,31 @@ hipError_t build_tree(p3t_ctx *c, int64_t n, const double *pos3, const double *v
   double *rec = reinterpret_cast<double *>(c->wnode);
   hipLaunchKernelGGL(k_pack, dim3(g1d(n)), dim3(256), 0, s, n, pos3, vel3, mass, r_out, r_search, rec);
   hipLaunchKernelGGL(k_gather, dim3(g1d(n)), dim3(256), 0, s, n, v, rec, c->sx, c->sy, c->sz, c->svx, c->svy, c->svz,
-                     c->sm, c->sro, c->sinv, c->sreach, c->srs, c->sid);
+                     c->sm, c->sro, c->sinv, c->sreach, c->srs, c->sid,
+                     &c->cnt->n_chunks);
   if (n > 1) {
     hipLaunchKernelGGL(k_radix_tree, dim3(g1d(n - 1)), dim3(256), 0, s, (int)n, k, c->wnode, c->parent,
-                       c->group_flag);
+                       c->group_node, &c->cnt->n_chunks, c->visit);
   }
   return moments_pass(c, n, n > 1);
 }
 
 // Moments, boxes and groups of the current topology (the bottom-up pass);
-// chunk_flags_ready: the radix tree has just flagged the chunk roots.
-static hipError_t moments_pass(p3t_ctx *c, int64_t n, bool chunk_flags_ready) {
+// chunks_ready: the radix tree has just listed the chunk roots and cleared
+// the arrival counters.
+static hipError_t moments_pass(p3t_ctx *c, int64_t n, bool chunks_ready) {
   hipStream_t s = c->stream;
   hipError_t e;
   const int64_t n_nodes = 2 * n - 1;
-  if ((e = fill_i32(c->visit, 0, n > 1 ? n - 1 : 1, s)) != hipSuccess) return e;
-  // chunk roots (into group_node / node_scan, both free until the groups are formed)
-  if (!chunk_flags_ready)
+  if (!chunks_ready) {
+    if ((e = fill_i32(c->visit, 0, n > 1 ? n - 1 : 1, s)) != hipSuccess) return e;
+    // chunk roots (into group_node / node_scan, both free until the groups are formed)
     hipLaunchKernelGGL(k_chunk_flag, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n, c->wnode, c->parent, c->group_flag);
-  if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_chunk_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag, c->node_scan,
-                     c->group_node, c->cnt);
+    if ((e = scan_i32_to_i64(c->group_flag, c->node_scan, n_nodes, c->scan_tmp, c->scan_tmp_cap, s)) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_chunk_compact, dim3(g1d(n_nodes)), dim3(256), 0, s, (int)n_nodes, c->group_flag,
+                       c->node_scan, c->group_node, c->cnt);
+  }
   hipLaunchKernelGGL(k_moments_local, dim3(c->n_cu * 2), dim3(MOM_T), 0, s, (int)n, c->sx, c->sy, c->sz, c->sm,
                      c->sreach, c->wnode, c->cmom, c->parent, c->visit, c->group_node, c->cnt, c->P.n_leaf_max);
   const unsigned gflag = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (n_nodes + 1023) / 1024));
